@@ -1,0 +1,250 @@
+/*
+ * dobfs.h -- direction-optimized breadth-first search on one AMD Instinct
+ * MI355X (gfx950), exposed as a C ABI.
+ *
+ * Method: Yang, Buluc & Owens, "Implementing Push-Pull Efficiently in
+ * GraphBLAS" (arXiv 1804.03327). One BFS level computes the masked Boolean
+ * matvec f' = A^T f .* not(v) over the semiring ({0,1}, OR, AND, 0)
+ * (Section 4, Algorithm 1) either column-based ("push", Equation 5,
+ * Section 6.2) or row-based with a mask and early exit ("pull", Equation 4,
+ * Algorithm 2, Sections 5.2-5.4); a per-level rule picks the direction
+ * (Section 6.3).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Graph: A(u,v) = 1 for an edge u->v. CSR(A): csr_colind[csr_rowptr[u] ..
+ *    csr_rowptr[u+1]) are the out-neighbours of u (used by push).
+ *    CSC(A): csc_rowind[csc_colptr[v] .. csc_colptr[v+1]) are the
+ *    in-neighbours of v (used by pull). Indices are int32; nnz <= 2^31-1.
+ *    Rows need not be sorted; self-loops and duplicates are accepted. For an
+ *    undirected graph pass the same arrays twice.
+ *  - Bit vectors: bit i of a length-V vector is bit (i & 31) of uint32 word
+ *    i >> 5; ceil(V/32) words. Bits at positions >= V are ignored on input
+ *    and written as 0 on output.
+ *  - Device pointers are HIP device memory of the graph's device. Host
+ *    pointers are ordinary host memory. `stream` is a hipStream_t (NULL =
+ *    the null stream); all device work of a call is ordered on it.
+ *  - Every function returns a dobfs_status. Nothing aborts or throws across
+ *    the ABI. On failure dobfs_last_error() gives a message for the calling
+ *    thread, and no output has been written unless stated.
+ *  - Thread safety: graphs are immutable after creation. Calls on one graph
+ *    from several threads are safe when each passes its own workspace; calls
+ *    that let the library use its internal workspace (workspace = NULL) must
+ *    not overlap on one graph.
+ */
+#ifndef DOBFS_H
+#define DOBFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DOBFS_OK = 0,
+  DOBFS_ERR_INVALID_ARG = 1,         /* bad size, pointer, index or option */
+  DOBFS_ERR_OUT_OF_MEMORY = 2,       /* device or pinned-host allocation failed */
+  DOBFS_ERR_DEVICE = 3,              /* a HIP call failed (no GPU, launch error ...) */
+  DOBFS_ERR_WORKSPACE_TOO_SMALL = 4, /* ws_bytes below the *_workspace_bytes figure */
+  DOBFS_ERR_UNSUPPORTED = 5,         /* option combination not implemented */
+  DOBFS_ERR_INTERNAL = 6
+} dobfs_status;
+
+typedef struct dobfs_graph_s *dobfs_graph;
+
+/* ------------------------------------------------------------------ graphs */
+
+/* Accepted for compatibility; the checks below are always made. */
+enum { DOBFS_UPLOAD_VALIDATE = 1u };
+
+/*
+ * Copy a graph from host memory to device `device` (Section 6: the matrix is
+ * held as CSR for push and CSC for pull). The library owns the device copy
+ * until dobfs_graph_destroy. Checked before anything is allocated: V >= 1,
+ * 0 <= nnz <= 2^31-1, non-null arrays (colind/rowind may be NULL when
+ * nnz = 0), offsets start at 0, never decrease and end at nnz, and every
+ * index lies in [0, V) (O(V + nnz) on the host). flags: 0 or
+ * DOBFS_UPLOAD_VALIDATE. Returns INVALID_ARG on a failed check, DEVICE /
+ * OUT_OF_MEMORY on HIP failures; *out is set only on success. When the CSR
+ * and CSC pointers are the same (an undirected graph), one copy is stored.
+ */
+dobfs_status dobfs_graph_upload(int32_t V, int64_t nnz, const int32_t *csr_rowptr,
+                                const int32_t *csr_colind, const int32_t *csc_colptr,
+                                const int32_t *csc_rowind, int32_t device, uint32_t flags,
+                                dobfs_graph *out);
+
+/*
+ * Same, from arrays already in device memory of `device`. The arrays are
+ * BORROWED: the caller keeps them alive and unchanged until the graph is
+ * destroyed. The same checks run on the device (offsets monotone from 0 to
+ * nnz, indices in [0, V)). Work is ordered on `stream`; the call returns
+ * after it completes.
+ */
+dobfs_status dobfs_graph_wrap_device(int32_t V, int64_t nnz, const int32_t *csr_rowptr,
+                                     const int32_t *csr_colind, const int32_t *csc_colptr,
+                                     const int32_t *csc_rowind, int32_t device, uint32_t flags,
+                                     void *stream, dobfs_graph *out);
+
+/* Free the graph's device memory and its internal workspace. NULL is a no-op. */
+dobfs_status dobfs_graph_destroy(dobfs_graph g);
+
+/* Vertex and edge counts of a graph (either pointer may be NULL). */
+dobfs_status dobfs_graph_info(dobfs_graph g, int32_t *V, int64_t *nnz, int32_t *device);
+
+/* ---------------------------------------------------------- BFS options */
+
+enum {
+  DOBFS_DIR_PUSH = 0, /* column-based masked matvec over CSR(A) (Algorithm 3, Equation 5) */
+  DOBFS_DIR_PULL = 1  /* row-based masked matvec over CSC(A) (Algorithm 2, Equation 4) */
+};
+
+/* Which optimizations of Table 2 are active (each row adds to the previous). */
+enum {
+  DOBFS_MODE_FULL = 0,           /* direction change + masking + early exit + operand reuse */
+  DOBFS_MODE_PUSH_ONLY = 1,      /* push at every level (Table 2 "Structure only") */
+  DOBFS_MODE_PULL_UNMASKED = 2,  /* pull computes every row from the frontier, mask after */
+  DOBFS_MODE_PULL_MASKED = 3,    /* pull computes unvisited rows only, scans whole rows */
+  DOBFS_MODE_PULL_MASKED_EE = 4, /* as above, stopping at the first parent found */
+  DOBFS_MODE_PULL_ONLY = 5       /* FULL's pull at every level (no direction change) */
+};
+
+enum {
+  DOBFS_HEUR_RATIO = 0, /* Section 6.3: r = nnz(f)/V against alpha (up) and beta (down) */
+  DOBFS_HEUR_EDGES = 1  /* Beamer's rule: push->pull when m_f/m_u > alpha; back when nnz(f)/V < beta */
+};
+
+enum {
+  DOBFS_OPT_TIME_KERNELS = 1u /* record HIP events around every launch; fills *_ms stats */
+};
+
+typedef struct {
+  int32_t mode;              /* DOBFS_MODE_* */
+  int32_t heuristic;         /* DOBFS_HEUR_* */
+  float alpha, beta;         /* switch points; 0.01 and 0.01 by default (Section 6.3) */
+  const int8_t *forced_dirs; /* host, optional: direction of levels 0 .. n_forced-1 */
+  int32_t n_forced;          /* levels past n_forced follow the mode and heuristic */
+  uint32_t flags;            /* DOBFS_OPT_* */
+} dobfs_options;
+
+/* Fill *opt with the defaults (FULL, RATIO, alpha = beta = 0.01). */
+dobfs_status dobfs_options_default(dobfs_options *opt);
+
+/*
+ * The direction rule of Section 6.3 as a pure host function. After a level
+ * run in direction `dir` that turned a frontier of nf vertices into one of
+ * n_new vertices, returns the direction for the next level:
+ *   RATIO: push->pull when n_new > nf and n_new > alpha*V;
+ *          pull->push when n_new < nf and n_new < beta*V; otherwise unchanged.
+ *   EDGES: push->pull when m_f > alpha*m_u (m_f = out-edges of the new
+ *          frontier, m_u = out-edges of unvisited vertices);
+ *          pull->push when n_new < beta*V.
+ * alpha and beta are compared in double precision.
+ */
+int32_t dobfs_next_direction(const dobfs_options *opt, int32_t dir, int64_t V, int64_t nf,
+                             int64_t n_new, int64_t m_f, int64_t m_u);
+
+/* ---------------------------------------------------------- statistics */
+
+typedef struct {
+  int32_t dir;     /* direction of this level */
+  int32_t nf;      /* frontier size entering the level, nnz(f) */
+  int32_t n_new;   /* vertices discovered by the level */
+  int32_t pad;
+  int64_t edges;   /* push: nnz(m_f^+) adjacency entries read; pull: in-neighbours checked */
+  int64_t m_f;     /* push: out-edges of the input frontier (0 on pull levels) */
+  float ms_main;   /* push expand or pull kernel time (DOBFS_OPT_TIME_KERNELS), else 0 */
+  float ms_aux;    /* push scan + format conversion time, else 0 */
+} dobfs_level_stats;
+
+typedef struct {
+  int32_t levels;           /* levels run (the last one discovers nothing) */
+  int32_t cap;              /* capacity of `level` (caller sets; may be 0) */
+  dobfs_level_stats *level; /* host array of cap entries, caller-owned, may be NULL */
+  float ms_total;           /* device time of the whole call (events) */
+  float ms_init;            /* init kernel time (DOBFS_OPT_TIME_KERNELS) */
+  int64_t reached;          /* vertices with depth >= 0 */
+} dobfs_stats;
+
+/* ----------------------------------------------------------------- BFS */
+
+/*
+ * Device bytes of workspace one dobfs_bfs call on graph g needs (two visited
+ * bitmaps, two frontier bitmaps, two frontier queues of V entries, the push
+ * scan arrays and a small control block). opt may be NULL.
+ */
+dobfs_status dobfs_bfs_workspace_bytes(dobfs_graph g, const dobfs_options *opt, size_t *bytes);
+
+/*
+ * Breadth-first search from `source` (Algorithm 1). On return
+ *   depth[v]  = hops on a shortest path source->v, -1 if unreachable
+ *               (Algorithm 1's level numbers minus one: source 0);
+ *   parent[v] = an in-neighbour u of v with depth[u] = depth[v]-1,
+ *               parent[source] = source, -1 if unreachable. On pull levels
+ *               it is the first such u in CSC order (early exit); on push
+ *               levels any such u.
+ * depth: device int32[V], required. parent: device int32[V] or NULL.
+ * workspace: device memory of at least dobfs_bfs_workspace_bytes, or NULL
+ * for a library-owned one. stats: host, optional (opt->flags may add
+ * per-kernel times). The call blocks until results are final (the level loop
+ * reads one small counter block back per level). source outside [0,V) ->
+ * INVALID_ARG with nothing written.
+ */
+dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options *opt, int32_t *depth,
+                       int32_t *parent, void *workspace, size_t ws_bytes, void *stream,
+                       dobfs_stats *stats);
+
+/* -------------------------------------------------------- standalone mxv */
+
+enum {
+  DOBFS_MXV_EARLY_EXIT = 1u, /* pull: stop a row at its first hit (Algorithm 2, break) */
+  DOBFS_MXV_ACCUM_OR = 2u    /* y = y OR result instead of y = result (Algorithms 2-3, accum) */
+};
+
+/* Device bytes of workspace a dobfs_mxv call on g needs. */
+dobfs_status dobfs_mxv_workspace_bytes(dobfs_graph g, size_t *bytes);
+
+/*
+ * y = (A^T x) .* m over ({0,1}, OR, AND, 0) (Equations 2-5, Section 3.2):
+ *   t(i)    = OR over edges j->i of x(j)
+ *   pass(i) = mask_bits == NULL ? 1 : (mask(i) XOR complement)
+ *   y(i)    = ACCUM_OR ? y(i) OR (t(i) AND pass(i)) : t(i) AND pass(i)
+ * The four variants of Section 6.3 / Table 1:
+ *   direction PULL, mask NULL : ROW_MXV        (every row)
+ *   direction PULL, mask      : ROW_MASKED_MXV (rows that pass only)
+ *   direction PUSH, mask NULL : COL_MXV
+ *   direction PUSH, mask      : COL_MASKED_MXV (expand, dedupe, then filter)
+ * x is given as a device bit vector x_bits, or (x_bits NULL) as a device
+ * index list x_idx[0..x_nnz) of distinct vertices; the call converts it to
+ * the form its direction reads (dense for pull, sparse for push).
+ * EARLY_EXIT applies to pull only (a column-based matvec cannot exit early).
+ * Outputs (device): y_bits (required, ceil(V/32) words); y_idx (optional,
+ * int32[V]): the set bits of y in ascending order; y_witness (optional,
+ * int32[V]): for every i with t(i) AND pass(i), a j with x(j) = 1 and an edge
+ * j->i (pull: the first in CSC order); other entries are left unchanged.
+ * y_nnz (host, optional): popcount of y; when y_nnz or y_idx is given the
+ * call blocks until done, otherwise it only enqueues work on `stream`.
+ */
+dobfs_status dobfs_mxv(dobfs_graph g, const uint32_t *x_bits, const int32_t *x_idx,
+                       int32_t x_nnz, const uint32_t *mask_bits, int32_t complement,
+                       int32_t direction, uint32_t flags, uint32_t *y_bits, int32_t *y_idx,
+                       int32_t *y_witness, int32_t *y_nnz, void *workspace, size_t ws_bytes,
+                       void *stream);
+
+/* ------------------------------------------------------------- errors */
+
+/* Static name of a status code. */
+const char *dobfs_status_string(dobfs_status s);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char *dobfs_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t dobfs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DOBFS_H */

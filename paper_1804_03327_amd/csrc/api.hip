@@ -1,0 +1,711 @@
+// Host runtime and C ABI of libdobfs (declared in include/dobfs.h).
+//
+// The BFS level loop of Algorithm 1 runs on the host: each level launches the
+// push kernels (scan + load-balanced expand) or the pull kernel, then reads a
+// 32-byte counter block back (nnz of the new frontier, edges touched), and
+// applies the direction rule of Section 6.3 to pick the next level's kernel.
+
+#include "dobfs.h"
+#include "dobfs_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+using namespace dobfs;
+
+struct dobfs_graph_s {
+  int device = 0;
+  int32_t V = 0;
+  int64_t nnz = 0;
+  int32_t nwords = 0;
+  const int32_t* rowptr = nullptr;  // CSR(A)
+  const int32_t* colind = nullptr;
+  const int32_t* colptr = nullptr;  // CSC(A)
+  const int32_t* rowind = nullptr;
+  uint32_t* nz_in = nullptr;        // rows of CSC(A) with at least one entry
+  void* owned[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::mutex mu;                    // guards the internal workspace
+  void* ws = nullptr;
+  size_t ws_size = 0;
+};
+
+namespace {
+
+thread_local std::string t_last_error;
+
+dobfs_status fail(dobfs_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  t_last_error = buf;
+  return s;
+}
+
+dobfs_status hip_fail(hipError_t e, const char* what, int line) {
+  return fail(e == hipErrorOutOfMemory ? DOBFS_ERR_OUT_OF_MEMORY : DOBFS_ERR_DEVICE,
+              "%s failed: %s (api.hip:%d)", what, hipGetErrorString(e), line);
+}
+
+#define HIPCK(expr)                                               \
+  do {                                                            \
+    hipError_t e_ = (expr);                                       \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr, __LINE__);  \
+  } while (0)
+
+// Makes `device` current for the scope of a call and restores the caller's.
+struct DeviceScope {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceScope(int device) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    err = hipSetDevice(device);
+  }
+  ~DeviceScope() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace layout of one call (BFS and mxv share it).
+struct Layout {
+  size_t visA, visB, FA, FB, Q0, Q1, S, R, flags, ctrl, total;
+  int64_t nflags;
+};
+
+Layout plan(int32_t V) {
+  Layout L{};
+  const size_t wb = size_t(words_of(V)) * 4, vb = size_t(V) * 4;
+  L.nflags = std::max<int64_t>(scan_tiles(V), d2s_tiles(words_of(V))) + 1;
+  size_t cur = 0;
+  auto take = [&](size_t bytes) {
+    size_t off = cur;
+    cur += align_up(bytes);
+    return off;
+  };
+  L.visA = take(wb);
+  L.visB = take(wb);
+  L.FA = take(wb);
+  L.FB = take(wb);
+  L.Q0 = take(vb);
+  L.Q1 = take(vb);
+  L.S = take(vb);
+  L.R = take(vb);
+  L.flags = take(size_t(L.nflags) * 8);
+  L.ctrl = take(sizeof(Ctrl));
+  L.total = cur;
+  return L;
+}
+
+// Pinned host copy of the control block, one per thread (never freed: it
+// must outlive any call and HIP may already be torn down at thread exit).
+Ctrl* host_ctrl() {
+  thread_local Ctrl* p = nullptr;
+  if (!p) {
+    void* q = nullptr;
+    if (hipHostMalloc(&q, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) return nullptr;
+    p = static_cast<Ctrl*>(q);
+  }
+  return p;
+}
+
+// Per-thread, per-device events for the level loop's timers.
+constexpr int kEvents = 6;
+hipEvent_t* events_for(int device) {
+  thread_local hipEvent_t ev[16][kEvents];
+  thread_local bool made[16] = {};
+  if (device < 0 || device >= 16) return nullptr;
+  if (!made[device]) {
+    for (int k = 0; k < kEvents; ++k)
+      if (hipEventCreate(&ev[device][k]) != hipSuccess) return nullptr;
+    made[device] = true;
+  }
+  return ev[device];
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+  return ms;
+}
+
+dobfs_options defaults() {
+  dobfs_options o;
+  std::memset(&o, 0, sizeof o);
+  o.mode = DOBFS_MODE_FULL;
+  o.heuristic = DOBFS_HEUR_RATIO;
+  o.alpha = 0.01f;
+  o.beta = 0.01f;
+  return o;
+}
+
+dobfs_status check_options(const dobfs_options& o) {
+  if (o.mode < DOBFS_MODE_FULL || o.mode > DOBFS_MODE_PULL_ONLY)
+    return fail(DOBFS_ERR_INVALID_ARG, "unknown mode %d", o.mode);
+  if (o.heuristic != DOBFS_HEUR_RATIO && o.heuristic != DOBFS_HEUR_EDGES)
+    return fail(DOBFS_ERR_INVALID_ARG, "unknown heuristic %d", o.heuristic);
+  if (!std::isfinite(o.alpha) || !std::isfinite(o.beta) || o.alpha < 0.f || o.beta < 0.f)
+    return fail(DOBFS_ERR_INVALID_ARG, "alpha and beta must be finite and >= 0");
+  if (o.n_forced < 0 || (o.n_forced > 0 && !o.forced_dirs))
+    return fail(DOBFS_ERR_INVALID_ARG, "forced_dirs missing for n_forced = %d", o.n_forced);
+  for (int32_t k = 0; k < o.n_forced; ++k)
+    if (o.forced_dirs[k] != DOBFS_DIR_PUSH && o.forced_dirs[k] != DOBFS_DIR_PULL)
+      return fail(DOBFS_ERR_INVALID_ARG, "forced_dirs[%d] = %d is not a direction", k,
+                  int(o.forced_dirs[k]));
+  if (o.flags & ~uint32_t(DOBFS_OPT_TIME_KERNELS))
+    return fail(DOBFS_ERR_INVALID_ARG, "unknown option flags 0x%x", o.flags);
+  return DOBFS_OK;
+}
+
+dobfs_status check_offsets_host(int32_t V, int64_t nnz, const int32_t* ptr, const char* name) {
+  if (ptr[0] != 0) return fail(DOBFS_ERR_INVALID_ARG, "%s[0] = %d, expected 0", name, ptr[0]);
+  for (int32_t i = 0; i < V; ++i)
+    if (ptr[i + 1] < ptr[i])
+      return fail(DOBFS_ERR_INVALID_ARG, "%s decreases at %d (%d -> %d)", name, i, ptr[i],
+                  ptr[i + 1]);
+  if (int64_t(ptr[V]) != nnz)
+    return fail(DOBFS_ERR_INVALID_ARG, "%s[V] = %d, expected nnz = %lld", name, ptr[V],
+                (long long)nnz);
+  return DOBFS_OK;
+}
+
+dobfs_status check_args(int32_t V, int64_t nnz, const void* a, const void* b, const void* c,
+                        const void* d, int32_t device, dobfs_graph* out) {
+  if (!out) return fail(DOBFS_ERR_INVALID_ARG, "out is NULL");
+  if (V < 1 || V > INT32_MAX - 64) return fail(DOBFS_ERR_INVALID_ARG, "V = %d out of range", V);
+  if (nnz < 0 || nnz > INT32_MAX)
+    return fail(DOBFS_ERR_INVALID_ARG, "nnz = %lld out of range [0, 2^31-1]", (long long)nnz);
+  if (!a || !c) return fail(DOBFS_ERR_INVALID_ARG, "row/column offset array is NULL");
+  if (nnz > 0 && (!b || !d)) return fail(DOBFS_ERR_INVALID_ARG, "index array is NULL");
+  if (device < 0) return fail(DOBFS_ERR_INVALID_ARG, "device %d", device);
+  return DOBFS_OK;
+}
+
+dobfs_status check_device(int32_t device) {
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0) return fail(DOBFS_ERR_DEVICE, "no HIP device available");
+  if (device < 0 || device >= n)
+    return fail(DOBFS_ERR_INVALID_ARG, "device %d not in [0, %d)", device, n);
+  return DOBFS_OK;
+}
+
+dobfs_status finish_graph(dobfs_graph g, hipStream_t s) {
+  void* p = nullptr;
+  HIPCK(hipMalloc(&p, size_t(std::max(g->nwords, 1)) * 4));
+  g->nz_in = static_cast<uint32_t*>(p);
+  HIPCK(launch_nz_bits(s, g->colptr, g->V, g->nz_in));
+  HIPCK(hipStreamSynchronize(s));
+  return DOBFS_OK;
+}
+
+void free_graph(dobfs_graph g) {
+  if (!g) return;
+  for (void* p : g->owned)
+    if (p) (void)hipFree(p);
+  if (g->nz_in) (void)hipFree(g->nz_in);
+  if (g->ws) (void)hipFree(g->ws);
+  delete g;
+}
+
+// Workspace for a call: the caller's, or the graph's own (grown on demand;
+// the lock is held for the duration of the call).
+dobfs_status get_workspace(dobfs_graph g, void* workspace, size_t ws_bytes, size_t need,
+                           std::unique_lock<std::mutex>& lock, uint8_t** base) {
+  if (workspace) {
+    if (ws_bytes < need)
+      return fail(DOBFS_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes,
+                  need);
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+      return fail(DOBFS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    *base = static_cast<uint8_t*>(workspace);
+    return DOBFS_OK;
+  }
+  lock = std::unique_lock<std::mutex>(g->mu);
+  if (g->ws_size < need) {
+    if (g->ws) {
+      HIPCK(hipDeviceSynchronize());
+      HIPCK(hipFree(g->ws));
+      g->ws = nullptr;
+      g->ws_size = 0;
+    }
+    HIPCK(hipMalloc(&g->ws, need));
+    g->ws_size = need;
+  }
+  *base = static_cast<uint8_t*>(g->ws);
+  return DOBFS_OK;
+}
+
+// Number of blocks for the push expand kernel: it strides over edge chunks,
+// so a fixed grid that fills the GPU several times suffices.
+constexpr int32_t kExpandBlocks = 2048;
+
+}  // namespace
+
+extern "C" {
+
+const char* dobfs_status_string(dobfs_status s) {
+  switch (s) {
+    case DOBFS_OK: return "DOBFS_OK";
+    case DOBFS_ERR_INVALID_ARG: return "DOBFS_ERR_INVALID_ARG";
+    case DOBFS_ERR_OUT_OF_MEMORY: return "DOBFS_ERR_OUT_OF_MEMORY";
+    case DOBFS_ERR_DEVICE: return "DOBFS_ERR_DEVICE";
+    case DOBFS_ERR_WORKSPACE_TOO_SMALL: return "DOBFS_ERR_WORKSPACE_TOO_SMALL";
+    case DOBFS_ERR_UNSUPPORTED: return "DOBFS_ERR_UNSUPPORTED";
+    case DOBFS_ERR_INTERNAL: return "DOBFS_ERR_INTERNAL";
+  }
+  return "DOBFS_ERR_UNKNOWN";
+}
+
+const char* dobfs_last_error(void) { return t_last_error.c_str(); }
+
+int32_t dobfs_version(void) { return 100; }
+
+dobfs_status dobfs_options_default(dobfs_options* opt) {
+  if (!opt) return fail(DOBFS_ERR_INVALID_ARG, "opt is NULL");
+  *opt = defaults();
+  return DOBFS_OK;
+}
+
+int32_t dobfs_next_direction(const dobfs_options* opt, int32_t dir, int64_t V, int64_t nf,
+                             int64_t n_new, int64_t m_f, int64_t m_u) {
+  const dobfs_options o = opt ? *opt : defaults();
+  const double a = double(o.alpha), b = double(o.beta);
+  if (o.heuristic == DOBFS_HEUR_EDGES) {
+    if (dir == DOBFS_DIR_PUSH) return double(m_f) > a * double(m_u) ? DOBFS_DIR_PULL : DOBFS_DIR_PUSH;
+    return double(n_new) < b * double(V) ? DOBFS_DIR_PUSH : DOBFS_DIR_PULL;
+  }
+  if (dir == DOBFS_DIR_PUSH)
+    return (n_new > nf && double(n_new) > a * double(V)) ? DOBFS_DIR_PULL : DOBFS_DIR_PUSH;
+  return (n_new < nf && double(n_new) < b * double(V)) ? DOBFS_DIR_PUSH : DOBFS_DIR_PULL;
+}
+
+dobfs_status dobfs_graph_upload(int32_t V, int64_t nnz, const int32_t* csr_rowptr,
+                                const int32_t* csr_colind, const int32_t* csc_colptr,
+                                const int32_t* csc_rowind, int32_t device, uint32_t flags,
+                                dobfs_graph* out) {
+  t_last_error.clear();
+  dobfs_status st = check_args(V, nnz, csr_rowptr, csr_colind, csc_colptr, csc_rowind, device, out);
+  if (st != DOBFS_OK) return st;
+  if (flags & ~uint32_t(DOBFS_UPLOAD_VALIDATE))
+    return fail(DOBFS_ERR_INVALID_ARG, "unknown upload flags 0x%x", flags);
+  if ((st = check_offsets_host(V, nnz, csr_rowptr, "csr_rowptr")) != DOBFS_OK) return st;
+  if ((st = check_offsets_host(V, nnz, csc_colptr, "csc_colptr")) != DOBFS_OK) return st;
+  {  // indices are always checked: an out-of-range entry would send kernels out of bounds
+    for (int64_t p = 0; p < nnz; ++p) {
+      if (csr_colind[p] < 0 || csr_colind[p] >= V)
+        return fail(DOBFS_ERR_INVALID_ARG, "csr_colind[%lld] = %d out of range", (long long)p,
+                    csr_colind[p]);
+      if (csc_rowind[p] < 0 || csc_rowind[p] >= V)
+        return fail(DOBFS_ERR_INVALID_ARG, "csc_rowind[%lld] = %d out of range", (long long)p,
+                    csc_rowind[p]);
+    }
+  }
+  if ((st = check_device(device)) != DOBFS_OK) return st;
+  DeviceScope ds(device);
+  if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice", __LINE__);
+  dobfs_graph g = new dobfs_graph_s;
+  g->device = device;
+  g->V = V;
+  g->nnz = nnz;
+  g->nwords = words_of(V);
+  const bool shared = (csr_rowptr == csc_colptr) && (csr_colind == csc_rowind);
+  auto upload = [&](const int32_t* src, size_t n, int slot) -> const int32_t* {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(n, 1) * 4) != hipSuccess) return nullptr;
+    g->owned[slot] = p;
+    if (n && hipMemcpy(p, src, n * 4, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    return static_cast<const int32_t*>(p);
+  };
+  g->rowptr = upload(csr_rowptr, size_t(V) + 1, 0);
+  g->colind = g->rowptr ? upload(csr_colind, size_t(nnz), 1) : nullptr;
+  if (shared) {
+    g->colptr = g->rowptr;
+    g->rowind = g->colind;
+  } else if (g->colind) {
+    g->colptr = upload(csc_colptr, size_t(V) + 1, 2);
+    g->rowind = g->colptr ? upload(csc_rowind, size_t(nnz), 3) : nullptr;
+  }
+  if (!g->rowptr || !g->colind || !g->colptr || !g->rowind) {
+    hipError_t e = hipGetLastError();
+    free_graph(g);
+    return hip_fail(e == hipSuccess ? hipErrorOutOfMemory : e, "graph upload", __LINE__);
+  }
+  if ((st = finish_graph(g, nullptr)) != DOBFS_OK) {
+    free_graph(g);
+    return st;
+  }
+  *out = g;
+  return DOBFS_OK;
+}
+
+dobfs_status dobfs_graph_wrap_device(int32_t V, int64_t nnz, const int32_t* csr_rowptr,
+                                     const int32_t* csr_colind, const int32_t* csc_colptr,
+                                     const int32_t* csc_rowind, int32_t device, uint32_t flags,
+                                     void* stream, dobfs_graph* out) {
+  t_last_error.clear();
+  dobfs_status st = check_args(V, nnz, csr_rowptr, csr_colind, csc_colptr, csc_rowind, device, out);
+  if (st != DOBFS_OK) return st;
+  if (flags & ~uint32_t(DOBFS_UPLOAD_VALIDATE))
+    return fail(DOBFS_ERR_INVALID_ARG, "unknown upload flags 0x%x", flags);
+  if ((st = check_device(device)) != DOBFS_OK) return st;
+  DeviceScope ds(device);
+  if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice", __LINE__);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int32_t* err = nullptr;
+  HIPCK(hipMalloc(&err, 4));
+  int32_t herr = 0;
+  hipError_t e = hipMemsetAsync(err, 0, 4, s);
+  if (e == hipSuccess) e = launch_check_offsets(s, csr_rowptr, V, nnz, err);
+  if (e == hipSuccess) e = launch_check_offsets(s, csc_colptr, V, nnz, err);
+  if (e == hipSuccess && nnz > 0) {  // indices always checked (see dobfs_graph_upload)
+    e = launch_check_indices(s, csr_colind, nnz, V, err);
+    if (e == hipSuccess) e = launch_check_indices(s, csc_rowind, nnz, V, err);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(err);
+  if (e != hipSuccess) return hip_fail(e, "device offset check", __LINE__);
+  if (herr) return fail(DOBFS_ERR_INVALID_ARG, "device graph arrays failed checks (code %d)", herr);
+  dobfs_graph g = new dobfs_graph_s;
+  g->device = device;
+  g->V = V;
+  g->nnz = nnz;
+  g->nwords = words_of(V);
+  g->rowptr = csr_rowptr;
+  g->colind = csr_colind;
+  g->colptr = csc_colptr;
+  g->rowind = csc_rowind;
+  if ((st = finish_graph(g, s)) != DOBFS_OK) {
+    free_graph(g);
+    return st;
+  }
+  *out = g;
+  return DOBFS_OK;
+}
+
+dobfs_status dobfs_graph_destroy(dobfs_graph g) {
+  t_last_error.clear();
+  if (!g) return DOBFS_OK;
+  DeviceScope ds(g->device);
+  free_graph(g);
+  return DOBFS_OK;
+}
+
+dobfs_status dobfs_graph_info(dobfs_graph g, int32_t* V, int64_t* nnz, int32_t* device) {
+  if (!g) return fail(DOBFS_ERR_INVALID_ARG, "graph is NULL");
+  if (V) *V = g->V;
+  if (nnz) *nnz = g->nnz;
+  if (device) *device = g->device;
+  return DOBFS_OK;
+}
+
+dobfs_status dobfs_bfs_workspace_bytes(dobfs_graph g, const dobfs_options* opt, size_t* bytes) {
+  (void)opt;
+  if (!g || !bytes) return fail(DOBFS_ERR_INVALID_ARG, "graph or bytes is NULL");
+  *bytes = plan(g->V).total;
+  return DOBFS_OK;
+}
+
+dobfs_status dobfs_mxv_workspace_bytes(dobfs_graph g, size_t* bytes) {
+  if (!g || !bytes) return fail(DOBFS_ERR_INVALID_ARG, "graph or bytes is NULL");
+  *bytes = plan(g->V).total;
+  return DOBFS_OK;
+}
+
+dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_in, int32_t* depth,
+                       int32_t* parent, void* workspace, size_t ws_bytes, void* stream,
+                       dobfs_stats* stats) {
+  t_last_error.clear();
+  if (!g) return fail(DOBFS_ERR_INVALID_ARG, "graph is NULL");
+  if (!depth) return fail(DOBFS_ERR_INVALID_ARG, "depth is NULL");
+  if (source < 0 || source >= g->V)
+    return fail(DOBFS_ERR_INVALID_ARG, "source %d not in [0, %d)", source, g->V);
+  const dobfs_options opt = opt_in ? *opt_in : defaults();
+  dobfs_status st = check_options(opt);
+  if (st != DOBFS_OK) return st;
+  if (stats && stats->cap > 0 && !stats->level)
+    return fail(DOBFS_ERR_INVALID_ARG, "stats->level is NULL with cap = %d", stats->cap);
+
+  DeviceScope ds(g->device);
+  if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice", __LINE__);
+  const Layout L = plan(g->V);
+  std::unique_lock<std::mutex> lock;
+  uint8_t* ws = nullptr;
+  if ((st = get_workspace(g, workspace, ws_bytes, L.total, lock, &ws)) != DOBFS_OK) return st;
+  Ctrl* host = host_ctrl();
+  if (!host) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
+  hipEvent_t* ev = events_for(g->device);
+  if (!ev) return fail(DOBFS_ERR_DEVICE, "event creation failed");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  const int32_t V = g->V, nwords = g->nwords;
+  uint32_t* vis = reinterpret_cast<uint32_t*>(ws + L.visA);
+  uint32_t* vis_other = reinterpret_cast<uint32_t*>(ws + L.visB);
+  uint32_t* fcur = reinterpret_cast<uint32_t*>(ws + L.FA);
+  uint32_t* fnext = reinterpret_cast<uint32_t*>(ws + L.FB);
+  int32_t* qcur = reinterpret_cast<int32_t*>(ws + L.Q0);
+  int32_t* qnext = reinterpret_cast<int32_t*>(ws + L.Q1);
+  int32_t* S = reinterpret_cast<int32_t*>(ws + L.S);
+  int32_t* R = reinterpret_cast<int32_t*>(ws + L.R);
+  uint64_t* flags = reinterpret_cast<uint64_t*>(ws + L.flags);
+  Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
+
+  const bool timing = (opt.flags & DOBFS_OPT_TIME_KERNELS) != 0;
+  const bool reuse = opt.mode == DOBFS_MODE_FULL || opt.mode == DOBFS_MODE_PULL_ONLY ||
+                     opt.mode == DOBFS_MODE_PUSH_ONLY;
+  const bool early_exit = opt.mode != DOBFS_MODE_PULL_MASKED && opt.mode != DOBFS_MODE_PULL_UNMASKED;
+  const bool mask_after = opt.mode == DOBFS_MODE_PULL_UNMASKED;
+  const bool edges_rule = opt.heuristic == DOBFS_HEUR_EDGES;
+  const int32_t* out_rowptr = edges_rule ? g->rowptr : nullptr;
+
+  HIPCK(hipEventRecord(ev[0], s));
+  HIPCK(launch_bfs_init(s, V, nwords, source, g->rowptr, depth, parent, vis, qcur, ctrl, flags,
+                        L.nflags));
+  if (timing) HIPCK(hipEventRecord(ev[1], s));
+
+  int32_t dir = opt.mode == DOBFS_MODE_PULL_ONLY ? DOBFS_DIR_PULL : DOBFS_DIR_PUSH;
+  int64_t nf = 1, reached = 1, m_u = -1;
+  bool queue_valid = true, f_valid = false;
+  unsigned long long tb = 0;
+  uint32_t epoch = 1;
+  int32_t level = 0;
+  float ms_init = 0.f;
+  for (;;) {
+    if (level < opt.n_forced) dir = opt.forced_dirs[level];
+    LevelSlot* slot = &ctrl->slot[level % kSlots];
+    LevelSlot* reset = &ctrl->slot[(level + 1) % kSlots];
+    if (timing) HIPCK(hipEventRecord(ev[2], s));
+    if (dir == DOBFS_DIR_PUSH) {
+      if (!queue_valid) {
+        // pull -> push: the discovered set becomes a sorted list (DENSE2SPARSE)
+        HIPCK(launch_d2s(s, reuse ? vis : fcur, reuse ? vis_other : nullptr, nwords, V, qcur, ctrl,
+                         tb, epoch, flags, &ctrl->d2s_count));
+        tb += (unsigned long long)d2s_tiles(nwords);
+        ++epoch;
+        queue_valid = true;
+      }
+      const int64_t tiles = std::max<int64_t>(1, scan_tiles(nf));
+      HIPCK(launch_push_scan(s, tiles, qcur, int32_t(nf), nullptr, g->rowptr, S, R, ctrl, tb, epoch,
+                             flags, slot, reset));
+      tb += (unsigned long long)tiles;
+      ++epoch;
+      if (timing) HIPCK(hipEventRecord(ev[3], s));
+      ExpandArgs ea{};
+      ea.Q = qcur;
+      ea.nf = int32_t(nf);
+      ea.S = S;
+      ea.R = R;
+      ea.colind = g->colind;
+      ea.ctrl = ctrl;
+      ea.claim = vis;
+      ea.depth = depth;
+      ea.parent = parent;
+      ea.level = level;
+      ea.Qout = qnext;
+      ea.out_rowptr = out_rowptr;
+      ea.slot = slot;
+      ea.reset = reset;
+      HIPCK(launch_push_expand(s, kExpandBlocks, ea));
+      std::swap(qcur, qnext);
+      f_valid = false;
+    } else {
+      if (!reuse && !f_valid) {
+        // push -> pull without operand reuse: the frontier list becomes a bit vector (SPARSE2DENSE)
+        HIPCK(launch_fill(s, fcur, nwords, 0u));
+        HIPCK(launch_s2d(s, qcur, int32_t(nf), nullptr, V, fcur));
+        f_valid = true;
+      }
+      if (timing) HIPCK(hipEventRecord(ev[3], s));
+      PullArgs pa{};
+      pa.V = V;
+      pa.nwords = nwords;
+      pa.colptr = g->colptr;
+      pa.rowind = g->rowind;
+      pa.x = reuse ? vis : fcur;  // operand reuse: A^T v .* not(v) (Section 5.4)
+      pa.mask = vis;
+      pa.complement = 1;
+      pa.mask_after = mask_after ? 1 : 0;
+      pa.nz = g->nz_in;
+      pa.out_base = vis;
+      pa.out = vis_other;
+      pa.found_out = reuse ? nullptr : fnext;
+      pa.depth = depth;
+      pa.parent = parent;
+      pa.level = level;
+      pa.out_rowptr = out_rowptr;
+      pa.slot = slot;
+      pa.reset = reset;
+      HIPCK(launch_pull(s, early_exit, pa));
+      std::swap(vis, vis_other);
+      if (!reuse) {
+        std::swap(fcur, fnext);
+        f_valid = true;
+      }
+      queue_valid = false;
+    }
+    if (timing) HIPCK(hipEventRecord(ev[4], s));
+    HIPCK(hipMemcpyAsync(host, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    const LevelSlot r = host->slot[level % kSlots];
+    const int64_t n_new = r.count;
+    if (level == 0) {
+      if (timing) ms_init = elapsed(ev[0], ev[1]);
+      m_u = g->nnz - host->src_outdeg;
+    }
+    if (stats && level < stats->cap) {
+      dobfs_level_stats& ls = stats->level[level];
+      ls.dir = dir;
+      ls.nf = int32_t(nf);
+      ls.n_new = int32_t(n_new);
+      ls.pad = 0;
+      ls.edges = int64_t(r.edges);
+      ls.m_f = dir == DOBFS_DIR_PUSH ? int64_t(r.mf) : 0;
+      ls.ms_main = timing ? elapsed(ev[3], ev[4]) : 0.f;
+      ls.ms_aux = timing ? elapsed(ev[2], ev[3]) : 0.f;
+    }
+    reached += n_new;
+    if (n_new == 0) break;
+    if (edges_rule) m_u -= int64_t(r.mnew);
+    int32_t next = dobfs_next_direction(&opt, dir, V, nf, n_new, int64_t(r.mnew), m_u);
+    if (opt.mode == DOBFS_MODE_PUSH_ONLY) next = DOBFS_DIR_PUSH;
+    if (opt.mode == DOBFS_MODE_PULL_ONLY) next = DOBFS_DIR_PULL;
+    dir = next;
+    nf = n_new;
+    ++level;
+    if (level > V) return fail(DOBFS_ERR_INTERNAL, "level loop did not terminate");
+  }
+  HIPCK(hipEventRecord(ev[5], s));
+  HIPCK(hipEventSynchronize(ev[5]));
+  if (stats) {
+    stats->levels = level + 1;
+    stats->ms_total = elapsed(ev[0], ev[5]);
+    stats->ms_init = ms_init;
+    stats->reached = reached;
+  }
+  return DOBFS_OK;
+}
+
+dobfs_status dobfs_mxv(dobfs_graph g, const uint32_t* x_bits, const int32_t* x_idx,
+                       int32_t x_nnz, const uint32_t* mask_bits, int32_t complement,
+                       int32_t direction, uint32_t flags_in, uint32_t* y_bits, int32_t* y_idx,
+                       int32_t* y_witness, int32_t* y_nnz, void* workspace, size_t ws_bytes,
+                       void* stream) {
+  t_last_error.clear();
+  if (!g) return fail(DOBFS_ERR_INVALID_ARG, "graph is NULL");
+  if (!y_bits) return fail(DOBFS_ERR_INVALID_ARG, "y_bits is NULL");
+  if (direction != DOBFS_DIR_PUSH && direction != DOBFS_DIR_PULL)
+    return fail(DOBFS_ERR_INVALID_ARG, "direction %d", direction);
+  if (flags_in & ~uint32_t(DOBFS_MXV_EARLY_EXIT | DOBFS_MXV_ACCUM_OR))
+    return fail(DOBFS_ERR_INVALID_ARG, "unknown mxv flags 0x%x", flags_in);
+  if (!x_bits && (x_nnz < 0 || x_nnz > g->V || (x_nnz > 0 && !x_idx)))
+    return fail(DOBFS_ERR_INVALID_ARG, "x: need x_bits, or x_idx with 0 <= x_nnz <= V");
+  DeviceScope ds(g->device);
+  if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice", __LINE__);
+  const Layout L = plan(g->V);
+  std::unique_lock<std::mutex> lock;
+  uint8_t* ws = nullptr;
+  dobfs_status st = get_workspace(g, workspace, ws_bytes, L.total, lock, &ws);
+  if (st != DOBFS_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int32_t V = g->V, nwords = g->nwords;
+  uint32_t* rbits = reinterpret_cast<uint32_t*>(ws + L.visA);
+  uint32_t* xbits = reinterpret_cast<uint32_t*>(ws + L.FA);
+  int32_t* list = reinterpret_cast<int32_t*>(ws + L.Q0);
+  int32_t* S = reinterpret_cast<int32_t*>(ws + L.S);
+  int32_t* R = reinterpret_cast<int32_t*>(ws + L.R);
+  uint64_t* flags = reinterpret_cast<uint64_t*>(ws + L.flags);
+  Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
+  const bool accum = (flags_in & DOBFS_MXV_ACCUM_OR) != 0;
+  unsigned long long tb = 0;
+  uint32_t epoch = 1;
+
+  HIPCK(launch_ctrl_init(s, ctrl, flags, L.nflags));
+  LevelSlot* out_slot;
+  if (direction == DOBFS_DIR_PULL) {
+    const uint32_t* x = x_bits;
+    if (!x) {
+      HIPCK(launch_fill(s, xbits, nwords, 0u));
+      if (x_nnz > 0) HIPCK(launch_s2d(s, x_idx, x_nnz, nullptr, V, xbits));
+      x = xbits;
+    }
+    PullArgs pa{};
+    pa.V = V;
+    pa.nwords = nwords;
+    pa.colptr = g->colptr;
+    pa.rowind = g->rowind;
+    pa.x = x;
+    pa.mask = mask_bits;
+    pa.complement = complement ? 1 : 0;
+    pa.mask_after = 0;
+    pa.nz = g->nz_in;
+    pa.out_base = accum ? y_bits : nullptr;
+    pa.out = y_bits;
+    pa.parent = y_witness;
+    pa.slot = &ctrl->slot[0];
+    HIPCK(launch_pull(s, (flags_in & DOBFS_MXV_EARLY_EXIT) != 0, pa));
+    out_slot = &ctrl->slot[0];
+  } else {
+    const int32_t* q = x_idx;
+    int32_t nf = x_nnz;
+    const uint32_t* nf_dev = nullptr;
+    int64_t tiles = std::max<int64_t>(1, scan_tiles(nf));
+    if (x_bits) {
+      // dense input: DENSE2SPARSE first, its length stays on the device
+      HIPCK(launch_d2s(s, x_bits, nullptr, nwords, V, list, ctrl, tb, epoch, flags,
+                       &ctrl->d2s_count));
+      tb += (unsigned long long)d2s_tiles(nwords);
+      ++epoch;
+      q = list;
+      nf = 0;
+      nf_dev = &ctrl->d2s_count;
+      tiles = std::max<int64_t>(1, scan_tiles(V));
+    }
+    HIPCK(launch_fill(s, rbits, nwords, 0u));
+    HIPCK(launch_push_scan(s, tiles, q, nf, nf_dev, g->rowptr, S, R, ctrl, tb, epoch, flags,
+                           &ctrl->slot[0], nullptr));
+    tb += (unsigned long long)tiles;
+    ++epoch;
+    ExpandArgs ea{};
+    ea.Q = q;
+    ea.nf = nf;
+    ea.nf_dev = nf_dev;
+    ea.S = S;
+    ea.R = R;
+    ea.colind = g->colind;
+    ea.ctrl = ctrl;
+    ea.claim = rbits;
+    ea.mask = mask_bits;
+    ea.complement = complement ? 1 : 0;
+    ea.parent = y_witness;
+    ea.slot = &ctrl->slot[0];
+    HIPCK(launch_push_expand(s, kExpandBlocks, ea));
+    HIPCK(launch_mxv_finalize(s, y_bits, rbits, nwords, V, accum ? 1 : 0, &ctrl->slot[1]));
+    out_slot = &ctrl->slot[1];
+  }
+  if (y_idx) {
+    HIPCK(launch_d2s(s, y_bits, nullptr, nwords, V, y_idx, ctrl, tb, epoch, flags,
+                     &ctrl->d2s_count));
+    tb += (unsigned long long)d2s_tiles(nwords);
+    ++epoch;
+  }
+  if (y_nnz || y_idx) {
+    Ctrl* host = host_ctrl();
+    if (!host) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
+    HIPCK(hipMemcpyAsync(host, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    if (y_nnz) *y_nnz = int32_t(host->slot[out_slot - ctrl->slot].aux);
+  } else {
+    HIPCK(hipGetLastError());
+  }
+  return DOBFS_OK;
+}
+
+}  // extern "C"
