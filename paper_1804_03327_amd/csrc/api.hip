@@ -76,14 +76,15 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace layout of one call (BFS and mxv share it).
 struct Layout {
-  size_t visA, visB, FA, FB, Q0, Q1, S, R, flags, ctrl, total;
-  int64_t nflags;
+  size_t visA, visB, FA, FB, Q0, Q1, S, R, chunks, flags, ctrl, total;
+  int64_t nflags, nchunks;
 };
 
-Layout plan(int32_t V) {
+Layout plan(int32_t V, int64_t nnz) {
   Layout L{};
   const size_t wb = size_t(words_of(V)) * 4, vb = size_t(V) * 4;
   L.nflags = std::max<int64_t>(scan_tiles(V), d2s_tiles(words_of(V))) + 1;
+  L.nchunks = max_chunks(nnz);
   size_t cur = 0;
   auto take = [&](size_t bytes) {
     size_t off = cur;
@@ -98,6 +99,7 @@ Layout plan(int32_t V) {
   L.Q1 = take(vb);
   L.S = take(vb);
   L.R = take(vb);
+  L.chunks = take(size_t(L.nchunks) * 4);
   L.flags = take(size_t(L.nflags) * 8);
   L.ctrl = take(sizeof(Ctrl));
   L.total = cur;
@@ -243,9 +245,6 @@ dobfs_status get_workspace(dobfs_graph g, void* workspace, size_t ws_bytes, size
   return DOBFS_OK;
 }
 
-// Number of blocks for the push expand kernel: it strides over edge chunks,
-// so a fixed grid that fills the GPU several times suffices.
-constexpr int32_t kExpandBlocks = 2048;
 
 }  // namespace
 
@@ -410,13 +409,13 @@ dobfs_status dobfs_graph_info(dobfs_graph g, int32_t* V, int64_t* nnz, int32_t* 
 dobfs_status dobfs_bfs_workspace_bytes(dobfs_graph g, const dobfs_options* opt, size_t* bytes) {
   (void)opt;
   if (!g || !bytes) return fail(DOBFS_ERR_INVALID_ARG, "graph or bytes is NULL");
-  *bytes = plan(g->V).total;
+  *bytes = plan(g->V, g->nnz).total;
   return DOBFS_OK;
 }
 
 dobfs_status dobfs_mxv_workspace_bytes(dobfs_graph g, size_t* bytes) {
   if (!g || !bytes) return fail(DOBFS_ERR_INVALID_ARG, "graph or bytes is NULL");
-  *bytes = plan(g->V).total;
+  *bytes = plan(g->V, g->nnz).total;
   return DOBFS_OK;
 }
 
@@ -436,7 +435,7 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
 
   DeviceScope ds(g->device);
   if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice", __LINE__);
-  const Layout L = plan(g->V);
+  const Layout L = plan(g->V, g->nnz);
   std::unique_lock<std::mutex> lock;
   uint8_t* ws = nullptr;
   if ((st = get_workspace(g, workspace, ws_bytes, L.total, lock, &ws)) != DOBFS_OK) return st;
@@ -455,6 +454,7 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   int32_t* qnext = reinterpret_cast<int32_t*>(ws + L.Q1);
   int32_t* S = reinterpret_cast<int32_t*>(ws + L.S);
   int32_t* R = reinterpret_cast<int32_t*>(ws + L.R);
+  int32_t* chunks = reinterpret_cast<int32_t*>(ws + L.chunks);
   uint64_t* flags = reinterpret_cast<uint64_t*>(ws + L.flags);
   Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
 
@@ -464,11 +464,10 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   const bool early_exit = opt.mode != DOBFS_MODE_PULL_MASKED && opt.mode != DOBFS_MODE_PULL_UNMASKED;
   const bool mask_after = opt.mode == DOBFS_MODE_PULL_UNMASKED;
   const bool edges_rule = opt.heuristic == DOBFS_HEUR_EDGES;
-  const int32_t* out_rowptr = edges_rule ? g->rowptr : nullptr;
 
   HIPCK(hipEventRecord(ev[0], s));
-  HIPCK(launch_bfs_init(s, V, nwords, source, g->rowptr, depth, parent, vis, qcur, ctrl, flags,
-                        L.nflags));
+  HIPCK(launch_bfs_init(s, V, nwords, source, g->rowptr, g->colptr, depth, parent, vis, qcur, ctrl,
+                        flags, L.nflags));
   if (timing) HIPCK(hipEventRecord(ev[1], s));
 
   int32_t dir = opt.mode == DOBFS_MODE_PULL_ONLY ? DOBFS_DIR_PULL : DOBFS_DIR_PUSH;
@@ -480,8 +479,9 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   float ms_init = 0.f;
   for (;;) {
     if (level < opt.n_forced) dir = opt.forced_dirs[level];
-    LevelSlot* slot = &ctrl->slot[level % kSlots];
-    LevelSlot* reset = &ctrl->slot[(level + 1) % kSlots];
+    const int32_t si = level % kSlots, ri = (level + 1) % kSlots;
+    LevelSlot* slot = &ctrl->slot[si];
+    LevelSlot* reset = &ctrl->slot[ri];
     if (timing) HIPCK(hipEventRecord(ev[2], s));
     if (dir == DOBFS_DIR_PUSH) {
       if (!queue_valid) {
@@ -493,8 +493,8 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
         queue_valid = true;
       }
       const int64_t tiles = std::max<int64_t>(1, scan_tiles(nf));
-      HIPCK(launch_push_scan(s, tiles, qcur, int32_t(nf), nullptr, g->rowptr, S, R, ctrl, tb, epoch,
-                             flags, slot, reset));
+      HIPCK(launch_push_scan(s, tiles, qcur, int32_t(nf), nullptr, g->rowptr, S, R, chunks, ctrl, tb,
+                             epoch, flags, si, reset, ri));
       tb += (unsigned long long)tiles;
       ++epoch;
       if (timing) HIPCK(hipEventRecord(ev[3], s));
@@ -503,6 +503,7 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
       ea.nf = int32_t(nf);
       ea.S = S;
       ea.R = R;
+      ea.chunk_first = chunks;
       ea.colind = g->colind;
       ea.ctrl = ctrl;
       ea.claim = vis;
@@ -510,9 +511,12 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
       ea.parent = parent;
       ea.level = level;
       ea.Qout = qnext;
-      ea.out_rowptr = out_rowptr;
+      ea.qslot = si;
+      ea.out_rowptr = edges_rule ? g->rowptr : nullptr;
+      ea.in_colptr = edges_rule ? g->colptr : nullptr;
       ea.slot = slot;
       ea.reset = reset;
+      ea.reset_level = ri;
       HIPCK(launch_push_expand(s, kExpandBlocks, ea));
       std::swap(qcur, qnext);
       f_valid = false;
@@ -540,9 +544,12 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
       pa.depth = depth;
       pa.parent = parent;
       pa.level = level;
-      pa.out_rowptr = out_rowptr;
+      pa.count_out = 0;
+      pa.edge_rule = edges_rule ? 1 : 0;
       pa.slot = slot;
       pa.reset = reset;
+      pa.reset_level = ri;
+      pa.ctrl = ctrl;
       HIPCK(launch_pull(s, early_exit, pa));
       std::swap(vis, vis_other);
       if (!reuse) {
@@ -554,11 +561,11 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
     if (timing) HIPCK(hipEventRecord(ev[4], s));
     HIPCK(hipMemcpyAsync(host, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
-    const LevelSlot r = host->slot[level % kSlots];
-    const int64_t n_new = r.count;
+    const LevelTotals r = sum_slot(host->slot[si]);
+    const int64_t n_new = int64_t(r.count);
     if (level == 0) {
       if (timing) ms_init = elapsed(ev[0], ev[1]);
-      m_u = g->nnz - host->src_outdeg;
+      m_u = g->nnz - host->src_indeg;  // in-edges left for a pull to scan
     }
     if (stats && level < stats->cap) {
       dobfs_level_stats& ls = stats->level[level];
@@ -567,13 +574,13 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
       ls.n_new = int32_t(n_new);
       ls.pad = 0;
       ls.edges = int64_t(r.edges);
-      ls.m_f = dir == DOBFS_DIR_PUSH ? int64_t(r.mf) : 0;
+      ls.m_f = dir == DOBFS_DIR_PUSH ? int64_t(host->mf[si]) : 0;
       ls.ms_main = timing ? elapsed(ev[3], ev[4]) : 0.f;
       ls.ms_aux = timing ? elapsed(ev[2], ev[3]) : 0.f;
     }
     reached += n_new;
     if (n_new == 0) break;
-    if (edges_rule) m_u -= int64_t(r.mnew);
+    if (edges_rule) m_u -= int64_t(r.insub);
     int32_t next = dobfs_next_direction(&opt, dir, V, nf, n_new, int64_t(r.mnew), m_u);
     if (opt.mode == DOBFS_MODE_PUSH_ONLY) next = DOBFS_DIR_PUSH;
     if (opt.mode == DOBFS_MODE_PULL_ONLY) next = DOBFS_DIR_PULL;
@@ -609,7 +616,7 @@ dobfs_status dobfs_mxv(dobfs_graph g, const uint32_t* x_bits, const int32_t* x_i
     return fail(DOBFS_ERR_INVALID_ARG, "x: need x_bits, or x_idx with 0 <= x_nnz <= V");
   DeviceScope ds(g->device);
   if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice", __LINE__);
-  const Layout L = plan(g->V);
+  const Layout L = plan(g->V, g->nnz);
   std::unique_lock<std::mutex> lock;
   uint8_t* ws = nullptr;
   dobfs_status st = get_workspace(g, workspace, ws_bytes, L.total, lock, &ws);
@@ -621,6 +628,7 @@ dobfs_status dobfs_mxv(dobfs_graph g, const uint32_t* x_bits, const int32_t* x_i
   int32_t* list = reinterpret_cast<int32_t*>(ws + L.Q0);
   int32_t* S = reinterpret_cast<int32_t*>(ws + L.S);
   int32_t* R = reinterpret_cast<int32_t*>(ws + L.R);
+  int32_t* chunks = reinterpret_cast<int32_t*>(ws + L.chunks);
   uint64_t* flags = reinterpret_cast<uint64_t*>(ws + L.flags);
   Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
   const bool accum = (flags_in & DOBFS_MXV_ACCUM_OR) != 0;
@@ -649,28 +657,31 @@ dobfs_status dobfs_mxv(dobfs_graph g, const uint32_t* x_bits, const int32_t* x_i
     pa.out_base = accum ? y_bits : nullptr;
     pa.out = y_bits;
     pa.parent = y_witness;
+    pa.count_out = 1;
     pa.slot = &ctrl->slot[0];
     HIPCK(launch_pull(s, (flags_in & DOBFS_MXV_EARLY_EXIT) != 0, pa));
     out_slot = &ctrl->slot[0];
   } else {
-    const int32_t* q = x_idx;
-    int32_t nf = x_nnz;
-    const uint32_t* nf_dev = nullptr;
-    int64_t tiles = std::max<int64_t>(1, scan_tiles(nf));
-    if (x_bits) {
-      // dense input: DENSE2SPARSE first, its length stays on the device
-      HIPCK(launch_d2s(s, x_bits, nullptr, nwords, V, list, ctrl, tb, epoch, flags,
-                       &ctrl->d2s_count));
-      tb += (unsigned long long)d2s_tiles(nwords);
-      ++epoch;
-      q = list;
-      nf = 0;
-      nf_dev = &ctrl->d2s_count;
-      tiles = std::max<int64_t>(1, scan_tiles(V));
+    // The column-based matvec reads x as a sorted list of distinct indices:
+    // a dense x goes through DENSE2SPARSE; a given list is made canonical the
+    // same way (scatter, then compact), so repeated indices cannot inflate
+    // the expansion. The list length stays on the device.
+    const uint32_t* xd = x_bits;
+    if (!xd) {
+      HIPCK(launch_fill(s, xbits, nwords, 0u));
+      if (x_nnz > 0) HIPCK(launch_s2d(s, x_idx, x_nnz, nullptr, V, xbits));
+      xd = xbits;
     }
+    HIPCK(launch_d2s(s, xd, nullptr, nwords, V, list, ctrl, tb, epoch, flags, &ctrl->d2s_count));
+    tb += (unsigned long long)d2s_tiles(nwords);
+    ++epoch;
+    const int32_t* q = list;
+    const int32_t nf = 0;
+    const uint32_t* nf_dev = &ctrl->d2s_count;
+    const int64_t tiles = std::max<int64_t>(1, scan_tiles(V));
     HIPCK(launch_fill(s, rbits, nwords, 0u));
-    HIPCK(launch_push_scan(s, tiles, q, nf, nf_dev, g->rowptr, S, R, ctrl, tb, epoch, flags,
-                           &ctrl->slot[0], nullptr));
+    HIPCK(launch_push_scan(s, tiles, q, nf, nf_dev, g->rowptr, S, R, chunks, ctrl, tb, epoch, flags,
+                           0, nullptr, 0));
     tb += (unsigned long long)tiles;
     ++epoch;
     ExpandArgs ea{};
@@ -679,6 +690,7 @@ dobfs_status dobfs_mxv(dobfs_graph g, const uint32_t* x_bits, const int32_t* x_i
     ea.nf_dev = nf_dev;
     ea.S = S;
     ea.R = R;
+    ea.chunk_first = chunks;
     ea.colind = g->colind;
     ea.ctrl = ctrl;
     ea.claim = rbits;
@@ -701,7 +713,7 @@ dobfs_status dobfs_mxv(dobfs_graph g, const uint32_t* x_bits, const int32_t* x_i
     if (!host) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
     HIPCK(hipMemcpyAsync(host, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
-    if (y_nnz) *y_nnz = int32_t(host->slot[out_slot - ctrl->slot].aux);
+    if (y_nnz) *y_nnz = int32_t(sum_slot(host->slot[out_slot - ctrl->slot]).aux);
   } else {
     HIPCK(hipGetLastError());
   }

@@ -9,42 +9,73 @@
 
 namespace dobfs {
 
-// Per-level counters the kernels accumulate and the host reads back once per
-// level (one 32-byte copy).
-struct LevelSlot {
+// ---- per-level counters ----
+// Same-address device atomics serialize (about 11 ns each on MI355X), so
+// every block adds its partial sums into one of kStripes counters, each on
+// its own 128-byte line; the host adds the stripes up after the level.
+constexpr int kStripes = 32;
+struct alignas(128) Stripe {
   uint32_t count;  // vertices discovered (BFS) / result bits (mxv)
-  uint32_t aux;    // popcount of the whole output vector (mxv)
+  uint32_t aux;    // mxv: popcount of the whole output vector
   uint64_t edges;  // adjacency entries read (push) or in-neighbours checked (pull)
-  uint64_t mf;     // push: out-edges of the input frontier
-  uint64_t mnew;   // out-edges of the vertices discovered (only when asked for)
+  uint64_t mnew;   // out-edges of the vertices discovered (edge-count rule only)
+  uint64_t insub;  // in-edges of the vertices discovered (edge-count rule only)
 };
-
-constexpr int kSlots = 4;
+struct LevelSlot {
+  Stripe s[kStripes];
+};
+constexpr int kSlots = 4;  // level L accumulates into slot L % kSlots
 
 struct Ctrl {
   unsigned long long ticket;  // tile tickets of the single-pass scans (monotone within a call)
   uint32_t mf32;              // m_f of the latest push scan, read by the expand kernel
   uint32_t d2s_count;         // output length of the latest dense-to-sparse conversion
   int64_t src_outdeg;         // out-degree of the BFS source
-  uint32_t pad[10];
+  int64_t src_indeg;          // in-degree of the BFS source
+  uint32_t qcount[kSlots];    // frontier-list append counter of each level
+  uint64_t mf[kSlots];        // push: out-edges of the input frontier
+  uint8_t pad[128 - 48 - 8 * kSlots];
   LevelSlot slot[kSlots];
 };
-static_assert(sizeof(LevelSlot) == 32, "slot layout");
+static_assert(sizeof(Stripe) == 128, "stripe layout");
+static_assert(offsetof(Ctrl, slot) % 128 == 0, "slots start on a line");
+
+// Host-side totals of one level.
+struct LevelTotals {
+  uint64_t count, aux, edges, mnew, insub;
+};
+inline LevelTotals sum_slot(const LevelSlot& s) {
+  LevelTotals t{0, 0, 0, 0, 0};
+  for (int k = 0; k < kStripes; ++k) {
+    t.count += s.s[k].count;
+    t.aux += s.s[k].aux;
+    t.edges += s.s[k].edges;
+    t.mnew += s.s[k].mnew;
+    t.insub += s.s[k].insub;
+  }
+  return t;
+}
 
 // ---- launch geometry (all kernels use 256-thread blocks = 4 wave64) ----
 constexpr int kThreads = 256;
-constexpr int kScanIPT = 8;                          // push scan: frontier entries per thread
-constexpr int kScanTile = kThreads * kScanIPT;      // 2048 entries per tile
-constexpr int kExpandChunk = 1024;                   // push expand: edges per chunk
-constexpr int kExpandWin = kExpandChunk + 1;         // frontier entries cached in LDS per chunk
-constexpr int kPullTileWords = 64;                   // pull: bitmap words owned by a block
-constexpr int kPullTileV = kPullTileWords * 32;      // 2048 rows per block
-constexpr int kPullFirst = 4;                        // in-neighbours one thread checks before handing a row to its wave
-constexpr int kD2STile = kThreads;                   // D2S: one word per thread
+constexpr int kScanIPT = 8;                       // push scan: frontier entries per thread
+constexpr int kScanTile = kThreads * kScanIPT;   // 2048 entries per tile
+constexpr int kExpandEPT = 4;                     // push expand: edges per thread per chunk
+constexpr int kExpandChunk = kThreads * kExpandEPT;  // 1024 edges per chunk
+constexpr int kExpandWin = kExpandChunk + 1;      // frontier entries cached in LDS per chunk
+constexpr int kExpandBuf = 4096;                  // winners buffered in LDS before a queue flush
+constexpr int kExpandBlocks = 1024;               // expand grid (strides over chunks)
+constexpr int kPullTileWords = 64;                // pull: bitmap words owned by a block
+constexpr int kPullTileV = kPullTileWords * 32;   // 2048 rows per block
+constexpr int kPullFirst = 4;                     // in-neighbours one thread checks before handing a row to its wave
+constexpr int kPullBatch = 4;                     // candidate rows a thread works on at once
+constexpr int kD2SWPT = 4;                        // D2S: words per thread
+constexpr int kD2STile = kThreads * kD2SWPT;      // 1024 words per tile
 
 inline int32_t words_of(int64_t V) { return int32_t((V + 31) / 32); }
 inline int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 inline int64_t d2s_tiles(int64_t nwords) { return (nwords + kD2STile - 1) / kD2STile; }
+inline int64_t max_chunks(int64_t nnz) { return nnz / kExpandChunk + 2; }
 
 // ---- kernel argument blocks ----
 struct PullArgs {
@@ -62,9 +93,12 @@ struct PullArgs {
   int32_t* depth;            // nullable
   int32_t* parent;           // nullable: parent (BFS) or witness (mxv)
   int32_t level;
-  const int32_t* out_rowptr; // nullable: CSR(A) offsets; adds out-degrees of results to slot->mnew
+  int32_t count_out;         // 1: add popcount(out) to the stripes' aux (mxv)
+  int32_t edge_rule;         // 1: add in-degrees of the results to the stripes' insub
   LevelSlot* slot;
   LevelSlot* reset;          // nullable: zeroed by block 0 before use by the next level
+  int32_t reset_level;       // slot index of `reset` (its queue counter is zeroed too)
+  Ctrl* ctrl;
 };
 
 struct ExpandArgs {
@@ -73,8 +107,9 @@ struct ExpandArgs {
   const uint32_t* nf_dev;    // nullable: frontier length on the device
   const int32_t* S;          // exclusive scan of out-degrees
   const int32_t* R;          // row start of each frontier vertex
+  const int32_t* chunk_first;  // first frontier entry of every edge chunk
   const int32_t* colind;
-  const Ctrl* ctrl;          // mf32 = total edges
+  Ctrl* ctrl;                // mf32 = total edges; qcount = append counter
   uint32_t* claim;           // bitmap claimed with atomicOr (visited / result)
   const uint32_t* mask;      // nullable: filter before the claim
   int32_t complement;
@@ -82,20 +117,25 @@ struct ExpandArgs {
   int32_t* parent;           // nullable: parent / witness
   int32_t level;
   int32_t* Qout;             // nullable: winners appended here
-  const int32_t* out_rowptr; // nullable: CSR(A) offsets; adds out-degrees of winners to slot->mnew
+  int32_t qslot;             // which ctrl->qcount counts the appends
+  const int32_t* out_rowptr; // nullable: CSR(A) offsets; out-degrees of winners -> mnew
+  const int32_t* in_colptr;  // nullable: CSC(A) offsets; in-degrees of winners -> insub
   LevelSlot* slot;
   LevelSlot* reset;
+  int32_t reset_level;
 };
 
 // ---- launchers (kernels.hip); each returns hipGetLastError() ----
 hipError_t launch_bfs_init(hipStream_t s, int32_t V, int32_t nwords, int32_t source,
-                           const int32_t* rowptr, int32_t* depth, int32_t* parent, uint32_t* vis,
-                           int32_t* Q, Ctrl* ctrl, uint64_t* flags, int64_t nflags);
+                           const int32_t* rowptr, const int32_t* colptr, int32_t* depth,
+                           int32_t* parent, uint32_t* vis, int32_t* Q, Ctrl* ctrl, uint64_t* flags,
+                           int64_t nflags);
 hipError_t launch_ctrl_init(hipStream_t s, Ctrl* ctrl, uint64_t* flags, int64_t nflags);
 hipError_t launch_push_scan(hipStream_t s, int64_t tiles, const int32_t* Q, int32_t nf,
                             const uint32_t* nf_dev, const int32_t* rowptr, int32_t* S, int32_t* R,
-                            Ctrl* ctrl, unsigned long long ticket_base, uint32_t epoch,
-                            uint64_t* flags, LevelSlot* slot, LevelSlot* reset);
+                            int32_t* chunk_first, Ctrl* ctrl, unsigned long long ticket_base,
+                            uint32_t epoch, uint64_t* flags, int32_t level_slot, LevelSlot* reset,
+                            int32_t reset_level);
 hipError_t launch_push_expand(hipStream_t s, int32_t blocks, const ExpandArgs& a);
 hipError_t launch_pull(hipStream_t s, bool early_exit, const PullArgs& a);
 hipError_t launch_d2s(hipStream_t s, const uint32_t* a, const uint32_t* b_not, int32_t nwords,
