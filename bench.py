@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--no-validate", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many BFS steps (for rocprofv3), print nothing else")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="with --profile-steps: also copy this many MiB device-to-device once, "
+                         "the known-size reference for scaling PMC byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -128,6 +131,15 @@ def main():
     opt_timed = dobfs.make_options("full", time_kernels=True)
 
     if args.profile_steps:
+        if args.copy_mb:
+            n = args.copy_mb << 20
+            src_t = torch.ones(n, dtype=torch.uint8, device="cuda")
+            dst_t = torch.empty_like(src_t)
+            torch.cuda.synchronize()
+            dst_t.copy_(src_t)
+            torch.cuda.synchronize()
+            log("reference copy of %d bytes done" % n)
+            del src_t, dst_t
         for k in range(args.profile_steps):
             for s in sources:
                 runner.run(s, opt=opt_plain, stream=stream)
