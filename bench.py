@@ -93,6 +93,10 @@ def main():
     ap.add_argument("--edgefactor", type=int, default=16)
     ap.add_argument("--sources", type=int, default=64)
     ap.add_argument("--cpu-sources", type=int, default=8, help="oracle sample size (0: skip)")
+    ap.add_argument("--heuristic", choices=("ratio", "edges"), default="ratio",
+                    help="direction rule: Section 6.3 ratio form or the edge-count form")
+    ap.add_argument("--alpha", type=float, default=None)
+    ap.add_argument("--beta", type=float, default=None)
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--no-validate", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -127,8 +131,15 @@ def main():
     indeg_nz = hg.in_degree() > 0
     runner = BfsRunner(g, with_parent=True)
     stream = torch.cuda.current_stream()
-    opt_plain = dobfs.make_options("full")
-    opt_timed = dobfs.make_options("full", time_kernels=True)
+    heur = dobfs.HEUR_EDGES if args.heuristic == "edges" else dobfs.HEUR_RATIO
+    alpha = args.alpha if args.alpha is not None else (1 / 14 if heur == dobfs.HEUR_EDGES else 0.01)
+    beta = args.beta if args.beta is not None else (1 / 24 if heur == dobfs.HEUR_EDGES else 0.01)
+
+    def options(mode, time_kernels=False):
+        return dobfs.make_options(mode, heur, alpha, beta, time_kernels=time_kernels)
+
+    opt_plain = options("full")
+    opt_timed = options("full", time_kernels=True)
 
     if args.profile_steps:
         if args.copy_mb:
@@ -259,7 +270,7 @@ def main():
     if not args.no_ablation:
         ablation = {}
         for mode in ("push_only", "pull_unmasked", "pull_masked", "pull_masked_ee", "full"):
-            o = dobfs.make_options(mode)
+            o = options(mode)
             for s in sources[:4]:
                 runner.run(s, opt=o, stream=stream)
             torch.cuda.synchronize()
@@ -278,7 +289,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "rmat%d_ef%d" % (args.scale, args.edgefactor), "vertices": hg.V,
                    "directed_edges": hg.nnz, "sources_per_step": len(sources), "mode": "full",
-                   "heuristic": "ratio alpha=beta=0.01", "teps_edges": "graph500",
+                   "heuristic": "%s alpha=%.4g beta=%.4g" % (args.heuristic, alpha, beta),
+                   "teps_edges": "graph500",
                    "rmat_abcd": [0.57, 0.19, 0.19, 0.05], "graph_seed": 1, "source_seed": 2},
         "gteps_paper_convention": round(gteps_paper, 3),
         "bfs_ms_median": round(float(np.median(bfs_ms)), 4),

@@ -9,6 +9,8 @@
 #include "dobfs_internal.h"
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -28,6 +30,8 @@ struct dobfs_graph_s {
   const int32_t* colptr = nullptr;  // CSC(A)
   const int32_t* rowind = nullptr;
   uint32_t* nz_in = nullptr;        // rows of CSC(A) with at least one entry
+  int32_t* head = nullptr;          // first entry of every CSC(A) column (-1 if empty)
+  std::atomic<int32_t> last_levels{8};  // level count of the previous BFS (first batch size)
   void* owned[4] = {nullptr, nullptr, nullptr, nullptr};
   std::mutex mu;                    // guards the internal workspace
   void* ws = nullptr;
@@ -76,14 +80,14 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace layout of one call (BFS and mxv share it).
 struct Layout {
-  size_t visA, visB, FA, FB, Q0, Q1, S, R, chunks, flags, ctrl, total;
+  size_t visA, visB, FA, FB, Q0, Q1, S, R, chunks, flagsA, flagsB, ctrl, total;
   int64_t nflags, nchunks;
 };
 
 Layout plan(int32_t V, int64_t nnz) {
   Layout L{};
   const size_t wb = size_t(words_of(V)) * 4, vb = size_t(V) * 4;
-  L.nflags = std::max<int64_t>(scan_tiles(V), d2s_tiles(words_of(V))) + 1;
+  L.nflags = flag_entries(V);
   L.nchunks = max_chunks(nnz);
   size_t cur = 0;
   auto take = [&](size_t bytes) {
@@ -100,7 +104,8 @@ Layout plan(int32_t V, int64_t nnz) {
   L.S = take(vb);
   L.R = take(vb);
   L.chunks = take(size_t(L.nchunks) * 4);
-  L.flags = take(size_t(L.nflags) * 8);
+  L.flagsA = take(size_t(L.nflags) * 8);
+  L.flagsB = take(size_t(L.nflags) * 8);
   L.ctrl = take(sizeof(Ctrl));
   L.total = cur;
   return L;
@@ -118,8 +123,37 @@ Ctrl* host_ctrl() {
   return p;
 }
 
-// Per-thread, per-device events for the level loop's timers.
-constexpr int kEvents = 6;
+// Pinned host buffer the level loop's report kernel writes, one per thread.
+HostReport* host_report() {
+  thread_local HostReport* p = nullptr;
+  if (!p) {
+    void* q = nullptr;
+    if (hipHostMalloc(&q, sizeof(HostReport), hipHostMallocDefault) != hipSuccess) return nullptr;
+    p = static_cast<HostReport*>(q);
+    p->seq = 0;
+  }
+  return p;
+}
+
+// Wait until the report with sequence number `seq` has landed: spin on the
+// pinned word for a short while (a kernel-to-host write takes ~6 us where a
+// stream synchronisation takes ~15 us), then block on the stream, which also
+// surfaces any device error.
+hipError_t wait_report(const HostReport* r, uint32_t seq, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t it = 1;; ++it) {
+    if (__atomic_load_n(&r->seq, __ATOMIC_ACQUIRE) == seq) return hipSuccess;
+    if ((it & 255) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(2000)) break;
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  return __atomic_load_n(&r->seq, __ATOMIC_ACQUIRE) == seq ? hipSuccess : hipErrorUnknown;
+}
+
+// Per-thread, per-device events for the level loop's timers: two per level
+// of a batch, plus start / init / end.
+constexpr int kEvStart = 2 * kMaxBatch + 2, kEvInit = kEvStart + 1, kEvEnd = kEvStart + 2;
+constexpr int kEvents = kEvEnd + 1;
 hipEvent_t* events_for(int device) {
   thread_local hipEvent_t ev[16][kEvents];
   thread_local bool made[16] = {};
@@ -204,6 +238,9 @@ dobfs_status finish_graph(dobfs_graph g, hipStream_t s) {
   HIPCK(hipMalloc(&p, size_t(std::max(g->nwords, 1)) * 4));
   g->nz_in = static_cast<uint32_t*>(p);
   HIPCK(launch_nz_bits(s, g->colptr, g->V, g->nz_in));
+  HIPCK(hipMalloc(&p, size_t(g->V) * 4));
+  g->head = static_cast<int32_t*>(p);
+  HIPCK(launch_head(s, g->colptr, g->rowind, g->V, g->head));
   HIPCK(hipStreamSynchronize(s));
   return DOBFS_OK;
 }
@@ -213,6 +250,7 @@ void free_graph(dobfs_graph g) {
   for (void* p : g->owned)
     if (p) (void)hipFree(p);
   if (g->nz_in) (void)hipFree(g->nz_in);
+  if (g->head) (void)hipFree(g->head);
   if (g->ws) (void)hipFree(g->ws);
   delete g;
 }
@@ -276,14 +314,8 @@ dobfs_status dobfs_options_default(dobfs_options* opt) {
 int32_t dobfs_next_direction(const dobfs_options* opt, int32_t dir, int64_t V, int64_t nf,
                              int64_t n_new, int64_t m_f, int64_t m_u) {
   const dobfs_options o = opt ? *opt : defaults();
-  const double a = double(o.alpha), b = double(o.beta);
-  if (o.heuristic == DOBFS_HEUR_EDGES) {
-    if (dir == DOBFS_DIR_PUSH) return double(m_f) > a * double(m_u) ? DOBFS_DIR_PULL : DOBFS_DIR_PUSH;
-    return double(n_new) < b * double(V) ? DOBFS_DIR_PUSH : DOBFS_DIR_PULL;
-  }
-  if (dir == DOBFS_DIR_PUSH)
-    return (n_new > nf && double(n_new) > a * double(V)) ? DOBFS_DIR_PULL : DOBFS_DIR_PUSH;
-  return (n_new < nf && double(n_new) < b * double(V)) ? DOBFS_DIR_PUSH : DOBFS_DIR_PULL;
+  return next_direction_rule(o.heuristic, double(o.alpha), double(o.beta), dir, V, nf, n_new, m_f,
+                             m_u);
 }
 
 dobfs_status dobfs_graph_upload(int32_t V, int64_t nnz, const int32_t* csr_rowptr,
@@ -418,7 +450,6 @@ dobfs_status dobfs_mxv_workspace_bytes(dobfs_graph g, size_t* bytes) {
   *bytes = plan(g->V, g->nnz).total;
   return DOBFS_OK;
 }
-
 dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_in, int32_t* depth,
                        int32_t* parent, void* workspace, size_t ws_bytes, void* stream,
                        dobfs_stats* stats) {
@@ -439,161 +470,127 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   std::unique_lock<std::mutex> lock;
   uint8_t* ws = nullptr;
   if ((st = get_workspace(g, workspace, ws_bytes, L.total, lock, &ws)) != DOBFS_OK) return st;
-  Ctrl* host = host_ctrl();
-  if (!host) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
+  HostReport* rep = host_report();
+  if (!rep) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
+  thread_local uint32_t report_seq = 0;
+  const bool timing = (opt.flags & DOBFS_OPT_TIME_KERNELS) != 0;
   hipEvent_t* ev = events_for(g->device);
   if (!ev) return fail(DOBFS_ERR_DEVICE, "event creation failed");
   hipStream_t s = static_cast<hipStream_t>(stream);
 
-  const int32_t V = g->V, nwords = g->nwords;
-  uint32_t* vis = reinterpret_cast<uint32_t*>(ws + L.visA);
-  uint32_t* vis_other = reinterpret_cast<uint32_t*>(ws + L.visB);
-  uint32_t* fcur = reinterpret_cast<uint32_t*>(ws + L.FA);
-  uint32_t* fnext = reinterpret_cast<uint32_t*>(ws + L.FB);
-  int32_t* qcur = reinterpret_cast<int32_t*>(ws + L.Q0);
-  int32_t* qnext = reinterpret_cast<int32_t*>(ws + L.Q1);
-  int32_t* S = reinterpret_cast<int32_t*>(ws + L.S);
-  int32_t* R = reinterpret_cast<int32_t*>(ws + L.R);
-  int32_t* chunks = reinterpret_cast<int32_t*>(ws + L.chunks);
-  uint64_t* flags = reinterpret_cast<uint64_t*>(ws + L.flags);
-  Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
+  BfsArgs a{};
+  a.V = g->V;
+  a.nwords = g->nwords;
+  a.nnz = g->nnz;
+  a.rowptr = g->rowptr;
+  a.colind = g->colind;
+  a.colptr = g->colptr;
+  a.rowind = g->rowind;
+  a.head = g->head;
+  a.nz_in = g->nz_in;
+  a.depth = depth;
+  a.parent = parent;
+  a.vis[0] = reinterpret_cast<uint32_t*>(ws + L.visA);
+  a.vis[1] = reinterpret_cast<uint32_t*>(ws + L.visB);
+  a.F[0] = reinterpret_cast<uint32_t*>(ws + L.FA);
+  a.F[1] = reinterpret_cast<uint32_t*>(ws + L.FB);
+  a.Q[0] = reinterpret_cast<int32_t*>(ws + L.Q0);
+  a.Q[1] = reinterpret_cast<int32_t*>(ws + L.Q1);
+  a.S = reinterpret_cast<int32_t*>(ws + L.S);
+  a.R = reinterpret_cast<int32_t*>(ws + L.R);
+  a.chunk_first = reinterpret_cast<int32_t*>(ws + L.chunks);
+  a.flagsA = reinterpret_cast<uint64_t*>(ws + L.flagsA);
+  a.flagsB = reinterpret_cast<uint64_t*>(ws + L.flagsB);
+  a.ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
+  a.mode = opt.mode;
+  a.heuristic = opt.heuristic;
+  a.alpha = double(opt.alpha);
+  a.beta = double(opt.beta);
+  a.reuse = (opt.mode == DOBFS_MODE_FULL || opt.mode == DOBFS_MODE_PULL_ONLY ||
+             opt.mode == DOBFS_MODE_PUSH_ONLY) ? 1 : 0;
+  a.early_exit = (opt.mode != DOBFS_MODE_PULL_MASKED && opt.mode != DOBFS_MODE_PULL_UNMASKED) ? 1 : 0;
+  a.mask_after = opt.mode == DOBFS_MODE_PULL_UNMASKED ? 1 : 0;
+  a.need_F = a.reuse ? 0 : 1;
+  a.edge_rule = opt.heuristic == DOBFS_HEUR_EDGES ? 1 : 0;
+  auto forced = [&](int64_t l) -> int32_t {
+    return l < opt.n_forced ? int32_t(opt.forced_dirs[l]) : -1;
+  };
+  const int32_t dir0 = forced(0) >= 0 ? forced(0)
+                                      : (opt.mode == DOBFS_MODE_PULL_ONLY ? DOBFS_DIR_PULL : DOBFS_DIR_PUSH);
 
-  const bool timing = (opt.flags & DOBFS_OPT_TIME_KERNELS) != 0;
-  const bool reuse = opt.mode == DOBFS_MODE_FULL || opt.mode == DOBFS_MODE_PULL_ONLY ||
-                     opt.mode == DOBFS_MODE_PUSH_ONLY;
-  const bool early_exit = opt.mode != DOBFS_MODE_PULL_MASKED && opt.mode != DOBFS_MODE_PULL_UNMASKED;
-  const bool mask_after = opt.mode == DOBFS_MODE_PULL_UNMASKED;
-  const bool edges_rule = opt.heuristic == DOBFS_HEUR_EDGES;
-
-  HIPCK(hipEventRecord(ev[0], s));
-  HIPCK(launch_bfs_init(s, V, nwords, source, g->rowptr, g->colptr, depth, parent, vis, qcur, ctrl,
-                        flags, L.nflags));
+  // Levels run in batches: level l is level_prep(l) then level_main(l); the
+  // state that decides level l+1 is computed on the device by level_prep(l+1),
+  // which also records level l's counters. The host reads the state back once
+  // per batch; levels enqueued past the end exit at once.
+  // Event layout when timing: ev[2k] before level_prep of the k-th level of
+  // the batch, ev[2k+1] between its two kernels.
+  HIPCK(hipEventRecord(ev[kEvStart], s));
+  HIPCK(launch_bfs_init(s, a, source, dir0));
+  if (timing) HIPCK(hipEventRecord(ev[kEvInit], s));
+  int64_t lvl = 0, levels = -1, reached = 1;
+  // First batch: one level more than the previous traversal on this graph
+  // needed (a level enqueued past the end costs a few microseconds, a second
+  // batch a host round trip); later batches start at 4 and double.
+  int32_t batch = std::min(std::max(g->last_levels.load(std::memory_order_relaxed) + 1, 2), kMaxBatch);
+  int32_t next_batch = 4;
+  float ms_init = 0.f, first_aux = 0.f;  // first_aux: level_prep time of a batch's first level
+  if (timing) HIPCK(hipEventRecord(ev[0], s));
+  HIPCK(launch_level_prep(s, a, 0, forced(0)));
   if (timing) HIPCK(hipEventRecord(ev[1], s));
-
-  int32_t dir = opt.mode == DOBFS_MODE_PULL_ONLY ? DOBFS_DIR_PULL : DOBFS_DIR_PUSH;
-  int64_t nf = 1, reached = 1, m_u = -1;
-  bool queue_valid = true, f_valid = false;
-  unsigned long long tb = 0;
-  uint32_t epoch = 1;
-  int32_t level = 0;
-  float ms_init = 0.f;
-  for (;;) {
-    if (level < opt.n_forced) dir = opt.forced_dirs[level];
-    const int32_t si = level % kSlots, ri = (level + 1) % kSlots;
-    LevelSlot* slot = &ctrl->slot[si];
-    LevelSlot* reset = &ctrl->slot[ri];
-    if (timing) HIPCK(hipEventRecord(ev[2], s));
-    if (dir == DOBFS_DIR_PUSH) {
-      if (!queue_valid) {
-        // pull -> push: the discovered set becomes a sorted list (DENSE2SPARSE)
-        HIPCK(launch_d2s(s, reuse ? vis : fcur, reuse ? vis_other : nullptr, nwords, V, qcur, ctrl,
-                         tb, epoch, flags, &ctrl->d2s_count));
-        tb += (unsigned long long)d2s_tiles(nwords);
-        ++epoch;
-        queue_valid = true;
-      }
-      const int64_t tiles = std::max<int64_t>(1, scan_tiles(nf));
-      HIPCK(launch_push_scan(s, tiles, qcur, int32_t(nf), nullptr, g->rowptr, S, R, chunks, ctrl, tb,
-                             epoch, flags, si, reset, ri));
-      tb += (unsigned long long)tiles;
-      ++epoch;
-      if (timing) HIPCK(hipEventRecord(ev[3], s));
-      ExpandArgs ea{};
-      ea.Q = qcur;
-      ea.nf = int32_t(nf);
-      ea.S = S;
-      ea.R = R;
-      ea.chunk_first = chunks;
-      ea.colind = g->colind;
-      ea.ctrl = ctrl;
-      ea.claim = vis;
-      ea.depth = depth;
-      ea.parent = parent;
-      ea.level = level;
-      ea.Qout = qnext;
-      ea.qslot = si;
-      ea.out_rowptr = edges_rule ? g->rowptr : nullptr;
-      ea.in_colptr = edges_rule ? g->colptr : nullptr;
-      ea.slot = slot;
-      ea.reset = reset;
-      ea.reset_level = ri;
-      HIPCK(launch_push_expand(s, kExpandBlocks, ea));
-      std::swap(qcur, qnext);
-      f_valid = false;
-    } else {
-      if (!reuse && !f_valid) {
-        // push -> pull without operand reuse: the frontier list becomes a bit vector (SPARSE2DENSE)
-        HIPCK(launch_fill(s, fcur, nwords, 0u));
-        HIPCK(launch_s2d(s, qcur, int32_t(nf), nullptr, V, fcur));
-        f_valid = true;
-      }
-      if (timing) HIPCK(hipEventRecord(ev[3], s));
-      PullArgs pa{};
-      pa.V = V;
-      pa.nwords = nwords;
-      pa.colptr = g->colptr;
-      pa.rowind = g->rowind;
-      pa.x = reuse ? vis : fcur;  // operand reuse: A^T v .* not(v) (Section 5.4)
-      pa.mask = vis;
-      pa.complement = 1;
-      pa.mask_after = mask_after ? 1 : 0;
-      pa.nz = g->nz_in;
-      pa.out_base = vis;
-      pa.out = vis_other;
-      pa.found_out = reuse ? nullptr : fnext;
-      pa.depth = depth;
-      pa.parent = parent;
-      pa.level = level;
-      pa.count_out = 0;
-      pa.edge_rule = edges_rule ? 1 : 0;
-      pa.slot = slot;
-      pa.reset = reset;
-      pa.reset_level = ri;
-      pa.ctrl = ctrl;
-      HIPCK(launch_pull(s, early_exit, pa));
-      std::swap(vis, vis_other);
-      if (!reuse) {
-        std::swap(fcur, fnext);
-        f_valid = true;
-      }
-      queue_valid = false;
+  while (levels < 0) {
+    const int64_t l1 = lvl + batch - 1;
+    for (int64_t l = lvl; l <= l1; ++l) {
+      const int32_t k = int32_t(l - lvl);
+      if (timing && k > 0) HIPCK(hipEventRecord(ev[2 * k + 1], s));
+      HIPCK(launch_level_main(s, a, int32_t(l)));
+      if (timing) HIPCK(hipEventRecord(ev[2 * k + 2], s));
+      HIPCK(launch_level_prep(s, a, int32_t(l + 1), forced(l + 1)));
     }
-    if (timing) HIPCK(hipEventRecord(ev[4], s));
-    HIPCK(hipMemcpyAsync(host, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-    HIPCK(hipStreamSynchronize(s));
-    const LevelTotals r = sum_slot(host->slot[si]);
-    const int64_t n_new = int64_t(r.count);
-    if (level == 0) {
-      if (timing) ms_init = elapsed(ev[0], ev[1]);
-      m_u = g->nnz - host->src_indeg;  // in-edges left for a pull to scan
+    if (timing) HIPCK(hipEventRecord(ev[2 * batch + 1], s));
+    const uint32_t seq = ++report_seq;
+    HIPCK(launch_report(s, a.ctrl, int32_t(lvl), batch, rep, seq));
+    HIPCK(wait_report(rep, seq, s));
+    if (timing) {
+      if (lvl == 0) {
+        ms_init = elapsed(ev[kEvStart], ev[kEvInit]);
+        first_aux = elapsed(ev[0], ev[1]);
+      }
     }
-    if (stats && level < stats->cap) {
-      dobfs_level_stats& ls = stats->level[level];
-      ls.dir = dir;
-      ls.nf = int32_t(nf);
-      ls.n_new = int32_t(n_new);
-      ls.pad = 0;
-      ls.edges = int64_t(r.edges);
-      ls.m_f = dir == DOBFS_DIR_PUSH ? int64_t(host->mf[si]) : 0;
-      ls.ms_main = timing ? elapsed(ev[3], ev[4]) : 0.f;
-      ls.ms_aux = timing ? elapsed(ev[2], ev[3]) : 0.f;
+    const LevelState& end = rep->end;
+    const int64_t last = end.done ? int64_t(end.levels) - 1 : l1;  // last level that ran
+    for (int64_t l = lvl; l <= last; ++l) {
+      const LevelRecord& r = rep->rec[l - lvl];
+      reached += r.n_new;
+      if (stats && l < stats->cap) {
+        dobfs_level_stats& ls = stats->level[l];
+        const int32_t k = int32_t(l - lvl);
+        ls.dir = r.dir;
+        ls.nf = r.nf;
+        ls.n_new = r.n_new;
+        ls.pad = 0;
+        ls.edges = r.edges;
+        ls.m_f = r.m_f;
+        ls.ms_aux = timing ? (k == 0 ? first_aux : elapsed(ev[2 * k], ev[2 * k + 1])) : 0.f;
+        ls.ms_main = timing ? elapsed(ev[2 * k + 1], ev[2 * k + 2]) : 0.f;
+      }
     }
-    reached += n_new;
-    if (n_new == 0) break;
-    if (edges_rule) m_u -= int64_t(r.insub);
-    int32_t next = dobfs_next_direction(&opt, dir, V, nf, n_new, int64_t(r.mnew), m_u);
-    if (opt.mode == DOBFS_MODE_PUSH_ONLY) next = DOBFS_DIR_PUSH;
-    if (opt.mode == DOBFS_MODE_PULL_ONLY) next = DOBFS_DIR_PULL;
-    dir = next;
-    nf = n_new;
-    ++level;
-    if (level > V) return fail(DOBFS_ERR_INTERNAL, "level loop did not terminate");
+    if (end.done) {
+      levels = end.levels;
+      break;
+    }
+    if (l1 + 1 > int64_t(g->V) + 1) return fail(DOBFS_ERR_INTERNAL, "level loop did not terminate");
+    if (timing) first_aux = elapsed(ev[2 * batch], ev[2 * batch + 1]);  // level_prep(l1 + 1)
+    lvl = l1 + 1;
+    batch = next_batch;
+    next_batch = std::min(2 * next_batch, kMaxBatch);
+    if (timing) HIPCK(hipEventRecord(ev[1], s));  // level_prep(lvl) ran in the previous batch
   }
-  HIPCK(hipEventRecord(ev[5], s));
-  HIPCK(hipEventSynchronize(ev[5]));
+  HIPCK(hipEventRecord(ev[kEvEnd], s));
+  HIPCK(hipEventSynchronize(ev[kEvEnd]));
+  g->last_levels.store(int32_t(levels), std::memory_order_relaxed);
   if (stats) {
-    stats->levels = level + 1;
-    stats->ms_total = elapsed(ev[0], ev[5]);
+    stats->levels = int32_t(levels);
+    stats->ms_total = elapsed(ev[kEvStart], ev[kEvEnd]);
     stats->ms_init = ms_init;
     stats->reached = reached;
   }
@@ -629,19 +626,19 @@ dobfs_status dobfs_mxv(dobfs_graph g, const uint32_t* x_bits, const int32_t* x_i
   int32_t* S = reinterpret_cast<int32_t*>(ws + L.S);
   int32_t* R = reinterpret_cast<int32_t*>(ws + L.R);
   int32_t* chunks = reinterpret_cast<int32_t*>(ws + L.chunks);
-  uint64_t* flags = reinterpret_cast<uint64_t*>(ws + L.flags);
+  uint64_t* flagsA = reinterpret_cast<uint64_t*>(ws + L.flagsA);
+  uint64_t* flagsB = reinterpret_cast<uint64_t*>(ws + L.flagsB);
   Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
   const bool accum = (flags_in & DOBFS_MXV_ACCUM_OR) != 0;
-  unsigned long long tb = 0;
-  uint32_t epoch = 1;
 
-  HIPCK(launch_ctrl_init(s, ctrl, flags, L.nflags));
+  HIPCK(launch_ctrl_init(s, ctrl, flagsA, L.nflags));
+  HIPCK(launch_fill(s, reinterpret_cast<uint32_t*>(flagsB), L.nflags * 2, 0u));
   LevelSlot* out_slot;
   if (direction == DOBFS_DIR_PULL) {
     const uint32_t* x = x_bits;
     if (!x) {
       HIPCK(launch_fill(s, xbits, nwords, 0u));
-      if (x_nnz > 0) HIPCK(launch_s2d(s, x_idx, x_nnz, nullptr, V, xbits));
+      if (x_nnz > 0) HIPCK(launch_s2d(s, x_idx, x_nnz, V, xbits));
       x = xbits;
     }
     PullArgs pa{};
@@ -649,6 +646,7 @@ dobfs_status dobfs_mxv(dobfs_graph g, const uint32_t* x_bits, const int32_t* x_i
     pa.nwords = nwords;
     pa.colptr = g->colptr;
     pa.rowind = g->rowind;
+    pa.head = g->head;
     pa.x = x;
     pa.mask = mask_bits;
     pa.complement = complement ? 1 : 0;
@@ -657,61 +655,74 @@ dobfs_status dobfs_mxv(dobfs_graph g, const uint32_t* x_bits, const int32_t* x_i
     pa.out_base = accum ? y_bits : nullptr;
     pa.out = y_bits;
     pa.parent = y_witness;
+    pa.early_exit = (flags_in & DOBFS_MXV_EARLY_EXIT) ? 1 : 0;
     pa.count_out = 1;
     pa.slot = &ctrl->slot[0];
-    HIPCK(launch_pull(s, (flags_in & DOBFS_MXV_EARLY_EXIT) != 0, pa));
+    HIPCK(launch_pull(s, pa));
     out_slot = &ctrl->slot[0];
   } else {
-    // The column-based matvec reads x as a sorted list of distinct indices:
-    // a dense x goes through DENSE2SPARSE; a given list is made canonical the
-    // same way (scatter, then compact), so repeated indices cannot inflate
-    // the expansion. The list length stays on the device.
+    // The column-based matvec reads x as a sorted list of distinct indices
+    // with its degree prefix: a dense x goes through DENSE2SPARSE fused with
+    // the degree scan; a given list is made canonical the same way (scatter,
+    // then compact), so repeated indices cannot inflate the expansion. The
+    // list length and edge total stay on the device.
     const uint32_t* xd = x_bits;
     if (!xd) {
       HIPCK(launch_fill(s, xbits, nwords, 0u));
-      if (x_nnz > 0) HIPCK(launch_s2d(s, x_idx, x_nnz, nullptr, V, xbits));
+      if (x_nnz > 0) HIPCK(launch_s2d(s, x_idx, x_nnz, V, xbits));
       xd = xbits;
     }
-    HIPCK(launch_d2s(s, xd, nullptr, nwords, V, list, ctrl, tb, epoch, flags, &ctrl->d2s_count));
-    tb += (unsigned long long)d2s_tiles(nwords);
-    ++epoch;
-    const int32_t* q = list;
-    const int32_t nf = 0;
-    const uint32_t* nf_dev = &ctrl->d2s_count;
-    const int64_t tiles = std::max<int64_t>(1, scan_tiles(V));
+    ScanBitsArgs sb{};
+    sb.a = xd;
+    sb.nwords = nwords;
+    sb.V = V;
+    sb.rowptr = g->rowptr;
+    sb.Qout = list;
+    sb.S = S;
+    sb.R = R;
+    sb.chunk_first = chunks;
+    sb.flagsA = flagsA;
+    sb.flagsB = flagsB;
+    sb.epochA = 1;
+    sb.epochB = 2;
+    sb.ticket = &ctrl->ticket[0];
+    sb.nf_out = &ctrl->nf32;
+    sb.mf_out = &ctrl->mf32;
+    HIPCK(launch_scan_bits(s, sb));
     HIPCK(launch_fill(s, rbits, nwords, 0u));
-    HIPCK(launch_push_scan(s, tiles, q, nf, nf_dev, g->rowptr, S, R, chunks, ctrl, tb, epoch, flags,
-                           0, nullptr, 0));
-    tb += (unsigned long long)tiles;
-    ++epoch;
     ExpandArgs ea{};
-    ea.Q = q;
-    ea.nf = nf;
-    ea.nf_dev = nf_dev;
+    ea.Q = list;
     ea.S = S;
     ea.R = R;
     ea.chunk_first = chunks;
     ea.colind = g->colind;
-    ea.ctrl = ctrl;
     ea.claim = rbits;
     ea.mask = mask_bits;
     ea.complement = complement ? 1 : 0;
     ea.parent = y_witness;
     ea.slot = &ctrl->slot[0];
-    HIPCK(launch_push_expand(s, kExpandBlocks, ea));
+    HIPCK(launch_expand(s, ea, &ctrl->mf32, &ctrl->nf32));
     HIPCK(launch_mxv_finalize(s, y_bits, rbits, nwords, V, accum ? 1 : 0, &ctrl->slot[1]));
     out_slot = &ctrl->slot[1];
   }
   if (y_idx) {
-    HIPCK(launch_d2s(s, y_bits, nullptr, nwords, V, y_idx, ctrl, tb, epoch, flags,
-                     &ctrl->d2s_count));
-    tb += (unsigned long long)d2s_tiles(nwords);
-    ++epoch;
+    ScanBitsArgs sb{};
+    sb.a = y_bits;
+    sb.nwords = nwords;
+    sb.V = V;
+    sb.Qout = y_idx;
+    sb.flagsA = flagsA;
+    sb.flagsB = flagsB;
+    sb.epochA = 3;
+    sb.epochB = 4;
+    sb.ticket = &ctrl->ticket[1];
+    sb.nf_out = &ctrl->nf32;
+    HIPCK(launch_scan_bits(s, sb));
   }
   if (y_nnz || y_idx) {
     Ctrl* host = host_ctrl();
     if (!host) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
-    HIPCK(hipMemcpyAsync(host, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIPCK(hipMemcpyAsync(host, ctrl, offsetof(Ctrl, ring), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
     if (y_nnz) *y_nnz = int32_t(sum_slot(host->slot[out_slot - ctrl->slot]).aux);
   } else {

@@ -12,7 +12,7 @@ namespace dobfs {
 // ---- per-level counters ----
 // Same-address device atomics serialize (about 11 ns each on MI355X), so
 // every block adds its partial sums into one of kStripes counters, each on
-// its own 128-byte line; the host adds the stripes up after the level.
+// its own 128-byte line; readers add the stripes up.
 constexpr int kStripes = 32;
 struct alignas(128) Stripe {
   uint32_t count;  // vertices discovered (BFS) / result bits (mxv)
@@ -26,16 +26,38 @@ struct LevelSlot {
 };
 constexpr int kSlots = 4;  // level L accumulates into slot L % kSlots
 
+// Traversal state entering a level, written by that level's first kernel.
+struct alignas(64) LevelState {
+  int32_t dir;         // DOBFS_DIR_* of this level
+  int32_t done;        // 1: a previous level discovered nothing; nothing left to do
+  int32_t list_valid;  // 1: the frontier is already a list (the previous level pushed)
+  int32_t vis_idx;     // which of the two visited bitmaps is current
+  int32_t nf;          // frontier size entering the level
+  int32_t levels;      // when done: number of levels run
+  int32_t level;       // index of this level
+  int32_t pad0;
+  int64_t m_u;         // edge-count rule: in-edges of still-unvisited vertices
+};
+// Per-level statistics for the host, written by the next level's first kernel.
+struct LevelRecord {
+  int32_t dir, nf, n_new, pad;
+  int64_t edges, m_f;
+  uint64_t mnew, insub;
+};
+constexpr int kRing = 1024;  // levels of state / records kept on the device
+
 struct Ctrl {
-  unsigned long long ticket;  // tile tickets of the single-pass scans (monotone within a call)
-  uint32_t mf32;              // m_f of the latest push scan, read by the expand kernel
-  uint32_t d2s_count;         // output length of the latest dense-to-sparse conversion
-  int64_t src_outdeg;         // out-degree of the BFS source
-  int64_t src_indeg;          // in-degree of the BFS source
-  uint32_t qcount[kSlots];    // frontier-list append counter of each level
-  uint64_t mf[kSlots];        // push: out-edges of the input frontier
-  uint8_t pad[128 - 48 - 8 * kSlots];
+  unsigned long long ticket[2];  // scan tile tickets, one counter per level parity
+  uint32_t mf32;                 // m_f of the latest frontier scan (expand reads it)
+  uint32_t nf32;                 // frontier length of the latest bitmap scan
+  int64_t src_outdeg;            // out-degree of the BFS source
+  int64_t src_indeg;             // in-degree of the BFS source
+  uint32_t qcount[kSlots];       // frontier-list append counter of each level
+  uint32_t mf[kSlots];           // push: out-edges of the level's input frontier
+  uint8_t pad[128 - 56 - 4 * kSlots];
   LevelSlot slot[kSlots];
+  LevelState ring[kRing];
+  LevelRecord rec[kRing];
 };
 static_assert(sizeof(Stripe) == 128, "stripe layout");
 static_assert(offsetof(Ctrl, slot) % 128 == 0, "slots start on a line");
@@ -58,30 +80,41 @@ inline LevelTotals sum_slot(const LevelSlot& s) {
 
 // ---- launch geometry (all kernels use 256-thread blocks = 4 wave64) ----
 constexpr int kThreads = 256;
-constexpr int kScanIPT = 8;                       // push scan: frontier entries per thread
-constexpr int kScanTile = kThreads * kScanIPT;   // 2048 entries per tile
-constexpr int kExpandEPT = 4;                     // push expand: edges per thread per chunk
-constexpr int kExpandChunk = kThreads * kExpandEPT;  // 1024 edges per chunk
-constexpr int kExpandWin = kExpandChunk + 1;      // frontier entries cached in LDS per chunk
-constexpr int kExpandBuf = 4096;                  // winners buffered in LDS before a queue flush
-constexpr int kExpandBlocks = 1024;               // expand grid (strides over chunks)
-constexpr int kPullTileWords = 64;                // pull: bitmap words owned by a block
-constexpr int kPullTileV = kPullTileWords * 32;   // 2048 rows per block
-constexpr int kPullFirst = 4;                     // in-neighbours one thread checks before handing a row to its wave
-constexpr int kPullBatch = 4;                     // candidate rows a thread works on at once
-constexpr int kD2SWPT = 4;                        // D2S: words per thread
-constexpr int kD2STile = kThreads * kD2SWPT;      // 1024 words per tile
+constexpr int kScanIPT = 8;                          // list scan: frontier entries per thread
+constexpr int kScanTile = kThreads * kScanIPT;      // 2048 entries per tile
+constexpr int kBitsWPT = 4;                          // bitmap scan: words per thread
+constexpr int kBitsTile = kThreads * kBitsWPT;      // 1024 words (32768 vertices) per tile
+constexpr int kScanBlocksMax = 256;                  // scan grids stride over tiles by ticket
+constexpr int kExpandEPT = 4;                        // expand: edges per thread per chunk
+constexpr int kExpandChunk = kThreads * kExpandEPT; // 1024 edges per chunk
+constexpr int kExpandWin = kExpandChunk + 1;         // frontier entries cached in LDS per chunk
+constexpr int kExpandBuf = 2048;                     // winners buffered in LDS before a list flush
+constexpr int kExpandBlocks = 1024;                  // expand grid (strides over chunks)
+constexpr int kPullTileWords = 64;                   // pull: bitmap words owned by a block
+constexpr int kPullTileV = kPullTileWords * 32;      // 2048 rows per block
+constexpr int kPullFirst = 4;                        // in-neighbours one thread checks before handing a row to its wave
+constexpr int kPullBatch = 4;                        // candidate rows a thread works on at once
 
 inline int32_t words_of(int64_t V) { return int32_t((V + 31) / 32); }
 inline int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
-inline int64_t d2s_tiles(int64_t nwords) { return (nwords + kD2STile - 1) / kD2STile; }
+inline int64_t bits_tiles(int64_t nwords) { return (nwords + kBitsTile - 1) / kBitsTile; }
+inline int64_t pull_tiles(int64_t nwords) { return (nwords + kPullTileWords - 1) / kPullTileWords; }
 inline int64_t max_chunks(int64_t nnz) { return nnz / kExpandChunk + 2; }
+inline int64_t flag_entries(int64_t V) {
+  const int64_t a = scan_tiles(V), b = bits_tiles(words_of(V));
+  return (a > b ? a : b) + 1;
+}
+inline int32_t scan_grid(int64_t V) {
+  const int64_t t = flag_entries(V);
+  return int32_t(t < kScanBlocksMax ? t : kScanBlocksMax);
+}
 
-// ---- kernel argument blocks ----
+// ---- argument blocks ----
 struct PullArgs {
   int32_t V, nwords;
   const int32_t* colptr;
   const int32_t* rowind;
+  const int32_t* head;       // first entry of every CSC column (-1 if empty)
   const uint32_t* x;         // input vector bits
   const uint32_t* mask;      // nullable: rows that pass = mask XOR complement
   int32_t complement;
@@ -93,23 +126,20 @@ struct PullArgs {
   int32_t* depth;            // nullable
   int32_t* parent;           // nullable: parent (BFS) or witness (mxv)
   int32_t level;
+  int32_t early_exit;
   int32_t count_out;         // 1: add popcount(out) to the stripes' aux (mxv)
   int32_t edge_rule;         // 1: add in-degrees of the results to the stripes' insub
   LevelSlot* slot;
-  LevelSlot* reset;          // nullable: zeroed by block 0 before use by the next level
-  int32_t reset_level;       // slot index of `reset` (its queue counter is zeroed too)
-  Ctrl* ctrl;
 };
 
 struct ExpandArgs {
   const int32_t* Q;          // frontier list
-  int32_t nf;                // frontier length (used when nf_dev is null)
-  const uint32_t* nf_dev;    // nullable: frontier length on the device
+  int32_t nf;
   const int32_t* S;          // exclusive scan of out-degrees
   const int32_t* R;          // row start of each frontier vertex
   const int32_t* chunk_first;  // first frontier entry of every edge chunk
   const int32_t* colind;
-  Ctrl* ctrl;                // mf32 = total edges; qcount = append counter
+  uint32_t m;                // total edges of the expansion
   uint32_t* claim;           // bitmap claimed with atomicOr (visited / result)
   const uint32_t* mask;      // nullable: filter before the claim
   int32_t complement;
@@ -117,39 +147,104 @@ struct ExpandArgs {
   int32_t* parent;           // nullable: parent / witness
   int32_t level;
   int32_t* Qout;             // nullable: winners appended here
-  int32_t qslot;             // which ctrl->qcount counts the appends
-  const int32_t* out_rowptr; // nullable: CSR(A) offsets; out-degrees of winners -> mnew
-  const int32_t* in_colptr;  // nullable: CSC(A) offsets; in-degrees of winners -> insub
+  uint32_t* qcount;          // append counter for Qout
+  uint32_t* found_out;       // nullable: winners' bits also set here
+  const int32_t* out_rowptr; // nullable: out-degrees of winners -> mnew
+  const int32_t* in_colptr;  // nullable: in-degrees of winners -> insub
   LevelSlot* slot;
-  LevelSlot* reset;
-  int32_t reset_level;
+};
+
+// Everything a BFS level kernel needs; the per-level choices come from the
+// LevelState the level's first kernel writes.
+struct BfsArgs {
+  int32_t V, nwords;
+  int64_t nnz;
+  const int32_t* rowptr;
+  const int32_t* colind;
+  const int32_t* colptr;
+  const int32_t* rowind;
+  const int32_t* head;       // first entry of every CSC column (-1 if empty)
+  const uint32_t* nz_in;
+  int32_t* depth;
+  int32_t* parent;
+  uint32_t* vis[2];
+  uint32_t* F[2];            // frontier bitmaps (modes without operand reuse)
+  int32_t* Q[2];             // frontier lists, level L reads Q[L % 2]
+  int32_t* S;
+  int32_t* R;
+  int32_t* chunk_first;
+  uint64_t* flagsA;
+  uint64_t* flagsB;
+  Ctrl* ctrl;
+  int32_t mode;
+  int32_t heuristic;
+  double alpha, beta;
+  int32_t reuse;             // pull reads the visited set (operand reuse)
+  int32_t early_exit;
+  int32_t mask_after;        // unmasked pull
+  int32_t need_F;            // frontier bitmaps maintained
+  int32_t edge_rule;
+};
+
+struct ScanBitsArgs {
+  const uint32_t* a;         // bits = a AND NOT b_not
+  const uint32_t* b_not;     // nullable
+  int32_t nwords, V;
+  const int32_t* rowptr;     // nullable: no degrees / S / R / chunk table
+  int32_t* Qout;             // the set bits as an ascending list
+  int32_t* S;
+  int32_t* R;
+  int32_t* chunk_first;
+  uint64_t* flagsA;
+  uint64_t* flagsB;
+  uint32_t epochA, epochB;
+  unsigned long long* ticket;
+  uint32_t* nf_out;          // list length
+  uint32_t* mf_out;          // total degree (when rowptr)
 };
 
 // ---- launchers (kernels.hip); each returns hipGetLastError() ----
-hipError_t launch_bfs_init(hipStream_t s, int32_t V, int32_t nwords, int32_t source,
-                           const int32_t* rowptr, const int32_t* colptr, int32_t* depth,
-                           int32_t* parent, uint32_t* vis, int32_t* Q, Ctrl* ctrl, uint64_t* flags,
-                           int64_t nflags);
+hipError_t launch_bfs_init(hipStream_t s, const BfsArgs& a, int32_t source, int32_t dir0);
+hipError_t launch_level_prep(hipStream_t s, const BfsArgs& a, int32_t level, int32_t forced_dir);
+hipError_t launch_level_main(hipStream_t s, const BfsArgs& a, int32_t level);
 hipError_t launch_ctrl_init(hipStream_t s, Ctrl* ctrl, uint64_t* flags, int64_t nflags);
-hipError_t launch_push_scan(hipStream_t s, int64_t tiles, const int32_t* Q, int32_t nf,
-                            const uint32_t* nf_dev, const int32_t* rowptr, int32_t* S, int32_t* R,
-                            int32_t* chunk_first, Ctrl* ctrl, unsigned long long ticket_base,
-                            uint32_t epoch, uint64_t* flags, int32_t level_slot, LevelSlot* reset,
-                            int32_t reset_level);
-hipError_t launch_push_expand(hipStream_t s, int32_t blocks, const ExpandArgs& a);
-hipError_t launch_pull(hipStream_t s, bool early_exit, const PullArgs& a);
-hipError_t launch_d2s(hipStream_t s, const uint32_t* a, const uint32_t* b_not, int32_t nwords,
-                      int32_t V, int32_t* out, Ctrl* ctrl, unsigned long long ticket_base,
-                      uint32_t epoch, uint64_t* flags, uint32_t* count_out);
+hipError_t launch_scan_bits(hipStream_t s, const ScanBitsArgs& a);
+hipError_t launch_expand(hipStream_t s, const ExpandArgs& a, const uint32_t* m_dev,
+                         const uint32_t* nf_dev);
+hipError_t launch_pull(hipStream_t s, const PullArgs& a);
 hipError_t launch_fill(hipStream_t s, uint32_t* p, int64_t n, uint32_t v);
-hipError_t launch_s2d(hipStream_t s, const int32_t* idx, int32_t n, const uint32_t* n_dev,
-                      int32_t V, uint32_t* bits);
+hipError_t launch_s2d(hipStream_t s, const int32_t* idx, int32_t n, int32_t V, uint32_t* bits);
 hipError_t launch_mxv_finalize(hipStream_t s, uint32_t* y, const uint32_t* r, int32_t nwords,
                                int32_t V, int accum, LevelSlot* slot);
 hipError_t launch_nz_bits(hipStream_t s, const int32_t* ptr, int32_t V, uint32_t* bits);
+hipError_t launch_head(hipStream_t s, const int32_t* ptr, const int32_t* ind, int32_t V,
+                       int32_t* head);
+// What the host needs after a batch of levels: the state after the batch and
+// the records of its levels. Written into pinned host memory by one block,
+// `seq` last (system-scope release), so the host can spin on it.
+constexpr int kMaxBatch = 64;
+struct HostReport {
+  LevelState end;
+  LevelRecord rec[kMaxBatch];
+  uint32_t seq;
+};
+hipError_t launch_report(hipStream_t s, const Ctrl* ctrl, int32_t l_first, int32_t n,
+                         HostReport* host, uint32_t seq);
 hipError_t launch_check_offsets(hipStream_t s, const int32_t* ptr, int32_t V, int64_t nnz,
                                 int32_t* err);
 hipError_t launch_check_indices(hipStream_t s, const int32_t* idx, int64_t nnz, int32_t V,
                                 int32_t* err);
+
+// Direction rule of Section 6.3 (and Beamer's edge form); identical on host and device.
+__host__ __device__ inline int32_t next_direction_rule(int32_t heuristic, double alpha, double beta,
+                                                       int32_t dir, int64_t V, int64_t nf,
+                                                       int64_t n_new, int64_t m_f, int64_t m_u) {
+  if (heuristic == 1) {  // edge counts
+    if (dir == 0) return double(m_f) > alpha * double(m_u) ? 1 : 0;
+    return double(n_new) < beta * double(V) ? 0 : 1;
+  }
+  if (dir == 0) return (n_new > nf && double(n_new) > alpha * double(V)) ? 1 : 0;
+  return (n_new < nf && double(n_new) < beta * double(V)) ? 0 : 1;
+}
 
 }  // namespace dobfs

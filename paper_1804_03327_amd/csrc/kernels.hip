@@ -6,15 +6,22 @@
 // mask lets through, stopping at the first hit (Equation 4, Algorithm 2,
 // Sections 5.2-5.4). Everything is integer / bitwise: no MFMA.
 //
+// A BFS level is exactly two kernels: level_prep decides the level's
+// direction on the device (the rule of Section 6.3, from the previous
+// level's counters) and, for push, turns the frontier into a list with its
+// degree prefix; level_main runs the push expansion or the pull. The host
+// enqueues many levels ahead and reads the state back once per batch.
+//
 // Memory layout (HBM): CSR(A) and CSC(A) int32 arrays; bit vectors as uint32
 // words (bit i = word i>>5, bit i&31); frontier lists as int32.
 //
 // Rates that shaped these kernels (measured on MI355X): random 4-byte loads
 // from a 512 KiB L2-resident bitmap ~270 G/s; atomics on distinct words
 // ~27 G/s; atomics on one address ~0.09 G/s (serialized); streaming reads
-// ~6.4 TB/s. So the bitmaps are read with plain loads first, per-level
-// counters are striped over kStripes lines, and list appends are batched per
-// block in LDS.
+// ~6.4 TB/s; a kernel boundary ~3 us; a host round trip ~15 us. So the
+// bitmaps are read with plain loads first, per-level counters are striped
+// over kStripes lines, list appends are batched per block in LDS, and levels
+// are decided on the device.
 
 #include "dobfs_internal.h"
 
@@ -120,28 +127,19 @@ __device__ __forceinline__ void zero_stripe(Stripe& st) {
   st.insub = 0;
 }
 
-// Zero the counters of the next level (block 0), before any of its kernels runs.
-__device__ __forceinline__ void reset_slot(Ctrl* ctrl, LevelSlot* r, int32_t r_level) {
-  if (!r || blockIdx.x != 0) return;
-  for (int k = threadIdx.x; k < kStripes; k += blockDim.x) zero_stripe(r->s[k]);
-  if (threadIdx.x == 0 && ctrl) {
-    ctrl->qcount[r_level] = 0;
-    ctrl->mf[r_level] = 0;
-  }
-}
-
 // ---- single-pass tile prefix (decoupled look-back) ----
 // Tile descriptors are one 64-bit word: [epoch:30][status:2][value:32], so a
 // single atomic store publishes status and value together. Tiles are numbered
-// by a ticket taken at block start, so every tile a block waits on belongs to
-// a block that is already running and publishes without waiting itself.
+// by tickets taken when a block is ready to work on one, so every tile a
+// block waits on belongs to a running block that publishes without waiting.
 __device__ __forceinline__ uint64_t pack_flag(uint32_t epoch, uint32_t status, uint32_t value) {
   return (uint64_t(epoch) << 34) | (uint64_t(status) << 32) | uint64_t(value);
 }
 
-__device__ __forceinline__ uint32_t take_ticket(Ctrl* ctrl, unsigned long long base) {
+__device__ __forceinline__ uint32_t take_ticket(unsigned long long* ticket) {
   __shared__ uint32_t s_tile;
-  if (threadIdx.x == 0) s_tile = uint32_t(atomicAdd(&ctrl->ticket, 1ull) - base);
+  __syncthreads();  // every thread is done with the previous tile's s_tile
+  if (threadIdx.x == 0) s_tile = uint32_t(atomicAdd(ticket, 1ull));
   __syncthreads();
   return s_tile;
 }
@@ -199,143 +197,124 @@ __device__ uint32_t tile_exclusive_prefix(uint64_t* flags, uint32_t tile, uint32
   return s_excl;
 }
 
-// ---------------------------------------------------------------- init
-// Algorithm 1 initialisation: depth/parent unreached except the source,
-// visited = {s}, frontier list = [s]; also clears the control block and the
-// scan tile descriptors of this call.
-__global__ __launch_bounds__(kThreads) void k_bfs_init(int32_t V, int32_t nwords, int32_t source,
-                                                       const int32_t* rowptr, const int32_t* colptr,
-                                                       int32_t* depth, int32_t* parent,
-                                                       uint32_t* vis, int32_t* Q, Ctrl* ctrl,
-                                                       uint64_t* flags, int64_t nflags) {
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  // 16-byte stores when both outputs allow them
-  const bool vec = (reinterpret_cast<uintptr_t>(depth) % 16 == 0) &&
-                   (!parent || reinterpret_cast<uintptr_t>(parent) % 16 == 0);
-  const int64_t nvec = vec ? V / 4 : 0;
-  int4* d4 = reinterpret_cast<int4*>(depth);
-  int4* p4 = reinterpret_cast<int4*>(parent);
-  for (int64_t i = t0; i < nvec; i += stride) {
-    const int64_t b = i * 4;
-    int4 d = make_int4(-1, -1, -1, -1), p = d;
-    if (source >= b && source < b + 4) {
-      const int k = int(source - b);
-      if (k == 0) { d.x = 0; p.x = source; }
-      if (k == 1) { d.y = 0; p.y = source; }
-      if (k == 2) { d.z = 0; p.z = source; }
-      if (k == 3) { d.w = 0; p.w = source; }
-    }
-    d4[i] = d;
-    if (parent) p4[i] = p;
-  }
-  for (int64_t i = nvec * 4 + t0; i < V; i += stride) {
-    depth[i] = (i == source) ? 0 : -1;
-    if (parent) parent[i] = (i == source) ? source : -1;
-  }
-  for (int64_t w = t0; w < nwords; w += stride)
-    vis[w] = (w == (source >> 5)) ? (1u << (source & 31)) : 0u;
-  for (int64_t k = t0; k < nflags; k += stride) flags[k] = 0;
-  if (blockIdx.x == 0) {
-    for (int k = threadIdx.x; k < kSlots * kStripes; k += blockDim.x)
-      zero_stripe(ctrl->slot[k / kStripes].s[k % kStripes]);
-    if (threadIdx.x == 0) {
-      Q[0] = source;
-      ctrl->ticket = 0;
-      ctrl->mf32 = 0;
-      ctrl->d2s_count = 0;
-      ctrl->src_outdeg = rowptr[source + 1] - rowptr[source];
-      ctrl->src_indeg = colptr[source + 1] - colptr[source];
-      for (int s = 0; s < kSlots; ++s) {
-        ctrl->qcount[s] = 0;
-        ctrl->mf[s] = 0;
-      }
-    }
-  }
+// Chunks of kExpandChunk edges whose first edge lies in [run, run + deg):
+// the vertex at list position k is their first vertex.
+__device__ __forceinline__ void mark_chunks(int32_t* chunk_first, uint32_t run, int32_t deg, int32_t k) {
+  if (deg <= 0) return;
+  const uint32_t c0 = (run + kExpandChunk - 1) / kExpandChunk;
+  const uint32_t c1 = (run + uint32_t(deg) - 1) / kExpandChunk;
+  for (uint32_t c = c0; c <= c1; ++c) chunk_first[c] = k;
 }
 
-__global__ __launch_bounds__(kThreads) void k_ctrl_init(Ctrl* ctrl, uint64_t* flags,
-                                                        int64_t nflags) {
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  for (int64_t k = t0; k < nflags; k += stride) flags[k] = 0;
-  if (blockIdx.x == 0) {
-    for (int k = threadIdx.x; k < kSlots * kStripes; k += blockDim.x)
-      zero_stripe(ctrl->slot[k / kStripes].s[k % kStripes]);
-    if (threadIdx.x == 0) {
-      ctrl->ticket = 0;
-      ctrl->mf32 = 0;
-      ctrl->d2s_count = 0;
-      ctrl->src_outdeg = 0;
-      ctrl->src_indeg = 0;
-      for (int s = 0; s < kSlots; ++s) {
-        ctrl->qcount[s] = 0;
-        ctrl->mf[s] = 0;
-      }
-    }
-  }
-}
-
-// ----------------------------------------------------------- push: scan
+// --------------------------------------------------- frontier list scans
 // Out-degree of every frontier vertex and its exclusive prefix sum (the
 // "length" and "scan" steps of the column-based matvec, Section 6.2): S[k] is
 // where vertex Q[k]'s adjacency starts in the concatenated expansion, R[k] its
-// row start in CSR(A). Every vertex whose adjacency segment contains the
-// first edge of a kExpandChunk-edge chunk records itself as that chunk's
-// first vertex, which is all the expand kernel needs to find its work (the
-// load-balanced gather). The last tile stores m_f = nnz(m_f^+).
-__global__ __launch_bounds__(kThreads) void k_push_scan(const int32_t* __restrict__ Q, int32_t nf_arg,
-                                                        const uint32_t* nf_dev,
-                                                        const int32_t* __restrict__ rowptr,
-                                                        int32_t* __restrict__ S,
-                                                        int32_t* __restrict__ R,
-                                                        int32_t* __restrict__ chunk_first,
-                                                        Ctrl* ctrl, unsigned long long ticket_base,
-                                                        uint32_t epoch, uint64_t* flags,
-                                                        int32_t level_slot, LevelSlot* reset,
-                                                        int32_t reset_level) {
-  reset_slot(ctrl, reset, reset_level);
-  const int32_t nf = nf_dev ? int32_t(*nf_dev) : nf_arg;
-  const uint32_t tile = take_ticket(ctrl, ticket_base);
-  const int64_t first = int64_t(tile) * kScanTile;
-  if (first >= nf && tile != 0) return;  // beyond the list: nobody waits for this tile
-  const int64_t base = first + int64_t(threadIdx.x) * kScanIPT;
-  int32_t deg[kScanIPT], st[kScanIPT];
-  uint32_t sum = 0;
+// row start in CSR(A), and every chunk of kExpandChunk edges records its
+// first vertex, which is all the expand step needs to find its work (the
+// load-balanced gather). Blocks take tiles by ticket until the list is done.
+__device__ void scan_list(const int32_t* __restrict__ Q, int32_t nf, const int32_t* __restrict__ rowptr,
+                          int32_t* __restrict__ S, int32_t* __restrict__ R,
+                          int32_t* __restrict__ chunk_first, uint64_t* flags, uint32_t epoch,
+                          unsigned long long* ticket, uint32_t* mf_out) {
+  const uint32_t ntiles = uint32_t(nf > 0 ? (nf + kScanTile - 1) / kScanTile : 1);
+  if (blockIdx.x >= ntiles) return;  // no tile for this block: take no ticket
+  const bool one_each = ntiles <= gridDim.x;
+  for (bool first = true;; first = false) {
+    if (one_each && !first) return;  // every tile has a block of its own
+    const uint32_t tile = take_ticket(ticket);
+    if (tile >= ntiles) return;
+    const int64_t base = int64_t(tile) * kScanTile + int64_t(threadIdx.x) * kScanIPT;
+    int32_t deg[kScanIPT], st[kScanIPT];
+    uint32_t sum = 0;
 #pragma unroll
-  for (int k = 0; k < kScanIPT; ++k) {
-    deg[k] = 0;
-    st[k] = 0;
-    if (base + k < nf) {
-      const int32_t u = Q[base + k];
-      const int32_t b = rowptr[u], e = rowptr[u + 1];
-      deg[k] = e - b;
-      st[k] = b;
-      sum += uint32_t(e - b);
-    }
-  }
-  uint32_t agg;
-  const uint32_t excl = block_excl_scan(sum, &agg);
-  const uint32_t tile_excl = tile_exclusive_prefix(flags, tile, epoch, agg);
-  uint32_t run = tile_excl + excl;
-#pragma unroll
-  for (int k = 0; k < kScanIPT; ++k) {
-    if (base + k < nf) {
-      S[base + k] = int32_t(run);
-      R[base + k] = st[k];
-      if (deg[k] > 0) {
-        // chunks whose first edge lies in [run, run + deg)
-        const uint32_t c0 = (run + kExpandChunk - 1) / kExpandChunk;
-        const uint32_t c1 = (run + uint32_t(deg[k]) - 1) / kExpandChunk;
-        for (uint32_t c = c0; c <= c1; ++c) chunk_first[c] = int32_t(base + k);
+    for (int k = 0; k < kScanIPT; ++k) {
+      deg[k] = 0;
+      st[k] = 0;
+      if (base + k < nf) {
+        const int32_t u = Q[base + k];
+        const int32_t b = rowptr[u], e = rowptr[u + 1];
+        deg[k] = e - b;
+        st[k] = b;
+        sum += uint32_t(e - b);
       }
-      run += uint32_t(deg[k]);
     }
+    uint32_t agg;
+    const uint32_t excl = block_excl_scan(sum, &agg);
+    const uint32_t tile_excl = tile_exclusive_prefix(flags, tile, epoch, agg);
+    uint32_t run = tile_excl + excl;
+#pragma unroll
+    for (int k = 0; k < kScanIPT; ++k) {
+      if (base + k < nf) {
+        S[base + k] = int32_t(run);
+        R[base + k] = st[k];
+        mark_chunks(chunk_first, run, deg[k], int32_t(base + k));
+        run += uint32_t(deg[k]);
+      }
+    }
+    if (tile == ntiles - 1 && threadIdx.x == 0) *mf_out = tile_excl + agg;
   }
-  const bool last = (nf == 0) ? (tile == 0) : (tile == uint32_t((nf - 1) / kScanTile));
-  if (last && threadIdx.x == 0) {
-    ctrl->mf32 = tile_excl + agg;
-    ctrl->mf[level_slot] = uint64_t(tile_excl + agg);
+}
+
+// The set bits of (a AND NOT b_not) as an ascending list (DENSE2SPARSE of
+// Section 6.3), fused with the same degree prefix when rowptr is given: two
+// look-back chains, one over vertex counts and one over degree sums.
+__device__ void scan_bits(const ScanBitsArgs& a) {
+  const uint32_t ntiles = uint32_t((a.nwords + kBitsTile - 1) / kBitsTile);
+  if (blockIdx.x >= ntiles) return;  // no tile for this block: take no ticket
+  const bool one_each = ntiles <= gridDim.x;
+  for (bool first = true;; first = false) {
+    if (one_each && !first) return;  // every tile has a block of its own
+    const uint32_t tile = take_ticket(a.ticket);
+    if (tile >= ntiles) return;
+    const int32_t wbase = int32_t(tile) * kBitsTile + threadIdx.x * kBitsWPT;
+    uint32_t bits[kBitsWPT];
+    uint32_t c = 0, d = 0;
+#pragma unroll
+    for (int k = 0; k < kBitsWPT; ++k) {
+      const int32_t w = wbase + k;
+      bits[k] = 0;
+      if (w < a.nwords)
+        bits[k] = a.a[w] & (a.b_not ? ~a.b_not[w] : 0xffffffffu) & valid_bits(w, a.V);
+      c += __popc(bits[k]);
+      if (a.rowptr) {
+        uint32_t b = bits[k];
+        while (b) {
+          const int32_t v = w * 32 + __ffs(b) - 1;
+          d += uint32_t(a.rowptr[v + 1] - a.rowptr[v]);
+          b &= b - 1;
+        }
+      }
+    }
+    uint32_t agg_c, agg_d = 0;
+    const uint32_t excl_c = block_excl_scan(c, &agg_c);
+    uint32_t excl_d = 0;
+    if (a.rowptr) excl_d = block_excl_scan(d, &agg_d);
+    const uint32_t pc = tile_exclusive_prefix(a.flagsA, tile, a.epochA, agg_c);
+    uint32_t pd = 0;
+    if (a.rowptr) pd = tile_exclusive_prefix(a.flagsB, tile, a.epochB, agg_d);
+    uint32_t pos = pc + excl_c, run = pd + excl_d;
+#pragma unroll
+    for (int k = 0; k < kBitsWPT; ++k) {
+      uint32_t b = bits[k];
+      while (b) {
+        const int32_t v = (wbase + k) * 32 + __ffs(b) - 1;
+        a.Qout[pos] = v;
+        if (a.rowptr) {
+          const int32_t rb = a.rowptr[v], deg = a.rowptr[v + 1] - rb;
+          a.S[pos] = int32_t(run);
+          a.R[pos] = rb;
+          mark_chunks(a.chunk_first, run, deg, int32_t(pos));
+          run += uint32_t(deg);
+        }
+        ++pos;
+        b &= b - 1;
+      }
+    }
+    if (tile == ntiles - 1 && threadIdx.x == 0) {
+      *a.nf_out = pc + agg_c;
+      if (a.mf_out) *a.mf_out = pd + agg_d;
+    }
   }
 }
 
@@ -347,40 +326,43 @@ __device__ __forceinline__ int32_t thread_search(const int32_t* S, int32_t lo, i
   return lo;
 }
 
-// --------------------------------------------------------- push: expand
+// ----------------------------------------------------------------- push
+struct ExpandShared {
+  int32_t sS[kExpandWin], sR[kExpandWin], sQ[kExpandWin];
+  int32_t buf[kExpandBuf];
+  uint32_t nbuf, base;
+};
+
 // Load-balanced gather over the concatenated adjacency of the frontier: a
 // block takes chunks of kExpandChunk consecutive edges; each edge finds its
-// frontier vertex by a search over the scan (the interval-gather step of
-// Section 6.2), so supervertices spread over many blocks and adjacent lanes
-// read adjacent column indices. Each thread carries kExpandEPT edges at once
-// so their loads overlap. The merge + mask filter of the paper's sort-based
-// version is one atomicOr per edge whose target still looks unvisited: the
-// first setter of a bit owns the vertex (Boolean OR makes any winner exact),
-// which both deduplicates and applies the mask not(v). Winners are buffered
-// in LDS and appended to the next frontier list with one atomic per flush.
-__global__ __launch_bounds__(kThreads) void k_push_expand(ExpandArgs a) {
-  __shared__ int32_t sS[kExpandWin], sR[kExpandWin], sQ[kExpandWin];
-  __shared__ int32_t s_buf[kExpandBuf];
-  __shared__ uint32_t s_nbuf, s_base;
-  reset_slot(a.ctrl, a.reset, a.reset_level);
-  const int32_t nf = a.nf_dev ? int32_t(*a.nf_dev) : a.nf;
-  const uint32_t m = a.ctrl->mf32;
+// frontier vertex by a search over the chunk's window of the scan (the
+// interval-gather step of Section 6.2), so supervertices spread over many
+// blocks and adjacent lanes read adjacent column indices. Each thread carries
+// kExpandEPT edges at once so their loads overlap. The merge + mask filter of
+// the paper's sort-based version is one atomicOr per edge whose target still
+// looks unvisited: the first setter of a bit owns the vertex (Boolean OR
+// makes any winner exact), which both deduplicates and applies the mask
+// not(v). Winners are buffered in LDS and appended to the next frontier list
+// with one atomic per flush.
+__device__ void expand_body(const ExpandArgs& a, ExpandShared& sh) {
+  const int32_t nf = a.nf;
+  const uint32_t m = a.m;
   if (nf <= 0 || m == 0) return;
   const uint32_t nchunks = (m + kExpandChunk - 1) / kExpandChunk;
   if (blockIdx.x >= nchunks) return;
-  if (threadIdx.x == 0) s_nbuf = 0;
+  if (threadIdx.x == 0) sh.nbuf = 0;
   unsigned long long won_total = 0, mnew = 0, insub = 0;
   const uint32_t cflip = a.complement ? 1u : 0u;
 
   auto flush = [&]() {  // all threads; callers are past a barrier
-    const uint32_t nb = s_nbuf;
+    const uint32_t nb = sh.nbuf;
     if (nb == 0) return;
-    if (threadIdx.x == 0) s_base = atomicAdd(&a.ctrl->qcount[a.qslot], nb);
+    if (threadIdx.x == 0) sh.base = atomicAdd(a.qcount, nb);
     __syncthreads();
-    const uint32_t b = s_base;
-    for (uint32_t k = threadIdx.x; k < nb; k += kThreads) a.Qout[b + k] = s_buf[k];
+    const uint32_t b = sh.base;
+    for (uint32_t k = threadIdx.x; k < nb; k += kThreads) a.Qout[b + k] = sh.buf[k];
     __syncthreads();
-    if (threadIdx.x == 0) s_nbuf = 0;
+    if (threadIdx.x == 0) sh.nbuf = 0;
     __syncthreads();
   };
 
@@ -391,13 +373,13 @@ __global__ __launch_bounds__(kThreads) void k_push_expand(ExpandArgs a) {
     const int32_t k1 = (c + 1 < nchunks) ? a.chunk_first[c + 1] : nf - 1;
     const int32_t n = k1 - k0 + 1;
     const bool in_lds = n <= kExpandWin;
-    __syncthreads();  // previous chunk's LDS readers are done, s_nbuf is settled
-    if (a.Qout && s_nbuf + kExpandChunk > kExpandBuf) flush();
+    __syncthreads();  // previous chunk's LDS readers are done, nbuf is settled
+    if (a.Qout && sh.nbuf + kExpandChunk > kExpandBuf) flush();
     if (in_lds) {
       for (int32_t i = threadIdx.x; i < n; i += kThreads) {
-        sS[i] = a.S[k0 + i];
-        sR[i] = a.R[k0 + i];
-        sQ[i] = a.Q[k0 + i];
+        sh.sS[i] = a.S[k0 + i];
+        sh.sR[i] = a.R[k0 + i];
+        sh.sQ[i] = a.Q[k0 + i];
       }
     }
     __syncthreads();
@@ -412,8 +394,8 @@ __global__ __launch_bounds__(kThreads) void k_push_expand(ExpandArgs a) {
       if (valid[t]) {
         int32_t s, rs;
         if (in_lds) {
-          const int32_t kk = thread_search(sS, 0, n, e);
-          s = sS[kk]; rs = sR[kk]; u[t] = sQ[kk];
+          const int32_t kk = thread_search(sh.sS, 0, n, e);
+          s = sh.sS[kk]; rs = sh.sR[kk]; u[t] = sh.sQ[kk];
         } else {
           const int32_t kk = thread_search(a.S, k0, k1 + 1, e);
           s = a.S[kk]; rs = a.R[kk]; u[t] = a.Q[kk];
@@ -443,6 +425,7 @@ __global__ __launch_bounds__(kThreads) void k_push_expand(ExpandArgs a) {
         ++won_total;
         if (a.depth) a.depth[w[t]] = a.level + 1;
         if (a.parent) a.parent[w[t]] = u[t];
+        if (a.found_out) atomicOr(a.found_out + (w[t] >> 5), 1u << (w[t] & 31));
         if (a.out_rowptr) mnew += uint64_t(a.out_rowptr[w[t] + 1] - a.out_rowptr[w[t]]);
         if (a.in_colptr) insub += uint64_t(a.in_colptr[w[t] + 1] - a.in_colptr[w[t]]);
       }
@@ -452,9 +435,9 @@ __global__ __launch_bounds__(kThreads) void k_push_expand(ExpandArgs a) {
           const int cnt = __popcll(bal);
           const int leader = __ffsll((unsigned long long)bal) - 1;
           uint32_t p = 0;
-          if (lane() == leader) p = atomicAdd(&s_nbuf, uint32_t(cnt));
+          if (lane() == leader) p = atomicAdd(&sh.nbuf, uint32_t(cnt));
           p = __shfl(p, leader, 64);
-          if (won[t]) s_buf[p + __popcll(bal & lanemask_lt())] = w[t];
+          if (won[t]) sh.buf[p + __popcll(bal & lanemask_lt())] = w[t];
         }
       }
     }
@@ -472,35 +455,36 @@ __global__ __launch_bounds__(kThreads) void k_push_expand(ExpandArgs a) {
   }
 }
 
-// ------------------------------------------------------------------ pull
-// Row-based masked matvec (Algorithm 2) over CSC(A). A block owns 64 bitmap
-// words (2048 rows): it lists the rows its mask lets through (output
-// sparsity, Section 5.2), lets one thread check the first kPullFirst
-// in-neighbours of each row in stored order and stop at the first hit
-// (early exit, Section 5.3), and hands longer unresolved rows to a whole
-// wave, which checks 64 in-neighbours per step and keeps the lowest hit, so
-// the reported parent is always the first in stored order. A thread works on
-// kPullBatch rows at once so their loads overlap. Results gather in LDS and
-// the block writes its words of the output vector whole, so no atomics touch
-// the output bitmap. `x` (the input vector) is never written here, which
-// keeps the visited snapshot exact when x = visited (operand reuse,
-// Section 5.4).
+// ----------------------------------------------------------------- pull
+struct PullShared {
+  uint16_t cand[kPullTileV];
+  uint16_t lng[kPullTileV];
+  uint32_t found[kPullTileWords];
+  int32_t ncand, nlong;
+};
+
+// Row-based masked matvec (Algorithm 2) over CSC(A) for the rows of one
+// tile of 64 bitmap words (2048 rows): list the rows the mask lets through
+// (output sparsity, Section 5.2); one thread checks the first kPullFirst
+// in-neighbours of each row in stored order and stops at the first hit
+// (early exit, Section 5.3); longer unresolved rows go to a whole wave, which
+// checks 64 in-neighbours per step and keeps the lowest hit, so the reported
+// parent is always the first in stored order. A thread works on kPullBatch
+// rows at once so their loads overlap. Results gather in LDS and the tile's
+// words of the output vector are written whole, so no atomics touch the
+// output bitmap. `x` (the input vector) is never written here, which keeps
+// the visited snapshot exact when x = visited (operand reuse, Section 5.4).
 template <bool EE>
-__global__ __launch_bounds__(kThreads) void k_pull(PullArgs a) {
-  __shared__ uint16_t s_cand[kPullTileV];
-  __shared__ uint16_t s_long[kPullTileV];
-  __shared__ uint32_t s_found[kPullTileWords];
-  __shared__ int32_t s_ncand, s_nlong;
-  reset_slot(a.ctrl, a.reset, a.reset_level);
+__device__ void pull_body(const PullArgs& a, int32_t tile, PullShared& sh) {
   const int tid = threadIdx.x;
-  const int32_t w0 = blockIdx.x * kPullTileWords;
+  const int32_t w0 = tile * kPullTileWords;
   const int32_t v0 = w0 * 32;
   const uint32_t cflip = a.complement ? 0xffffffffu : 0u;
 
   if (tid < 64) {  // wave 0 lists the candidate rows of the tile in order
     const int32_t w = w0 + tid;
     uint32_t cand = 0;
-    s_found[tid] = 0;
+    sh.found[tid] = 0;
     if (w < a.nwords) {
       const uint32_t pass = a.mask ? (a.mask[w] ^ cflip) : 0xffffffffu;
       cand = (a.mask_after ? 0xffffffffu : pass) & a.nz[w] & valid_bits(w, a.V);
@@ -511,22 +495,22 @@ __global__ __launch_bounds__(kThreads) void k_pull(PullArgs a) {
     uint32_t bits = cand;
     while (bits) {
       const int b = __ffs(bits) - 1;
-      s_cand[pos++] = uint16_t(tid * 32 + b);
+      sh.cand[pos++] = uint16_t(tid * 32 + b);
       bits &= bits - 1;
     }
     if (tid == 63) {
-      s_ncand = incl;
-      s_nlong = 0;
+      sh.ncand = incl;
+      sh.nlong = 0;
     }
   }
   __syncthreads();
-  const int32_t ncand = s_ncand;
+  const int32_t ncand = sh.ncand;
   unsigned long long checks = 0, insub = 0;
 
   auto record = [&](int32_t off, int32_t j, int32_t indeg) {
     const int32_t i = v0 + off;
     if (a.mask_after && a.mask && !(get_bit(a.mask, i) ^ (cflip & 1u))) return;
-    atomicOr(&s_found[off >> 5], 1u << (off & 31));
+    atomicOr(&sh.found[off >> 5], 1u << (off & 31));
     if (a.depth) a.depth[i] = a.level + 1;
     if (a.parent) a.parent[i] = j;
     if (a.edge_rule) insub += uint64_t(indeg);
@@ -538,17 +522,23 @@ __global__ __launch_bounds__(kThreads) void k_pull(PullArgs a) {
 #pragma unroll
     for (int t = 0; t < kPullBatch; ++t) {
       const int32_t idx = base + t * kThreads + tid;
-      off[t] = idx < ncand ? int32_t(s_cand[idx]) : -1;
+      off[t] = idx < ncand ? int32_t(sh.cand[idx]) : -1;
     }
+    // the first in-neighbour of every row sits in a dense array: one
+    // coalesced read instead of a line of the index array per row
+#pragma unroll
+    for (int t = 0; t < kPullBatch; ++t) j[t] = off[t] >= 0 ? a.head[v0 + off[t]] : -1;
+#pragma unroll
+    for (int t = 0; t < kPullBatch; ++t) hit[t] = j[t] >= 0 && get_bit(a.x, j[t]);
 #pragma unroll
     for (int t = 0; t < kPullBatch; ++t) {
-      beg[t] = off[t] >= 0 ? a.colptr[v0 + off[t]] : 0;
-      end[t] = off[t] >= 0 ? a.colptr[v0 + off[t] + 1] : 0;
+      beg[t] = 0;
+      end[t] = 1;  // a hit row needs its extent only for the edge-count rule
+      if (off[t] >= 0 && (!hit[t] || !EE || a.edge_rule)) {
+        beg[t] = a.colptr[v0 + off[t]];
+        end[t] = a.colptr[v0 + off[t] + 1];
+      }
     }
-#pragma unroll
-    for (int t = 0; t < kPullBatch; ++t) j[t] = beg[t] < end[t] ? a.rowind[beg[t]] : 0;
-#pragma unroll
-    for (int t = 0; t < kPullBatch; ++t) hit[t] = beg[t] < end[t] && get_bit(a.x, j[t]);
 #pragma unroll
     for (int t = 0; t < kPullBatch; ++t) {
       if (off[t] < 0) continue;
@@ -563,24 +553,24 @@ __global__ __launch_bounds__(kThreads) void k_pull(PullArgs a) {
       if (EE) {
         checks += uint64_t(h >= 0 ? p - beg[t] + 1 : lim - beg[t]);
         if (h >= 0) record(off[t], h, end[t] - beg[t]);
-        else if (end[t] > lim) s_long[atomicAdd(&s_nlong, 1)] = uint16_t(base + t * kThreads + tid);
+        else if (end[t] > lim) sh.lng[atomicAdd(&sh.nlong, 1)] = uint16_t(base + t * kThreads + tid);
       } else {
         // no early exit: every in-neighbour is examined; the first hit is kept
         checks += uint64_t(lim - beg[t]);
         if (h >= 0) record(off[t], h, end[t] - beg[t]);
         if (end[t] > lim)
-          s_long[atomicAdd(&s_nlong, 1)] = uint16_t((base + t * kThreads + tid) | (h >= 0 ? 0x8000 : 0));
+          sh.lng[atomicAdd(&sh.nlong, 1)] = uint16_t((base + t * kThreads + tid) | (h >= 0 ? 0x8000 : 0));
       }
     }
   }
   __syncthreads();
 
-  const int32_t nlong = s_nlong;
+  const int32_t nlong = sh.nlong;
   const int wv = tid >> 6;
   for (int32_t r = wv; r < nlong; r += kThreads / 64) {
-    const uint16_t ent = s_long[r];
+    const uint16_t ent = sh.lng[r];
     const bool done = (ent & 0x8000) != 0;
-    const int32_t off = s_cand[ent & 0x7fff];
+    const int32_t off = sh.cand[ent & 0x7fff];
     const int32_t i = v0 + off;
     const int32_t beg0 = a.colptr[i], end = a.colptr[i + 1];
     const int32_t beg = beg0 + kPullFirst;
@@ -622,7 +612,7 @@ __global__ __launch_bounds__(kThreads) void k_pull(PullArgs a) {
   if (tid < kPullTileWords) {
     const int32_t w = w0 + tid;
     if (w < a.nwords) {
-      const uint32_t f = s_found[tid];
+      const uint32_t f = sh.found[tid];
       const uint32_t o = ((a.out_base ? a.out_base[w] : 0u) | f) & valid_bits(w, a.V);
       a.out[w] = o;
       if (a.found_out) a.found_out[w] = f;
@@ -635,41 +625,300 @@ __global__ __launch_bounds__(kThreads) void k_pull(PullArgs a) {
   if (tid == 0) stripe_add(a.slot, v[0], v[1], v[2], 0, v[3]);
 }
 
-// ------------------------------------------------- dense-to-sparse convert
-// Set bits of (a AND NOT b_not) as an ascending index list (DENSE2SPARSE of
-// Section 6.3): popcount per word, block scan, tile prefix, write.
-__global__ __launch_bounds__(kThreads) void k_d2s(const uint32_t* __restrict__ a,
-                                                  const uint32_t* __restrict__ b_not,
-                                                  int32_t nwords, int32_t V,
-                                                  int32_t* __restrict__ out, Ctrl* ctrl,
-                                                  unsigned long long ticket_base, uint32_t epoch,
-                                                  uint64_t* flags, uint32_t* count_out) {
-  const uint32_t tile = take_ticket(ctrl, ticket_base);
-  const int32_t wbase = int32_t(tile) * kD2STile + threadIdx.x * kD2SWPT;
-  uint32_t bits[kD2SWPT];
-  uint32_t c = 0;
-#pragma unroll
-  for (int k = 0; k < kD2SWPT; ++k) {
-    const int32_t w = wbase + k;
-    bits[k] = 0;
-    if (w < nwords) bits[k] = a[w] & (b_not ? ~b_not[w] : 0xffffffffu) & valid_bits(w, V);
-    c += __popc(bits[k]);
+// ----------------------------------------------------- BFS level kernels
+// Algorithm 1 initialisation: depth/parent unreached except the source,
+// visited = {s}, frontier list = [s] (and frontier bitmap = {s} when the
+// mode keeps one); clears the counters and scan descriptors and writes the
+// state entering level 0.
+__global__ __launch_bounds__(kThreads) void k_bfs_init(BfsArgs a, int32_t source, int32_t dir0,
+                                                       int64_t nflags) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int32_t V = a.V;
+  // 16-byte stores when both outputs allow them
+  const bool vec = (reinterpret_cast<uintptr_t>(a.depth) % 16 == 0) &&
+                   (!a.parent || reinterpret_cast<uintptr_t>(a.parent) % 16 == 0);
+  const int64_t nvec = vec ? V / 4 : 0;
+  int4* d4 = reinterpret_cast<int4*>(a.depth);
+  int4* p4 = reinterpret_cast<int4*>(a.parent);
+  for (int64_t i = t0; i < nvec; i += stride) {
+    const int64_t b = i * 4;
+    int4 d = make_int4(-1, -1, -1, -1), p = d;
+    if (source >= b && source < b + 4) {
+      const int k = int(source - b);
+      if (k == 0) { d.x = 0; p.x = source; }
+      if (k == 1) { d.y = 0; p.y = source; }
+      if (k == 2) { d.z = 0; p.z = source; }
+      if (k == 3) { d.w = 0; p.w = source; }
+    }
+    d4[i] = d;
+    if (a.parent) p4[i] = p;
   }
-  uint32_t agg;
-  const uint32_t excl = block_excl_scan(c, &agg);
-  const uint32_t tile_excl = tile_exclusive_prefix(flags, tile, epoch, agg);
-  uint32_t pos = tile_excl + excl;
-#pragma unroll
-  for (int k = 0; k < kD2SWPT; ++k) {
-    uint32_t b = bits[k];
-    while (b) {
-      const int i = __ffs(b) - 1;
-      out[pos++] = (wbase + k) * 32 + i;
-      b &= b - 1;
+  for (int64_t i = nvec * 4 + t0; i < V; i += stride) {
+    a.depth[i] = (i == source) ? 0 : -1;
+    if (a.parent) a.parent[i] = (i == source) ? source : -1;
+  }
+  const uint32_t sbit = 1u << (source & 31);
+  for (int64_t w = t0; w < a.nwords; w += stride) {
+    const uint32_t v = (w == (source >> 5)) ? sbit : 0u;
+    a.vis[0][w] = v;
+    if (a.need_F) a.F[0][w] = v;
+  }
+  for (int64_t k = t0; k < nflags; k += stride) {
+    a.flagsA[k] = 0;
+    a.flagsB[k] = 0;
+  }
+  if (blockIdx.x == 0) {
+    Ctrl* c = a.ctrl;
+    for (int k = threadIdx.x; k < kSlots * kStripes; k += blockDim.x)
+      zero_stripe(c->slot[k / kStripes].s[k % kStripes]);
+    if (threadIdx.x == 0) {
+      a.Q[0][0] = source;
+      c->ticket[0] = 0;
+      c->ticket[1] = 0;
+      c->mf32 = 0;
+      c->nf32 = 0;
+      c->src_outdeg = a.rowptr[source + 1] - a.rowptr[source];
+      c->src_indeg = a.colptr[source + 1] - a.colptr[source];
+      for (int s = 0; s < kSlots; ++s) {
+        c->qcount[s] = 0;
+        c->mf[s] = 0;
+      }
+      LevelState st;
+      st.dir = dir0;
+      st.done = 0;
+      st.list_valid = 1;
+      st.vis_idx = 0;
+      st.nf = 1;
+      st.levels = 0;
+      st.level = 0;
+      st.pad0 = 0;
+      st.m_u = a.nnz - c->src_indeg;
+      c->ring[0] = st;
     }
   }
-  const uint32_t ntiles = uint32_t((nwords + kD2STile - 1) / kD2STile);
-  if (tile == ntiles - 1 && threadIdx.x == 0) *count_out = tile_excl + agg;
+}
+
+// The state entering level L, from the state entering L-1 and the counters
+// L-1 left: the direction rule of Section 6.3 (or Beamer's edge form),
+// forced directions and mode overrides, buffer parities. Every thread
+// computes it from uniform addresses, which the compiler serves with scalar
+// loads; this measured several microseconds faster per launch than one wave
+// computing it and broadcasting it through LDS. All blocks of a level_prep
+// compute the same state.
+__device__ LevelState level_state(const BfsArgs& a, int32_t L, int32_t forced, LevelTotals* tot_out) {
+  const Ctrl* c = a.ctrl;
+  LevelTotals t{0, 0, 0, 0, 0};
+  LevelState st;
+  if (L == 0) {
+    st = c->ring[0];
+    if (forced >= 0) st.dir = forced;
+    *tot_out = t;
+    return st;
+  }
+  const LevelState prev = c->ring[(L - 1) % kRing];
+  st = prev;
+  st.level = L;
+  if (!prev.done) {
+    const LevelSlot& sl = c->slot[(L - 1) % kSlots];
+    for (int k = 0; k < kStripes; ++k) {
+      t.count += sl.s[k].count;
+      t.edges += sl.s[k].edges;
+      t.mnew += sl.s[k].mnew;
+      t.insub += sl.s[k].insub;
+    }
+    if (t.count == 0) {
+      st.done = 1;
+      st.levels = L;
+    } else {
+      const int64_t n_new = int64_t(t.count);
+      const int64_t m_u = prev.m_u - (a.edge_rule ? int64_t(t.insub) : 0);
+      int32_t next = next_direction_rule(a.heuristic, a.alpha, a.beta, prev.dir, a.V, prev.nf, n_new,
+                                         int64_t(t.mnew), m_u);
+      if (a.mode == 1) next = 0;  // push only
+      if (a.mode == 5) next = 1;  // pull only
+      if (forced >= 0) next = forced;
+      st.dir = next;
+      st.nf = int32_t(n_new);
+      st.list_valid = prev.dir == 0 ? 1 : 0;  // a push level appended its winners to Q[L % 2]
+      st.vis_idx = prev.dir == 1 ? (prev.vis_idx ^ 1) : prev.vis_idx;
+      st.m_u = m_u;
+    }
+  }
+  *tot_out = t;
+  return st;
+}
+
+// First kernel of level L: decide the level (device-side), publish state
+// and the previous level's record, reset the next level's counters, and for a
+// push level build the frontier list with its degree prefix.
+__global__ __launch_bounds__(kThreads) void k_level_prep(BfsArgs a, int32_t L, int32_t forced) {
+  Ctrl* c = a.ctrl;
+  LevelTotals tot;
+  const LevelState st = level_state(a, L, forced, &tot);
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      c->ring[L % kRing] = st;
+      if (L >= 1) {
+        const LevelState prev = c->ring[(L - 1) % kRing];
+        if (!prev.done) {
+          LevelRecord r;
+          r.dir = prev.dir;
+          r.nf = prev.nf;
+          r.n_new = int32_t(tot.count);
+          r.pad = 0;
+          r.edges = int64_t(tot.edges);
+          r.m_f = prev.dir == 0 ? int64_t(c->mf[(L - 1) % kSlots]) : 0;  // written by level_prep(L-1)
+          r.mnew = tot.mnew;
+          r.insub = tot.insub;
+          c->rec[(L - 1) % kRing] = r;
+        }
+      }
+      c->qcount[(L + 1) % kSlots] = 0;
+      c->mf[(L + 1) % kSlots] = 0;
+      c->ticket[(L + 1) % 2] = 0;
+    }
+    for (int k = threadIdx.x; k < kStripes; k += blockDim.x) zero_stripe(c->slot[(L + 1) % kSlots].s[k]);
+  }
+  if (st.done) return;
+  if (st.dir != 0) return;
+  uint32_t* mf_out = &c->mf[L % kSlots];
+  if (a.need_F) {  // winners of this push level will be set in F[(L+1)%2]
+    uint32_t* fn = a.F[(L + 1) % 2];
+    for (int32_t w = blockIdx.x * kThreads + threadIdx.x; w < a.nwords; w += gridDim.x * kThreads) fn[w] = 0;
+  }
+  if (st.list_valid) {
+    scan_list(a.Q[L % 2], st.nf, a.rowptr, a.S, a.R, a.chunk_first, a.flagsA, uint32_t(2 * L + 1),
+              &c->ticket[L % 2], mf_out);
+  } else {
+    ScanBitsArgs sb;
+    if (a.reuse) {  // discovered at the last pull = new visited AND NOT old visited
+      sb.a = a.vis[st.vis_idx];
+      sb.b_not = a.vis[st.vis_idx ^ 1];
+    } else {
+      sb.a = a.F[L % 2];
+      sb.b_not = nullptr;
+    }
+    sb.nwords = a.nwords;
+    sb.V = a.V;
+    sb.rowptr = a.rowptr;
+    sb.Qout = a.Q[L % 2];
+    sb.S = a.S;
+    sb.R = a.R;
+    sb.chunk_first = a.chunk_first;
+    sb.flagsA = a.flagsA;
+    sb.flagsB = a.flagsB;
+    sb.epochA = uint32_t(2 * L + 1);
+    sb.epochB = uint32_t(2 * L + 2);
+    sb.ticket = &c->ticket[L % 2];
+    sb.nf_out = &c->nf32;
+    sb.mf_out = mf_out;
+    scan_bits(sb);
+  }
+}
+
+union LevelShared {
+  ExpandShared e;
+  PullShared p;
+};
+
+// Second kernel of level L: the push expansion or the pull, as level_prep
+// decided.
+template <bool EE>
+__global__ __launch_bounds__(kThreads) void k_level_main(BfsArgs a, int32_t L) {
+  __shared__ LevelShared sh;
+  Ctrl* c = a.ctrl;
+  const LevelState st = c->ring[L % kRing];
+  if (st.done) return;
+  LevelSlot* slot = &c->slot[L % kSlots];
+  if (st.dir == 0) {
+    ExpandArgs e;
+    e.Q = a.Q[L % 2];
+    e.nf = st.nf;
+    e.S = a.S;
+    e.R = a.R;
+    e.chunk_first = a.chunk_first;
+    e.colind = a.colind;
+    e.m = uint32_t(c->mf[L % kSlots]);
+    e.claim = a.vis[st.vis_idx];
+    e.mask = nullptr;
+    e.complement = 0;
+    e.depth = a.depth;
+    e.parent = a.parent;
+    e.level = L;
+    e.Qout = a.Q[(L + 1) % 2];
+    e.qcount = &c->qcount[L % kSlots];
+    e.found_out = a.need_F ? a.F[(L + 1) % 2] : nullptr;
+    e.out_rowptr = a.edge_rule ? a.rowptr : nullptr;
+    e.in_colptr = a.edge_rule ? a.colptr : nullptr;
+    e.slot = slot;
+    expand_body(e, sh.e);
+  } else {
+    const int32_t tiles = (a.nwords + kPullTileWords - 1) / kPullTileWords;
+    if (int32_t(blockIdx.x) >= tiles) return;
+    PullArgs p;
+    p.V = a.V;
+    p.nwords = a.nwords;
+    p.colptr = a.colptr;
+    p.rowind = a.rowind;
+    p.head = a.head;
+    p.x = a.reuse ? a.vis[st.vis_idx] : a.F[L % 2];  // operand reuse: A^T v .* not(v) (Section 5.4)
+    p.mask = a.vis[st.vis_idx];
+    p.complement = 1;
+    p.mask_after = a.mask_after;
+    p.nz = a.nz_in;
+    p.out_base = a.vis[st.vis_idx];
+    p.out = a.vis[st.vis_idx ^ 1];
+    p.found_out = a.need_F ? a.F[(L + 1) % 2] : nullptr;
+    p.depth = a.depth;
+    p.parent = a.parent;
+    p.level = L;
+    p.early_exit = EE;
+    p.count_out = 0;
+    p.edge_rule = a.edge_rule;
+    p.slot = slot;
+    pull_body<EE>(p, int32_t(blockIdx.x), sh.p);
+  }
+}
+
+// ------------------------------------------------------- mxv kernels
+__global__ __launch_bounds__(kThreads) void k_scan_bits(ScanBitsArgs a) { scan_bits(a); }
+
+__global__ __launch_bounds__(kThreads) void k_expand(ExpandArgs a, const uint32_t* m_dev,
+                                                     const uint32_t* nf_dev) {
+  __shared__ ExpandShared sh;
+  if (m_dev) a.m = *m_dev;
+  if (nf_dev) a.nf = int32_t(*nf_dev);
+  expand_body(a, sh);
+}
+
+template <bool EE>
+__global__ __launch_bounds__(kThreads) void k_pull(PullArgs a) {
+  __shared__ PullShared sh;
+  pull_body<EE>(a, int32_t(blockIdx.x), sh);
+}
+
+__global__ __launch_bounds__(kThreads) void k_ctrl_init(Ctrl* ctrl, uint64_t* flags,
+                                                        int64_t nflags) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (int64_t k = t0; k < nflags; k += stride) flags[k] = 0;
+  if (blockIdx.x == 0) {
+    for (int k = threadIdx.x; k < kSlots * kStripes; k += blockDim.x)
+      zero_stripe(ctrl->slot[k / kStripes].s[k % kStripes]);
+    if (threadIdx.x == 0) {
+      ctrl->ticket[0] = 0;
+      ctrl->ticket[1] = 0;
+      ctrl->mf32 = 0;
+      ctrl->nf32 = 0;
+      ctrl->src_outdeg = 0;
+      ctrl->src_indeg = 0;
+      for (int s = 0; s < kSlots; ++s) {
+        ctrl->qcount[s] = 0;
+        ctrl->mf[s] = 0;
+      }
+    }
+  }
 }
 
 // --------------------------------------------------------------- helpers
@@ -679,10 +928,8 @@ __global__ __launch_bounds__(kThreads) void k_fill(uint32_t* p, int64_t n, uint3
 }
 
 // SPARSE2DENSE: scatter an index list into a (zeroed) bit vector.
-__global__ __launch_bounds__(kThreads) void k_s2d(const int32_t* idx, int32_t n_arg,
-                                                  const uint32_t* n_dev, int32_t V,
+__global__ __launch_bounds__(kThreads) void k_s2d(const int32_t* idx, int32_t n, int32_t V,
                                                   uint32_t* bits) {
-  const int32_t n = n_dev ? int32_t(*n_dev) : n_arg;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += stride) {
     const int32_t v = idx[k];
@@ -722,6 +969,27 @@ __global__ __launch_bounds__(kThreads) void k_nz_bits(const int32_t* ptr, int32_
   bits[w] = b;
 }
 
+// First entry of every CSC column (-1 for an empty column): the pull's
+// first check reads it densely.
+__global__ __launch_bounds__(kThreads) void k_head(const int32_t* ptr, const int32_t* ind, int32_t V,
+                                                   int32_t* head) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < V; i += stride)
+    head[i] = ptr[i + 1] > ptr[i] ? ind[ptr[i]] : -1;
+}
+
+// Copies the state after a batch and the batch's level records into pinned
+// host memory, then publishes `seq` with a system-scope release.
+__global__ void k_report(const Ctrl* c, int32_t l_first, int32_t n, HostReport* host, uint32_t seq) {
+  for (int k = threadIdx.x; k < n; k += blockDim.x) host->rec[k] = c->rec[(l_first + k) % kRing];
+  if (threadIdx.x == 0) host->end = c->ring[(l_first + n) % kRing];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence_system();
+    __hip_atomic_store(&host->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_check_offsets(const int32_t* ptr, int32_t V, int64_t nnz,
                                                             int32_t* err) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
@@ -748,13 +1016,26 @@ inline unsigned grid_for(int64_t n, int64_t per_block, int64_t cap = 65535) {
 
 }  // namespace
 
-hipError_t launch_bfs_init(hipStream_t s, int32_t V, int32_t nwords, int32_t source,
-                           const int32_t* rowptr, const int32_t* colptr, int32_t* depth,
-                           int32_t* parent, uint32_t* vis, int32_t* Q, Ctrl* ctrl, uint64_t* flags,
-                           int64_t nflags) {
-  const int64_t n = std::max<int64_t>(std::max<int64_t>(V / 4 + 4, nwords), nflags);
-  hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, V,
-                     nwords, source, rowptr, colptr, depth, parent, vis, Q, ctrl, flags, nflags);
+hipError_t launch_bfs_init(hipStream_t s, const BfsArgs& a, int32_t source, int32_t dir0) {
+  const int64_t nflags = flag_entries(a.V);
+  const int64_t n = std::max<int64_t>(std::max<int64_t>(a.V / 4 + 4, a.nwords), nflags);
+  hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, a,
+                     source, dir0, nflags);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_prep(hipStream_t s, const BfsArgs& a, int32_t level, int32_t forced_dir) {
+  hipLaunchKernelGGL(k_level_prep, dim3(unsigned(scan_grid(a.V))), dim3(kThreads), 0, s, a, level,
+                     forced_dir);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_main(hipStream_t s, const BfsArgs& a, int32_t level) {
+  const unsigned g = unsigned(std::max<int64_t>(kExpandBlocks, pull_tiles(a.nwords)));
+  if (a.early_exit)
+    hipLaunchKernelGGL(k_level_main<true>, dim3(g), dim3(kThreads), 0, s, a, level);
+  else
+    hipLaunchKernelGGL(k_level_main<false>, dim3(g), dim3(kThreads), 0, s, a, level);
   return hipGetLastError();
 }
 
@@ -764,36 +1045,24 @@ hipError_t launch_ctrl_init(hipStream_t s, Ctrl* ctrl, uint64_t* flags, int64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_push_scan(hipStream_t s, int64_t tiles, const int32_t* Q, int32_t nf,
-                            const uint32_t* nf_dev, const int32_t* rowptr, int32_t* S, int32_t* R,
-                            int32_t* chunk_first, Ctrl* ctrl, unsigned long long ticket_base,
-                            uint32_t epoch, uint64_t* flags, int32_t level_slot, LevelSlot* reset,
-                            int32_t reset_level) {
-  hipLaunchKernelGGL(k_push_scan, dim3(unsigned(tiles)), dim3(kThreads), 0, s, Q, nf, nf_dev,
-                     rowptr, S, R, chunk_first, ctrl, ticket_base, epoch, flags, level_slot, reset,
-                     reset_level);
+hipError_t launch_scan_bits(hipStream_t s, const ScanBitsArgs& a) {
+  hipLaunchKernelGGL(k_scan_bits, dim3(unsigned(scan_grid(a.V))), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_push_expand(hipStream_t s, int32_t blocks, const ExpandArgs& a) {
-  hipLaunchKernelGGL(k_push_expand, dim3(unsigned(blocks)), dim3(kThreads), 0, s, a);
+hipError_t launch_expand(hipStream_t s, const ExpandArgs& a, const uint32_t* m_dev,
+                         const uint32_t* nf_dev) {
+  hipLaunchKernelGGL(k_expand, dim3(unsigned(kExpandBlocks)), dim3(kThreads), 0, s, a, m_dev,
+                     nf_dev);
   return hipGetLastError();
 }
 
-hipError_t launch_pull(hipStream_t s, bool early_exit, const PullArgs& a) {
-  const unsigned g = unsigned((a.nwords + kPullTileWords - 1) / kPullTileWords);
-  if (early_exit)
+hipError_t launch_pull(hipStream_t s, const PullArgs& a) {
+  const unsigned g = unsigned(pull_tiles(a.nwords));
+  if (a.early_exit)
     hipLaunchKernelGGL(k_pull<true>, dim3(g), dim3(kThreads), 0, s, a);
   else
     hipLaunchKernelGGL(k_pull<false>, dim3(g), dim3(kThreads), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_d2s(hipStream_t s, const uint32_t* a, const uint32_t* b_not, int32_t nwords,
-                      int32_t V, int32_t* out, Ctrl* ctrl, unsigned long long ticket_base,
-                      uint32_t epoch, uint64_t* flags, uint32_t* count_out) {
-  hipLaunchKernelGGL(k_d2s, dim3(unsigned(d2s_tiles(nwords))), dim3(kThreads), 0, s, a, b_not,
-                     nwords, V, out, ctrl, ticket_base, epoch, flags, count_out);
   return hipGetLastError();
 }
 
@@ -802,11 +1071,9 @@ hipError_t launch_fill(hipStream_t s, uint32_t* p, int64_t n, uint32_t v) {
   return hipGetLastError();
 }
 
-hipError_t launch_s2d(hipStream_t s, const int32_t* idx, int32_t n, const uint32_t* n_dev,
-                      int32_t V, uint32_t* bits) {
-  const int64_t cover = n_dev ? int64_t(V) : int64_t(n);
-  hipLaunchKernelGGL(k_s2d, dim3(grid_for(cover, kThreads * 4, 4096)), dim3(kThreads), 0, s, idx,
-                     n, n_dev, V, bits);
+hipError_t launch_s2d(hipStream_t s, const int32_t* idx, int32_t n, int32_t V, uint32_t* bits) {
+  hipLaunchKernelGGL(k_s2d, dim3(grid_for(n, kThreads * 4, 4096)), dim3(kThreads), 0, s, idx, n, V,
+                     bits);
   return hipGetLastError();
 }
 
@@ -820,6 +1087,19 @@ hipError_t launch_mxv_finalize(hipStream_t s, uint32_t* y, const uint32_t* r, in
 hipError_t launch_nz_bits(hipStream_t s, const int32_t* ptr, int32_t V, uint32_t* bits) {
   hipLaunchKernelGGL(k_nz_bits, dim3(grid_for(words_of(V), kThreads, 1u << 30)), dim3(kThreads),
                      0, s, ptr, V, bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_head(hipStream_t s, const int32_t* ptr, const int32_t* ind, int32_t V,
+                       int32_t* head) {
+  hipLaunchKernelGGL(k_head, dim3(grid_for(V, kThreads, 8192)), dim3(kThreads), 0, s, ptr, ind, V,
+                     head);
+  return hipGetLastError();
+}
+
+hipError_t launch_report(hipStream_t s, const Ctrl* ctrl, int32_t l_first, int32_t n,
+                         HostReport* host, uint32_t seq) {
+  hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, ctrl, l_first, n, host, seq);
   return hipGetLastError();
 }
 
