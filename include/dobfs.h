@@ -138,7 +138,9 @@ dobfs_status dobfs_options_default(dobfs_options *opt);
  *   RATIO: push->pull when n_new > nf and n_new > alpha*V;
  *          pull->push when n_new < nf and n_new < beta*V; otherwise unchanged.
  *   EDGES: push->pull when m_f > alpha*m_u (m_f = out-edges of the new
- *          frontier, m_u = out-edges of unvisited vertices);
+ *          frontier, the push's next work; m_u = in-edges of the vertices
+ *          still unvisited, the most a pull could scan; on an undirected
+ *          graph both are plain degrees);
  *          pull->push when n_new < beta*V.
  * alpha and beta are compared in double precision.
  */

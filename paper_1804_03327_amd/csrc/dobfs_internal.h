@@ -88,11 +88,22 @@ constexpr int kScanBlocksMax = 256;                  // scan grids stride over t
 constexpr int kExpandEPT = 4;                        // expand: edges per thread per chunk
 constexpr int kExpandChunk = kThreads * kExpandEPT; // 1024 edges per chunk
 constexpr int kExpandWin = kExpandChunk + 1;         // frontier entries cached in LDS per chunk
-constexpr int kExpandBuf = 2048;                     // winners buffered in LDS before a list flush
+#ifndef DOBFS_EXPAND_BUF
+#define DOBFS_EXPAND_BUF 2048
+#endif
+#ifndef DOBFS_PULL_FIRST
+#define DOBFS_PULL_FIRST 4
+#endif
+#ifndef DOBFS_PULL_MID
+#define DOBFS_PULL_MID 32
+#endif
+constexpr int kExpandBuf = DOBFS_EXPAND_BUF;          // winners buffered in LDS before a list flush
 constexpr int kExpandBlocks = 1024;                  // expand grid (strides over chunks)
 constexpr int kPullTileWords = 64;                   // pull: bitmap words owned by a block
 constexpr int kPullTileV = kPullTileWords * 32;      // 2048 rows per block
-constexpr int kPullFirst = 4;                        // in-neighbours one thread checks before handing a row to its wave
+constexpr int kPullFirst = DOBFS_PULL_FIRST;          // in-neighbours checked breadth-first over a thread's rows
+constexpr int kPullMid = DOBFS_PULL_MID;              // rows still open continue thread-per-row up to here
+constexpr int kPullStep = 4;                          // in-neighbours a thread loads at once past kPullFirst
 constexpr int kPullBatch = 4;                        // candidate rows a thread works on at once
 
 inline int32_t words_of(int64_t V) { return int32_t((V + 31) / 32); }

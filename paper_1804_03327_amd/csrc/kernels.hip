@@ -458,22 +458,26 @@ __device__ void expand_body(const ExpandArgs& a, ExpandShared& sh) {
 // ----------------------------------------------------------------- pull
 struct PullShared {
   uint16_t cand[kPullTileV];
+  uint16_t mid[kPullTileV];
   uint16_t lng[kPullTileV];
   uint32_t found[kPullTileWords];
-  int32_t ncand, nlong;
+  int32_t ncand, nmid, nlong;
 };
 
 // Row-based masked matvec (Algorithm 2) over CSC(A) for the rows of one
 // tile of 64 bitmap words (2048 rows): list the rows the mask lets through
-// (output sparsity, Section 5.2); one thread checks the first kPullFirst
-// in-neighbours of each row in stored order and stops at the first hit
-// (early exit, Section 5.3); longer unresolved rows go to a whole wave, which
-// checks 64 in-neighbours per step and keeps the lowest hit, so the reported
-// parent is always the first in stored order. A thread works on kPullBatch
-// rows at once so their loads overlap. Results gather in LDS and the tile's
-// words of the output vector are written whole, so no atomics touch the
-// output bitmap. `x` (the input vector) is never written here, which keeps
-// the visited snapshot exact when x = visited (operand reuse, Section 5.4).
+// (output sparsity, Section 5.2) and check each row's in-neighbours in stored
+// order, stopping at the first hit (early exit, Section 5.3). Three phases
+// keep many loads in flight: the first kPullFirst in-neighbours of all of a
+// thread's rows, position by position (position 0 from the dense head array);
+// then rows still open, one per thread, kPullStep positions per load round,
+// up to kPullMid; then what is left, one row per wave, 64 in-neighbours per
+// step with the lowest hitting lane kept. Every phase scans positions in
+// order and keeps the first hit, so the reported parent is always the first
+// in stored order. Results gather in LDS and the tile's words of the output
+// vector are written whole, so no atomics touch the output bitmap. `x` (the
+// input vector) is never written here, which keeps the visited snapshot exact
+// when x = visited (operand reuse, Section 5.4).
 template <bool EE>
 __device__ void pull_body(const PullArgs& a, int32_t tile, PullShared& sh) {
   const int tid = threadIdx.x;
@@ -500,6 +504,7 @@ __device__ void pull_body(const PullArgs& a, int32_t tile, PullShared& sh) {
     }
     if (tid == 63) {
       sh.ncand = incl;
+      sh.nmid = 0;
       sh.nlong = 0;
     }
   }
@@ -516,9 +521,9 @@ __device__ void pull_body(const PullArgs& a, int32_t tile, PullShared& sh) {
     if (a.edge_rule) insub += uint64_t(indeg);
   };
 
+  // phase 1: positions 0 .. kPullFirst-1 of a batch of rows per thread
   for (int32_t base = 0; base < ncand; base += kPullBatch * kThreads) {
-    int32_t off[kPullBatch], beg[kPullBatch], end[kPullBatch], j[kPullBatch];
-    bool hit[kPullBatch];
+    int32_t off[kPullBatch], beg[kPullBatch], end[kPullBatch], hitj[kPullBatch], cnt[kPullBatch];
 #pragma unroll
     for (int t = 0; t < kPullBatch; ++t) {
       const int32_t idx = base + t * kThreads + tid;
@@ -527,44 +532,79 @@ __device__ void pull_body(const PullArgs& a, int32_t tile, PullShared& sh) {
     // the first in-neighbour of every row sits in a dense array: one
     // coalesced read instead of a line of the index array per row
 #pragma unroll
-    for (int t = 0; t < kPullBatch; ++t) j[t] = off[t] >= 0 ? a.head[v0 + off[t]] : -1;
+    for (int t = 0; t < kPullBatch; ++t) hitj[t] = off[t] >= 0 ? a.head[v0 + off[t]] : -1;
 #pragma unroll
-    for (int t = 0; t < kPullBatch; ++t) hit[t] = j[t] >= 0 && get_bit(a.x, j[t]);
+    for (int t = 0; t < kPullBatch; ++t) {
+      cnt[t] = off[t] >= 0 ? 1 : 0;
+      if (hitj[t] >= 0 && !get_bit(a.x, hitj[t])) hitj[t] = -1;
+    }
 #pragma unroll
     for (int t = 0; t < kPullBatch; ++t) {
       beg[t] = 0;
-      end[t] = 1;  // a hit row needs its extent only for the edge-count rule
-      if (off[t] >= 0 && (!hit[t] || !EE || a.edge_rule)) {
+      end[t] = 1;  // a row settled by its first entry needs its extent only for the edge-count rule
+      if (off[t] >= 0 && (hitj[t] < 0 || !EE || a.edge_rule)) {
         beg[t] = a.colptr[v0 + off[t]];
         end[t] = a.colptr[v0 + off[t] + 1];
       }
     }
 #pragma unroll
+    for (int q = 1; q < kPullFirst; ++q) {
+      int32_t jj[kPullBatch];
+      bool live[kPullBatch];
+#pragma unroll
+      for (int t = 0; t < kPullBatch; ++t) {
+        live[t] = off[t] >= 0 && beg[t] + q < end[t] && (!EE || hitj[t] < 0);
+        jj[t] = live[t] ? a.rowind[beg[t] + q] : 0;
+      }
+#pragma unroll
+      for (int t = 0; t < kPullBatch; ++t) {
+        if (!live[t]) continue;
+        ++cnt[t];
+        if (hitj[t] < 0 && get_bit(a.x, jj[t])) hitj[t] = jj[t];
+      }
+    }
+#pragma unroll
     for (int t = 0; t < kPullBatch; ++t) {
       if (off[t] < 0) continue;
-      const int32_t lim = min(end[t], beg[t] + kPullFirst);
-      int32_t h = hit[t] ? j[t] : -1, p = beg[t];
-      if (!hit[t]) {
-        for (p = beg[t] + 1; p < lim; ++p) {
-          const int32_t jj = a.rowind[p];
-          if (get_bit(a.x, jj)) { h = jj; break; }
-        }
-      }
-      if (EE) {
-        checks += uint64_t(h >= 0 ? p - beg[t] + 1 : lim - beg[t]);
-        if (h >= 0) record(off[t], h, end[t] - beg[t]);
-        else if (end[t] > lim) sh.lng[atomicAdd(&sh.nlong, 1)] = uint16_t(base + t * kThreads + tid);
-      } else {
-        // no early exit: every in-neighbour is examined; the first hit is kept
-        checks += uint64_t(lim - beg[t]);
-        if (h >= 0) record(off[t], h, end[t] - beg[t]);
-        if (end[t] > lim)
-          sh.lng[atomicAdd(&sh.nlong, 1)] = uint16_t((base + t * kThreads + tid) | (h >= 0 ? 0x8000 : 0));
-      }
+      checks += uint64_t(cnt[t]);
+      if (hitj[t] >= 0) record(off[t], hitj[t], end[t] - beg[t]);
+      if (end[t] > beg[t] + kPullFirst && (!EE || hitj[t] < 0))
+        sh.mid[atomicAdd(&sh.nmid, 1)] = uint16_t((base + t * kThreads + tid) | (hitj[t] >= 0 ? 0x8000 : 0));
     }
   }
   __syncthreads();
 
+  // phase 2: open rows, one per thread, kPullStep positions per load round
+  const int32_t nmid = sh.nmid;
+  for (int32_t r = tid; r < nmid; r += kThreads) {
+    const uint16_t ent = sh.mid[r];
+    const bool done = (ent & 0x8000) != 0;  // no early exit: already recorded, keep counting
+    const int32_t off = sh.cand[ent & 0x7fff];
+    const int32_t i = v0 + off;
+    const int32_t beg0 = a.colptr[i], end = a.colptr[i + 1];
+    const int32_t lim = min(end, beg0 + kPullMid);
+    int32_t hit = -1;
+    unsigned long long n = 0;
+    for (int32_t p = beg0 + kPullFirst; p < lim && (!EE || hit < 0); p += kPullStep) {
+      int32_t jj[kPullStep];
+#pragma unroll
+      for (int u = 0; u < kPullStep; ++u) jj[u] = p + u < lim ? a.rowind[p + u] : -1;
+#pragma unroll
+      for (int u = 0; u < kPullStep; ++u) {
+        if (jj[u] < 0) continue;
+        if (EE && hit >= 0) continue;  // stopped at the first hit of this round
+        ++n;
+        if (hit < 0 && !done && get_bit(a.x, jj[u])) hit = jj[u];
+      }
+    }
+    checks += n;
+    if (hit >= 0) record(off, hit, end - beg0);
+    if (end > lim && (!EE || hit < 0))
+      sh.lng[atomicAdd(&sh.nlong, 1)] = uint16_t((ent & 0x7fff) | ((done || hit >= 0) ? 0x8000 : 0));
+  }
+  __syncthreads();
+
+  // phase 3: what is left, one row per wave, 64 in-neighbours per step
   const int32_t nlong = sh.nlong;
   const int wv = tid >> 6;
   for (int32_t r = wv; r < nlong; r += kThreads / 64) {
@@ -573,7 +613,7 @@ __device__ void pull_body(const PullArgs& a, int32_t tile, PullShared& sh) {
     const int32_t off = sh.cand[ent & 0x7fff];
     const int32_t i = v0 + off;
     const int32_t beg0 = a.colptr[i], end = a.colptr[i + 1];
-    const int32_t beg = beg0 + kPullFirst;
+    const int32_t beg = beg0 + kPullMid;
     int32_t hit = -1;
     unsigned long long n = 0;
     for (int32_t p = beg; p < end; p += 64) {
