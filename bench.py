@@ -25,7 +25,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "GTEPS DOBFS RMAT-22 (1 GPU)"
-KERNEL_SRC = os.path.join(ROOT, "paper_1804_03327_amd", "csrc", "kernels.hip")
+KERNEL_DIR = os.path.join(ROOT, "paper_1804_03327_amd", "csrc")
 
 
 def log(*a):
@@ -33,8 +33,13 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """SHA-256 (16 hex digits) over the device sources: the kernels and the headers they include."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(KERNEL_DIR)):
+        if name.endswith((".hip", ".h")) and name != "api.hip":
+            with open(os.path.join(KERNEL_DIR, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
 # ------------------------------------------------------------- byte model
@@ -84,6 +89,62 @@ def load_traffic(kernel: str):
     return t.get("bytes_per_launch")
 
 
+def measure_batched(args, heur, alpha, beta):
+    """Multi-source BFS: 64 sources per launch on RMAT-20 (edge factor 16), against the same 64
+    queries run one after another through the single-source call on the same GPU. A query's
+    latency is its launch's duration (all 64 are admitted together and finish together)."""
+    import torch
+    import gen
+    import oracle
+    from paper_1804_03327_amd import dobfs
+    from paper_1804_03327_amd.helpers import BfsRunner, upload
+
+    hb = gen.rmat(args.batched_scale, args.edgefactor, seed=1)
+    srcs = [int(x) for x in gen.sample_sources(hb, 64, seed=5)]
+    gb = upload(hb, device=0)
+    stream = torch.cuda.current_stream()
+    opt = dobfs.make_options("full", heur, alpha, beta)
+    ws = torch.empty(dobfs.bfs_batch_workspace_bytes(gb, 64), dtype=torch.uint8, device="cuda")
+    depth = torch.empty(64 * gb.V, dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        dobfs.bfs_batch(gb, srcs, depth, opt=opt, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    lat = []
+    t_all = time.perf_counter()
+    for _ in range(args.batched_launches):
+        t1 = time.perf_counter()
+        dobfs.bfs_batch(gb, srcs, depth, opt=opt, workspace=ws, stream=stream)  # blocks until final
+        lat.append(time.perf_counter() - t1)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t_all
+    qps = 64 * args.batched_launches / t_all
+    d = depth.cpu().numpy().reshape(64, gb.V)
+    rows_ok = all(np.array_equal(d[b], oracle.bfs(hb, srcs[b])[0]) for b in (0, 63))
+    if not rows_ok:
+        raise SystemExit("bench: multi-source depth rows differ from the oracle")
+    # the same queries one at a time through the single-source path
+    r = BfsRunner(gb, with_parent=True)
+    for s in srcs[:8]:
+        r.run(s, opt=opt, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(2):
+        for s in srcs:
+            dobfs.bfs(gb, s, r.depth, r.parent, opt, r.ws, stream=stream)
+    torch.cuda.synchronize()
+    qps_seq = 2 * 64 / (time.perf_counter() - t1)
+    lat_ms = np.array(lat) * 1e3
+    res = {"workload": "rmat%d_ef%d, 64 sources per launch (seed 5)" % (args.batched_scale, args.edgefactor),
+           "queries_per_s": round(qps, 1), "sequential_single_source_queries_per_s": round(qps_seq, 1),
+           "speedup_vs_sequential": round(qps / qps_seq, 2),
+           "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
+           "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 3),
+           "launches": args.batched_launches, "rows_checked_against_oracle": [0, 63]}
+    log("batched:", json.dumps(res))
+    del ws, depth, r
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,11 +154,15 @@ def main():
     ap.add_argument("--edgefactor", type=int, default=16)
     ap.add_argument("--sources", type=int, default=64)
     ap.add_argument("--cpu-sources", type=int, default=8, help="oracle sample size (0: skip)")
-    ap.add_argument("--heuristic", choices=("ratio", "edges"), default="ratio",
+    ap.add_argument("--heuristic", choices=("ratio", "edges"), default="edges",
                     help="direction rule: Section 6.3 ratio form or the edge-count form")
     ap.add_argument("--alpha", type=float, default=None)
     ap.add_argument("--beta", type=float, default=None)
     ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the multi-source (64 sources per launch) RMAT-20 measurement")
+    ap.add_argument("--batched-scale", type=int, default=20)
+    ap.add_argument("--batched-launches", type=int, default=20)
     ap.add_argument("--no-validate", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many BFS steps (for rocprofv3), print nothing else")
@@ -170,16 +235,12 @@ def main():
     torch.cuda.synchronize()
     log("warm-up done")
 
-    # timed region: K steps x 64 sources, per-kernel HIP events recorded by the library
-    caps = 64
-    pool = [[dobfs.make_stats(caps) for _ in sources] for _ in range(args.steps)]
+    # timed region: K steps x 64 sources, nothing but the BFS calls
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
-        row = pool[k]
-        for i, s in enumerate(sources):
-            dobfs.bfs(g, s, runner.depth, runner.parent, opt_timed, runner.ws, stream=stream,
-                      stats=row[i])
+        for s in sources:
+            dobfs.bfs(g, s, runner.depth, runner.parent, opt_plain, runner.ws, stream=stream)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     ms_per_step = 1e3 * t_total / args.steps
@@ -189,9 +250,31 @@ def main():
     log("timed: %.3f ms/step, %.2f GTEPS (graph500 count), %.2f GTEPS (nnz/time)" % (
         ms_per_step, gteps, gteps_paper))
 
-    # per-kernel times and algorithmic bytes over the timed region
+    # roofline pass: the same K steps again with HIP events around every
+    # kernel (recorded by the library on this stream); per-kernel durations
+    # and algorithmic bytes come from here
+    caps = 64
+    pool = [[dobfs.make_stats(caps) for _ in sources] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_ev = time.perf_counter()
+    for k in range(args.steps):
+        row = pool[k]
+        for i, s in enumerate(sources):
+            dobfs.bfs(g, s, runner.depth, runner.parent, opt_timed, runner.ws, stream=stream,
+                      stats=row[i])
+    torch.cuda.synchronize()
+    t_ev = time.perf_counter() - t_ev
+
+    # GPU kernels: k_bfs_init, k_level_prep (direction + frontier scan), k_level_main
+    # (push expand or pull); the push / pull split of level_main is reported beside them
     kinds = {k: {"ms": 0.0, "launches": 0, "bytes": 0.0} for k in
-             ("push_scan", "push_expand", "pull", "init")}
+             ("level_prep", "level_main", "init", "main_push", "main_pull")}
+
+    def add(kind, ms, nbytes):
+        kinds[kind]["ms"] += ms
+        kinds[kind]["launches"] += 1
+        kinds[kind]["bytes"] += nbytes
+
     bfs_ms = []
     for k in range(args.steps):
         for i, s in enumerate(sources):
@@ -199,35 +282,33 @@ def main():
             if st.levels > st.cap:
                 raise RuntimeError("level stats truncated: %d levels > cap %d" % (st.levels, st.cap))
             bfs_ms.append(st.ms_total)
-            kinds["init"]["ms"] += st.ms_init
-            kinds["init"]["launches"] += 1
-            kinds["init"]["bytes"] += bytes_init(hg.V)
+            add("init", st.ms_init, bytes_init(hg.V))
             prev = dobfs.DIR_PUSH
             for L, lv in enumerate(dobfs.stats_levels(st)):
                 if lv["dir"] == dobfs.DIR_PUSH:
-                    kinds["push_expand"]["ms"] += lv["ms_main"]
-                    kinds["push_expand"]["launches"] += 1
-                    kinds["push_expand"]["bytes"] += bytes_push_expand(lv["nf"], lv["m_f"], lv["n_new"])
-                    kinds["push_scan"]["ms"] += lv["ms_aux"]  # includes a pull->push conversion
-                    kinds["push_scan"]["launches"] += 1
-                    kinds["push_scan"]["bytes"] += bytes_push_scan(lv["nf"]) + (
-                        bytes_d2s(hg.V, lv["nf"]) if (prev == dobfs.DIR_PULL) else 0)
+                    prep = bytes_push_scan(lv["nf"]) + (bytes_d2s(hg.V, lv["nf"]) if prev == dobfs.DIR_PULL else 0)
+                    main = bytes_push_expand(lv["nf"], lv["m_f"], lv["n_new"])
+                    add("main_push", lv["ms_main"], main)
                 else:
                     nc = cand_tables[s][L] if L < len(cand_tables[s]) else cand_tables[s][-1]
-                    kinds["pull"]["ms"] += lv["ms_main"]
-                    kinds["pull"]["launches"] += 1
-                    kinds["pull"]["bytes"] += bytes_pull(hg.V, int(nc), lv["edges"], lv["n_new"])
+                    prep = 0
+                    main = bytes_pull(hg.V, int(nc), lv["edges"], lv["n_new"])
+                    add("main_pull", lv["ms_main"], main)
+                add("level_prep", lv["ms_aux"], prep)
+                add("level_main", lv["ms_main"], main)
                 prev = lv["dir"]
-    dom = max(kinds, key=lambda k: kinds[k]["ms"])
+    dom = max(("level_prep", "level_main", "init"), key=lambda k: kinds[k]["ms"])
     kd = kinds[dom]
     avg_ms = kd["ms"] / max(1, kd["launches"])
     per_launch = kd["bytes"] / max(1, kd["launches"])
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     traffic = load_traffic(dom)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "algorithmic_bytes_per_launch": round(per_launch), "avg_launch_us": round(avg_ms * 1e3, 3),
-                "launches": kd["launches"]}
+    roofline = {"bound": "hbm", "kernel": "k_" + dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "algorithmic_bytes_per_launch": round(per_launch),
+                "avg_launch_us": round(avg_ms * 1e3, 3), "launches": kd["launches"],
+                "timing": "HIP events around each kernel, on the BFS stream, over a repeat of the "
+                          "timed steps (%.1f ms/step with events)" % (1e3 * t_ev / args.steps)}
     kernel_table = {k: {"total_ms": round(v["ms"], 3), "launches": v["launches"],
                         "avg_us": round(1e3 * v["ms"] / max(1, v["launches"]), 3),
                         "GBps": round(v["bytes"] / max(1e-12, v["ms"] * 1e-3) / 1e9, 1)}
@@ -282,6 +363,28 @@ def main():
             ablation[mode] = round(sum(edges_g500[s] for s in sources) / dt / 1e9, 3)
         log("ablation GTEPS:", json.dumps(ablation))
 
+    # the other direction rule on the same workload, for comparison
+    other = None
+    if not args.no_ablation:
+        oh = dobfs.HEUR_RATIO if heur == dobfs.HEUR_EDGES else dobfs.HEUR_EDGES
+        oo = dobfs.make_options("full", oh, 0.01 if oh == dobfs.HEUR_RATIO else 1 / 14,
+                                0.01 if oh == dobfs.HEUR_RATIO else 1 / 24)
+        for s in sources[:4]:
+            runner.run(s, opt=oo, stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for s in sources:
+            runner.run(s, opt=oo, stream=stream)
+        torch.cuda.synchronize()
+        other = {"heuristic": "ratio alpha=beta=0.01" if oh == dobfs.HEUR_RATIO else
+                 "edges alpha=1/14 beta=1/24",
+                 "gteps": round(sum(edges_g500[s] for s in sources) / (time.perf_counter() - t1) / 1e9, 3)}
+        log("other rule:", json.dumps(other))
+
+    batched = None
+    if not args.no_batched:
+        batched = measure_batched(args, heur, alpha, beta)
+
     out = {
         "metric": METRIC, "value": round(gteps, 3), "unit": "GTEPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -298,7 +401,9 @@ def main():
         "kernels": kernel_table,
         "cpu_baseline": cpu,
         "ablation_gteps": ablation,
+        "other_direction_rule": other,
         "validated": validated,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

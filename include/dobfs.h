@@ -189,13 +189,47 @@ dobfs_status dobfs_bfs_workspace_bytes(dobfs_graph g, const dobfs_options *opt, 
  * depth: device int32[V], required. parent: device int32[V] or NULL.
  * workspace: device memory of at least dobfs_bfs_workspace_bytes, or NULL
  * for a library-owned one. stats: host, optional (opt->flags may add
- * per-kernel times). The call blocks until results are final (the level loop
- * reads one small counter block back per level). source outside [0,V) ->
- * INVALID_ARG with nothing written.
+ * per-kernel times). The call blocks until results are final: each level's
+ * direction is decided on the device, and the host reads the traversal state
+ * back once per batch of levels. source outside [0,V) -> INVALID_ARG with
+ * nothing written.
  */
 dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options *opt, int32_t *depth,
                        int32_t *parent, void *workspace, size_t ws_bytes, void *stream,
                        dobfs_stats *stats);
+
+/* ------------------------------------------------------ multi-source BFS */
+
+/* Device bytes of workspace a dobfs_bfs_batch call with k sources needs
+ * (k in [1, 64]; it grows by 2*k bytes per vertex for the level table). */
+dobfs_status dobfs_bfs_batch_workspace_bytes(dobfs_graph g, int32_t k, size_t *bytes);
+
+/*
+ * k breadth-first searches at once (1 <= k <= 64), one per entry of
+ * `sources` (host int32[k], each in [0,V); repeats allowed). Algorithm 1
+ * with the frontier vector widened to a k-column bit matrix: one level is the
+ * masked Boolean matrix product F' = A^T F .* not(Vis) over (OR, AND), in
+ * push form (column-based, Equation 5 per column) or pull form (row-based
+ * with early exit once every missing source is found, Sections 5.2-5.4),
+ * the direction chosen per level for the whole batch by opt's rule applied
+ * to the batch's frontier (vertices with any frontier bit) and edge counts.
+ * On return depth[b*V + v] is the hop count of a shortest path
+ * sources[b] -> v, -1 if unreachable: row b equals what dobfs_bfs from
+ * sources[b] returns in `depth`. No parents are produced.
+ * depth: device int32[k*V], row-major, required. workspace: device memory
+ * of at least dobfs_bfs_batch_workspace_bytes(g, k), 256-byte aligned, or
+ * NULL for a library-owned one (shared with the other calls on g and
+ * serialised with them). opt: modes FULL, PUSH_ONLY and PULL_ONLY (others
+ * -> UNSUPPORTED), both heuristics, forced directions. stats: as for
+ * dobfs_bfs, with nf and n_new counting vertices that carry any source bit
+ * and `reached` counting (vertex, source) pairs. Blocks until depth is
+ * final. Errors: k out of range, a source outside [0,V) or a NULL pointer
+ * -> INVALID_ARG with nothing written; a traversal deeper than 65533 levels
+ * -> UNSUPPORTED (levels are kept in 16 bits).
+ */
+dobfs_status dobfs_bfs_batch(dobfs_graph g, const int32_t *sources, int32_t k,
+                             const dobfs_options *opt, int32_t *depth, void *workspace,
+                             size_t ws_bytes, void *stream, dobfs_stats *stats);
 
 /* -------------------------------------------------------- standalone mxv */
 

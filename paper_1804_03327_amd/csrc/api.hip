@@ -1,9 +1,10 @@
 // Host runtime and C ABI of libdobfs (declared in include/dobfs.h).
 //
-// The BFS level loop of Algorithm 1 runs on the host: each level launches the
-// push kernels (scan + load-balanced expand) or the pull kernel, then reads a
-// 32-byte counter block back (nnz of the new frontier, edges touched), and
-// applies the direction rule of Section 6.3 to pick the next level's kernel.
+// The BFS level loop of Algorithm 1 is enqueued from the host in batches of
+// levels; each level's direction (the rule of Section 6.3) is decided on the
+// device from the previous level's counters, and the host reads the state
+// back once per batch from pinned memory. Single-source and multi-source
+// traversals share the loop and differ in their kernels.
 
 #include "dobfs.h"
 #include "dobfs_internal.h"
@@ -32,6 +33,7 @@ struct dobfs_graph_s {
   uint32_t* nz_in = nullptr;        // rows of CSC(A) with at least one entry
   int32_t* head = nullptr;          // first entry of every CSC(A) column (-1 if empty)
   std::atomic<int32_t> last_levels{8};  // level count of the previous BFS (first batch size)
+  std::atomic<int32_t> last_levels_mb{8};  // the same for multi-source traversals
   void* owned[4] = {nullptr, nullptr, nullptr, nullptr};
   std::mutex mu;                    // guards the internal workspace
   void* ws = nullptr;
@@ -107,6 +109,41 @@ Layout plan(int32_t V, int64_t nnz) {
   L.flagsA = take(size_t(L.nflags) * 8);
   L.flagsB = take(size_t(L.nflags) * 8);
   L.ctrl = take(sizeof(Ctrl));
+  L.total = cur;
+  return L;
+}
+
+// Workspace layout of a multi-source call with k sources.
+struct BatchLayout {
+  size_t visA, visB, FA, FB, nzF, Q0, Q1, S, R, chunks, flagsA, flagsB, ctrl, lvl, total;
+  int64_t nflags, nchunks;
+};
+
+BatchLayout plan_batch(int32_t V, int64_t nnz, int32_t k) {
+  BatchLayout L{};
+  const size_t wb = size_t(words_of(V)) * 4, vb = size_t(V) * 4, qb = size_t(V) * 8;
+  L.nflags = flag_entries(V);
+  L.nchunks = max_chunks(nnz);
+  size_t cur = 0;
+  auto take = [&](size_t bytes) {
+    size_t off = cur;
+    cur += align_up(bytes);
+    return off;
+  };
+  L.visA = take(qb);
+  L.visB = take(qb);
+  L.FA = take(qb);
+  L.FB = take(qb);
+  L.nzF = take(wb);
+  L.Q0 = take(vb);
+  L.Q1 = take(vb);
+  L.S = take(vb);
+  L.R = take(vb);
+  L.chunks = take(size_t(L.nchunks) * 4);
+  L.flagsA = take(size_t(L.nflags) * 8);
+  L.flagsB = take(size_t(L.nflags) * 8);
+  L.ctrl = take(sizeof(Ctrl));
+  L.lvl = take(size_t(V) * size_t(k) * 2);
   L.total = cur;
   return L;
 }
@@ -283,6 +320,92 @@ dobfs_status get_workspace(dobfs_graph g, void* workspace, size_t ws_bytes, size
   return DOBFS_OK;
 }
 
+
+// Result of a level loop.
+struct LoopResult {
+  int64_t levels = 0;   // levels run (the last discovered nothing)
+  int64_t sum_new = 0;  // vertices discovered over all levels
+  int64_t sum_aux = 0;  // multi-source: (vertex, source) pairs discovered
+  LevelState end{};     // state after the last level
+};
+
+// The level loop shared by the single- and multi-source traversals. Level l
+// is prep(l) then main(l); the state that decides level l+1 is computed on
+// the device by prep(l+1), which also records level l's counters. The host
+// enqueues levels in batches and reads the state back once per batch (a
+// report kernel writes it to pinned memory); levels enqueued past the end
+// exit at once. The first batch is one level longer than the previous
+// traversal of the same kind needed (a level past the end costs a few
+// microseconds, a second batch a host round trip); later batches start at 4
+// and double. The init kernel and ev[kEvStart] precede the call.
+// Event layout when timing: ev[2k] before prep of the k-th level of the
+// batch, ev[2k+1] between its two kernels.
+template <class Prep, class Main, class Forced>
+dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool timing, hipEvent_t* ev,
+                        Forced forced, Prep prep, Main main, const Ctrl* ctrl, int64_t max_levels,
+                        dobfs_status too_deep, dobfs_stats* stats, LoopResult* res) {
+  HostReport* rep = host_report();
+  if (!rep) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
+  thread_local uint32_t report_seq = 0;
+  int64_t lvl = 0;
+  int32_t batch = std::min(std::max(last_levels.load(std::memory_order_relaxed) + 1, 2), kMaxBatch);
+  int32_t next_batch = 4;
+  float first_aux = 0.f;  // prep time of a batch's first level
+  if (timing) HIPCK(hipEventRecord(ev[0], s));
+  HIPCK(prep(0, forced(0)));
+  if (timing) HIPCK(hipEventRecord(ev[1], s));
+  while (true) {
+    if (lvl + batch > max_levels) batch = int32_t(max_levels - lvl);
+    const int64_t l1 = lvl + batch - 1;
+    for (int64_t l = lvl; l <= l1; ++l) {
+      const int32_t k = int32_t(l - lvl);
+      if (timing && k > 0) HIPCK(hipEventRecord(ev[2 * k + 1], s));
+      HIPCK(main(int32_t(l)));
+      if (timing) HIPCK(hipEventRecord(ev[2 * k + 2], s));
+      HIPCK(prep(int32_t(l + 1), forced(l + 1)));
+    }
+    if (timing) HIPCK(hipEventRecord(ev[2 * batch + 1], s));
+    const uint32_t seq = ++report_seq;
+    HIPCK(launch_report(s, ctrl, int32_t(lvl), batch, rep, seq));
+    HIPCK(wait_report(rep, seq, s));
+    if (timing && lvl == 0) first_aux = elapsed(ev[0], ev[1]);
+    const LevelState& end = rep->end;
+    const int64_t last = end.done ? int64_t(end.levels) - 1 : l1;  // last level that ran
+    for (int64_t l = lvl; l <= last; ++l) {
+      const LevelRecord& r = rep->rec[l - lvl];
+      res->sum_new += r.n_new;
+      res->sum_aux += int64_t(r.aux);
+      if (stats && l < stats->cap) {
+        dobfs_level_stats& ls = stats->level[l];
+        const int32_t k = int32_t(l - lvl);
+        ls.dir = r.dir;
+        ls.nf = r.nf;
+        ls.n_new = r.n_new;
+        ls.pad = 0;
+        ls.edges = r.edges;
+        ls.m_f = r.m_f;
+        ls.ms_aux = timing ? (k == 0 ? first_aux : elapsed(ev[2 * k], ev[2 * k + 1])) : 0.f;
+        ls.ms_main = timing ? elapsed(ev[2 * k + 1], ev[2 * k + 2]) : 0.f;
+      }
+    }
+    if (end.done) {
+      res->levels = end.levels;
+      res->end = end;
+      break;
+    }
+    if (l1 + 1 >= max_levels) {
+      (void)hipStreamSynchronize(s);
+      return fail(too_deep, "traversal needs more than %lld levels", (long long)max_levels);
+    }
+    if (timing) first_aux = elapsed(ev[2 * batch], ev[2 * batch + 1]);  // prep(l1 + 1)
+    lvl = l1 + 1;
+    batch = next_batch;
+    next_batch = std::min(2 * next_batch, kMaxBatch);
+    if (timing) HIPCK(hipEventRecord(ev[1], s));  // prep(lvl) ran in the previous batch
+  }
+  last_levels.store(int32_t(res->levels), std::memory_order_relaxed);
+  return DOBFS_OK;
+}
 
 }  // namespace
 
@@ -470,9 +593,6 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   std::unique_lock<std::mutex> lock;
   uint8_t* ws = nullptr;
   if ((st = get_workspace(g, workspace, ws_bytes, L.total, lock, &ws)) != DOBFS_OK) return st;
-  HostReport* rep = host_report();
-  if (!rep) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
-  thread_local uint32_t report_seq = 0;
   const bool timing = (opt.flags & DOBFS_OPT_TIME_KERNELS) != 0;
   hipEvent_t* ev = events_for(g->device);
   if (!ev) return fail(DOBFS_ERR_DEVICE, "event creation failed");
@@ -518,81 +638,127 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   const int32_t dir0 = forced(0) >= 0 ? forced(0)
                                       : (opt.mode == DOBFS_MODE_PULL_ONLY ? DOBFS_DIR_PULL : DOBFS_DIR_PUSH);
 
-  // Levels run in batches: level l is level_prep(l) then level_main(l); the
-  // state that decides level l+1 is computed on the device by level_prep(l+1),
-  // which also records level l's counters. The host reads the state back once
-  // per batch; levels enqueued past the end exit at once.
-  // Event layout when timing: ev[2k] before level_prep of the k-th level of
-  // the batch, ev[2k+1] between its two kernels.
   HIPCK(hipEventRecord(ev[kEvStart], s));
   HIPCK(launch_bfs_init(s, a, source, dir0));
   if (timing) HIPCK(hipEventRecord(ev[kEvInit], s));
-  int64_t lvl = 0, levels = -1, reached = 1;
-  // First batch: one level more than the previous traversal on this graph
-  // needed (a level enqueued past the end costs a few microseconds, a second
-  // batch a host round trip); later batches start at 4 and double.
-  int32_t batch = std::min(std::max(g->last_levels.load(std::memory_order_relaxed) + 1, 2), kMaxBatch);
-  int32_t next_batch = 4;
-  float ms_init = 0.f, first_aux = 0.f;  // first_aux: level_prep time of a batch's first level
-  if (timing) HIPCK(hipEventRecord(ev[0], s));
-  HIPCK(launch_level_prep(s, a, 0, forced(0)));
-  if (timing) HIPCK(hipEventRecord(ev[1], s));
-  while (levels < 0) {
-    const int64_t l1 = lvl + batch - 1;
-    for (int64_t l = lvl; l <= l1; ++l) {
-      const int32_t k = int32_t(l - lvl);
-      if (timing && k > 0) HIPCK(hipEventRecord(ev[2 * k + 1], s));
-      HIPCK(launch_level_main(s, a, int32_t(l)));
-      if (timing) HIPCK(hipEventRecord(ev[2 * k + 2], s));
-      HIPCK(launch_level_prep(s, a, int32_t(l + 1), forced(l + 1)));
-    }
-    if (timing) HIPCK(hipEventRecord(ev[2 * batch + 1], s));
-    const uint32_t seq = ++report_seq;
-    HIPCK(launch_report(s, a.ctrl, int32_t(lvl), batch, rep, seq));
-    HIPCK(wait_report(rep, seq, s));
-    if (timing) {
-      if (lvl == 0) {
-        ms_init = elapsed(ev[kEvStart], ev[kEvInit]);
-        first_aux = elapsed(ev[0], ev[1]);
-      }
-    }
-    const LevelState& end = rep->end;
-    const int64_t last = end.done ? int64_t(end.levels) - 1 : l1;  // last level that ran
-    for (int64_t l = lvl; l <= last; ++l) {
-      const LevelRecord& r = rep->rec[l - lvl];
-      reached += r.n_new;
-      if (stats && l < stats->cap) {
-        dobfs_level_stats& ls = stats->level[l];
-        const int32_t k = int32_t(l - lvl);
-        ls.dir = r.dir;
-        ls.nf = r.nf;
-        ls.n_new = r.n_new;
-        ls.pad = 0;
-        ls.edges = r.edges;
-        ls.m_f = r.m_f;
-        ls.ms_aux = timing ? (k == 0 ? first_aux : elapsed(ev[2 * k], ev[2 * k + 1])) : 0.f;
-        ls.ms_main = timing ? elapsed(ev[2 * k + 1], ev[2 * k + 2]) : 0.f;
-      }
-    }
-    if (end.done) {
-      levels = end.levels;
-      break;
-    }
-    if (l1 + 1 > int64_t(g->V) + 1) return fail(DOBFS_ERR_INTERNAL, "level loop did not terminate");
-    if (timing) first_aux = elapsed(ev[2 * batch], ev[2 * batch + 1]);  // level_prep(l1 + 1)
-    lvl = l1 + 1;
-    batch = next_batch;
-    next_batch = std::min(2 * next_batch, kMaxBatch);
-    if (timing) HIPCK(hipEventRecord(ev[1], s));  // level_prep(lvl) ran in the previous batch
-  }
+  LoopResult res;
+  st = run_levels(
+      g->last_levels, s, timing, ev, forced,
+      [&](int32_t l, int32_t f) { return launch_level_prep(s, a, l, f); },
+      [&](int32_t l) { return launch_level_main(s, a, l); }, a.ctrl, int64_t(g->V) + 2,
+      DOBFS_ERR_INTERNAL, stats, &res);
+  if (st != DOBFS_OK) return st;
   HIPCK(hipEventRecord(ev[kEvEnd], s));
   HIPCK(hipEventSynchronize(ev[kEvEnd]));
-  g->last_levels.store(int32_t(levels), std::memory_order_relaxed);
   if (stats) {
-    stats->levels = int32_t(levels);
+    stats->levels = int32_t(res.levels);
     stats->ms_total = elapsed(ev[kEvStart], ev[kEvEnd]);
-    stats->ms_init = ms_init;
-    stats->reached = reached;
+    stats->ms_init = timing ? elapsed(ev[kEvStart], ev[kEvInit]) : 0.f;
+    stats->reached = 1 + res.sum_new;
+  }
+  return DOBFS_OK;
+}
+
+dobfs_status dobfs_bfs_batch_workspace_bytes(dobfs_graph g, int32_t k, size_t* bytes) {
+  if (!g || !bytes) return fail(DOBFS_ERR_INVALID_ARG, "graph or bytes is NULL");
+  if (k < 1 || k > kMaxSources) return fail(DOBFS_ERR_INVALID_ARG, "k = %d not in [1, 64]", k);
+  *bytes = plan_batch(g->V, g->nnz, k).total;
+  return DOBFS_OK;
+}
+
+dobfs_status dobfs_bfs_batch(dobfs_graph g, const int32_t* sources, int32_t k,
+                             const dobfs_options* opt_in, int32_t* depth, void* workspace,
+                             size_t ws_bytes, void* stream, dobfs_stats* stats) {
+  t_last_error.clear();
+  if (!g) return fail(DOBFS_ERR_INVALID_ARG, "graph is NULL");
+  if (!depth) return fail(DOBFS_ERR_INVALID_ARG, "depth is NULL");
+  if (!sources) return fail(DOBFS_ERR_INVALID_ARG, "sources is NULL");
+  if (k < 1 || k > kMaxSources) return fail(DOBFS_ERR_INVALID_ARG, "k = %d not in [1, 64]", k);
+  for (int32_t b = 0; b < k; ++b)
+    if (sources[b] < 0 || sources[b] >= g->V)
+      return fail(DOBFS_ERR_INVALID_ARG, "sources[%d] = %d not in [0, %d)", b, sources[b], g->V);
+  const dobfs_options opt = opt_in ? *opt_in : defaults();
+  dobfs_status st = check_options(opt);
+  if (st != DOBFS_OK) return st;
+  if (opt.mode != DOBFS_MODE_FULL && opt.mode != DOBFS_MODE_PUSH_ONLY && opt.mode != DOBFS_MODE_PULL_ONLY)
+    return fail(DOBFS_ERR_UNSUPPORTED, "multi-source BFS runs modes FULL, PUSH_ONLY and PULL_ONLY");
+  if (stats && stats->cap > 0 && !stats->level)
+    return fail(DOBFS_ERR_INVALID_ARG, "stats->level is NULL with cap = %d", stats->cap);
+
+  DeviceScope ds(g->device);
+  if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice", __LINE__);
+  const BatchLayout L = plan_batch(g->V, g->nnz, k);
+  std::unique_lock<std::mutex> lock;
+  uint8_t* ws = nullptr;
+  if ((st = get_workspace(g, workspace, ws_bytes, L.total, lock, &ws)) != DOBFS_OK) return st;
+  const bool timing = (opt.flags & DOBFS_OPT_TIME_KERNELS) != 0;
+  hipEvent_t* ev = events_for(g->device);
+  if (!ev) return fail(DOBFS_ERR_DEVICE, "event creation failed");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  BatchArgs a{};
+  a.V = g->V;
+  a.nwords = g->nwords;
+  a.nnz = g->nnz;
+  a.rowptr = g->rowptr;
+  a.colind = g->colind;
+  a.colptr = g->colptr;
+  a.rowind = g->rowind;
+  a.nz_in = g->nz_in;
+  a.lvl = reinterpret_cast<uint16_t*>(ws + L.lvl);
+  a.k = k;
+  a.active = k == 64 ? ~0ull : ((1ull << k) - 1ull);
+  a.vis[0] = reinterpret_cast<uint64_t*>(ws + L.visA);
+  a.vis[1] = reinterpret_cast<uint64_t*>(ws + L.visB);
+  a.F[0] = reinterpret_cast<uint64_t*>(ws + L.FA);
+  a.F[1] = reinterpret_cast<uint64_t*>(ws + L.FB);
+  a.nzF = reinterpret_cast<uint32_t*>(ws + L.nzF);
+  a.Q[0] = reinterpret_cast<int32_t*>(ws + L.Q0);
+  a.Q[1] = reinterpret_cast<int32_t*>(ws + L.Q1);
+  a.S = reinterpret_cast<int32_t*>(ws + L.S);
+  a.R = reinterpret_cast<int32_t*>(ws + L.R);
+  a.chunk_first = reinterpret_cast<int32_t*>(ws + L.chunks);
+  a.flagsA = reinterpret_cast<uint64_t*>(ws + L.flagsA);
+  a.flagsB = reinterpret_cast<uint64_t*>(ws + L.flagsB);
+  a.ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
+  a.mode = opt.mode;
+  a.heuristic = opt.heuristic;
+  a.alpha = double(opt.alpha);
+  a.beta = double(opt.beta);
+  a.edge_rule = opt.heuristic == DOBFS_HEUR_EDGES ? 1 : 0;
+  a.nuniq = 0;
+  for (int32_t b = 0; b < k; ++b) {
+    a.src[b] = sources[b];
+    bool seen = false;
+    for (int32_t c = 0; c < a.nuniq; ++c) seen = seen || a.uniq[c] == sources[b];
+    if (!seen) a.uniq[a.nuniq++] = sources[b];
+  }
+  auto forced = [&](int64_t l) -> int32_t {
+    return l < opt.n_forced ? int32_t(opt.forced_dirs[l]) : -1;
+  };
+  const int32_t dir0 = forced(0) >= 0 ? forced(0)
+                                      : (opt.mode == DOBFS_MODE_PULL_ONLY ? DOBFS_DIR_PULL : DOBFS_DIR_PUSH);
+  // levels are kept as uint16 (level L stamps L + 1)
+  const int64_t cap = std::min<int64_t>(int64_t(g->V) + 2, 0xfffe);
+
+  HIPCK(hipEventRecord(ev[kEvStart], s));
+  HIPCK(launch_mb_init(s, a, dir0, L.nflags));
+  if (timing) HIPCK(hipEventRecord(ev[kEvInit], s));
+  LoopResult res;
+  st = run_levels(
+      g->last_levels_mb, s, timing, ev, forced,
+      [&](int32_t l, int32_t f) { return launch_mb_prep(s, a, l, f); },
+      [&](int32_t l) { return launch_mb_main(s, a, l); }, a.ctrl, cap,
+      cap < int64_t(g->V) + 2 ? DOBFS_ERR_UNSUPPORTED : DOBFS_ERR_INTERNAL, stats, &res);
+  if (st != DOBFS_OK) return st;
+  HIPCK(launch_mb_depth(s, a, a.vis[res.end.vis_idx], depth));
+  HIPCK(hipEventRecord(ev[kEvEnd], s));
+  HIPCK(hipEventSynchronize(ev[kEvEnd]));
+  if (stats) {
+    stats->levels = int32_t(res.levels);
+    stats->ms_total = elapsed(ev[kEvStart], ev[kEvEnd]);
+    stats->ms_init = timing ? elapsed(ev[kEvStart], ev[kEvInit]) : 0.f;
+    stats->reached = k + res.sum_aux;  // (vertex, source) pairs, the sources included
   }
   return DOBFS_OK;
 }

@@ -1,0 +1,405 @@
+// Device helpers shared by the single-source and the multi-source kernels:
+// wave and block reductions, striped level counters, the single-pass tile
+// prefix (decoupled look-back) and the frontier scans that turn a list or a
+// bitmap into the degree prefix the load-balanced expansion reads. Every
+// translation unit that includes this gets its own copy (anonymous namespace).
+#pragma once
+
+#include "dobfs_internal.h"
+
+namespace dobfs {
+namespace {
+
+constexpr uint32_t kStatusAgg = 1, kStatusPrefix = 2;
+
+__device__ __forceinline__ int lane() { return int(__lane_id()); }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane()) - 1ull; }
+
+__device__ __forceinline__ uint32_t get_bit(const uint32_t* b, int32_t i) {
+  return (b[i >> 5] >> (i & 31)) & 1u;
+}
+
+// Bits of word w that are inside [0, V).
+__device__ __forceinline__ uint32_t valid_bits(int32_t w, int32_t V) {
+  const int32_t lo = w * 32;
+  if (lo + 32 <= V) return 0xffffffffu;
+  if (lo >= V) return 0u;
+  return (1u << (V - lo)) - 1u;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int t = __shfl_up(v, d, 64);
+    if (lane() >= d) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// A value every lane holds alike, moved to scalar registers.
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
+  return uint64_t(lo) | (uint64_t(hi) << 32);
+}
+
+// Exclusive scan over the 256 threads of a block; *total gets the block sum.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t s_w[kThreads / 64];
+  const int wv = threadIdx.x >> 6;
+  uint32_t incl = uint32_t(wave_incl_scan(int(v)));
+  if (lane() == 63) s_w[wv] = incl;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < kThreads / 64; ++k) {
+    uint32_t t = s_w[k];
+    before += (k < wv) ? t : 0u;
+    all += t;
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - v;
+}
+
+// Block-wide sums of four 64-bit values (one barrier pair).
+__device__ __forceinline__ void block_sum4(unsigned long long v[4]) {
+  __shared__ unsigned long long s_w[4][kThreads / 64];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = wave_sum64(v[k]);
+  if (lane() == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s_w[k][threadIdx.x >> 6] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    unsigned long long t = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) t += s_w[k][w];
+    v[k] = t;
+  }
+  __syncthreads();
+}
+
+// Adds a block's totals into its stripe of the level slot (thread 0 only).
+__device__ __forceinline__ void stripe_add(LevelSlot* slot, unsigned long long count,
+                                           unsigned long long aux, unsigned long long edges,
+                                           unsigned long long mnew, unsigned long long insub) {
+  Stripe* st = &slot->s[blockIdx.x % kStripes];
+  if (count) atomicAdd(&st->count, uint32_t(count));
+  if (aux) atomicAdd(&st->aux, uint32_t(aux));
+  if (edges) atomicAdd(&st->edges, edges);
+  if (mnew) atomicAdd(&st->mnew, mnew);
+  if (insub) atomicAdd(&st->insub, insub);
+}
+
+__device__ __forceinline__ void zero_stripe(Stripe& st) {
+  st.count = 0;
+  st.aux = 0;
+  st.edges = 0;
+  st.mnew = 0;
+  st.insub = 0;
+}
+
+// ---- single-pass tile prefix (decoupled look-back) ----
+// Tile descriptors are one 64-bit word: [epoch:30][status:2][value:32], so a
+// single atomic store publishes status and value together. Tiles are numbered
+// by tickets taken when a block is ready to work on one, so every tile a
+// block waits on belongs to a running block that publishes without waiting.
+__device__ __forceinline__ uint64_t pack_flag(uint32_t epoch, uint32_t status, uint32_t value) {
+  return (uint64_t(epoch) << 34) | (uint64_t(status) << 32) | uint64_t(value);
+}
+
+__device__ __forceinline__ uint32_t take_ticket(unsigned long long* ticket) {
+  __shared__ uint32_t s_tile;
+  __syncthreads();  // every thread is done with the previous tile's s_tile
+  if (threadIdx.x == 0) s_tile = uint32_t(atomicAdd(ticket, 1ull));
+  __syncthreads();
+  return s_tile;
+}
+
+// Returns the sum of all values of tiles before `tile` (called by every thread).
+__device__ uint32_t tile_exclusive_prefix(uint64_t* flags, uint32_t tile, uint32_t epoch,
+                                          uint32_t aggregate) {
+  __shared__ uint32_t s_excl;
+  if (threadIdx.x < 64) {
+    if (tile == 0) {
+      if (lane() == 0) {
+        __hip_atomic_store(&flags[0], pack_flag(epoch, kStatusPrefix, aggregate), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        s_excl = 0;
+      }
+    } else {
+      if (lane() == 0)
+        __hip_atomic_store(&flags[tile], pack_flag(epoch, kStatusAgg, aggregate), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      uint32_t excl = 0;
+      int64_t pos = int64_t(tile) - 1;
+      while (true) {
+        const int64_t idx = pos - lane();
+        uint64_t f = 0;
+        uint32_t st = kStatusPrefix;  // lanes before tile 0 never matter: tile 0 is a prefix
+        if (idx >= 0) {
+          f = __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          st = (uint32_t(f >> 34) == epoch) ? uint32_t(f >> 32) & 3u : 0u;
+        }
+        while (__any(st == 0)) {
+          __builtin_amdgcn_s_sleep(1);
+          if (st == 0) {
+            f = __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            st = (uint32_t(f >> 34) == epoch) ? uint32_t(f >> 32) & 3u : 0u;
+          }
+        }
+        const uint32_t v = (idx >= 0) ? uint32_t(f) : 0u;
+        const uint64_t pm = __ballot(st == kStatusPrefix);
+        if (pm) {
+          const int first = __ffsll((unsigned long long)pm) - 1;
+          excl += wave_sum(lane() <= first ? v : 0u);
+          break;
+        }
+        excl += wave_sum(v);
+        pos -= 64;
+      }
+      if (lane() == 0) {
+        __hip_atomic_store(&flags[tile], pack_flag(epoch, kStatusPrefix, excl + aggregate),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_excl = excl;
+      }
+    }
+  }
+  __syncthreads();
+  return s_excl;
+}
+
+// Chunks of kExpandChunk edges whose first edge lies in [run, run + deg):
+// the vertex at list position k is their first vertex.
+__device__ __forceinline__ void mark_chunks(int32_t* chunk_first, uint32_t run, int32_t deg, int32_t k) {
+  if (deg <= 0) return;
+  const uint32_t c0 = (run + kExpandChunk - 1) / kExpandChunk;
+  const uint32_t c1 = (run + uint32_t(deg) - 1) / kExpandChunk;
+  for (uint32_t c = c0; c <= c1; ++c) chunk_first[c] = k;
+}
+
+// --------------------------------------------------- frontier list scans
+// Out-degree of every frontier vertex and its exclusive prefix sum (the
+// "length" and "scan" steps of the column-based matvec, Section 6.2): S[k] is
+// where vertex Q[k]'s adjacency starts in the concatenated expansion, R[k] its
+// row start in CSR(A), and every chunk of kExpandChunk edges records its
+// first vertex, which is all the expand step needs to find its work (the
+// load-balanced gather). Blocks take tiles by ticket until the list is done.
+__device__ void scan_list(const int32_t* __restrict__ Q, int32_t nf, const int32_t* __restrict__ rowptr,
+                          int32_t* __restrict__ S, int32_t* __restrict__ R,
+                          int32_t* __restrict__ chunk_first, uint64_t* flags, uint32_t epoch,
+                          unsigned long long* ticket, uint32_t* mf_out) {
+  const uint32_t ntiles = uint32_t(nf > 0 ? (nf + kScanTile - 1) / kScanTile : 1);
+  if (blockIdx.x >= ntiles) return;  // no tile for this block: take no ticket
+  const bool one_each = ntiles <= gridDim.x;
+  for (bool first = true;; first = false) {
+    if (one_each && !first) return;  // every tile has a block of its own
+    const uint32_t tile = take_ticket(ticket);
+    if (tile >= ntiles) return;
+    const int64_t base = int64_t(tile) * kScanTile + int64_t(threadIdx.x) * kScanIPT;
+    int32_t deg[kScanIPT], st[kScanIPT];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanIPT; ++k) {
+      deg[k] = 0;
+      st[k] = 0;
+      if (base + k < nf) {
+        const int32_t u = Q[base + k];
+        const int32_t b = rowptr[u], e = rowptr[u + 1];
+        deg[k] = e - b;
+        st[k] = b;
+        sum += uint32_t(e - b);
+      }
+    }
+    uint32_t agg;
+    const uint32_t excl = block_excl_scan(sum, &agg);
+    const uint32_t tile_excl = tile_exclusive_prefix(flags, tile, epoch, agg);
+    uint32_t run = tile_excl + excl;
+#pragma unroll
+    for (int k = 0; k < kScanIPT; ++k) {
+      if (base + k < nf) {
+        S[base + k] = int32_t(run);
+        R[base + k] = st[k];
+        mark_chunks(chunk_first, run, deg[k], int32_t(base + k));
+        run += uint32_t(deg[k]);
+      }
+    }
+    if (tile == ntiles - 1 && threadIdx.x == 0) *mf_out = tile_excl + agg;
+  }
+}
+
+// The set bits of (a AND NOT b_not) as an ascending list (DENSE2SPARSE of
+// Section 6.3), fused with the same degree prefix when rowptr is given: two
+// look-back chains, one over vertex counts and one over degree sums.
+__device__ void scan_bits(const ScanBitsArgs& a) {
+  const uint32_t ntiles = uint32_t((a.nwords + kBitsTile - 1) / kBitsTile);
+  if (blockIdx.x >= ntiles) return;  // no tile for this block: take no ticket
+  const bool one_each = ntiles <= gridDim.x;
+  for (bool first = true;; first = false) {
+    if (one_each && !first) return;  // every tile has a block of its own
+    const uint32_t tile = take_ticket(a.ticket);
+    if (tile >= ntiles) return;
+    const int32_t wbase = int32_t(tile) * kBitsTile + threadIdx.x * kBitsWPT;
+    uint32_t bits[kBitsWPT];
+    uint32_t c = 0, d = 0;
+#pragma unroll
+    for (int k = 0; k < kBitsWPT; ++k) {
+      const int32_t w = wbase + k;
+      bits[k] = 0;
+      if (w < a.nwords)
+        bits[k] = a.a[w] & (a.b_not ? ~a.b_not[w] : 0xffffffffu) & valid_bits(w, a.V);
+      c += __popc(bits[k]);
+      if (a.rowptr) {
+        uint32_t b = bits[k];
+        while (b) {
+          const int32_t v = w * 32 + __ffs(b) - 1;
+          d += uint32_t(a.rowptr[v + 1] - a.rowptr[v]);
+          b &= b - 1;
+        }
+      }
+    }
+    uint32_t agg_c, agg_d = 0;
+    const uint32_t excl_c = block_excl_scan(c, &agg_c);
+    uint32_t excl_d = 0;
+    if (a.rowptr) excl_d = block_excl_scan(d, &agg_d);
+    const uint32_t pc = tile_exclusive_prefix(a.flagsA, tile, a.epochA, agg_c);
+    uint32_t pd = 0;
+    if (a.rowptr) pd = tile_exclusive_prefix(a.flagsB, tile, a.epochB, agg_d);
+    uint32_t pos = pc + excl_c, run = pd + excl_d;
+#pragma unroll
+    for (int k = 0; k < kBitsWPT; ++k) {
+      uint32_t b = bits[k];
+      while (b) {
+        const int32_t v = (wbase + k) * 32 + __ffs(b) - 1;
+        a.Qout[pos] = v;
+        if (a.rowptr) {
+          const int32_t rb = a.rowptr[v], deg = a.rowptr[v + 1] - rb;
+          a.S[pos] = int32_t(run);
+          a.R[pos] = rb;
+          mark_chunks(a.chunk_first, run, deg, int32_t(pos));
+          run += uint32_t(deg);
+        }
+        ++pos;
+        b &= b - 1;
+      }
+    }
+    if (tile == ntiles - 1 && threadIdx.x == 0) {
+      *a.nf_out = pc + agg_c;
+      if (a.mf_out) *a.mf_out = pd + agg_d;
+    }
+  }
+}
+
+__device__ __forceinline__ int32_t thread_search(const int32_t* S, int32_t lo, int32_t hi, uint32_t e) {
+  while (hi - lo > 1) {
+    const int32_t mid = lo + (hi - lo) / 2;
+    if (uint32_t(S[mid]) <= e) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// The state entering level L, from the state entering L-1 and the counters
+// L-1 left: the direction rule of Section 6.3 (or Beamer's edge form),
+// forced directions and mode overrides, buffer parities. Every thread
+// computes it from uniform addresses, which the compiler serves with scalar
+// loads; this measured several microseconds faster per launch than one wave
+// computing it and broadcasting it through LDS. All blocks of a level_prep
+// compute the same state.
+template <class Args>
+__device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, LevelTotals* tot_out) {
+  const Ctrl* c = a.ctrl;
+  LevelTotals t{0, 0, 0, 0, 0};
+  LevelState st;
+  if (L == 0) {
+    st = c->ring[0];
+    if (forced >= 0) st.dir = forced;
+    *tot_out = t;
+    return st;
+  }
+  const LevelState prev = c->ring[(L - 1) % kRing];
+  st = prev;
+  st.level = L;
+  if (!prev.done) {
+    const LevelSlot& sl = c->slot[(L - 1) % kSlots];
+    // lane k reads stripe k (one round trip for the whole slot) and the wave
+    // adds them up; the totals are uniform, so they go back to scalar registers
+    const int k = lane();
+    const Stripe* sk = &sl.s[k & (kStripes - 1)];
+    const bool mine = k < kStripes;
+    const uint64_t v0 = mine ? uint64_t(sk->count) | (uint64_t(sk->aux) << 32) : 0ull;
+    const uint64_t v1 = mine ? sk->edges : 0ull, v2 = mine ? sk->mnew : 0ull, v3 = mine ? sk->insub : 0ull;
+    const uint64_t lo = wave_sum64(v0 & 0xffffffffull), hi = wave_sum64(v0 >> 32);
+    t.count = uniform64(lo);
+    t.aux = uniform64(hi);
+    t.edges = uniform64(wave_sum64(v1));
+    t.mnew = uniform64(wave_sum64(v2));
+    t.insub = uniform64(wave_sum64(v3));
+    if (t.count == 0) {
+      st.done = 1;
+      st.levels = L;
+    } else {
+      const int64_t n_new = int64_t(t.count);
+      const int64_t m_u = prev.m_u - (a.edge_rule ? int64_t(t.insub) : 0);
+      int32_t next = next_direction_rule(a.heuristic, a.alpha, a.beta, prev.dir, a.V, prev.nf, n_new,
+                                         int64_t(t.mnew), m_u);
+      if (a.mode == 1) next = 0;  // push only
+      if (a.mode == 5) next = 1;  // pull only
+      if (forced >= 0) next = forced;
+      st.dir = next;
+      st.nf = int32_t(n_new);
+      st.list_valid = prev.dir == 0 ? 1 : 0;  // a push level appended its winners to Q[L % 2]
+      st.vis_idx = prev.dir == 1 ? (prev.vis_idx ^ 1) : prev.vis_idx;
+      st.m_u = m_u;
+    }
+  }
+  *tot_out = t;
+  return st;
+}
+
+// Block 0 of level L's first kernel: publish the level's state and the
+// record of level L-1, and clear the counters level L+1 will add into
+// (nothing reads them before the next kernel boundary).
+__device__ void publish_level(Ctrl* c, int32_t L, const LevelState& st, const LevelTotals& tot) {
+  if (blockIdx.x != 0) return;
+  if (threadIdx.x == 0) {
+    c->ring[L % kRing] = st;
+    if (L >= 1) {
+      const LevelState prev = c->ring[(L - 1) % kRing];
+      if (!prev.done) {
+        LevelRecord r;
+        r.dir = prev.dir;
+        r.nf = prev.nf;
+        r.n_new = int32_t(tot.count);
+        r.pad = 0;
+        r.edges = int64_t(tot.edges);
+        r.m_f = prev.dir == 0 ? int64_t(c->mf[(L - 1) % kSlots]) : 0;  // written by the scan of L-1
+        r.mnew = tot.mnew;
+        r.insub = tot.insub;
+        r.aux = tot.aux;
+        c->rec[(L - 1) % kRing] = r;
+      }
+    }
+    c->qcount[(L + 1) % kSlots] = 0;
+    c->mf[(L + 1) % kSlots] = 0;
+    c->ticket[(L + 1) % 2] = 0;
+  }
+  for (int k = threadIdx.x; k < kStripes; k += blockDim.x) zero_stripe(c->slot[(L + 1) % kSlots].s[k]);
+}
+
+}  // namespace
+}  // namespace dobfs

@@ -16,10 +16,11 @@ namespace dobfs {
 constexpr int kStripes = 32;
 struct alignas(128) Stripe {
   uint32_t count;  // vertices discovered (BFS) / result bits (mxv)
-  uint32_t aux;    // mxv: popcount of the whole output vector
+  uint32_t aux;    // mxv: popcount of the whole output vector; multi-source: (vertex, source) pairs
   uint64_t edges;  // adjacency entries read (push) or in-neighbours checked (pull)
   uint64_t mnew;   // out-edges of the vertices discovered (edge-count rule only)
-  uint64_t insub;  // in-edges of the vertices discovered (edge-count rule only)
+  uint64_t insub;  // in-edges of the vertices discovered (edge-count rule only; multi-source:
+                   // of the vertices every source has now reached)
 };
 struct LevelSlot {
   Stripe s[kStripes];
@@ -43,6 +44,7 @@ struct LevelRecord {
   int32_t dir, nf, n_new, pad;
   int64_t edges, m_f;
   uint64_t mnew, insub;
+  uint64_t aux;        // multi-source: (vertex, source) pairs discovered
 };
 constexpr int kRing = 1024;  // levels of state / records kept on the device
 
@@ -197,6 +199,40 @@ struct BfsArgs {
   int32_t edge_rule;
 };
 
+// ---- multi-source BFS: up to 64 sources, one bit of a uint64 per source ----
+constexpr int kMaxSources = 64;
+struct BatchArgs {
+  int32_t V, nwords;
+  int64_t nnz;
+  const int32_t* rowptr;
+  const int32_t* colind;
+  const int32_t* colptr;
+  const int32_t* rowind;
+  const uint32_t* nz_in;
+  uint16_t* lvl;             // [V][k]: level at which source b reached v (valid where vis bit b is set)
+  int32_t k;                 // sources
+  int32_t nuniq;             // distinct sources
+  uint64_t active;           // the k source bits
+  uint64_t* vis[2];          // per vertex: sources that reached it
+  uint64_t* F[2];            // per vertex: sources whose frontier holds it; level L reads F[L % 2]
+  uint32_t* nzF;             // one bit per vertex: its next-frontier word is nonzero (pull output)
+  int32_t* Q[2];
+  int32_t* S;
+  int32_t* R;
+  int32_t* chunk_first;
+  uint64_t* flagsA;
+  uint64_t* flagsB;
+  Ctrl* ctrl;
+  int32_t mode;
+  int32_t heuristic;
+  double alpha, beta;
+  int32_t edge_rule;
+  int32_t src[kMaxSources];  // source of bit b
+  int32_t uniq[kMaxSources]; // the distinct sources: the first frontier list
+};
+constexpr int kMbMid = 32;    // multi-source pull: in-neighbours a thread scans before a wave takes over
+constexpr int kMbLong = 512;  // multi-source pull: rows a tile can hand to its waves
+
 struct ScanBitsArgs {
   const uint32_t* a;         // bits = a AND NOT b_not
   const uint32_t* b_not;     // nullable
@@ -241,6 +277,10 @@ struct HostReport {
 };
 hipError_t launch_report(hipStream_t s, const Ctrl* ctrl, int32_t l_first, int32_t n,
                          HostReport* host, uint32_t seq);
+hipError_t launch_mb_init(hipStream_t s, const BatchArgs& a, int32_t dir0, int64_t nflags);
+hipError_t launch_mb_prep(hipStream_t s, const BatchArgs& a, int32_t level, int32_t forced_dir);
+hipError_t launch_mb_main(hipStream_t s, const BatchArgs& a, int32_t level);
+hipError_t launch_mb_depth(hipStream_t s, const BatchArgs& a, const uint64_t* vis, int32_t* depth);
 hipError_t launch_check_offsets(hipStream_t s, const int32_t* ptr, int32_t V, int64_t nnz,
                                 int32_t* err);
 hipError_t launch_check_indices(hipStream_t s, const int32_t* idx, int64_t nnz, int32_t V,

@@ -83,6 +83,9 @@ def load():
         "dobfs_next_direction": (i32, [ctypes.POINTER(Options), i32, i64, i64, i64, i64, i64]),
         "dobfs_bfs_workspace_bytes": (i32, [vp, ctypes.POINTER(Options), ctypes.POINTER(sz)]),
         "dobfs_bfs": (i32, [vp, i32, ctypes.POINTER(Options), vp, vp, vp, sz, vp, ctypes.POINTER(Stats)]),
+        "dobfs_bfs_batch_workspace_bytes": (i32, [vp, i32, ctypes.POINTER(sz)]),
+        "dobfs_bfs_batch": (i32, [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(Options), vp, vp, sz, vp,
+                                  ctypes.POINTER(Stats)]),
         "dobfs_mxv_workspace_bytes": (i32, [vp, ctypes.POINTER(sz)]),
         "dobfs_mxv": (i32, [vp, vp, vp, i32, vp, i32, i32, u32, vp, vp, vp, ctypes.POINTER(i32), vp,
                             sz, vp]),
@@ -227,6 +230,12 @@ def bfs_workspace_bytes(g: Graph, opt=None) -> int:
     return n.value
 
 
+def bfs_batch_workspace_bytes(g: Graph, k: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load().dobfs_bfs_batch_workspace_bytes(g.handle, int(k), ctypes.byref(n)))
+    return n.value
+
+
 def mxv_workspace_bytes(g: Graph) -> int:
     n = ctypes.c_size_t()
     _check(load().dobfs_mxv_workspace_bytes(g.handle, ctypes.byref(n)))
@@ -264,6 +273,26 @@ def bfs(g: Graph, source: int, depth, parent=None, opt=None, workspace=None, ws_
     _check(lib.dobfs_bfs(g.handle, int(source), ctypes.byref(opt) if opt is not None else None,
                          d, p, w, nbytes, _stream(stream, g.device),
                          ctypes.byref(stats) if stats is not None else None))
+    return stats
+
+
+def bfs_batch(g: Graph, sources, depth, opt=None, workspace=None, ws_bytes=None, stream=None,
+              stats=None):
+    """dobfs_bfs_batch: `sources` a host sequence of k ints (1 <= k <= 64); depth an int32 CUDA
+    tensor of k*V elements (row b = depths from sources[b]); workspace a uint8 CUDA tensor or None."""
+    import torch
+    lib = load()
+    src = [int(x) for x in sources]
+    k = len(src)
+    arr = (ctypes.c_int32 * max(k, 1))(*src)
+    d = _dptr(depth, torch.int32, k * g.V, "depth")
+    w = _dptr(workspace, torch.uint8, 0, "workspace")
+    nbytes = workspace.numel() if workspace is not None else 0
+    if ws_bytes is not None:
+        nbytes = int(ws_bytes)
+    _check(lib.dobfs_bfs_batch(g.handle, arr, k, ctypes.byref(opt) if opt is not None else None, d, w,
+                               nbytes, _stream(stream, g.device),
+                               ctypes.byref(stats) if stats is not None else None))
     return stats
 
 

@@ -1,0 +1,200 @@
+"""GPU parity of the multi-source BFS (dobfs_bfs_batch) against the CPU oracle, through the C
+ABI.
+
+Every depth row must equal the oracle's single-source depths from that row's source, bit for
+bit, in every supported mode and under forced push/pull schedules. Per-level statistics are
+checked against what the oracle's depth rows fix: the vertices carrying any frontier bit at
+each level, the (vertex, source) pairs reached, and the level count."""
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1804_03327_amd import dobfs  # noqa: E402
+from paper_1804_03327_amd.helpers import upload  # noqa: E402
+
+PUSH, PULL = dobfs.DIR_PUSH, dobfs.DIR_PULL
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _graphs():
+    rng = np.random.default_rng(7)
+    V = 100_003  # ragged last bitmap word and tile
+    m = 8 * V
+    src = rng.integers(0, V, m)
+    dst = (src + rng.zipf(1.6, m)) % V
+    return {
+        "rmat10": gen.rmat(10, 16, seed=1),
+        "rmat14": gen.rmat(14, 16, seed=1),
+        "directed100003": gen.from_edges(V, src, dst, directed=True, name="directed100003"),
+        "lattice37": gen.lattice3d(37, 0.05, seed=3),
+        "grid61x53": gen.grid2d(61, 53),
+    }
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    out = {}
+    for name, hg in _graphs().items():
+        _say("upload", name, hg.V, hg.nnz)
+        out[name] = (hg, upload(hg, validate=True))
+    return out
+
+
+_ref_cache = {}
+
+
+def _ref(hg, s):
+    key = (hg.name, hg.V, int(s))
+    if key not in _ref_cache:
+        _ref_cache[key] = oracle.bfs(hg, int(s))[0]
+    return _ref_cache[key]
+
+
+def _sources(hg, k, seed):
+    return [int(x) for x in gen.sample_sources(hg, k, seed)]
+
+
+def _run(g, sources, opt=None, cap=256):
+    k = len(sources)
+    depth = torch.full((k * g.V,), -7, dtype=torch.int32, device="cuda")
+    st = dobfs.make_stats(cap)
+    dobfs.bfs_batch(g, sources, depth, opt=opt, stats=st)
+    return depth.cpu().numpy().reshape(k, g.V), st
+
+
+def _check(hg, sources, d, st, tag):
+    refs = [_ref(hg, s) for s in sources]
+    for b, s in enumerate(sources):
+        bad = int((d[b] != refs[b]).sum())
+        assert bad == 0, "%s: row %d (source %d): %d depths differ" % (tag, b, s, bad)
+    R = np.stack(refs)
+    ecc = int(R.max())
+    assert st.levels == ecc + 1, "%s: %d levels, oracle says %d" % (tag, st.levels, ecc + 1)
+    assert st.reached == int((R >= 0).sum()), tag + ": reached pairs"
+    lv = dobfs.stats_levels(st)
+    for L, row in enumerate(lv):
+        nf = int((R == L).any(axis=0).sum())
+        n_new = int((R == L + 1).any(axis=0).sum())
+        assert (row["nf"], row["n_new"]) == (nf, n_new), "%s: level %d sizes %s vs (%d, %d)" % (
+            tag, L, (row["nf"], row["n_new"]), nf, n_new)
+
+
+@pytest.mark.parametrize("name", ["rmat10", "rmat14", "directed100003", "lattice37", "grid61x53"])
+def test_batch_modes_match_oracle(graphs, name):
+    hg, g = graphs[name]
+    srcs = _sources(hg, 64, 11)
+    for mode in ["full", "push_only", "pull_only"]:
+        for heur, a, b in [(dobfs.HEUR_RATIO, 0.01, 0.01), (dobfs.HEUR_EDGES, 1 / 14, 1 / 24)]:
+            tag = "%s k=64 %s heur=%d" % (name, mode, heur)
+            _say(tag)
+            d, st = _run(g, srcs, dobfs.make_options(mode, heur, a, b))
+            _check(hg, srcs, d, st, tag)
+            dirs = [x["dir"] for x in dobfs.stats_levels(st)]
+            if mode == "push_only":
+                assert set(dirs) == {PUSH}
+            if mode == "pull_only":
+                assert set(dirs) == {PULL}
+
+
+@pytest.mark.parametrize("k", [1, 2, 31, 33, 63, 64])
+def test_batch_widths(graphs, k):
+    hg, g = graphs["rmat14"]
+    srcs = _sources(hg, k, 100 + k)
+    d, st = _run(g, srcs)
+    _check(hg, srcs, d, st, "rmat14 k=%d" % k)
+
+
+def test_batch_forced_schedules(graphs):
+    hg, g = graphs["rmat14"]
+    srcs = _sources(hg, 40, 21)
+    rng = np.random.default_rng(3)
+    scheds = [[PUSH, PULL] * 8, [PULL, PUSH] * 8, [PUSH, PUSH, PULL, PULL] * 4]
+    scheds += [list(rng.integers(0, 2, 16)) for _ in range(5)]
+    for sc in scheds:
+        tag = "forced %s" % "".join(str(int(x)) for x in sc)
+        _say(tag)
+        d, st = _run(g, srcs, dobfs.make_options("full", forced_dirs=[int(x) for x in sc]))
+        _check(hg, srcs, d, st, tag)
+        dirs = [x["dir"] for x in dobfs.stats_levels(st)]
+        assert dirs == [int(x) for x in sc[: len(dirs)]], tag
+
+
+def test_batch_duplicates_and_isolated(graphs):
+    hg, g = graphs["rmat14"]
+    deg = np.diff(hg.rowptr)
+    iso = [int(x) for x in np.nonzero(deg == 0)[0][:3]]
+    assert len(iso) == 3
+    s = _sources(hg, 10, 5)
+    srcs = s + s[:4] + iso + [s[0]] * 5  # repeats and degree-0 sources
+    d, st = _run(g, srcs)
+    _check(hg, srcs, d, st, "duplicates+isolated")
+
+
+def test_batch_repeated_calls_reuse_workspace(graphs):
+    """Back-to-back calls with different sources and widths on one workspace: nothing of a
+    previous call may leak into the next (frontier words, level table, counters)."""
+    hg, g = graphs["directed100003"]
+    k_max = 64
+    ws = torch.empty(dobfs.bfs_batch_workspace_bytes(g, k_max), dtype=torch.uint8, device="cuda")
+    for it, k in enumerate([64, 5, 64, 17, 1, 64]):
+        srcs = _sources(hg, k, 300 + it)
+        depth = torch.full((k * g.V,), -7, dtype=torch.int32, device="cuda")
+        st = dobfs.make_stats(256)
+        mode = ["full", "pull_only", "push_only"][it % 3]
+        dobfs.bfs_batch(g, srcs, depth, opt=dobfs.make_options(mode), workspace=ws, stats=st)
+        _check(hg, srcs, depth.cpu().numpy().reshape(k, g.V), st, "repeat %d k=%d %s" % (it, k, mode))
+
+
+def test_batch_small_graphs():
+    cases = {
+        "one_vertex": gen.from_edges(1, np.zeros(0, np.int64), np.zeros(0, np.int64), directed=False),
+        "path9": gen.from_edges(9, np.arange(8), np.arange(1, 9), directed=False),
+        "directed_path": gen.from_edges(3, np.array([0, 1]), np.array([1, 2]), directed=True),
+        "two_parts": gen.from_edges(70, np.array([0, 1, 2, 40, 41]), np.array([1, 2, 3, 41, 42]),
+                                    directed=False),
+        "self_loops_dups": gen.from_edges(5, np.array([0, 0, 1, 1, 2, 3]), np.array([0, 1, 1, 2, 2, 4]),
+                                          directed=True, keep_self_loops=True, keep_duplicates=True),
+    }
+    for name, hg in cases.items():
+        g = upload(hg)
+        for srcs in ([0], list(range(min(hg.V, 64))), [hg.V - 1] * 3):
+            for mode in ["full", "push_only", "pull_only"]:
+                d, st = _run(g, srcs, dobfs.make_options(mode))
+                _check(hg, srcs, d, st, "%s %s k=%d" % (name, mode, len(srcs)))
+
+
+def test_batch_errors(graphs):
+    hg, g = graphs["rmat10"]
+    depth = torch.zeros(64 * g.V, dtype=torch.int32, device="cuda")
+    with pytest.raises(dobfs.DobfsError) as e:
+        dobfs.bfs_batch(g, [], depth)
+    assert e.value.status == dobfs.ERR_INVALID_ARG
+    with pytest.raises(dobfs.DobfsError) as e:
+        dobfs.bfs_batch(g, list(range(65)), torch.zeros(65 * g.V, dtype=torch.int32, device="cuda"))
+    assert e.value.status == dobfs.ERR_INVALID_ARG
+    with pytest.raises(dobfs.DobfsError) as e:
+        dobfs.bfs_batch(g, [0, g.V], depth)
+    assert e.value.status == dobfs.ERR_INVALID_ARG
+    with pytest.raises(dobfs.DobfsError) as e:
+        dobfs.bfs_batch(g, [0, 1], depth, opt=dobfs.make_options("pull_masked"))
+    assert e.value.status == dobfs.ERR_UNSUPPORTED
+    need = dobfs.bfs_batch_workspace_bytes(g, 2)
+    ws = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(dobfs.DobfsError) as e:
+        dobfs.bfs_batch(g, [0, 1], depth, workspace=ws)
+    assert e.value.status == dobfs.ERR_WORKSPACE_TOO_SMALL
+    assert dobfs.bfs_batch_workspace_bytes(g, 64) > dobfs.bfs_batch_workspace_bytes(g, 1)
