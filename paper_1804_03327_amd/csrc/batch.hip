@@ -22,12 +22,6 @@
 namespace dobfs {
 namespace {
 
-__device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v |= __shfl_xor(v, d, 64);
-  return v;
-}
-
 // Level L+1 for every source bit in `bits` of vertex v.
 __device__ __forceinline__ void stamp_levels(uint16_t* lvl, int32_t k, int32_t v, uint64_t bits,
                                              int32_t level) {
@@ -88,6 +82,7 @@ __global__ __launch_bounds__(kThreads) void k_mb_init(BatchArgs a, int32_t dir0,
       st.level = 0;
       st.pad0 = 0;
       st.m_u = a.nnz;  // in-edges of vertices some source has not reached yet
+      st.active = a.active;
       c->ring[0] = st;
     }
   }
@@ -122,6 +117,7 @@ __device__ void mb_expand_body(const BatchArgs& a, int32_t L, const LevelState& 
   const uint64_t active = a.active;
   if (threadIdx.x == 0) sh.nbuf = 0;
   unsigned long long nvert = 0, nbits = 0, mnew = 0, insub = 0;
+  uint64_t fbits = 0;
 
   auto flush = [&]() {
     const uint32_t nb = sh.nbuf;
@@ -188,6 +184,7 @@ __device__ void mb_expand_body(const BatchArgs& a, int32_t L, const LevelState& 
           const uint64_t oldf = atomicOr((unsigned long long*)(Fn + w[t]), (unsigned long long)nb);
           stamp_levels(a.lvl, a.k, w[t], nb, L);
           nbits += uint64_t(__popcll(nb));
+          fbits |= nb;
           if (oldf == 0) {
             listed[t] = true;
             ++nvert;
@@ -215,7 +212,9 @@ __device__ void mb_expand_body(const BatchArgs& a, int32_t L, const LevelState& 
   flush();
   unsigned long long v4[4] = {nvert, nbits, mnew, insub};
   block_sum4(v4);
+  fbits = block_or64(fbits);
   if (threadIdx.x == 0) {
+    stripe_or(&a.ctrl->slot[L % kSlots], fbits);
     unsigned long long edges = 0;
     for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x)
       edges += min(uint32_t(kExpandChunk), m - c * kExpandChunk);
@@ -247,7 +246,7 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
   const uint64_t* vin = a.vis[st.vis_idx];
   uint64_t* vout = a.vis[st.vis_idx ^ 1];
   uint64_t* Fn = a.F[(L + 1) % 2];
-  const uint64_t active = a.active;
+  const uint64_t active = st.active;  // a source with an empty frontier finds nothing more
   if (tid < kPullTileWords) sh.nzf[tid] = 0;
   if (tid == 0) {
     sh.ncand = 0;
@@ -278,6 +277,7 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
   __syncthreads();
   const int32_t ncand = sh.ncand;
   unsigned long long nvert = 0, nbits = 0, checks = 0, mnew = 0, insub = 0;
+  uint64_t fbits = 0;
 
   auto finish = [&](int r, uint64_t m, uint64_t found) {
     const int32_t v = v0 + r;
@@ -288,9 +288,10 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
     stamp_levels(a.lvl, a.k, v, found, L);
     ++nvert;
     nbits += uint64_t(__popcll(found));
+    fbits |= found;
     if (a.edge_rule) {
       mnew += uint64_t(a.rowptr[v + 1] - a.rowptr[v]);
-      if (((m | found) & active) == active) insub += uint64_t(a.colptr[v + 1] - a.colptr[v]);
+      if (((m | found) & a.active) == a.active) insub += uint64_t(a.colptr[v + 1] - a.colptr[v]);
     }
   };
 
@@ -357,7 +358,11 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
   block_sum4(v4);
   unsigned long long i4[4] = {insub, 0, 0, 0};
   block_sum4(i4);
-  if (tid == 0) stripe_add(&a.ctrl->slot[L % kSlots], v4[0], v4[1], v4[2], v4[3], i4[0]);
+  fbits = block_or64(fbits);
+  if (tid == 0) {
+    stripe_add(&a.ctrl->slot[L % kSlots], v4[0], v4[1], v4[2], v4[3], i4[0]);
+    stripe_or(&a.ctrl->slot[L % kSlots], fbits);
+  }
 }
 
 // --------------------------------------------------------- level kernels

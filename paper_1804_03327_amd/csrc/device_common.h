@@ -112,6 +112,31 @@ __device__ __forceinline__ void zero_stripe(Stripe& st) {
   st.edges = 0;
   st.mnew = 0;
   st.insub = 0;
+  st.fbits = 0;
+}
+
+__device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v |= __shfl_xor(v, d, 64);
+  return v;
+}
+
+// OR over the 256 threads of a block (every thread gets the result).
+__device__ __forceinline__ uint64_t block_or64(uint64_t v) {
+  __shared__ uint64_t s_o[kThreads / 64];
+  v = wave_or64(v);
+  if (lane() == 0) s_o[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint64_t t = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) t |= s_o[w];
+  __syncthreads();
+  return t;
+}
+
+// ORs a block's discovered source bits into its stripe (thread 0 only).
+__device__ __forceinline__ void stripe_or(LevelSlot* slot, uint64_t bits) {
+  if (bits) atomicOr((unsigned long long*)&slot->s[blockIdx.x % kStripes].fbits, (unsigned long long)bits);
 }
 
 // ---- single-pass tile prefix (decoupled look-back) ----
@@ -343,7 +368,9 @@ __device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, Leve
     const bool mine = k < kStripes;
     const uint64_t v0 = mine ? uint64_t(sk->count) | (uint64_t(sk->aux) << 32) : 0ull;
     const uint64_t v1 = mine ? sk->edges : 0ull, v2 = mine ? sk->mnew : 0ull, v3 = mine ? sk->insub : 0ull;
+    const uint64_t v4 = mine ? sk->fbits : 0ull;
     const uint64_t lo = wave_sum64(v0 & 0xffffffffull), hi = wave_sum64(v0 >> 32);
+    const uint64_t fb = uniform64(wave_or64(v4));
     t.count = uniform64(lo);
     t.aux = uniform64(hi);
     t.edges = uniform64(wave_sum64(v1));
@@ -365,6 +392,7 @@ __device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, Leve
       st.list_valid = prev.dir == 0 ? 1 : 0;  // a push level appended its winners to Q[L % 2]
       st.vis_idx = prev.dir == 1 ? (prev.vis_idx ^ 1) : prev.vis_idx;
       st.m_u = m_u;
+      st.active = fb;
     }
   }
   *tot_out = t;

@@ -21,6 +21,7 @@ struct alignas(128) Stripe {
   uint64_t mnew;   // out-edges of the vertices discovered (edge-count rule only)
   uint64_t insub;  // in-edges of the vertices discovered (edge-count rule only; multi-source:
                    // of the vertices every source has now reached)
+  uint64_t fbits;  // multi-source: OR of the source bits discovered
 };
 struct LevelSlot {
   Stripe s[kStripes];
@@ -38,6 +39,7 @@ struct alignas(64) LevelState {
   int32_t level;       // index of this level
   int32_t pad0;
   int64_t m_u;         // edge-count rule: in-edges of still-unvisited vertices
+  uint64_t active;     // multi-source: sources whose frontier entering the level is non-empty
 };
 // Per-level statistics for the host, written by the next level's first kernel.
 struct LevelRecord {

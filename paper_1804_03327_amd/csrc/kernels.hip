@@ -438,6 +438,7 @@ __global__ __launch_bounds__(kThreads) void k_bfs_init(BfsArgs a, int32_t source
       st.level = 0;
       st.pad0 = 0;
       st.m_u = a.nnz - c->src_indeg;
+      st.active = 0;
       c->ring[0] = st;
     }
   }
