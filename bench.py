@@ -6,8 +6,13 @@ is GTEPS with the Graph500 edge count (undirected edges with a reached endpoint)
 paper-convention figure (nnz(A) / time) is reported beside it. Prints one JSON line.
 
 Also reported: the HBM roofline of the dominant kernel (algorithmic bytes per launch over its
-HIP-event-timed duration inside the timed region), the CPU oracle on a bounded sample of the
-same workload, and the Table 2 ablation modes.
+average execution time, from each kernel's own start/end events in a repeat of the timed
+steps), the CPU oracle on a bounded sample of the same workload, the Table 2 ablation modes,
+the other direction rule, and the multi-source measurement: 64 sources per launch on RMAT-20
+against the same 64 queries run one at a time.
+
+--profile-steps / --profile-batched run only the BFS launches (for rocprofv3); --copy-mb adds
+one device copy of known size as the reference for scaling the PMC byte counters.
 """
 import argparse
 import hashlib
@@ -166,6 +171,9 @@ def main():
     ap.add_argument("--no-validate", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many BFS steps (for rocprofv3), print nothing else")
+    ap.add_argument("--profile-batched", type=int, default=0,
+                    help="only run this many multi-source launches on the batched workload "
+                         "(for rocprofv3), print nothing else")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="with --profile-steps: also copy this many MiB device-to-device once, "
                          "the known-size reference for scaling PMC byte counters")
@@ -185,6 +193,21 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+
+    if args.profile_batched:
+        hb = gen.rmat(args.batched_scale, args.edgefactor, seed=1)
+        srcs = [int(x) for x in gen.sample_sources(hb, 64, seed=5)]
+        gb = upload(hb, device=0)
+        ws = torch.empty(dobfs.bfs_batch_workspace_bytes(gb, 64), dtype=torch.uint8, device="cuda")
+        depth = torch.empty(64 * gb.V, dtype=torch.int32, device="cuda")
+        heur_b = dobfs.HEUR_EDGES if args.heuristic == "edges" else dobfs.HEUR_RATIO
+        ob = dobfs.make_options("full", heur_b, args.alpha if args.alpha is not None else (
+            1 / 14 if heur_b == dobfs.HEUR_EDGES else 0.01), args.beta if args.beta is not None else (
+            1 / 24 if heur_b == dobfs.HEUR_EDGES else 0.01))
+        for k in range(args.profile_batched):
+            dobfs.bfs_batch(gb, srcs, depth, opt=ob, workspace=ws)
+            log("profile batched launch %d done" % k)
+        return
 
     t0 = time.time()
     hg = gen.rmat(args.scale, args.edgefactor, seed=1)
@@ -216,9 +239,9 @@ def main():
             torch.cuda.synchronize()
             log("reference copy of %d bytes done" % n)
             del src_t, dst_t
-        for k in range(args.profile_steps):
+        for k in range(args.profile_steps):  # the configuration of the roofline pass
             for s in sources:
-                runner.run(s, opt=opt_plain, stream=stream)
+                runner.run(s, opt=opt_timed, stream=stream)
             torch.cuda.synchronize()
             log("profile step %d done" % k)
         return
@@ -250,9 +273,9 @@ def main():
     log("timed: %.3f ms/step, %.2f GTEPS (graph500 count), %.2f GTEPS (nnz/time)" % (
         ms_per_step, gteps, gteps_paper))
 
-    # roofline pass: the same K steps again with HIP events around every
-    # kernel (recorded by the library on this stream); per-kernel durations
-    # and algorithmic bytes come from here
+    # roofline pass: the same K steps again, every kernel launched with start
+    # and end events of its own execution (by the library, on this stream);
+    # per-kernel durations and algorithmic bytes come from here
     caps = 64
     pool = [[dobfs.make_stats(caps) for _ in sources] for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -307,8 +330,9 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "algorithmic_bytes_per_launch": round(per_launch),
                 "avg_launch_us": round(avg_ms * 1e3, 3), "launches": kd["launches"],
-                "timing": "HIP events around each kernel, on the BFS stream, over a repeat of the "
-                          "timed steps (%.1f ms/step with events)" % (1e3 * t_ev / args.steps)}
+                "timing": "each kernel's own start/end events (hipExtLaunchKernel) on the BFS stream, "
+                          "over a repeat of the timed steps (%.1f ms/step with events)" % (
+                              1e3 * t_ev / args.steps)}
     kernel_table = {k: {"total_ms": round(v["ms"], 3), "launches": v["launches"],
                         "avg_us": round(1e3 * v["ms"] / max(1, v["launches"]), 3),
                         "GBps": round(v["bytes"] / max(1e-12, v["ms"] * 1e-3) / 1e9, 1)}

@@ -116,7 +116,8 @@ enum {
 };
 
 enum {
-  DOBFS_OPT_TIME_KERNELS = 1u /* record HIP events around every launch; fills *_ms stats */
+  DOBFS_OPT_TIME_KERNELS = 1u /* every kernel launch records its own start and end (HIP
+                                 extended-launch events); fills the *_ms stats */
 };
 
 typedef struct {
@@ -156,8 +157,11 @@ typedef struct {
   int32_t pad;
   int64_t edges;   /* push: nnz(m_f^+) adjacency entries read; pull: in-neighbours checked */
   int64_t m_f;     /* push: out-edges of the input frontier (0 on pull levels) */
-  float ms_main;   /* push expand or pull kernel time (DOBFS_OPT_TIME_KERNELS), else 0 */
-  float ms_aux;    /* push scan + format conversion time, else 0 */
+  float ms_main;   /* execution time of the level's second kernel, the push expansion or the
+                      pull (DOBFS_OPT_TIME_KERNELS), else 0 */
+  float ms_aux;    /* execution time of the level's first kernel: the direction decision and,
+                      for push, the frontier scan (with the bitmap-to-list conversion after a
+                      pull level), else 0 */
 } dobfs_level_stats;
 
 typedef struct {
@@ -165,8 +169,8 @@ typedef struct {
   int32_t cap;              /* capacity of `level` (caller sets; may be 0) */
   dobfs_level_stats *level; /* host array of cap entries, caller-owned, may be NULL */
   float ms_total;           /* device time of the whole call (events) */
-  float ms_init;            /* init kernel time (DOBFS_OPT_TIME_KERNELS) */
-  int64_t reached;          /* vertices with depth >= 0 */
+  float ms_init;            /* init kernel execution time (DOBFS_OPT_TIME_KERNELS) */
+  int64_t reached;          /* vertices with depth >= 0 (multi-source: (vertex, source) pairs) */
 } dobfs_stats;
 
 /* ----------------------------------------------------------------- BFS */

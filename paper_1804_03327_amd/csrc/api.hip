@@ -187,9 +187,15 @@ hipError_t wait_report(const HostReport* r, uint32_t seq, hipStream_t s) {
   return __atomic_load_n(&r->seq, __ATOMIC_ACQUIRE) == seq ? hipSuccess : hipErrorUnknown;
 }
 
-// Per-thread, per-device events for the level loop's timers: two per level
-// of a batch, plus start / init / end.
-constexpr int kEvStart = 2 * kMaxBatch + 2, kEvInit = kEvStart + 1, kEvEnd = kEvStart + 2;
+// Per-thread, per-device events for the level loop's timers: the start and
+// end of every prep (kMaxBatch + 1 slots) and main (kMaxBatch slots) kernel
+// of a batch, of the init kernel, and of the whole call.
+constexpr int ev_p0(int j) { return j; }
+constexpr int ev_p1(int j) { return kMaxBatch + 1 + j; }
+constexpr int ev_m0(int k) { return 2 * kMaxBatch + 2 + k; }
+constexpr int ev_m1(int k) { return 3 * kMaxBatch + 2 + k; }
+constexpr int kEvStart = 4 * kMaxBatch + 2, kEvInit0 = kEvStart + 1, kEvInit1 = kEvStart + 2,
+              kEvEnd = kEvStart + 3;
 constexpr int kEvents = kEvEnd + 1;
 hipEvent_t* events_for(int device) {
   thread_local hipEvent_t ev[16][kEvents];
@@ -337,9 +343,10 @@ struct LoopResult {
 // exit at once. The first batch is one level longer than the previous
 // traversal of the same kind needed (a level past the end costs a few
 // microseconds, a second batch a host round trip); later batches start at 4
-// and double. The init kernel and ev[kEvStart] precede the call.
-// Event layout when timing: ev[2k] before prep of the k-th level of the
-// batch, ev[2k+1] between its two kernels.
+// and double. The init kernel and ev[kEvStart] precede the call. When
+// timing, every kernel gets start / end events of its own execution: the
+// k-th level of a batch uses prep slot k and main slot k, and the prep that
+// opens the next batch uses prep slot `batch`.
 template <class Prep, class Main, class Forced>
 dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool timing, hipEvent_t* ev,
                         Forced forced, Prep prep, Main main, const Ctrl* ctrl, int64_t max_levels,
@@ -351,24 +358,20 @@ dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool t
   int32_t batch = std::min(std::max(last_levels.load(std::memory_order_relaxed) + 1, 2), kMaxBatch);
   int32_t next_batch = 4;
   float first_aux = 0.f;  // prep time of a batch's first level
-  if (timing) HIPCK(hipEventRecord(ev[0], s));
-  HIPCK(prep(0, forced(0)));
-  if (timing) HIPCK(hipEventRecord(ev[1], s));
+  auto E = [&](int i) -> hipEvent_t { return timing ? ev[i] : nullptr; };
+  HIPCK(prep(0, forced(0), E(ev_p0(0)), E(ev_p1(0))));
   while (true) {
     if (lvl + batch > max_levels) batch = int32_t(max_levels - lvl);
     const int64_t l1 = lvl + batch - 1;
     for (int64_t l = lvl; l <= l1; ++l) {
       const int32_t k = int32_t(l - lvl);
-      if (timing && k > 0) HIPCK(hipEventRecord(ev[2 * k + 1], s));
-      HIPCK(main(int32_t(l)));
-      if (timing) HIPCK(hipEventRecord(ev[2 * k + 2], s));
-      HIPCK(prep(int32_t(l + 1), forced(l + 1)));
+      HIPCK(main(int32_t(l), E(ev_m0(k)), E(ev_m1(k))));
+      HIPCK(prep(int32_t(l + 1), forced(l + 1), E(ev_p0(k + 1)), E(ev_p1(k + 1))));
     }
-    if (timing) HIPCK(hipEventRecord(ev[2 * batch + 1], s));
     const uint32_t seq = ++report_seq;
     HIPCK(launch_report(s, ctrl, int32_t(lvl), batch, rep, seq));
     HIPCK(wait_report(rep, seq, s));
-    if (timing && lvl == 0) first_aux = elapsed(ev[0], ev[1]);
+    if (timing && lvl == 0) first_aux = elapsed(ev[ev_p0(0)], ev[ev_p1(0)]);
     const LevelState& end = rep->end;
     const int64_t last = end.done ? int64_t(end.levels) - 1 : l1;  // last level that ran
     for (int64_t l = lvl; l <= last; ++l) {
@@ -384,8 +387,8 @@ dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool t
         ls.pad = 0;
         ls.edges = r.edges;
         ls.m_f = r.m_f;
-        ls.ms_aux = timing ? (k == 0 ? first_aux : elapsed(ev[2 * k], ev[2 * k + 1])) : 0.f;
-        ls.ms_main = timing ? elapsed(ev[2 * k + 1], ev[2 * k + 2]) : 0.f;
+        ls.ms_aux = timing ? (k == 0 ? first_aux : elapsed(ev[ev_p0(k)], ev[ev_p1(k)])) : 0.f;
+        ls.ms_main = timing ? elapsed(ev[ev_m0(k)], ev[ev_m1(k)]) : 0.f;
       }
     }
     if (end.done) {
@@ -397,11 +400,10 @@ dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool t
       (void)hipStreamSynchronize(s);
       return fail(too_deep, "traversal needs more than %lld levels", (long long)max_levels);
     }
-    if (timing) first_aux = elapsed(ev[2 * batch], ev[2 * batch + 1]);  // prep(l1 + 1)
+    if (timing) first_aux = elapsed(ev[ev_p0(batch)], ev[ev_p1(batch)]);  // prep(l1 + 1)
     lvl = l1 + 1;
     batch = next_batch;
     next_batch = std::min(2 * next_batch, kMaxBatch);
-    if (timing) HIPCK(hipEventRecord(ev[1], s));  // prep(lvl) ran in the previous batch
   }
   last_levels.store(int32_t(res->levels), std::memory_order_relaxed);
   return DOBFS_OK;
@@ -639,13 +641,14 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
                                       : (opt.mode == DOBFS_MODE_PULL_ONLY ? DOBFS_DIR_PULL : DOBFS_DIR_PUSH);
 
   HIPCK(hipEventRecord(ev[kEvStart], s));
-  HIPCK(launch_bfs_init(s, a, source, dir0));
-  if (timing) HIPCK(hipEventRecord(ev[kEvInit], s));
+  HIPCK(launch_bfs_init(s, a, source, dir0, timing ? ev[kEvInit0] : nullptr,
+                        timing ? ev[kEvInit1] : nullptr));
   LoopResult res;
   st = run_levels(
       g->last_levels, s, timing, ev, forced,
-      [&](int32_t l, int32_t f) { return launch_level_prep(s, a, l, f); },
-      [&](int32_t l) { return launch_level_main(s, a, l); }, a.ctrl, int64_t(g->V) + 2,
+      [&](int32_t l, int32_t f, hipEvent_t t0, hipEvent_t t1) { return launch_level_prep(s, a, l, f, t0, t1); },
+      [&](int32_t l, hipEvent_t t0, hipEvent_t t1) { return launch_level_main(s, a, l, t0, t1); },
+      a.ctrl, int64_t(g->V) + 2,
       DOBFS_ERR_INTERNAL, stats, &res);
   if (st != DOBFS_OK) return st;
   HIPCK(hipEventRecord(ev[kEvEnd], s));
@@ -653,7 +656,7 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   if (stats) {
     stats->levels = int32_t(res.levels);
     stats->ms_total = elapsed(ev[kEvStart], ev[kEvEnd]);
-    stats->ms_init = timing ? elapsed(ev[kEvStart], ev[kEvInit]) : 0.f;
+    stats->ms_init = timing ? elapsed(ev[kEvInit0], ev[kEvInit1]) : 0.f;
     stats->reached = 1 + res.sum_new;
   }
   return DOBFS_OK;
@@ -742,13 +745,13 @@ dobfs_status dobfs_bfs_batch(dobfs_graph g, const int32_t* sources, int32_t k,
   const int64_t cap = std::min<int64_t>(int64_t(g->V) + 2, 0xfffe);
 
   HIPCK(hipEventRecord(ev[kEvStart], s));
-  HIPCK(launch_mb_init(s, a, dir0, L.nflags));
-  if (timing) HIPCK(hipEventRecord(ev[kEvInit], s));
+  HIPCK(launch_mb_init(s, a, dir0, L.nflags, timing ? ev[kEvInit0] : nullptr,
+                       timing ? ev[kEvInit1] : nullptr));
   LoopResult res;
   st = run_levels(
       g->last_levels_mb, s, timing, ev, forced,
-      [&](int32_t l, int32_t f) { return launch_mb_prep(s, a, l, f); },
-      [&](int32_t l) { return launch_mb_main(s, a, l); }, a.ctrl, cap,
+      [&](int32_t l, int32_t f, hipEvent_t t0, hipEvent_t t1) { return launch_mb_prep(s, a, l, f, t0, t1); },
+      [&](int32_t l, hipEvent_t t0, hipEvent_t t1) { return launch_mb_main(s, a, l, t0, t1); }, a.ctrl, cap,
       cap < int64_t(g->V) + 2 ? DOBFS_ERR_UNSUPPORTED : DOBFS_ERR_INTERNAL, stats, &res);
   if (st != DOBFS_OK) return st;
   HIPCK(launch_mb_depth(s, a, a.vis[res.end.vis_idx], depth));
@@ -757,7 +760,7 @@ dobfs_status dobfs_bfs_batch(dobfs_graph g, const int32_t* sources, int32_t k,
   if (stats) {
     stats->levels = int32_t(res.levels);
     stats->ms_total = elapsed(ev[kEvStart], ev[kEvEnd]);
-    stats->ms_init = timing ? elapsed(ev[kEvStart], ev[kEvInit]) : 0.f;
+    stats->ms_init = timing ? elapsed(ev[kEvInit0], ev[kEvInit1]) : 0.f;
     stats->reached = k + res.sum_aux;  // (vertex, source) pairs, the sources included
   }
   return DOBFS_OK;

@@ -461,23 +461,21 @@ __global__ __launch_bounds__(kThreads) void k_mb_depth(BatchArgs a, const uint64
 
 }  // namespace
 
-hipError_t launch_mb_init(hipStream_t s, const BatchArgs& a, int32_t dir0, int64_t nflags) {
+hipError_t launch_mb_init(hipStream_t s, const BatchArgs& a, int32_t dir0, int64_t nflags, hipEvent_t t0,
+                         hipEvent_t t1) {
   const int64_t n = std::max<int64_t>(a.V, nflags);
   const unsigned g = unsigned(std::min<int64_t>((n + kThreads - 1) / kThreads, 8192));
-  hipLaunchKernelGGL(k_mb_init, dim3(g > 0 ? g : 1), dim3(kThreads), 0, s, a, dir0, nflags);
-  return hipGetLastError();
+  return launch_k(k_mb_init, dim3(g > 0 ? g : 1), s, t0, t1, a, dir0, nflags);
 }
 
-hipError_t launch_mb_prep(hipStream_t s, const BatchArgs& a, int32_t level, int32_t forced_dir) {
-  hipLaunchKernelGGL(k_mb_prep, dim3(unsigned(scan_grid(a.V))), dim3(kThreads), 0, s, a, level,
-                     forced_dir);
-  return hipGetLastError();
+hipError_t launch_mb_prep(hipStream_t s, const BatchArgs& a, int32_t level, int32_t forced_dir,
+                         hipEvent_t t0, hipEvent_t t1) {
+  return launch_k(k_mb_prep, dim3(unsigned(scan_grid(a.V))), s, t0, t1, a, level, forced_dir);
 }
 
-hipError_t launch_mb_main(hipStream_t s, const BatchArgs& a, int32_t level) {
-  const unsigned g = unsigned(std::max<int64_t>(kExpandBlocks, pull_tiles(a.nwords)));
-  hipLaunchKernelGGL(k_mb_main, dim3(g), dim3(kThreads), 0, s, a, level);
-  return hipGetLastError();
+hipError_t launch_mb_main(hipStream_t s, const BatchArgs& a, int32_t level, hipEvent_t t0, hipEvent_t t1) {
+  const dim3 g(unsigned(std::max<int64_t>(kExpandBlocks, pull_tiles(a.nwords))));
+  return launch_k(k_mb_main, g, s, t0, t1, a, level);
 }
 
 hipError_t launch_mb_depth(hipStream_t s, const BatchArgs& a, const uint64_t* vis, int32_t* depth) {

@@ -7,6 +7,8 @@
 
 #include "dobfs_internal.h"
 
+#include <hip/hip_ext.h>
+
 namespace dobfs {
 namespace {
 
@@ -46,6 +48,16 @@ __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
   return v;
+}
+
+// Launch with optional kernel start / end events (hipExtLaunchKernel).
+template <class K, class... Args>
+hipError_t launch_k(K kernel, dim3 grid, hipStream_t s, hipEvent_t t0, hipEvent_t t1, Args... args) {
+  if (t0 || t1)
+    hipExtLaunchKernelGGL(kernel, grid, dim3(kThreads), 0, s, t0, t1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, dim3(kThreads), 0, s, args...);
+  return hipGetLastError();
 }
 
 // A value every lane holds alike, moved to scalar registers.

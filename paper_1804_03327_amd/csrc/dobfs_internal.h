@@ -252,10 +252,16 @@ struct ScanBitsArgs {
   uint32_t* mf_out;          // total degree (when rowptr)
 };
 
-// ---- launchers (kernels.hip); each returns hipGetLastError() ----
-hipError_t launch_bfs_init(hipStream_t s, const BfsArgs& a, int32_t source, int32_t dir0);
-hipError_t launch_level_prep(hipStream_t s, const BfsArgs& a, int32_t level, int32_t forced_dir);
-hipError_t launch_level_main(hipStream_t s, const BfsArgs& a, int32_t level);
+// ---- launchers (kernels.hip, batch.hip); each returns hipGetLastError() ----
+// Where a launcher takes events t0 / t1 they receive the kernel's own start
+// and end times (AMD's extended launch), so an event interval is the
+// kernel's execution alone, not the gap before it.
+hipError_t launch_bfs_init(hipStream_t s, const BfsArgs& a, int32_t source, int32_t dir0,
+                          hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+hipError_t launch_level_prep(hipStream_t s, const BfsArgs& a, int32_t level, int32_t forced_dir,
+                            hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+hipError_t launch_level_main(hipStream_t s, const BfsArgs& a, int32_t level, hipEvent_t t0 = nullptr,
+                            hipEvent_t t1 = nullptr);
 hipError_t launch_ctrl_init(hipStream_t s, Ctrl* ctrl, uint64_t* flags, int64_t nflags);
 hipError_t launch_scan_bits(hipStream_t s, const ScanBitsArgs& a);
 hipError_t launch_expand(hipStream_t s, const ExpandArgs& a, const uint32_t* m_dev,
@@ -279,9 +285,12 @@ struct HostReport {
 };
 hipError_t launch_report(hipStream_t s, const Ctrl* ctrl, int32_t l_first, int32_t n,
                          HostReport* host, uint32_t seq);
-hipError_t launch_mb_init(hipStream_t s, const BatchArgs& a, int32_t dir0, int64_t nflags);
-hipError_t launch_mb_prep(hipStream_t s, const BatchArgs& a, int32_t level, int32_t forced_dir);
-hipError_t launch_mb_main(hipStream_t s, const BatchArgs& a, int32_t level);
+hipError_t launch_mb_init(hipStream_t s, const BatchArgs& a, int32_t dir0, int64_t nflags,
+                         hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+hipError_t launch_mb_prep(hipStream_t s, const BatchArgs& a, int32_t level, int32_t forced_dir,
+                         hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+hipError_t launch_mb_main(hipStream_t s, const BatchArgs& a, int32_t level, hipEvent_t t0 = nullptr,
+                         hipEvent_t t1 = nullptr);
 hipError_t launch_mb_depth(hipStream_t s, const BatchArgs& a, const uint64_t* vis, int32_t* depth);
 hipError_t launch_check_offsets(hipStream_t s, const int32_t* ptr, int32_t V, int64_t nnz,
                                 int32_t* err);

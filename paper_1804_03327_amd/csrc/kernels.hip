@@ -688,27 +688,22 @@ inline unsigned grid_for(int64_t n, int64_t per_block, int64_t cap = 65535) {
 
 }  // namespace
 
-hipError_t launch_bfs_init(hipStream_t s, const BfsArgs& a, int32_t source, int32_t dir0) {
+hipError_t launch_bfs_init(hipStream_t s, const BfsArgs& a, int32_t source, int32_t dir0, hipEvent_t t0,
+                          hipEvent_t t1) {
   const int64_t nflags = flag_entries(a.V);
   const int64_t n = std::max<int64_t>(std::max<int64_t>(a.V / 4 + 4, a.nwords), nflags);
-  hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, a,
-                     source, dir0, nflags);
-  return hipGetLastError();
+  return launch_k(k_bfs_init, dim3(grid_for(n, kThreads, 8192)), s, t0, t1, a, source, dir0, nflags);
 }
 
-hipError_t launch_level_prep(hipStream_t s, const BfsArgs& a, int32_t level, int32_t forced_dir) {
-  hipLaunchKernelGGL(k_level_prep, dim3(unsigned(scan_grid(a.V))), dim3(kThreads), 0, s, a, level,
-                     forced_dir);
-  return hipGetLastError();
+hipError_t launch_level_prep(hipStream_t s, const BfsArgs& a, int32_t level, int32_t forced_dir,
+                            hipEvent_t t0, hipEvent_t t1) {
+  return launch_k(k_level_prep, dim3(unsigned(scan_grid(a.V))), s, t0, t1, a, level, forced_dir);
 }
 
-hipError_t launch_level_main(hipStream_t s, const BfsArgs& a, int32_t level) {
-  const unsigned g = unsigned(std::max<int64_t>(kExpandBlocks, pull_tiles(a.nwords)));
-  if (a.early_exit)
-    hipLaunchKernelGGL(k_level_main<true>, dim3(g), dim3(kThreads), 0, s, a, level);
-  else
-    hipLaunchKernelGGL(k_level_main<false>, dim3(g), dim3(kThreads), 0, s, a, level);
-  return hipGetLastError();
+hipError_t launch_level_main(hipStream_t s, const BfsArgs& a, int32_t level, hipEvent_t t0, hipEvent_t t1) {
+  const dim3 g(unsigned(std::max<int64_t>(kExpandBlocks, pull_tiles(a.nwords))));
+  if (a.early_exit) return launch_k(k_level_main<true>, g, s, t0, t1, a, level);
+  return launch_k(k_level_main<false>, g, s, t0, t1, a, level);
 }
 
 hipError_t launch_ctrl_init(hipStream_t s, Ctrl* ctrl, uint64_t* flags, int64_t nflags) {
