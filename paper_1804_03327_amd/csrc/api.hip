@@ -31,7 +31,7 @@ struct dobfs_graph_s {
   const int32_t* colptr = nullptr;  // CSC(A)
   const int32_t* rowind = nullptr;
   uint32_t* nz_in = nullptr;        // rows of CSC(A) with at least one entry
-  int32_t* head = nullptr;          // first entry of every CSC(A) column (-1 if empty)
+  int4* slab = nullptr;             // first kSlab entries of every CSC(A) column (-1 past its end)
   std::atomic<int32_t> last_levels{8};  // level count of the previous BFS (first batch size)
   std::atomic<int32_t> last_levels_mb{8};  // the same for multi-source traversals
   void* owned[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -281,9 +281,9 @@ dobfs_status finish_graph(dobfs_graph g, hipStream_t s) {
   HIPCK(hipMalloc(&p, size_t(std::max(g->nwords, 1)) * 4));
   g->nz_in = static_cast<uint32_t*>(p);
   HIPCK(launch_nz_bits(s, g->colptr, g->V, g->nz_in));
-  HIPCK(hipMalloc(&p, size_t(g->V) * 4));
-  g->head = static_cast<int32_t*>(p);
-  HIPCK(launch_head(s, g->colptr, g->rowind, g->V, g->head));
+  HIPCK(hipMalloc(&p, size_t(std::max(g->V, 1)) * sizeof(int4)));
+  g->slab = static_cast<int4*>(p);
+  HIPCK(launch_slab(s, g->colptr, g->rowind, g->V, g->slab));
   HIPCK(hipStreamSynchronize(s));
   return DOBFS_OK;
 }
@@ -293,7 +293,7 @@ void free_graph(dobfs_graph g) {
   for (void* p : g->owned)
     if (p) (void)hipFree(p);
   if (g->nz_in) (void)hipFree(g->nz_in);
-  if (g->head) (void)hipFree(g->head);
+  if (g->slab) (void)hipFree(g->slab);
   if (g->ws) (void)hipFree(g->ws);
   delete g;
 }
@@ -608,7 +608,7 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   a.colind = g->colind;
   a.colptr = g->colptr;
   a.rowind = g->rowind;
-  a.head = g->head;
+  a.slab = g->slab;
   a.nz_in = g->nz_in;
   a.depth = depth;
   a.parent = parent;
@@ -708,6 +708,7 @@ dobfs_status dobfs_bfs_batch(dobfs_graph g, const int32_t* sources, int32_t k,
   a.colptr = g->colptr;
   a.rowind = g->rowind;
   a.nz_in = g->nz_in;
+  a.slab = g->slab;
   a.lvl = reinterpret_cast<uint16_t*>(ws + L.lvl);
   a.k = k;
   a.active = k == 64 ? ~0ull : ((1ull << k) - 1ull);
@@ -815,7 +816,7 @@ dobfs_status dobfs_mxv(dobfs_graph g, const uint32_t* x_bits, const int32_t* x_i
     pa.nwords = nwords;
     pa.colptr = g->colptr;
     pa.rowind = g->rowind;
-    pa.head = g->head;
+    pa.slab = g->slab;
     pa.x = x;
     pa.mask = mask_bits;
     pa.complement = complement ? 1 : 0;

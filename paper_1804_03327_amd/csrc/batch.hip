@@ -231,13 +231,14 @@ struct MbPullShared {
   int32_t ncand, nlong;
 };
 
-// Row-based product over one tile of 2048 rows: rows that some source has
-// not reached (the mask, Section 5.2) and that have in-neighbours are listed;
-// each ORs the visited words of its in-neighbours in stored order and stops
-// once every missing source bit is found (early exit, Section 5.3). A thread
-// takes a row up to kMbMid in-neighbours, then a wave finishes it, 64 per
-// step. The tile's new visited words (old | found), next-frontier words and
-// nonzero bits are written whole; no atomics touch them.
+// Row-based product over one tile of 2048 rows: rows that a still-expanding
+// source has not reached (the mask, Section 5.2) and that have in-neighbours
+// are listed; each ORs the visited words of its in-neighbours in stored order
+// and stops once every missing source bit is found (early exit, Section 5.3).
+// A thread takes a row's slab (first kSlab in-neighbours, one read), then the
+// row up to kMbMid in-neighbours, then a wave finishes it, 64 per step. The
+// tile's new visited words (old | found), next-frontier words and nonzero
+// bits are written whole; no atomics touch them.
 __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st, int32_t tile,
                              MbPullShared& sh) {
   const int tid = threadIdx.x;
@@ -300,10 +301,24 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
     const int32_t v = v0 + r;
     const uint64_t m = vin[v];
     const uint64_t need = ~m & active;
+    // the slab: the row's first kSlab in-neighbours from one coalesced read
+    const int4 hd = a.slab[v];
+    const int32_t e[kSlab] = {hd.x, hd.y, hd.z, hd.w};
+    uint64_t acc = 0;
+#pragma unroll
+    for (int q = 0; q < kSlab; ++q) {
+      if (e[q] >= 0) {
+        acc |= vin[e[q]];
+        ++checks;
+      }
+    }
+    if ((acc & need) == need || hd.w < 0) {
+      finish(r, m, acc & need);
+      continue;
+    }
     const int32_t beg = a.colptr[v], end = a.colptr[v + 1];
     const int32_t lim = min(end, beg + kMbMid);
-    uint64_t acc = 0;
-    int32_t p = beg;
+    int32_t p = beg + kSlab;
     while (p < lim && (acc & need) != need) {
       int32_t j[4];
 #pragma unroll
@@ -375,12 +390,12 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
 __global__ __launch_bounds__(kThreads) void k_mb_prep(BatchArgs a, int32_t L, int32_t forced) {
   Ctrl* c = a.ctrl;
   LevelTotals tot;
-  const LevelState st = level_state(a, L, forced, &tot);
-  publish_level(c, L, st, tot);
+  LevelState prev;
+  const LevelState st = level_state(a, L, forced, &tot, &prev);
+  publish_level(c, L, st, prev, tot);
   if (st.done || st.dir != 0) return;
   uint64_t* Fn = a.F[(L + 1) % 2];
   if (L >= 1) {
-    const LevelState prev = c->ring[(L - 1) % kRing];
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (prev.list_valid || prev.dir == 0) {  // a push level always had its frontier as a list

@@ -358,7 +358,8 @@ __device__ __forceinline__ int32_t thread_search(const int32_t* S, int32_t lo, i
 // computing it and broadcasting it through LDS. All blocks of a level_prep
 // compute the same state.
 template <class Args>
-__device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, LevelTotals* tot_out) {
+__device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, LevelTotals* tot_out,
+                                  LevelState* prev_out) {
   const Ctrl* c = a.ctrl;
   LevelTotals t{0, 0, 0, 0, 0};
   LevelState st;
@@ -366,21 +367,24 @@ __device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, Leve
     st = c->ring[0];
     if (forced >= 0) st.dir = forced;
     *tot_out = t;
+    *prev_out = st;
     return st;
   }
+  // the previous state and the counters are loaded together (one round
+  // trip): lane k reads stripe k and the wave adds them up; the totals are
+  // uniform, so they go back to scalar registers
+  const LevelSlot& sl = c->slot[(L - 1) % kSlots];
+  const int k = lane();
+  const Stripe* sk = &sl.s[k & (kStripes - 1)];
+  const bool mine = k < kStripes;
+  const uint64_t v0 = mine ? uint64_t(sk->count) | (uint64_t(sk->aux) << 32) : 0ull;
+  const uint64_t v1 = mine ? sk->edges : 0ull, v2 = mine ? sk->mnew : 0ull, v3 = mine ? sk->insub : 0ull;
+  const uint64_t v4 = mine ? sk->fbits : 0ull;
   const LevelState prev = c->ring[(L - 1) % kRing];
+  *prev_out = prev;
   st = prev;
   st.level = L;
   if (!prev.done) {
-    const LevelSlot& sl = c->slot[(L - 1) % kSlots];
-    // lane k reads stripe k (one round trip for the whole slot) and the wave
-    // adds them up; the totals are uniform, so they go back to scalar registers
-    const int k = lane();
-    const Stripe* sk = &sl.s[k & (kStripes - 1)];
-    const bool mine = k < kStripes;
-    const uint64_t v0 = mine ? uint64_t(sk->count) | (uint64_t(sk->aux) << 32) : 0ull;
-    const uint64_t v1 = mine ? sk->edges : 0ull, v2 = mine ? sk->mnew : 0ull, v3 = mine ? sk->insub : 0ull;
-    const uint64_t v4 = mine ? sk->fbits : 0ull;
     const uint64_t lo = wave_sum64(v0 & 0xffffffffull), hi = wave_sum64(v0 >> 32);
     const uint64_t fb = uniform64(wave_or64(v4));
     t.count = uniform64(lo);
@@ -414,12 +418,12 @@ __device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, Leve
 // Block 0 of level L's first kernel: publish the level's state and the
 // record of level L-1, and clear the counters level L+1 will add into
 // (nothing reads them before the next kernel boundary).
-__device__ void publish_level(Ctrl* c, int32_t L, const LevelState& st, const LevelTotals& tot) {
+__device__ void publish_level(Ctrl* c, int32_t L, const LevelState& st, const LevelState& prev,
+                              const LevelTotals& tot) {
   if (blockIdx.x != 0) return;
   if (threadIdx.x == 0) {
     c->ring[L % kRing] = st;
     if (L >= 1) {
-      const LevelState prev = c->ring[(L - 1) % kRing];
       if (!prev.done) {
         LevelRecord r;
         r.dir = prev.dir;

@@ -95,9 +95,6 @@ constexpr int kExpandWin = kExpandChunk + 1;         // frontier entries cached 
 #ifndef DOBFS_EXPAND_BUF
 #define DOBFS_EXPAND_BUF 2048
 #endif
-#ifndef DOBFS_PULL_FIRST
-#define DOBFS_PULL_FIRST 4
-#endif
 #ifndef DOBFS_PULL_MID
 #define DOBFS_PULL_MID 32
 #endif
@@ -105,9 +102,13 @@ constexpr int kExpandBuf = DOBFS_EXPAND_BUF;          // winners buffered in LDS
 constexpr int kExpandBlocks = 1024;                  // expand grid (strides over chunks)
 constexpr int kPullTileWords = 64;                   // pull: bitmap words owned by a block
 constexpr int kPullTileV = kPullTileWords * 32;      // 2048 rows per block
-constexpr int kPullFirst = DOBFS_PULL_FIRST;          // in-neighbours checked breadth-first over a thread's rows
+constexpr int kSlab = 4;                              // in-neighbours per row kept in the dense slab
+constexpr int kPullFirst = kSlab;                     // pull phase 1 checks a row's slab entries
 constexpr int kPullMid = DOBFS_PULL_MID;              // rows still open continue thread-per-row up to here
-constexpr int kPullStep = 4;                          // in-neighbours a thread loads at once past kPullFirst
+#ifndef DOBFS_PULL_STEP
+#define DOBFS_PULL_STEP 4
+#endif
+constexpr int kPullStep = DOBFS_PULL_STEP;            // in-neighbours a thread loads at once past kPullFirst
 constexpr int kPullBatch = 4;                        // candidate rows a thread works on at once
 
 inline int32_t words_of(int64_t V) { return int32_t((V + 31) / 32); }
@@ -129,7 +130,7 @@ struct PullArgs {
   int32_t V, nwords;
   const int32_t* colptr;
   const int32_t* rowind;
-  const int32_t* head;       // first entry of every CSC column (-1 if empty)
+  const int4* slab;          // first kSlab entries of every CSC column (-1 past its end)
   const uint32_t* x;         // input vector bits
   const uint32_t* mask;      // nullable: rows that pass = mask XOR complement
   int32_t complement;
@@ -178,7 +179,7 @@ struct BfsArgs {
   const int32_t* colind;
   const int32_t* colptr;
   const int32_t* rowind;
-  const int32_t* head;       // first entry of every CSC column (-1 if empty)
+  const int4* slab;          // first kSlab entries of every CSC column (-1 past its end)
   const uint32_t* nz_in;
   int32_t* depth;
   int32_t* parent;
@@ -211,6 +212,7 @@ struct BatchArgs {
   const int32_t* colptr;
   const int32_t* rowind;
   const uint32_t* nz_in;
+  const int4* slab;          // first kSlab entries of every CSC column (-1 past its end)
   uint16_t* lvl;             // [V][k]: level at which source b reached v (valid where vis bit b is set)
   int32_t k;                 // sources
   int32_t nuniq;             // distinct sources
@@ -272,8 +274,7 @@ hipError_t launch_s2d(hipStream_t s, const int32_t* idx, int32_t n, int32_t V, u
 hipError_t launch_mxv_finalize(hipStream_t s, uint32_t* y, const uint32_t* r, int32_t nwords,
                                int32_t V, int accum, LevelSlot* slot);
 hipError_t launch_nz_bits(hipStream_t s, const int32_t* ptr, int32_t V, uint32_t* bits);
-hipError_t launch_head(hipStream_t s, const int32_t* ptr, const int32_t* ind, int32_t V,
-                       int32_t* head);
+hipError_t launch_slab(hipStream_t s, const int32_t* ptr, const int32_t* ind, int32_t V, int4* slab);
 // What the host needs after a batch of levels: the state after the batch and
 // the records of its levels. Written into pinned host memory by one block,
 // `seq` last (system-scope release), so the host can spin on it.

@@ -225,46 +225,48 @@ __device__ void pull_body(const PullArgs& a, int32_t tile, PullShared& sh) {
     if (a.edge_rule) insub += uint64_t(indeg);
   };
 
-  // phase 1: positions 0 .. kPullFirst-1 of a batch of rows per thread
+  // phase 1: the slab (first kSlab in-neighbours, one coalesced 16-byte read
+  // per row) of a batch of rows per thread; every bitmap word is loaded before
+  // any is tested so the loads overlap, and the first hit in stored order wins
   for (int32_t base = 0; base < ncand; base += kPullBatch * kThreads) {
     int32_t off[kPullBatch], beg[kPullBatch], end[kPullBatch], hitj[kPullBatch], cnt[kPullBatch];
+    int4 hd[kPullBatch];
 #pragma unroll
     for (int t = 0; t < kPullBatch; ++t) {
       const int32_t idx = base + t * kThreads + tid;
       off[t] = idx < ncand ? int32_t(sh.cand[idx]) : -1;
     }
-    // the first in-neighbour of every row sits in a dense array: one
-    // coalesced read instead of a line of the index array per row
 #pragma unroll
-    for (int t = 0; t < kPullBatch; ++t) hitj[t] = off[t] >= 0 ? a.head[v0 + off[t]] : -1;
+    for (int t = 0; t < kPullBatch; ++t) hd[t] = off[t] >= 0 ? a.slab[v0 + off[t]] : make_int4(-1, -1, -1, -1);
+    uint32_t wd[kPullBatch][kSlab];
 #pragma unroll
     for (int t = 0; t < kPullBatch; ++t) {
-      cnt[t] = off[t] >= 0 ? 1 : 0;
-      if (hitj[t] >= 0 && !get_bit(a.x, hitj[t])) hitj[t] = -1;
+      const int32_t e[kSlab] = {hd[t].x, hd[t].y, hd[t].z, hd[t].w};
+#pragma unroll
+      for (int q = 0; q < kSlab; ++q) wd[t][q] = e[q] >= 0 ? a.x[e[q] >> 5] : 0u;
+    }
+#pragma unroll
+    for (int t = 0; t < kPullBatch; ++t) {
+      const int32_t e[kSlab] = {hd[t].x, hd[t].y, hd[t].z, hd[t].w};
+      hitj[t] = -1;
+      cnt[t] = 0;
+#pragma unroll
+      for (int q = 0; q < kSlab; ++q) {
+        if (e[q] < 0 || (EE && hitj[t] >= 0)) continue;  // past the row's end / stopped at a hit
+        ++cnt[t];
+        if (hitj[t] < 0 && ((wd[t][q] >> (e[q] & 31)) & 1u)) hitj[t] = e[q];
+      }
     }
 #pragma unroll
     for (int t = 0; t < kPullBatch; ++t) {
       beg[t] = 0;
-      end[t] = 1;  // a row settled by its first entry needs its extent only for the edge-count rule
-      if (off[t] >= 0 && (hitj[t] < 0 || !EE || a.edge_rule)) {
+      end[t] = 0;
+      // the extent is needed past a full slab (unless settled) and, for a
+      // found row, by the edge-count rule
+      const bool more = hd[t].w >= 0 && (hitj[t] < 0 || !EE);
+      if (off[t] >= 0 && (more || (a.edge_rule && hitj[t] >= 0))) {
         beg[t] = a.colptr[v0 + off[t]];
         end[t] = a.colptr[v0 + off[t] + 1];
-      }
-    }
-#pragma unroll
-    for (int q = 1; q < kPullFirst; ++q) {
-      int32_t jj[kPullBatch];
-      bool live[kPullBatch];
-#pragma unroll
-      for (int t = 0; t < kPullBatch; ++t) {
-        live[t] = off[t] >= 0 && beg[t] + q < end[t] && (!EE || hitj[t] < 0);
-        jj[t] = live[t] ? a.rowind[beg[t] + q] : 0;
-      }
-#pragma unroll
-      for (int t = 0; t < kPullBatch; ++t) {
-        if (!live[t]) continue;
-        ++cnt[t];
-        if (hitj[t] < 0 && get_bit(a.x, jj[t])) hitj[t] = jj[t];
       }
     }
 #pragma unroll
@@ -272,7 +274,7 @@ __device__ void pull_body(const PullArgs& a, int32_t tile, PullShared& sh) {
       if (off[t] < 0) continue;
       checks += uint64_t(cnt[t]);
       if (hitj[t] >= 0) record(off[t], hitj[t], end[t] - beg[t]);
-      if (end[t] > beg[t] + kPullFirst && (!EE || hitj[t] < 0))
+      if (end[t] > beg[t] + kSlab && (!EE || hitj[t] < 0))
         sh.mid[atomicAdd(&sh.nmid, 1)] = uint16_t((base + t * kThreads + tid) | (hitj[t] >= 0 ? 0x8000 : 0));
     }
   }
@@ -450,8 +452,9 @@ __global__ __launch_bounds__(kThreads) void k_bfs_init(BfsArgs a, int32_t source
 __global__ __launch_bounds__(kThreads) void k_level_prep(BfsArgs a, int32_t L, int32_t forced) {
   Ctrl* c = a.ctrl;
   LevelTotals tot;
-  const LevelState st = level_state(a, L, forced, &tot);
-  publish_level(c, L, st, tot);
+  LevelState prev;
+  const LevelState st = level_state(a, L, forced, &tot, &prev);
+  publish_level(c, L, st, prev, tot);
   if (st.done) return;
   if (st.dir != 0) return;
   uint32_t* mf_out = &c->mf[L % kSlots];
@@ -533,7 +536,7 @@ __global__ __launch_bounds__(kThreads) void k_level_main(BfsArgs a, int32_t L) {
     p.nwords = a.nwords;
     p.colptr = a.colptr;
     p.rowind = a.rowind;
-    p.head = a.head;
+    p.slab = a.slab;
     p.x = a.reuse ? a.vis[st.vis_idx] : a.F[L % 2];  // operand reuse: A^T v .* not(v) (Section 5.4)
     p.mask = a.vis[st.vis_idx];
     p.complement = 1;
@@ -643,11 +646,14 @@ __global__ __launch_bounds__(kThreads) void k_nz_bits(const int32_t* ptr, int32_
 
 // First entry of every CSC column (-1 for an empty column): the pull's
 // first check reads it densely.
-__global__ __launch_bounds__(kThreads) void k_head(const int32_t* ptr, const int32_t* ind, int32_t V,
-                                                   int32_t* head) {
+__global__ __launch_bounds__(kThreads) void k_slab(const int32_t* ptr, const int32_t* ind, int32_t V,
+                                                   int4* slab) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < V; i += stride)
-    head[i] = ptr[i + 1] > ptr[i] ? ind[ptr[i]] : -1;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < V; i += stride) {
+    const int32_t b = ptr[i], d = ptr[i + 1] - b;
+    slab[i] = make_int4(d > 0 ? ind[b] : -1, d > 1 ? ind[b + 1] : -1, d > 2 ? ind[b + 2] : -1,
+                        d > 3 ? ind[b + 3] : -1);
+  }
 }
 
 // Copies the state after a batch and the batch's level records into pinned
@@ -757,10 +763,9 @@ hipError_t launch_nz_bits(hipStream_t s, const int32_t* ptr, int32_t V, uint32_t
   return hipGetLastError();
 }
 
-hipError_t launch_head(hipStream_t s, const int32_t* ptr, const int32_t* ind, int32_t V,
-                       int32_t* head) {
-  hipLaunchKernelGGL(k_head, dim3(grid_for(V, kThreads, 8192)), dim3(kThreads), 0, s, ptr, ind, V,
-                     head);
+hipError_t launch_slab(hipStream_t s, const int32_t* ptr, const int32_t* ind, int32_t V, int4* slab) {
+  hipLaunchKernelGGL(k_slab, dim3(grid_for(V, kThreads, 8192)), dim3(kThreads), 0, s, ptr, ind, V,
+                     slab);
   return hipGetLastError();
 }
 
