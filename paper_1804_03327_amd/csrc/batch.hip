@@ -224,14 +224,14 @@ __device__ void mb_expand_body(const BatchArgs& a, int32_t L, const LevelState& 
 
 // ----------------------------------------------------------------- pull
 struct MbPullShared {
-  uint16_t cand[kPullTileV];
+  uint16_t cand[kMbTileV];
   uint16_t lng[kMbLong];
   uint64_t lacc[kMbLong];
-  uint32_t nzf[kPullTileWords];
+  uint32_t nzf[kMbTileWords];
   int32_t ncand, nlong;
 };
 
-// Row-based product over one tile of 2048 rows: rows that a still-expanding
+// Row-based product over one tile of kMbTileV rows: rows that a still-expanding
 // source has not reached (the mask, Section 5.2) and that have in-neighbours
 // are listed; each ORs the visited words of its in-neighbours in stored order
 // and stops once every missing source bit is found (early exit, Section 5.3).
@@ -242,19 +242,19 @@ struct MbPullShared {
 __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st, int32_t tile,
                              MbPullShared& sh) {
   const int tid = threadIdx.x;
-  const int32_t w0 = tile * kPullTileWords;
+  const int32_t w0 = tile * kMbTileWords;
   const int32_t v0 = w0 * 32;
   const uint64_t* vin = a.vis[st.vis_idx];
   uint64_t* vout = a.vis[st.vis_idx ^ 1];
   uint64_t* Fn = a.F[(L + 1) % 2];
   const uint64_t active = st.active;  // a source with an empty frontier finds nothing more
-  if (tid < kPullTileWords) sh.nzf[tid] = 0;
+  if (tid < kMbTileWords) sh.nzf[tid] = 0;
   if (tid == 0) {
     sh.ncand = 0;
     sh.nlong = 0;
   }
   __syncthreads();
-  for (int r0 = 0; r0 < kPullTileV; r0 += kThreads) {
+  for (int r0 = 0; r0 < kMbTileV; r0 += kThreads) {
     const int r = r0 + tid;
     const int32_t v = v0 + r;
     bool cand = false;
@@ -368,7 +368,7 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
     }
   }
   __syncthreads();
-  if (tid < kPullTileWords && w0 + tid < a.nwords) a.nzF[w0 + tid] = sh.nzf[tid];
+  if (tid < kMbTileWords && w0 + tid < a.nwords) a.nzF[w0 + tid] = sh.nzf[tid];
   unsigned long long v4[4] = {nvert, nbits, checks, mnew};
   block_sum4(v4);
   unsigned long long i4[4] = {insub, 0, 0, 0};
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(kThreads) void k_mb_main(BatchArgs a, int32_t L) {
   if (st.dir == 0) {
     mb_expand_body(a, L, st, sh.e);
   } else {
-    const int32_t ntiles = (a.nwords + kPullTileWords - 1) / kPullTileWords;
+    const int32_t ntiles = (a.nwords + kMbTileWords - 1) / kMbTileWords;
     for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
       __syncthreads();  // LDS of the previous tile is no longer read
       mb_pull_body(a, L, st, t, sh.p);
@@ -489,7 +489,8 @@ hipError_t launch_mb_prep(hipStream_t s, const BatchArgs& a, int32_t level, int3
 }
 
 hipError_t launch_mb_main(hipStream_t s, const BatchArgs& a, int32_t level, hipEvent_t t0, hipEvent_t t1) {
-  const dim3 g(unsigned(std::max<int64_t>(kExpandBlocks, pull_tiles(a.nwords))));
+  const int64_t tiles = (int64_t(a.nwords) + kMbTileWords - 1) / kMbTileWords;
+  const dim3 g(unsigned(std::max<int64_t>(kExpandBlocks, tiles)));
   return launch_k(k_mb_main, g, s, t0, t1, a, level);
 }
 

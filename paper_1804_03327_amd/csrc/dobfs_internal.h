@@ -92,23 +92,14 @@ constexpr int kScanBlocksMax = 256;                  // scan grids stride over t
 constexpr int kExpandEPT = 4;                        // expand: edges per thread per chunk
 constexpr int kExpandChunk = kThreads * kExpandEPT; // 1024 edges per chunk
 constexpr int kExpandWin = kExpandChunk + 1;         // frontier entries cached in LDS per chunk
-#ifndef DOBFS_EXPAND_BUF
-#define DOBFS_EXPAND_BUF 2048
-#endif
-#ifndef DOBFS_PULL_MID
-#define DOBFS_PULL_MID 32
-#endif
-constexpr int kExpandBuf = DOBFS_EXPAND_BUF;          // winners buffered in LDS before a list flush
+constexpr int kExpandBuf = 2048;                     // winners buffered in LDS before a list flush
 constexpr int kExpandBlocks = 1024;                  // expand grid (strides over chunks)
 constexpr int kPullTileWords = 64;                   // pull: bitmap words owned by a block
 constexpr int kPullTileV = kPullTileWords * 32;      // 2048 rows per block
-constexpr int kSlab = 4;                              // in-neighbours per row kept in the dense slab
-constexpr int kPullFirst = kSlab;                     // pull phase 1 checks a row's slab entries
-constexpr int kPullMid = DOBFS_PULL_MID;              // rows still open continue thread-per-row up to here
-#ifndef DOBFS_PULL_STEP
-#define DOBFS_PULL_STEP 4
-#endif
-constexpr int kPullStep = DOBFS_PULL_STEP;            // in-neighbours a thread loads at once past kPullFirst
+constexpr int kSlab = 4;                             // in-neighbours per row kept in the dense slab
+constexpr int kPullFirst = kSlab;                    // pull phase 1 checks a row's slab entries
+constexpr int kPullMid = 32;                         // rows still open continue thread-per-row up to here
+constexpr int kPullStep = 4;                         // in-neighbours a thread loads at once past kPullFirst
 constexpr int kPullBatch = 4;                        // candidate rows a thread works on at once
 
 inline int32_t words_of(int64_t V) { return int32_t((V + 31) / 32); }
@@ -234,8 +225,10 @@ struct BatchArgs {
   int32_t src[kMaxSources];  // source of bit b
   int32_t uniq[kMaxSources]; // the distinct sources: the first frontier list
 };
-constexpr int kMbMid = 32;    // multi-source pull: in-neighbours a thread scans before a wave takes over
-constexpr int kMbLong = 512;  // multi-source pull: rows a tile can hand to its waves
+constexpr int kMbTileWords = 8;                 // multi-source pull: bitmap words of rows per block
+constexpr int kMbTileV = kMbTileWords * 32;     // 256 rows, one per thread: a tile's rows all run at once
+constexpr int kMbMid = 32;                      // multi-source pull: in-neighbours a thread scans before a wave takes over
+constexpr int kMbLong = kMbTileV;               // multi-source pull: rows a tile can hand to its waves
 
 struct ScanBitsArgs {
   const uint32_t* a;         // bits = a AND NOT b_not
