@@ -94,8 +94,9 @@ constexpr int kExpandChunk = kThreads * kExpandEPT; // 1024 edges per chunk
 constexpr int kExpandWin = kExpandChunk + 1;         // frontier entries cached in LDS per chunk
 constexpr int kExpandBuf = 2048;                     // winners buffered in LDS before a list flush
 constexpr int kExpandBlocks = 1024;                  // expand grid (strides over chunks)
-constexpr int kPullTileWords = 64;                   // pull: bitmap words owned by a block
-constexpr int kPullTileV = kPullTileWords * 32;      // 2048 rows per block
+constexpr int kPullTileWords = 128;                  // pull: bitmap words owned by a block (measured
+                                                     // best of 8..256 on RMAT-22: fewer, fuller blocks)
+constexpr int kPullTileV = kPullTileWords * 32;      // 4096 rows per block
 constexpr int kSlab = 4;                             // in-neighbours per row kept in the dense slab
 constexpr int kPullFirst = kSlab;                    // pull phase 1 checks a row's slab entries
 constexpr int kPullMid = 32;                         // rows still open continue thread-per-row up to here

@@ -169,14 +169,14 @@ struct PullShared {
 };
 
 // Row-based masked matvec (Algorithm 2) over CSC(A) for the rows of one
-// tile of 64 bitmap words (2048 rows): list the rows the mask lets through
+// tile of kPullTileWords bitmap words: list the rows the mask lets through
 // (output sparsity, Section 5.2) and check each row's in-neighbours in stored
 // order, stopping at the first hit (early exit, Section 5.3). Three phases
-// keep many loads in flight: the first kPullFirst in-neighbours of all of a
-// thread's rows, position by position (position 0 from the dense head array);
-// then rows still open, one per thread, kPullStep positions per load round,
-// up to kPullMid; then what is left, one row per wave, 64 in-neighbours per
-// step with the lowest hitting lane kept. Every phase scans positions in
+// keep many loads in flight: the slab (first kSlab in-neighbours, one 16-byte
+// read per row) of kPullBatch rows per thread at once; then rows still open,
+// one per thread, kPullStep positions per load round, up to kPullMid; then
+// what is left, one row per wave, 64 in-neighbours per step with the lowest
+// hitting lane kept. Every phase scans positions in
 // order and keeps the first hit, so the reported parent is always the first
 // in stored order. Results gather in LDS and the tile's words of the output
 // vector are written whole, so no atomics touch the output bitmap. `x` (the
@@ -189,22 +189,35 @@ __device__ void pull_body(const PullArgs& a, int32_t tile, PullShared& sh) {
   const int32_t v0 = w0 * 32;
   const uint32_t cflip = a.complement ? 0xffffffffu : 0u;
 
-  if (tid < 64) {  // wave 0 lists the candidate rows of the tile in order
-    const int32_t w = w0 + tid;
-    uint32_t cand = 0;
-    sh.found[tid] = 0;
-    if (w < a.nwords) {
-      const uint32_t pass = a.mask ? (a.mask[w] ^ cflip) : 0xffffffffu;
-      cand = (a.mask_after ? 0xffffffffu : pass) & a.nz[w] & valid_bits(w, a.V);
+  // wave 0 lists the candidate rows of the tile in order, each lane taking
+  // kWPL consecutive words
+  constexpr int kWPL = kPullTileWords > 64 ? kPullTileWords / 64 : 1;
+  static_assert(kPullTileWords <= 64 || kPullTileWords % 64 == 0, "whole words per lane");
+  if (tid < 64) {
+    uint32_t cw[kWPL];
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < kWPL; ++k) {
+      const int lw = tid * kWPL + k;  // word within the tile
+      const int32_t w = w0 + lw;
+      cw[k] = 0;
+      if (lw < kPullTileWords) sh.found[lw] = 0;
+      if (lw < kPullTileWords && w < a.nwords) {
+        const uint32_t pass = a.mask ? (a.mask[w] ^ cflip) : 0xffffffffu;
+        cw[k] = (a.mask_after ? 0xffffffffu : pass) & a.nz[w] & valid_bits(w, a.V);
+      }
+      c += __popc(cw[k]);
     }
-    const int c = __popc(cand);
     const int incl = wave_incl_scan(c);
     int pos = incl - c;
-    uint32_t bits = cand;
-    while (bits) {
-      const int b = __ffs(bits) - 1;
-      sh.cand[pos++] = uint16_t(tid * 32 + b);
-      bits &= bits - 1;
+#pragma unroll
+    for (int k = 0; k < kWPL; ++k) {
+      uint32_t bits = cw[k];
+      while (bits) {
+        const int b = __ffs(bits) - 1;
+        sh.cand[pos++] = uint16_t((tid * kWPL + k) * 32 + b);
+        bits &= bits - 1;
+      }
     }
     if (tid == 63) {
       sh.ncand = incl;
@@ -355,15 +368,15 @@ __device__ void pull_body(const PullArgs& a, int32_t tile, PullShared& sh) {
   __syncthreads();
 
   unsigned long long nfound = 0, nout = 0;
-  if (tid < kPullTileWords) {
-    const int32_t w = w0 + tid;
+  for (int lw = tid; lw < kPullTileWords; lw += kThreads) {
+    const int32_t w = w0 + lw;
     if (w < a.nwords) {
-      const uint32_t f = sh.found[tid];
+      const uint32_t f = sh.found[lw];
       const uint32_t o = ((a.out_base ? a.out_base[w] : 0u) | f) & valid_bits(w, a.V);
       a.out[w] = o;
       if (a.found_out) a.found_out[w] = f;
-      nfound = __popc(f);
-      nout = a.count_out ? __popc(o) : 0;
+      nfound += __popc(f);
+      nout += a.count_out ? __popc(o) : 0;
     }
   }
   unsigned long long v[4] = {nfound, nout, checks, insub};
