@@ -49,7 +49,8 @@ typedef enum {
   DOBFS_ERR_DEVICE = 3,              /* a HIP call failed (no GPU, launch error ...) */
   DOBFS_ERR_WORKSPACE_TOO_SMALL = 4, /* ws_bytes below the *_workspace_bytes figure */
   DOBFS_ERR_UNSUPPORTED = 5,         /* option combination not implemented */
-  DOBFS_ERR_INTERNAL = 6
+  DOBFS_ERR_INTERNAL = 6,
+  DOBFS_ERR_TIMEOUT = 7              /* dobfs_server_wait: the query was not done in time */
 } dobfs_status;
 
 typedef struct dobfs_graph_s *dobfs_graph;
@@ -234,6 +235,67 @@ dobfs_status dobfs_bfs_batch_workspace_bytes(dobfs_graph g, int32_t k, size_t *b
 dobfs_status dobfs_bfs_batch(dobfs_graph g, const int32_t *sources, int32_t k,
                              const dobfs_options *opt, int32_t *depth, void *workspace,
                              size_t ws_bytes, void *stream, dobfs_stats *stats);
+
+/* --------------------------------------------------------------- serving */
+
+/*
+ * A query server over device-resident graphs: single-source BFS queries
+ * arrive one at a time (dobfs_server_submit) and are answered by
+ * multi-source traversals (dobfs_bfs_batch semantics) that take up to
+ * max_batch queued queries of one graph at once, the graph whose oldest
+ * query has waited longest first. `slots` batches run at the same time,
+ * each on a host thread and HIP stream of its own, so queries that arrive
+ * while a batch is on the GPU are admitted into the next free slot and run
+ * beside it (continuous batching, not a single queue). A batch starts only
+ * when the device bytes of its workspace fit, together with the batches
+ * already running, in mem_budget (admission by memory); a batch is cut
+ * down to the number of sources that fits. Each query's depths are those
+ * dobfs_bfs returns for its source (the server runs no other arithmetic).
+ * The server owns its workspaces and streams; graphs stay owned by the
+ * caller and must outlive the server. Thread-safe: any thread may submit
+ * and wait.
+ */
+typedef struct dobfs_server_s *dobfs_server;
+
+typedef struct {
+  int32_t slots;      /* batches in flight at once, 1..16 (default 2) */
+  int32_t max_batch;  /* sources per batch, 1..64 (default 64) */
+  size_t mem_budget;  /* device bytes all running batches' workspaces may take together;
+                         0 = slots x the largest batch workspace (default 0) */
+  dobfs_options opt;  /* traversal options of every batch: modes FULL, PUSH_ONLY, PULL_ONLY */
+} dobfs_server_options;
+
+typedef struct {
+  int32_t graph, source;
+  int32_t batch_size;   /* queries answered by the same traversal */
+  int32_t status;       /* dobfs_status of the traversal */
+  double t_submit_ms;   /* steady-clock times in ms since the server was created */
+  double t_start_ms;    /* the batch was admitted and launched */
+  double t_done_ms;     /* depth is final in device memory */
+} dobfs_query_info;
+
+/* Defaults: 2 slots, batches of up to 64, no budget beyond the slots, default BFS options. */
+dobfs_status dobfs_server_options_default(dobfs_server_options *opt);
+
+/* graphs: host array of n_graphs handles on one device (copied). Allocates
+ * one workspace and stream per slot. Errors: INVALID_ARG, OUT_OF_MEMORY,
+ * DEVICE, UNSUPPORTED (options). */
+dobfs_status dobfs_server_create(const dobfs_graph *graphs, int32_t n_graphs,
+                                 const dobfs_server_options *opt, dobfs_server *out);
+
+/* Queue a BFS from `source` on graphs[graph]; `depth` (device int32[V] of that
+ * graph, caller-owned) receives the result and must stay valid until the
+ * query is done. *id identifies the query. Never blocks on the GPU. */
+dobfs_status dobfs_server_submit(dobfs_server s, int32_t graph, int32_t source, int32_t *depth,
+                                 uint64_t *id);
+
+/* Wait up to timeout_ms (< 0: no limit) for query `id`; DOBFS_ERR_TIMEOUT if
+ * it is still queued or running. On return *info (optional) describes it;
+ * the call returns the traversal's status once done. */
+dobfs_status dobfs_server_wait(dobfs_server s, uint64_t id, int32_t timeout_ms, dobfs_query_info *info);
+
+/* Answers every query already submitted, then frees the server. */
+dobfs_status dobfs_server_destroy(dobfs_server s);
 
 /* -------------------------------------------------------- standalone mxv */
 

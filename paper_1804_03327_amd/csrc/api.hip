@@ -422,6 +422,7 @@ const char* dobfs_status_string(dobfs_status s) {
     case DOBFS_ERR_WORKSPACE_TOO_SMALL: return "DOBFS_ERR_WORKSPACE_TOO_SMALL";
     case DOBFS_ERR_UNSUPPORTED: return "DOBFS_ERR_UNSUPPORTED";
     case DOBFS_ERR_INTERNAL: return "DOBFS_ERR_INTERNAL";
+    case DOBFS_ERR_TIMEOUT: return "DOBFS_ERR_TIMEOUT";
   }
   return "DOBFS_ERR_UNKNOWN";
 }
@@ -675,6 +676,20 @@ dobfs_status dobfs_bfs_batch(dobfs_graph g, const int32_t* sources, int32_t k,
   t_last_error.clear();
   if (!g) return fail(DOBFS_ERR_INVALID_ARG, "graph is NULL");
   if (!depth) return fail(DOBFS_ERR_INVALID_ARG, "depth is NULL");
+  if (k < 1 || k > kMaxSources) return fail(DOBFS_ERR_INVALID_ARG, "k = %d not in [1, 64]", k);
+  DepthRows rows{};
+  for (int32_t b = 0; b < k; ++b) rows.row[b] = depth + int64_t(b) * g->V;
+  return bfs_batch_rows(g, sources, k, opt_in, rows, workspace, ws_bytes, stream, stats);
+}
+
+}  // extern "C"
+
+// The multi-source traversal with each source's depth row at its own
+// address (dobfs_bfs_batch lays them out contiguously; the server writes
+// them straight into the callers' buffers).
+dobfs_status dobfs::bfs_batch_rows(dobfs_graph g, const int32_t* sources, int32_t k, const dobfs_options* opt_in,
+                            const DepthRows& rows, void* workspace, size_t ws_bytes, void* stream,
+                            dobfs_stats* stats) {
   if (!sources) return fail(DOBFS_ERR_INVALID_ARG, "sources is NULL");
   if (k < 1 || k > kMaxSources) return fail(DOBFS_ERR_INVALID_ARG, "k = %d not in [1, 64]", k);
   for (int32_t b = 0; b < k; ++b)
@@ -755,7 +770,7 @@ dobfs_status dobfs_bfs_batch(dobfs_graph g, const int32_t* sources, int32_t k,
       [&](int32_t l, hipEvent_t t0, hipEvent_t t1) { return launch_mb_main(s, a, l, t0, t1); }, a.ctrl, cap,
       cap < int64_t(g->V) + 2 ? DOBFS_ERR_UNSUPPORTED : DOBFS_ERR_INTERNAL, stats, &res);
   if (st != DOBFS_OK) return st;
-  HIPCK(launch_mb_depth(s, a, a.vis[res.end.vis_idx], depth));
+  HIPCK(launch_mb_depth(s, a, a.vis[res.end.vis_idx], rows));
   HIPCK(hipEventRecord(ev[kEvEnd], s));
   HIPCK(hipEventSynchronize(ev[kEvEnd]));
   if (stats) {
@@ -766,6 +781,18 @@ dobfs_status dobfs_bfs_batch(dobfs_graph g, const int32_t* sources, int32_t k,
   }
   return DOBFS_OK;
 }
+
+dobfs_status dobfs::set_error(dobfs_status s, const char* what) { return fail(s, "%s", what); }
+
+dobfs_status dobfs::check_batch_options(const dobfs_options& opt) {
+  dobfs_status st = check_options(opt);
+  if (st != DOBFS_OK) return st;
+  if (opt.mode != DOBFS_MODE_FULL && opt.mode != DOBFS_MODE_PUSH_ONLY && opt.mode != DOBFS_MODE_PULL_ONLY)
+    return fail(DOBFS_ERR_UNSUPPORTED, "multi-source BFS runs modes FULL, PUSH_ONLY and PULL_ONLY");
+  return DOBFS_OK;
+}
+
+extern "C" {
 
 dobfs_status dobfs_mxv(dobfs_graph g, const uint32_t* x_bits, const int32_t* x_idx,
                        int32_t x_nnz, const uint32_t* mask_bits, int32_t complement,

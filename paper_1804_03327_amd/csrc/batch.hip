@@ -451,11 +451,11 @@ __global__ __launch_bounds__(kThreads) void k_mb_main(BatchArgs a, int32_t L) {
   }
 }
 
-// depth[b][v] = level at which source b reached v, or -1: 64 vertices per
-// block step, read as whole [v][k] rows and written as coalesced runs of
-// each depth row.
+// rows.row[b][v] = level at which source b reached v, or -1: 64 vertices per
+// block step, read as whole [v][k] rows of the level table and written as
+// coalesced runs of each depth row.
 constexpr int kMbDepthV = 64;
-__global__ __launch_bounds__(kThreads) void k_mb_depth(BatchArgs a, const uint64_t* vis, int32_t* depth) {
+__global__ __launch_bounds__(kThreads) void k_mb_depth(BatchArgs a, const uint64_t* vis, DepthRows rows) {
   __shared__ uint16_t s_l[kMbDepthV * kMaxSources];
   __shared__ uint64_t s_v[kMbDepthV];
   const int32_t k = a.k;
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(kThreads) void k_mb_depth(BatchArgs a, const uint64
     __syncthreads();
     for (int32_t i = threadIdx.x; i < nv * k; i += kThreads) {
       const int32_t b = i / nv, j = i - b * nv;
-      depth[int64_t(b) * a.V + v0 + j] = ((s_v[j] >> b) & 1ull) ? int32_t(s_l[j * k + b]) : -1;
+      rows.row[b][v0 + j] = ((s_v[j] >> b) & 1ull) ? int32_t(s_l[j * k + b]) : -1;
     }
   }
 }
@@ -494,10 +494,10 @@ hipError_t launch_mb_main(hipStream_t s, const BatchArgs& a, int32_t level, hipE
   return launch_k(k_mb_main, g, s, t0, t1, a, level);
 }
 
-hipError_t launch_mb_depth(hipStream_t s, const BatchArgs& a, const uint64_t* vis, int32_t* depth) {
+hipError_t launch_mb_depth(hipStream_t s, const BatchArgs& a, const uint64_t* vis, const DepthRows& rows) {
   const int64_t nblk = (int64_t(a.V) + kMbDepthV - 1) / kMbDepthV;
   const unsigned g = unsigned(std::min<int64_t>(nblk, 4096));
-  hipLaunchKernelGGL(k_mb_depth, dim3(g > 0 ? g : 1), dim3(kThreads), 0, s, a, vis, depth);
+  hipLaunchKernelGGL(k_mb_depth, dim3(g > 0 ? g : 1), dim3(kThreads), 0, s, a, vis, rows);
   return hipGetLastError();
 }
 

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "dobfs.h"
+
 #include <cstddef>
 #include <cstdint>
 
@@ -286,11 +288,25 @@ hipError_t launch_mb_prep(hipStream_t s, const BatchArgs& a, int32_t level, int3
                          hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_mb_main(hipStream_t s, const BatchArgs& a, int32_t level, hipEvent_t t0 = nullptr,
                          hipEvent_t t1 = nullptr);
-hipError_t launch_mb_depth(hipStream_t s, const BatchArgs& a, const uint64_t* vis, int32_t* depth);
+// Destination of each source's depth row (int32[V], device).
+struct DepthRows {
+  int32_t* row[kMaxSources];
+};
+hipError_t launch_mb_depth(hipStream_t s, const BatchArgs& a, const uint64_t* vis, const DepthRows& rows);
 hipError_t launch_check_offsets(hipStream_t s, const int32_t* ptr, int32_t V, int64_t nnz,
                                 int32_t* err);
 hipError_t launch_check_indices(hipStream_t s, const int32_t* idx, int64_t nnz, int32_t V,
                                 int32_t* err);
+
+// ---- host runtime entry points shared between api.hip and serve.hip ----
+// Multi-source traversal writing source b's depths to rows.row[b].
+dobfs_status bfs_batch_rows(dobfs_graph g, const int32_t* sources, int32_t k, const dobfs_options* opt,
+                            const DepthRows& rows, void* workspace, size_t ws_bytes, void* stream,
+                            dobfs_stats* stats);
+// Options a multi-source traversal accepts (sets the thread's last error otherwise).
+dobfs_status check_batch_options(const dobfs_options& opt);
+// Records `what` as the calling thread's last error and returns s.
+dobfs_status set_error(dobfs_status s, const char* what);
 
 // Direction rule of Section 6.3 (and Beamer's edge form); identical on host and device.
 __host__ __device__ inline int32_t next_direction_rule(int32_t heuristic, double alpha, double beta,

@@ -1,0 +1,295 @@
+// Query server of libdobfs (declared in include/dobfs.h): single-source BFS
+// queries are answered by multi-source traversals that run several at a time.
+//
+// Each slot is a host thread with its own HIP stream and workspace. A free
+// slot takes the graph whose oldest queued query has waited longest, takes
+// up to max_batch queued queries of that graph in arrival order, waits until
+// its workspace bytes fit in the memory budget beside the batches already
+// running, and runs them as one multi-source traversal whose depth rows are
+// written straight into the callers' buffers. Queries that arrive while a
+// batch is on the GPU go to the next free slot, so their traversal overlaps
+// the running one on the device.
+
+#include "dobfs.h"
+#include "dobfs_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+using namespace dobfs;
+
+namespace {
+
+constexpr int kMaxSlots = 16;
+
+struct Query {
+  int32_t graph = 0, source = 0;
+  int32_t* depth = nullptr;
+  int32_t batch_size = 0;
+  int32_t status = DOBFS_OK;
+  bool done = false;
+  double t_submit = 0, t_start = 0, t_done = 0;
+};
+
+struct GraphInfo {
+  int32_t V = 0;
+  int64_t nnz = 0;
+};
+
+}  // namespace
+
+struct dobfs_server_s {
+  dobfs_server_options opt{};
+  std::vector<dobfs_graph> graphs;
+  std::vector<GraphInfo> info;
+  int device = 0;
+  size_t budget = 0, in_use = 0;
+  std::chrono::steady_clock::time_point t0;
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_mem, cv_done;
+  std::deque<Query> queries;       // every query, indexed by id
+  std::deque<uint64_t> pending;    // ids not yet taken, in arrival order
+  bool stop = false;
+
+  std::vector<std::thread> workers;
+  std::vector<hipStream_t> streams;
+  std::vector<void*> ws;
+  size_t ws_bytes = 0;
+
+  double now_ms() const {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+namespace {
+
+size_t batch_bytes(dobfs_graph g, int32_t k) {
+  size_t b = 0;
+  if (dobfs_bfs_batch_workspace_bytes(g, k, &b) != DOBFS_OK) return SIZE_MAX;
+  return b;
+}
+
+void worker(dobfs_server s, int slot) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty(); });
+    if (s->pending.empty()) break;  // stopping and nothing left
+    // the graph whose oldest query has waited longest, and up to max_batch of its queries
+    const int32_t gi = s->queries[s->pending.front()].graph;
+    std::vector<uint64_t> take;
+    for (auto it = s->pending.begin(); it != s->pending.end() && int32_t(take.size()) < s->opt.max_batch;) {
+      if (s->queries[*it].graph == gi) {
+        take.push_back(*it);
+        it = s->pending.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    // admission by memory: the batch's workspace must fit beside the running ones
+    int32_t k = int32_t(take.size());
+    while (k > 1 && batch_bytes(s->graphs[gi], k) > s->budget) --k;
+    for (size_t q = take.size(); q > size_t(k); --q) s->pending.push_front(take[q - 1]);  // back to the head, in order
+    take.resize(size_t(k));
+    const size_t need = batch_bytes(s->graphs[gi], k);
+    if (need > s->budget) {  // not even one source fits
+      const double t = s->now_ms();
+      for (uint64_t id : take) {
+        Query& q = s->queries[id];
+        q.status = DOBFS_ERR_OUT_OF_MEMORY;
+        q.batch_size = k;
+        q.t_start = q.t_done = t;
+        q.done = true;
+      }
+      s->cv_done.notify_all();
+      continue;
+    }
+    s->cv_mem.wait(lk, [&] { return s->in_use + need <= s->budget; });
+    s->in_use += need;
+    std::vector<int32_t> src(static_cast<size_t>(k));
+    DepthRows rows{};
+    const double t_start = s->now_ms();
+    for (int32_t b = 0; b < k; ++b) {
+      Query& q = s->queries[take[size_t(b)]];
+      src[size_t(b)] = q.source;
+      rows.row[b] = q.depth;
+      q.t_start = t_start;
+    }
+    lk.unlock();
+    const dobfs_status st = bfs_batch_rows(s->graphs[gi], src.data(), k, &s->opt.opt, rows,
+                                           s->ws[size_t(slot)], s->ws_bytes, s->streams[size_t(slot)],
+                                           nullptr);  // returns once the depth rows are final
+    lk.lock();
+    s->in_use -= need;
+    const double t_done = s->now_ms();
+    for (uint64_t id : take) {
+      Query& q = s->queries[id];
+      q.status = st;
+      q.batch_size = k;
+      q.t_done = t_done;
+      q.done = true;
+    }
+    s->cv_mem.notify_all();
+    s->cv_done.notify_all();
+    if (!s->pending.empty()) s->cv_work.notify_one();
+  }
+}
+
+void release(dobfs_server s) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  for (auto& t : s->workers)
+    if (t.joinable()) t.join();
+  (void)hipSetDevice(s->device);
+  for (hipStream_t st : s->streams)
+    if (st) (void)hipStreamDestroy(st);
+  for (void* p : s->ws)
+    if (p) (void)hipFree(p);
+  delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+dobfs_status dobfs_server_options_default(dobfs_server_options* o) {
+  if (!o) return set_error(DOBFS_ERR_INVALID_ARG, "options pointer is NULL");
+  *o = dobfs_server_options{};
+  o->slots = 2;
+  o->max_batch = 64;
+  o->mem_budget = 0;
+  return dobfs_options_default(&o->opt);
+}
+
+dobfs_status dobfs_server_create(const dobfs_graph* graphs, int32_t n_graphs, const dobfs_server_options* opt,
+                                 dobfs_server* out) {
+  if (!out) return set_error(DOBFS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!graphs || n_graphs < 1) return set_error(DOBFS_ERR_INVALID_ARG, "need at least one graph");
+  dobfs_server_options o;
+  if (opt) {
+    o = *opt;
+  } else {
+    dobfs_server_options_default(&o);
+  }
+  if (o.slots < 1 || o.slots > kMaxSlots) return set_error(DOBFS_ERR_INVALID_ARG, "slots must be in [1, 16]");
+  if (o.max_batch < 1 || o.max_batch > kMaxSources)
+    return set_error(DOBFS_ERR_INVALID_ARG, "max_batch must be in [1, 64]");
+  dobfs_status st = check_batch_options(o.opt);
+  if (st != DOBFS_OK) return st;
+  if (o.opt.n_forced > 0) return set_error(DOBFS_ERR_UNSUPPORTED, "forced directions are per traversal, not per server");
+
+  auto s = new dobfs_server_s();
+  s->opt = o;
+  s->t0 = std::chrono::steady_clock::now();
+  size_t largest = 0;
+  for (int32_t i = 0; i < n_graphs; ++i) {
+    GraphInfo gi;
+    int32_t dev = -1;
+    if (!graphs[i] || dobfs_graph_info(graphs[i], &gi.V, &gi.nnz, &dev) != DOBFS_OK) {
+      delete s;
+      return set_error(DOBFS_ERR_INVALID_ARG, "a graph handle is NULL or invalid");
+    }
+    if (i == 0) s->device = dev;
+    if (dev != s->device) {
+      delete s;
+      return set_error(DOBFS_ERR_INVALID_ARG, "all graphs of a server must be on one device");
+    }
+    s->graphs.push_back(graphs[i]);
+    s->info.push_back(gi);
+    largest = std::max(largest, batch_bytes(graphs[i], o.max_batch));
+  }
+  s->ws_bytes = largest;
+  s->budget = o.mem_budget ? o.mem_budget : largest * size_t(o.slots);
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  if (hipSetDevice(s->device) != hipSuccess) {
+    delete s;
+    return set_error(DOBFS_ERR_DEVICE, "hipSetDevice failed");
+  }
+  for (int k = 0; k < o.slots; ++k) {
+    hipStream_t stream = nullptr;
+    void* p = nullptr;
+    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) {
+      release(s);
+      if (prev >= 0) (void)hipSetDevice(prev);
+      return set_error(DOBFS_ERR_DEVICE, "hipStreamCreateWithFlags failed");
+    }
+    s->streams.push_back(stream);
+    if (hipMalloc(&p, largest) != hipSuccess) {
+      release(s);
+      if (prev >= 0) (void)hipSetDevice(prev);
+      return set_error(DOBFS_ERR_OUT_OF_MEMORY, "server workspace allocation failed");
+    }
+    s->ws.push_back(p);
+  }
+  if (prev >= 0) (void)hipSetDevice(prev);
+  for (int k = 0; k < o.slots; ++k) s->workers.emplace_back(worker, s, k);
+  *out = s;
+  return DOBFS_OK;
+}
+
+dobfs_status dobfs_server_submit(dobfs_server s, int32_t graph, int32_t source, int32_t* depth, uint64_t* id) {
+  if (!s || !id || !depth) return set_error(DOBFS_ERR_INVALID_ARG, "server, depth or id is NULL");
+  if (graph < 0 || graph >= int32_t(s->graphs.size()))
+    return set_error(DOBFS_ERR_INVALID_ARG, "graph index out of range");
+  if (source < 0 || source >= s->info[size_t(graph)].V)
+    return set_error(DOBFS_ERR_INVALID_ARG, "source out of range");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return set_error(DOBFS_ERR_INVALID_ARG, "server is shutting down");
+    Query q;
+    q.graph = graph;
+    q.source = source;
+    q.depth = depth;
+    q.t_submit = s->now_ms();
+    *id = uint64_t(s->queries.size());
+    s->queries.push_back(q);
+    s->pending.push_back(*id);
+  }
+  s->cv_work.notify_one();
+  return DOBFS_OK;
+}
+
+dobfs_status dobfs_server_wait(dobfs_server s, uint64_t id, int32_t timeout_ms, dobfs_query_info* info) {
+  if (!s) return set_error(DOBFS_ERR_INVALID_ARG, "server is NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (id >= s->queries.size()) return set_error(DOBFS_ERR_INVALID_ARG, "unknown query id");
+  auto ready = [&] { return s->queries[id].done; };
+  if (timeout_ms < 0) {
+    s->cv_done.wait(lk, ready);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready)) {
+    return set_error(DOBFS_ERR_TIMEOUT, "query not done yet");
+  }
+  const Query& q = s->queries[id];
+  if (info) {
+    info->graph = q.graph;
+    info->source = q.source;
+    info->batch_size = q.batch_size;
+    info->status = q.status;
+    info->t_submit_ms = q.t_submit;
+    info->t_start_ms = q.t_start;
+    info->t_done_ms = q.t_done;
+  }
+  if (q.status != DOBFS_OK) return set_error(dobfs_status(q.status), "the query's traversal failed");
+  return DOBFS_OK;
+}
+
+dobfs_status dobfs_server_destroy(dobfs_server s) {
+  if (!s) return set_error(DOBFS_ERR_INVALID_ARG, "server is NULL");
+  release(s);
+  return DOBFS_OK;
+}
+
+}  // extern "C"

@@ -16,7 +16,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "dobfs.h")
 
 # status codes
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_WORKSPACE_TOO_SMALL, ERR_UNSUPPORTED, \
-    ERR_INTERNAL = range(7)
+    ERR_INTERNAL, ERR_TIMEOUT = range(8)
 UPLOAD_VALIDATE = 1
 DIR_PUSH, DIR_PULL = 0, 1
 MODE_FULL, MODE_PUSH_ONLY, MODE_PULL_UNMASKED, MODE_PULL_MASKED, MODE_PULL_MASKED_EE, \
@@ -46,6 +46,18 @@ class Stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("cap", ctypes.c_int32),
                 ("level", ctypes.POINTER(LevelStats)), ("ms_total", ctypes.c_float),
                 ("ms_init", ctypes.c_float), ("reached", ctypes.c_int64)]
+
+
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("mem_budget", ctypes.c_size_t), ("opt", Options)]
+
+
+class QueryInfo(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_int32), ("source", ctypes.c_int32),
+                ("batch_size", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("t_submit_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double),
+                ("t_done_ms", ctypes.c_double)]
 
 
 class DobfsError(RuntimeError):
@@ -89,6 +101,12 @@ def load():
         "dobfs_mxv_workspace_bytes": (i32, [vp, ctypes.POINTER(sz)]),
         "dobfs_mxv": (i32, [vp, vp, vp, i32, vp, i32, i32, u32, vp, vp, vp, ctypes.POINTER(i32), vp,
                             sz, vp]),
+        "dobfs_server_options_default": (i32, [ctypes.POINTER(ServerOptions)]),
+        "dobfs_server_create": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(ServerOptions),
+                                      ctypes.POINTER(vp)]),
+        "dobfs_server_submit": (i32, [vp, i32, i32, vp, ctypes.POINTER(ctypes.c_uint64)]),
+        "dobfs_server_wait": (i32, [vp, ctypes.c_uint64, i32, ctypes.POINTER(QueryInfo)]),
+        "dobfs_server_destroy": (i32, [vp]),
         "dobfs_status_string": (ctypes.c_char_p, [i32]),
         "dobfs_last_error": (ctypes.c_char_p, []),
         "dobfs_version": (i32, []),
@@ -294,6 +312,57 @@ def bfs_batch(g: Graph, sources, depth, opt=None, workspace=None, ws_bytes=None,
                                nbytes, _stream(stream, g.device),
                                ctypes.byref(stats) if stats is not None else None))
     return stats
+
+
+class Server:
+    """Handle of a query server (dobfs_server) over device-resident graphs; destroyed by close()
+    or on garbage collection. Keeps the graphs and every submitted depth buffer alive until the
+    server is gone."""
+
+    def __init__(self, graphs, slots=2, max_batch=64, mem_budget=0, opt=None):
+        lib = load()
+        so = ServerOptions()
+        _check(lib.dobfs_server_options_default(ctypes.byref(so)))
+        so.slots, so.max_batch, so.mem_budget = int(slots), int(max_batch), int(mem_budget)
+        if opt is not None:
+            so.opt = opt
+        self.graphs = list(graphs)
+        arr = (ctypes.c_void_p * len(self.graphs))(*[g.handle for g in self.graphs])
+        h = ctypes.c_void_p()
+        _check(lib.dobfs_server_create(arr, len(self.graphs), ctypes.byref(so), ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, graph: int, source: int, depth) -> int:
+        """Queue a BFS; depth is an int32 CUDA tensor of the graph's V elements."""
+        import torch
+        g = self.graphs[graph] if 0 <= graph < len(self.graphs) else self.graphs[0]
+        d = _dptr(depth, torch.int32, g.V, "depth")
+        qid = ctypes.c_uint64()
+        _check(load().dobfs_server_submit(self.handle, int(graph), int(source), d, ctypes.byref(qid)))
+        self._keep[qid.value] = depth
+        return qid.value
+
+    def wait(self, qid: int, timeout_ms: int = -1) -> dict:
+        """Block until query qid is done (DobfsError with ERR_TIMEOUT past timeout_ms)."""
+        info = QueryInfo()
+        _check(load().dobfs_server_wait(self.handle, int(qid), int(timeout_ms), ctypes.byref(info)))
+        self._keep.pop(int(qid), None)
+        return dict(graph=info.graph, source=info.source, batch_size=info.batch_size,
+                    status=info.status, t_submit_ms=info.t_submit_ms, t_start_ms=info.t_start_ms,
+                    t_done_ms=info.t_done_ms)
+
+    def close(self):
+        if self.handle:
+            _check(load().dobfs_server_destroy(self.handle))
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def mxv(g: Graph, y_bits, x_bits=None, x_idx=None, x_nnz=None, mask_bits=None, complement=False,

@@ -1,0 +1,156 @@
+"""GPU tests of the query server (dobfs_server_*), through the C ABI.
+
+Each query's depths must be the same whether it runs alone (dobfs_bfs) or inside the
+server's mix of batches, and equal the oracle's; batches must really form and overlap on
+the device; the memory budget must bound the batches in flight and their width."""
+import random
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1804_03327_amd import dobfs  # noqa: E402
+from paper_1804_03327_amd.helpers import BfsRunner, upload  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    rng = np.random.default_rng(9)
+    V = 50_021
+    src = rng.integers(0, V, 6 * V)
+    dst = (src + rng.zipf(1.7, 6 * V)) % V
+    hgs = [gen.rmat(10, 16, seed=1), gen.rmat(14, 16, seed=1), gen.grid2d(61, 53),
+           gen.from_edges(V, src, dst, directed=True, name="directed50021")]
+    out = []
+    for hg in hgs:
+        _say("upload", hg.name, hg.V, hg.nnz)
+        out.append((hg, upload(hg)))
+    return out
+
+
+def _alone(g, source):
+    r = BfsRunner(g, with_parent=False)
+    r.run(source)
+    return r.result()[0]
+
+
+def _batches(infos):
+    """Group query infos into batches: same graph, start and end time."""
+    b = {}
+    for i in infos:
+        b.setdefault((i["graph"], i["t_start_ms"], i["t_done_ms"]), []).append(i)
+    return b
+
+
+def test_server_mix_equals_alone(graphs):
+    rnd = random.Random(4)
+    srv = dobfs.Server([g for _, g in graphs], slots=2, max_batch=64)
+    queries = []
+    for n in range(400):
+        gi = rnd.randrange(len(graphs))
+        hg, g = graphs[gi]
+        s = int(gen.sample_sources(hg, 1, seed=1000 + n)[0])
+        depth = torch.full((g.V,), -7, dtype=torch.int32, device="cuda")
+        queries.append((gi, s, depth, srv.submit(gi, s, depth)))
+        if rnd.random() < 0.3:
+            time.sleep(rnd.expovariate(1 / 0.002))  # bursts with pauses of ~2 ms on average
+    infos = [srv.wait(q[3]) for q in queries]
+    srv.close()
+    assert all(i["status"] == dobfs.OK for i in infos)
+    for (gi, s, depth, _), info in zip(queries, infos):
+        assert (info["graph"], info["source"]) == (gi, s)
+        assert info["t_submit_ms"] <= info["t_start_ms"] <= info["t_done_ms"]
+    # each result equals the same query run alone, and the oracle on a sample
+    torch.cuda.synchronize()
+    for k, (gi, s, depth, _) in enumerate(queries):
+        hg, g = graphs[gi]
+        d = depth.cpu().numpy()
+        assert np.array_equal(d, _alone(g, s)), "query %d (graph %s, source %d) differs from alone" % (k, hg.name, s)
+        if k % 20 == 0:
+            assert np.array_equal(d, oracle.bfs(hg, s)[0]), "query %d differs from the oracle" % k
+    # batching happened, and batches ran side by side on the device
+    b = _batches(infos)
+    assert max(len(v) for v in b.values()) > 1, "no query shared a traversal"
+    spans = sorted((k[1], k[2]) for k in b)
+    overlap = any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
+    _say("batches", len(b), "largest", max(len(v) for v in b.values()), "overlap", overlap)
+    assert overlap, "no two batches were in flight at once"
+
+
+def test_server_memory_budget(graphs):
+    hg, g = graphs[1]
+    need8 = dobfs.bfs_batch_workspace_bytes(g, 8)
+    # room for one 8-source batch: batches are cut to 8 and run one at a time
+    srv = dobfs.Server([g], slots=3, max_batch=64, mem_budget=need8)
+    qs = []
+    for n in range(120):
+        s = int(gen.sample_sources(hg, 1, seed=2000 + n)[0])
+        depth = torch.full((g.V,), -7, dtype=torch.int32, device="cuda")
+        qs.append((s, depth, srv.submit(0, s, depth)))
+    infos = [srv.wait(q[2]) for q in qs]
+    srv.close()
+    b = _batches(infos)
+    assert max(len(v) for v in b.values()) <= 8
+    spans = sorted((k[1], k[2]) for k in b)
+    assert all(spans[i + 1][0] >= spans[i][1] for i in range(len(spans) - 1)), "batches overlapped"
+    for s, depth, _ in qs:
+        assert np.array_equal(depth.cpu().numpy(), _alone(g, s))
+
+
+def test_server_budget_below_one_source(graphs):
+    hg, g = graphs[1]
+    srv = dobfs.Server([g], slots=1, mem_budget=1024)
+    depth = torch.zeros(g.V, dtype=torch.int32, device="cuda")
+    qid = srv.submit(0, 0, depth)
+    with pytest.raises(dobfs.DobfsError) as e:
+        srv.wait(qid)
+    assert e.value.status == dobfs.ERR_OUT_OF_MEMORY
+    srv.close()
+
+
+def test_server_destroy_answers_queued(graphs):
+    hg, g = graphs[0]
+    srv = dobfs.Server([g], slots=1, max_batch=4)
+    qs = []
+    for s in range(0, 200, 7):
+        depth = torch.full((g.V,), -7, dtype=torch.int32, device="cuda")
+        qs.append((s, depth, srv.submit(0, s, depth)))
+    srv.close()  # returns after every submitted query is answered
+    for s, depth, _ in qs:
+        assert np.array_equal(depth.cpu().numpy(), _alone(g, s))
+
+
+def test_server_errors(graphs):
+    hg, g = graphs[0]
+    srv = dobfs.Server([g])
+    depth = torch.zeros(g.V, dtype=torch.int32, device="cuda")
+    for gi, s in ((1, 0), (-1, 0), (0, g.V), (0, -1)):
+        with pytest.raises(dobfs.DobfsError) as e:
+            srv.submit(gi, s, depth)
+        assert e.value.status == dobfs.ERR_INVALID_ARG
+    with pytest.raises(dobfs.DobfsError) as e:
+        srv.wait(12345)
+    assert e.value.status == dobfs.ERR_INVALID_ARG
+    srv.close()
+    with pytest.raises(dobfs.DobfsError):
+        dobfs.Server([g], slots=0)
+    with pytest.raises(dobfs.DobfsError):
+        dobfs.Server([g], max_batch=65)
+    with pytest.raises(dobfs.DobfsError) as e:
+        dobfs.Server([g], opt=dobfs.make_options("pull_masked"))
+    assert e.value.status == dobfs.ERR_UNSUPPORTED
