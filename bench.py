@@ -8,8 +8,10 @@ paper-convention figure (nnz(A) / time) is reported beside it. Prints one JSON l
 Also reported: the HBM roofline of the dominant kernel (algorithmic bytes per launch over its
 average execution time, from each kernel's own start/end events in a repeat of the timed
 steps), the CPU oracle on a bounded sample of the same workload, the Table 2 ablation modes,
-the other direction rule, and the multi-source measurement: 64 sources per launch on RMAT-20
-against the same 64 queries run one at a time.
+the other direction rule, the multi-source measurement (64 sources per launch on RMAT-20
+against the same 64 queries run one at a time) and the query server (four graphs, Poisson
+arrivals at 1x and 2x the sequential capacity, p50/p99 latency against first-in first-out plain
+DOBFS).
 
 --profile-steps / --profile-batched run only the BFS launches (for rocprofv3); --copy-mb adds
 one device copy of known size as the reference for scaling the PMC byte counters.
@@ -150,6 +152,98 @@ def measure_batched(args, heur, alpha, beta):
     return res
 
 
+def measure_serving(args, hg22, g22, heur, alpha, beta):
+    """The query server on four device-resident graphs (RMAT-16, RMAT-20, RMAT-22, a 2048x2048
+    grid): single-source queries with a uniformly drawn graph and source (degree > 0, seed 6)
+    arrive as a Poisson stream at 1x and 2x the sequential capacity. Compared with the same
+    arrival sequence served first-in first-out by plain single-source DOBFS, one query at a
+    time, using each query's own measured service time (host gaps between queries ignored,
+    which favours the baseline). Latency = arrival to depth final in device memory."""
+    import threading
+    import torch
+    import gen
+    from paper_1804_03327_amd import dobfs
+    from paper_1804_03327_amd.helpers import BfsRunner, upload
+
+    specs = [("rmat16", gen.rmat(16, args.edgefactor, seed=1)), ("rmat20", gen.rmat(20, args.edgefactor, seed=1)),
+             ("rmat22", hg22), ("grid2048", gen.grid2d(2048, 2048))]
+    gs = [g22 if h is hg22 else upload(h, device=0) for _, h in specs]
+    opt = dobfs.make_options("full", heur, alpha, beta)
+    rng = np.random.default_rng(6)
+    N = args.serve_queries
+    pools = [np.asarray(gen.sample_sources(h, 256, seed=7 + i)) for i, (_, h) in enumerate(specs)]
+    qg = rng.integers(0, len(specs), N)
+    qs = [int(pools[gi][rng.integers(0, 256)]) for gi in qg]
+    # standalone service time of every query (plain single-source DOBFS)
+    runners = [BfsRunner(g, with_parent=True) for g in gs]
+    for gi, r in enumerate(runners):
+        r.run(int(pools[gi][0]), opt=opt)
+    torch.cuda.synchronize()
+    svc = np.zeros(N)
+    for i in range(N):
+        r = runners[qg[i]]
+        t1 = time.perf_counter()
+        dobfs.bfs(gs[qg[i]], qs[i], r.depth, r.parent, opt, r.ws)  # blocks until final
+        svc[i] = time.perf_counter() - t1
+    cap = 1.0 / float(svc.mean())
+    del runners
+    points = []
+    for mult in (1.0, 2.0):
+        lam = mult * cap
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, N))
+        # FIFO, one query at a time (Lindley recursion on the measured service times)
+        done, fifo_lat = 0.0, np.zeros(N)
+        for i in range(N):
+            start = max(arrivals[i], done)
+            done = start + svc[i]
+            fifo_lat[i] = done - arrivals[i]
+        fifo_qps = N / (done - arrivals[0])
+        outs = [torch.empty(gs[gi].V, dtype=torch.int32, device="cuda") for gi in qg]
+        srv = dobfs.Server(gs, slots=args.serve_slots, max_batch=64, opt=opt)
+        ids = [None] * N
+        infos = [None] * N
+        submitted = threading.Semaphore(0)
+
+        def waiter():
+            for i in range(N):
+                submitted.acquire()
+                infos[i] = srv.wait(ids[i])
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t_base = time.perf_counter()
+        for i in range(N):
+            delay = t_base + arrivals[i] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            ids[i] = srv.submit(int(qg[i]), qs[i], outs[i])
+            submitted.release()
+        th.join()
+        srv.close()
+        lat = np.array([x["t_done_ms"] - x["t_submit_ms"] for x in infos])
+        span = (max(x["t_done_ms"] for x in infos) - min(x["t_submit_ms"] for x in infos)) / 1e3
+        sizes = np.array([x["batch_size"] for x in infos])
+        points.append({"rate_x_sequential": mult, "offered_qps": round(lam, 1), "served_qps": round(N / span, 1),
+                       "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                       "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                       "mean_batch": round(float(sizes.mean()), 2),
+                       "fifo_plain_dobfs": {"served_qps": round(fifo_qps, 1),
+                                            "p50_ms": round(float(np.percentile(fifo_lat, 50)) * 1e3, 2),
+                                            "p99_ms": round(float(np.percentile(fifo_lat, 99)) * 1e3, 2)}})
+        log("serving %.1fx:" % mult, json.dumps(points[-1]))
+        del outs
+    for g in gs:
+        if g is not g22:
+            dobfs.graph_destroy(g)
+    return {"workload": "4 graphs (rmat16, rmat20, rmat22 ef%d; grid 2048x2048), uniform graph and "
+                        "source, Poisson arrivals (seed 6)" % args.edgefactor,
+            "queries_per_point": N, "slots": args.serve_slots, "max_batch": 64,
+            "sequential_capacity_qps": round(cap, 1),
+            "mean_service_ms": {name: round(float(svc[qg == gi].mean()) * 1e3, 3)
+                                for gi, (name, _) in enumerate(specs) if (qg == gi).any()},
+            "points": points}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +260,10 @@ def main():
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the multi-source (64 sources per launch) RMAT-20 measurement")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the query-server measurement (4 graphs, Poisson arrivals)")
+    ap.add_argument("--serve-queries", type=int, default=600)
+    ap.add_argument("--serve-slots", type=int, default=2)
     ap.add_argument("--batched-scale", type=int, default=20)
     ap.add_argument("--batched-launches", type=int, default=20)
     ap.add_argument("--no-validate", action="store_true")
@@ -409,6 +507,10 @@ def main():
     if not args.no_batched:
         batched = measure_batched(args, heur, alpha, beta)
 
+    serving = None
+    if not args.no_serving:
+        serving = measure_serving(args, hg, g, heur, alpha, beta)
+
     out = {
         "metric": METRIC, "value": round(gteps, 3), "unit": "GTEPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -428,6 +530,7 @@ def main():
         "other_direction_rule": other,
         "validated": validated,
         "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 
