@@ -635,6 +635,11 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   a.mask_after = opt.mode == DOBFS_MODE_PULL_UNMASKED ? 1 : 0;
   a.need_F = a.reuse ? 0 : 1;
   a.edge_rule = opt.heuristic == DOBFS_HEUR_EDGES ? 1 : 0;
+#ifdef DOBFS_NO_LOCAL_PUSH
+  a.local_push = 0;
+#else
+  a.local_push = 1;
+#endif
   auto forced = [&](int64_t l) -> int32_t {
     return l < opt.n_forced ? int32_t(opt.forced_dirs[l]) : -1;
   };

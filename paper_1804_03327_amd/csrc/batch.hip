@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kThreads) void k_mb_init(BatchArgs a, int32_t dir0,
       st.nf = a.nuniq;
       st.levels = 0;
       st.level = 0;
-      st.pad0 = 0;
+      st.local = 0;
       st.m_u = a.nnz;  // in-edges of vertices some source has not reached yet
       st.active = a.active;
       c->ring[0] = st;

@@ -125,6 +125,31 @@ __device__ __forceinline__ void zero_stripe(Stripe& st) {
   st.mnew = 0;
   st.insub = 0;
   st.fbits = 0;
+  st.maxdeg = 0;
+}
+
+// Raises a block's stripe's largest discovered out-degree (thread 0 only).
+__device__ __forceinline__ void stripe_max(LevelSlot* slot, uint32_t deg) {
+  if (deg) atomicMax(&slot->s[blockIdx.x % kStripes].maxdeg, deg);
+}
+
+__device__ __forceinline__ uint32_t wave_max32(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = max(v, uint32_t(__shfl_xor(int(v), d, 64)));
+  return v;
+}
+
+// Largest value over the 256 threads of a block (every thread gets it).
+__device__ __forceinline__ uint32_t block_max32(uint32_t v) {
+  __shared__ uint32_t s_m[kThreads / 64];
+  v = wave_max32(v);
+  if (lane() == 0) s_m[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint32_t t = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) t = max(t, s_m[w]);
+  __syncthreads();
+  return t;
 }
 
 __device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
@@ -380,6 +405,7 @@ __device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, Leve
   const uint64_t v0 = mine ? uint64_t(sk->count) | (uint64_t(sk->aux) << 32) : 0ull;
   const uint64_t v1 = mine ? sk->edges : 0ull, v2 = mine ? sk->mnew : 0ull, v3 = mine ? sk->insub : 0ull;
   const uint64_t v4 = mine ? sk->fbits : 0ull;
+  const uint32_t v5 = mine ? sk->maxdeg : 0u;
   const LevelState prev = c->ring[(L - 1) % kRing];
   *prev_out = prev;
   st = prev;
@@ -409,6 +435,9 @@ __device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, Leve
       st.vis_idx = prev.dir == 1 ? (prev.vis_idx ^ 1) : prev.vis_idx;
       st.m_u = m_u;
       st.active = fb;
+      // a push after a push gets its frontier as a list; small degrees need no global scan
+      const uint32_t md = __builtin_amdgcn_readfirstlane(wave_max32(v5));
+      st.local = (a.local_push && next == 0 && prev.dir == 0 && md <= uint32_t(kLocalDeg)) ? 1 : 0;
     }
   }
   *tot_out = t;

@@ -24,6 +24,7 @@ struct alignas(128) Stripe {
   uint64_t insub;  // in-edges of the vertices discovered (edge-count rule only; multi-source:
                    // of the vertices every source has now reached)
   uint64_t fbits;  // multi-source: OR of the source bits discovered
+  uint32_t maxdeg; // largest out-degree of the vertices a push level discovered
 };
 struct LevelSlot {
   Stripe s[kStripes];
@@ -39,7 +40,8 @@ struct alignas(64) LevelState {
   int32_t nf;          // frontier size entering the level
   int32_t levels;      // when done: number of levels run
   int32_t level;       // index of this level
-  int32_t pad0;
+  int32_t local;       // push level whose frontier is a list of small out-degrees: expanded with
+                       // block-local load balancing, no global scan
   int64_t m_u;         // edge-count rule: in-edges of still-unvisited vertices
   uint64_t active;     // multi-source: sources whose frontier entering the level is non-empty
 };
@@ -104,6 +106,7 @@ constexpr int kPullFirst = kSlab;                    // pull phase 1 checks a ro
 constexpr int kPullMid = 32;                         // rows still open continue thread-per-row up to here
 constexpr int kPullStep = 4;                         // in-neighbours a thread loads at once past kPullFirst
 constexpr int kPullBatch = 4;                        // candidate rows a thread works on at once
+constexpr int kLocalDeg = 32;                        // local push: largest out-degree in the frontier
 
 inline int32_t words_of(int64_t V) { return int32_t((V + 31) / 32); }
 inline int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
@@ -194,6 +197,7 @@ struct BfsArgs {
   int32_t mask_after;        // unmasked pull
   int32_t need_F;            // frontier bitmaps maintained
   int32_t edge_rule;
+  int32_t local_push;        // push levels of small out-degree may skip the global scan
 };
 
 // ---- multi-source BFS: up to 64 sources, one bit of a uint64 per source ----
@@ -225,6 +229,7 @@ struct BatchArgs {
   int32_t heuristic;
   double alpha, beta;
   int32_t edge_rule;
+  int32_t local_push;        // always 0: the multi-source push always scans
   int32_t src[kMaxSources];  // source of bit b
   int32_t uniq[kMaxSources]; // the distinct sources: the first frontier list
 };

@@ -56,6 +56,7 @@ __device__ void expand_body(const ExpandArgs& a, ExpandShared& sh) {
   if (blockIdx.x >= nchunks) return;
   if (threadIdx.x == 0) sh.nbuf = 0;
   unsigned long long won_total = 0, mnew = 0, insub = 0;
+  uint32_t maxdeg = 0;
   const uint32_t cflip = a.complement ? 1u : 0u;
 
   auto flush = [&]() {  // all threads; callers are past a barrier
@@ -130,7 +131,11 @@ __device__ void expand_body(const ExpandArgs& a, ExpandShared& sh) {
         if (a.depth) a.depth[w[t]] = a.level + 1;
         if (a.parent) a.parent[w[t]] = u[t];
         if (a.found_out) atomicOr(a.found_out + (w[t] >> 5), 1u << (w[t] & 31));
-        if (a.out_rowptr) mnew += uint64_t(a.out_rowptr[w[t] + 1] - a.out_rowptr[w[t]]);
+        if (a.out_rowptr) {
+          const uint32_t dw = uint32_t(a.out_rowptr[w[t] + 1] - a.out_rowptr[w[t]]);
+          mnew += dw;
+          maxdeg = max(maxdeg, dw);
+        }
         if (a.in_colptr) insub += uint64_t(a.in_colptr[w[t] + 1] - a.in_colptr[w[t]]);
       }
       if (a.Qout) {
@@ -150,12 +155,124 @@ __device__ void expand_body(const ExpandArgs& a, ExpandShared& sh) {
   if (a.Qout) flush();
   unsigned long long v[4] = {won_total, mnew, insub, 0};
   block_sum4(v);
+  maxdeg = block_max32(maxdeg);
   if (threadIdx.x == 0) {
     // every edge of a chunk is read exactly once; the block's chunks sum to its edges
     unsigned long long edges = 0;
     for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x)
       edges += min(uint32_t(kExpandChunk), m - c * kExpandChunk);
     stripe_add(a.slot, v[0], 0, edges, v[1], v[2]);
+    stripe_max(a.slot, maxdeg);
+  }
+}
+
+// Push for a frontier list whose out-degrees are all at most kLocalDeg:
+// the load balancing of the column-based matvec is done inside each block,
+// so the level needs no global degree scan. A block takes 256 frontier
+// vertices at a time, scans their degrees in LDS and walks the unit's edges
+// 1024 at a time, each edge finding its vertex by a search over the unit's
+// prefix; the claim and the winners' bookkeeping are those of expand_body.
+struct LocalShared {
+  int32_t off[kThreads + 1], beg[kThreads], src[kThreads];
+  int32_t buf[kExpandBuf];
+  uint32_t nbuf, base;
+};
+
+__device__ void local_expand_body(const ExpandArgs& a, LocalShared& sh) {
+  const int32_t nf = a.nf;
+  const int32_t nunits = (nf + kThreads - 1) / kThreads;
+  const int tid = threadIdx.x;
+  if (tid == 0) sh.nbuf = 0;
+  unsigned long long won_total = 0, mnew = 0, insub = 0, edges = 0;
+  uint32_t maxdeg = 0;
+
+  auto flush = [&]() {  // all threads; callers are past a barrier
+    const uint32_t nb = sh.nbuf;
+    if (nb == 0) return;
+    if (tid == 0) sh.base = atomicAdd(a.qcount, nb);
+    __syncthreads();
+    const uint32_t b = sh.base;
+    for (uint32_t k = tid; k < nb; k += kThreads) a.Qout[b + k] = sh.buf[k];
+    __syncthreads();
+    if (tid == 0) sh.nbuf = 0;
+    __syncthreads();
+  };
+
+  for (int32_t u = blockIdx.x; u < nunits; u += gridDim.x) {
+    const int32_t i = u * kThreads + tid;
+    int32_t v = -1, b = 0, d = 0;
+    if (i < nf) {
+      v = a.Q[i];
+      b = a.out_rowptr[v];
+      d = a.out_rowptr[v + 1] - b;
+    }
+    uint32_t total;
+    // the scan's first barrier also orders the previous unit's LDS reads before these writes
+    const uint32_t ex = block_excl_scan(uint32_t(d), &total);
+    sh.off[tid] = int32_t(ex);
+    sh.beg[tid] = b;
+    sh.src[tid] = v;
+    if (tid == 0) sh.off[kThreads] = int32_t(total);
+    const int32_t n = min(kThreads, nf - u * kThreads);
+    edges += tid == 0 ? total : 0;
+    for (uint32_t e0 = 0; e0 < total; e0 += kExpandChunk) {
+      __syncthreads();  // the unit's prefix is written, nbuf is settled
+      if (sh.nbuf + kExpandChunk > uint32_t(kExpandBuf)) flush();
+      int32_t w[kExpandEPT], uu[kExpandEPT];
+      bool valid[kExpandEPT], won[kExpandEPT];
+#pragma unroll
+      for (int t = 0; t < kExpandEPT; ++t) {
+        const uint32_t e = e0 + uint32_t(t * kThreads + tid);
+        valid[t] = e < total;
+        w[t] = 0;
+        uu[t] = 0;
+        if (valid[t]) {
+          const int32_t k = thread_search(sh.off, 0, n, e);
+          uu[t] = sh.src[k];
+          w[t] = a.colind[sh.beg[k] + int32_t(e - uint32_t(sh.off[k]))];
+        }
+      }
+      uint32_t seen[kExpandEPT];
+#pragma unroll
+      for (int t = 0; t < kExpandEPT; ++t) seen[t] = valid[t] ? a.claim[w[t] >> 5] : 0xffffffffu;
+#pragma unroll
+      for (int t = 0; t < kExpandEPT; ++t) {
+        const uint32_t bit = 1u << (w[t] & 31);
+        won[t] = false;
+        if (valid[t] && !(seen[t] & bit)) won[t] = !(atomicOr(a.claim + (w[t] >> 5), bit) & bit);
+      }
+#pragma unroll
+      for (int t = 0; t < kExpandEPT; ++t) {
+        if (won[t]) {
+          ++won_total;
+          a.depth[w[t]] = a.level + 1;
+          if (a.parent) a.parent[w[t]] = uu[t];
+          if (a.found_out) atomicOr(a.found_out + (w[t] >> 5), 1u << (w[t] & 31));
+          const uint32_t dw = uint32_t(a.out_rowptr[w[t] + 1] - a.out_rowptr[w[t]]);
+          mnew += dw;
+          maxdeg = max(maxdeg, dw);
+          if (a.in_colptr) insub += uint64_t(a.in_colptr[w[t] + 1] - a.in_colptr[w[t]]);
+        }
+        const uint64_t bal = __ballot(won[t]);
+        if (bal) {
+          const int cnt = __popcll(bal);
+          const int leader = __ffsll((unsigned long long)bal) - 1;
+          uint32_t p = 0;
+          if (lane() == leader) p = atomicAdd(&sh.nbuf, uint32_t(cnt));
+          p = __shfl(p, leader, 64);
+          if (won[t]) sh.buf[p + __popcll(bal & lanemask_lt())] = w[t];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  flush();
+  unsigned long long vv[4] = {won_total, mnew, insub, edges};
+  block_sum4(vv);
+  maxdeg = block_max32(maxdeg);
+  if (tid == 0) {
+    stripe_add(a.slot, vv[0], 0, vv[3], vv[1], vv[2]);
+    stripe_max(a.slot, maxdeg);
   }
 }
 
@@ -451,9 +568,9 @@ __global__ __launch_bounds__(kThreads) void k_bfs_init(BfsArgs a, int32_t source
       st.nf = 1;
       st.levels = 0;
       st.level = 0;
-      st.pad0 = 0;
       st.m_u = a.nnz - c->src_indeg;
       st.active = 0;
+      st.local = (a.local_push && dir0 == 0 && c->src_outdeg <= kLocalDeg) ? 1 : 0;
       c->ring[0] = st;
     }
   }
@@ -474,6 +591,10 @@ __global__ __launch_bounds__(kThreads) void k_level_prep(BfsArgs a, int32_t L, i
   if (a.need_F) {  // winners of this push level will be set in F[(L+1)%2]
     uint32_t* fn = a.F[(L + 1) % 2];
     for (int32_t w = blockIdx.x * kThreads + threadIdx.x; w < a.nwords; w += gridDim.x * kThreads) fn[w] = 0;
+  }
+  if (st.local) {  // no scan: m_f is the out-degree sum of the previous level's winners
+    if (blockIdx.x == 0 && threadIdx.x == 0) *mf_out = uint32_t(L == 0 ? c->src_outdeg : tot.mnew);
+    return;
   }
   if (st.list_valid) {
     scan_list(a.Q[L % 2], st.nf, a.rowptr, a.S, a.R, a.chunk_first, a.flagsA, uint32_t(2 * L + 1),
@@ -507,6 +628,7 @@ __global__ __launch_bounds__(kThreads) void k_level_prep(BfsArgs a, int32_t L, i
 
 union LevelShared {
   ExpandShared e;
+  LocalShared l;
   PullShared p;
 };
 
@@ -537,10 +659,13 @@ __global__ __launch_bounds__(kThreads) void k_level_main(BfsArgs a, int32_t L) {
     e.Qout = a.Q[(L + 1) % 2];
     e.qcount = &c->qcount[L % kSlots];
     e.found_out = a.need_F ? a.F[(L + 1) % 2] : nullptr;
-    e.out_rowptr = a.edge_rule ? a.rowptr : nullptr;
+    e.out_rowptr = a.rowptr;  // winners' out-degrees: m_f of the next level and its largest degree
     e.in_colptr = a.edge_rule ? a.colptr : nullptr;
     e.slot = slot;
-    expand_body(e, sh.e);
+    if (st.local)
+      local_expand_body(e, sh.l);
+    else
+      expand_body(e, sh.e);
   } else {
     const int32_t tiles = (a.nwords + kPullTileWords - 1) / kPullTileWords;
     if (int32_t(blockIdx.x) >= tiles) return;
