@@ -32,6 +32,7 @@ struct dobfs_graph_s {
   const int32_t* rowind = nullptr;
   uint32_t* nz_in = nullptr;        // rows of CSC(A) with at least one entry
   int4* slab = nullptr;             // first kSlab entries of every CSC(A) column (-1 past its end)
+  uint32_t max_outdeg = 0;          // largest CSR(A) row length
   std::atomic<int32_t> last_levels{8};  // level count of the previous BFS (first batch size)
   std::atomic<int32_t> last_levels_mb{8};  // the same for multi-source traversals
   void* owned[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -284,7 +285,15 @@ dobfs_status finish_graph(dobfs_graph g, hipStream_t s) {
   HIPCK(hipMalloc(&p, size_t(std::max(g->V, 1)) * sizeof(int4)));
   g->slab = static_cast<int4*>(p);
   HIPCK(launch_slab(s, g->colptr, g->rowind, g->V, g->slab));
-  HIPCK(hipStreamSynchronize(s));
+  uint32_t* dmax = nullptr;
+  HIPCK(hipMalloc(&p, sizeof(uint32_t)));
+  dmax = static_cast<uint32_t*>(p);
+  hipError_t e = hipMemsetAsync(dmax, 0, sizeof(uint32_t), s);
+  if (e == hipSuccess) e = launch_max_degree(s, g->rowptr, g->V, dmax);
+  if (e == hipSuccess) e = hipMemcpyAsync(&g->max_outdeg, dmax, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(dmax);
+  if (e != hipSuccess) return hip_fail(e, "max degree", __LINE__);
   return DOBFS_OK;
 }
 
@@ -635,11 +644,8 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   a.mask_after = opt.mode == DOBFS_MODE_PULL_UNMASKED ? 1 : 0;
   a.need_F = a.reuse ? 0 : 1;
   a.edge_rule = opt.heuristic == DOBFS_HEUR_EDGES ? 1 : 0;
-#ifdef DOBFS_NO_LOCAL_PUSH
-  a.local_push = 0;
-#else
   a.local_push = 1;
-#endif
+  a.low_degree = g->max_outdeg <= uint32_t(kLocalDeg) ? 1 : 0;
   auto forced = [&](int64_t l) -> int32_t {
     return l < opt.n_forced ? int32_t(opt.forced_dirs[l]) : -1;
   };

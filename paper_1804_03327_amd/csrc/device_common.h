@@ -437,7 +437,8 @@ __device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, Leve
       st.active = fb;
       // a push after a push gets its frontier as a list; small degrees need no global scan
       const uint32_t md = __builtin_amdgcn_readfirstlane(wave_max32(v5));
-      st.local = (a.local_push && next == 0 && prev.dir == 0 && md <= uint32_t(kLocalDeg)) ? 1 : 0;
+      st.local = (a.local_push && next == 0 && prev.dir == 0 && (a.low_degree || md <= uint32_t(kLocalDeg)))
+                     ? 1 : 0;
     }
   }
   *tot_out = t;
@@ -460,7 +461,8 @@ __device__ void publish_level(Ctrl* c, int32_t L, const LevelState& st, const Le
         r.n_new = int32_t(tot.count);
         r.pad = 0;
         r.edges = int64_t(tot.edges);
-        r.m_f = prev.dir == 0 ? int64_t(c->mf[(L - 1) % kSlots]) : 0;  // written by the scan of L-1
+        // a scanned push level's m_f comes from its scan; a local one reads exactly its m_f edges
+        r.m_f = prev.dir == 0 ? (prev.local ? int64_t(tot.edges) : int64_t(c->mf[(L - 1) % kSlots])) : 0;
         r.mnew = tot.mnew;
         r.insub = tot.insub;
         r.aux = tot.aux;

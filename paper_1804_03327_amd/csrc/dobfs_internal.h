@@ -107,6 +107,7 @@ constexpr int kPullMid = 32;                         // rows still open continue
 constexpr int kPullStep = 4;                         // in-neighbours a thread loads at once past kPullFirst
 constexpr int kPullBatch = 4;                        // candidate rows a thread works on at once
 constexpr int kLocalDeg = 32;                        // local push: largest out-degree in the frontier
+constexpr int kLocalUnit = 128;                      // local push: frontier vertices a block takes at once
 
 inline int32_t words_of(int64_t V) { return int32_t((V + 31) / 32); }
 inline int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
@@ -162,6 +163,7 @@ struct ExpandArgs {
   int32_t* Qout;             // nullable: winners appended here
   uint32_t* qcount;          // append counter for Qout
   uint32_t* found_out;       // nullable: winners' bits also set here
+  const int32_t* rowptr;     // CSR(A) offsets (local push: degrees of the frontier)
   const int32_t* out_rowptr; // nullable: out-degrees of winners -> mnew
   const int32_t* in_colptr;  // nullable: in-degrees of winners -> insub
   LevelSlot* slot;
@@ -198,6 +200,7 @@ struct BfsArgs {
   int32_t need_F;            // frontier bitmaps maintained
   int32_t edge_rule;
   int32_t local_push;        // push levels of small out-degree may skip the global scan
+  int32_t low_degree;        // every out-degree of the graph is <= kLocalDeg
 };
 
 // ---- multi-source BFS: up to 64 sources, one bit of a uint64 per source ----
@@ -230,6 +233,7 @@ struct BatchArgs {
   double alpha, beta;
   int32_t edge_rule;
   int32_t local_push;        // always 0: the multi-source push always scans
+  int32_t low_degree;        // unused here
   int32_t src[kMaxSources];  // source of bit b
   int32_t uniq[kMaxSources]; // the distinct sources: the first frontier list
 };
@@ -276,6 +280,7 @@ hipError_t launch_mxv_finalize(hipStream_t s, uint32_t* y, const uint32_t* r, in
                                int32_t V, int accum, LevelSlot* slot);
 hipError_t launch_nz_bits(hipStream_t s, const int32_t* ptr, int32_t V, uint32_t* bits);
 hipError_t launch_slab(hipStream_t s, const int32_t* ptr, const int32_t* ind, int32_t V, int4* slab);
+hipError_t launch_max_degree(hipStream_t s, const int32_t* ptr, int32_t V, uint32_t* out);
 // What the host needs after a batch of levels: the state after the batch and
 // the records of its levels. Written into pinned host memory by one block,
 // `seq` last (system-scope release), so the host can spin on it.

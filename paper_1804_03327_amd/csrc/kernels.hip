@@ -168,8 +168,8 @@ __device__ void expand_body(const ExpandArgs& a, ExpandShared& sh) {
 
 // Push for a frontier list whose out-degrees are all at most kLocalDeg:
 // the load balancing of the column-based matvec is done inside each block,
-// so the level needs no global degree scan. A block takes 256 frontier
-// vertices at a time, scans their degrees in LDS and walks the unit's edges
+// so the level needs no global degree scan. A block takes kLocalUnit
+// frontier vertices at a time, scans their degrees in LDS and walks the unit's edges
 // 1024 at a time, each edge finding its vertex by a search over the unit's
 // prefix; the claim and the winners' bookkeeping are those of expand_body.
 struct LocalShared {
@@ -180,7 +180,7 @@ struct LocalShared {
 
 __device__ void local_expand_body(const ExpandArgs& a, LocalShared& sh) {
   const int32_t nf = a.nf;
-  const int32_t nunits = (nf + kThreads - 1) / kThreads;
+  const int32_t nunits = (nf + kLocalUnit - 1) / kLocalUnit;
   const int tid = threadIdx.x;
   if (tid == 0) sh.nbuf = 0;
   unsigned long long won_total = 0, mnew = 0, insub = 0, edges = 0;
@@ -199,12 +199,12 @@ __device__ void local_expand_body(const ExpandArgs& a, LocalShared& sh) {
   };
 
   for (int32_t u = blockIdx.x; u < nunits; u += gridDim.x) {
-    const int32_t i = u * kThreads + tid;
+    const int32_t i = u * kLocalUnit + tid;
     int32_t v = -1, b = 0, d = 0;
-    if (i < nf) {
+    if (tid < kLocalUnit && i < nf) {
       v = a.Q[i];
-      b = a.out_rowptr[v];
-      d = a.out_rowptr[v + 1] - b;
+      b = a.rowptr[v];
+      d = a.rowptr[v + 1] - b;
     }
     uint32_t total;
     // the scan's first barrier also orders the previous unit's LDS reads before these writes
@@ -213,7 +213,7 @@ __device__ void local_expand_body(const ExpandArgs& a, LocalShared& sh) {
     sh.beg[tid] = b;
     sh.src[tid] = v;
     if (tid == 0) sh.off[kThreads] = int32_t(total);
-    const int32_t n = min(kThreads, nf - u * kThreads);
+    const int32_t n = min(kLocalUnit, nf - u * kLocalUnit);
     edges += tid == 0 ? total : 0;
     for (uint32_t e0 = 0; e0 < total; e0 += kExpandChunk) {
       __syncthreads();  // the unit's prefix is written, nbuf is settled
@@ -248,9 +248,11 @@ __device__ void local_expand_body(const ExpandArgs& a, LocalShared& sh) {
           a.depth[w[t]] = a.level + 1;
           if (a.parent) a.parent[w[t]] = uu[t];
           if (a.found_out) atomicOr(a.found_out + (w[t] >> 5), 1u << (w[t] & 31));
-          const uint32_t dw = uint32_t(a.out_rowptr[w[t] + 1] - a.out_rowptr[w[t]]);
-          mnew += dw;
-          maxdeg = max(maxdeg, dw);
+          if (a.out_rowptr) {
+            const uint32_t dw = uint32_t(a.out_rowptr[w[t] + 1] - a.out_rowptr[w[t]]);
+            mnew += dw;
+            maxdeg = max(maxdeg, dw);
+          }
           if (a.in_colptr) insub += uint64_t(a.in_colptr[w[t] + 1] - a.in_colptr[w[t]]);
         }
         const uint64_t bal = __ballot(won[t]);
@@ -592,10 +594,7 @@ __global__ __launch_bounds__(kThreads) void k_level_prep(BfsArgs a, int32_t L, i
     uint32_t* fn = a.F[(L + 1) % 2];
     for (int32_t w = blockIdx.x * kThreads + threadIdx.x; w < a.nwords; w += gridDim.x * kThreads) fn[w] = 0;
   }
-  if (st.local) {  // no scan: m_f is the out-degree sum of the previous level's winners
-    if (blockIdx.x == 0 && threadIdx.x == 0) *mf_out = uint32_t(L == 0 ? c->src_outdeg : tot.mnew);
-    return;
-  }
+  if (st.local) return;  // no scan: the expansion balances its load itself
   if (st.list_valid) {
     scan_list(a.Q[L % 2], st.nf, a.rowptr, a.S, a.R, a.chunk_first, a.flagsA, uint32_t(2 * L + 1),
               &c->ticket[L % 2], mf_out);
@@ -659,7 +658,10 @@ __global__ __launch_bounds__(kThreads) void k_level_main(BfsArgs a, int32_t L) {
     e.Qout = a.Q[(L + 1) % 2];
     e.qcount = &c->qcount[L % kSlots];
     e.found_out = a.need_F ? a.F[(L + 1) % 2] : nullptr;
-    e.out_rowptr = a.rowptr;  // winners' out-degrees: m_f of the next level and its largest degree
+    e.rowptr = a.rowptr;
+    // winners' out-degrees: the next level's m_f (edge-count rule) and its largest degree
+    // (whether it can skip the scan; known for all levels when the whole graph has low degree)
+    e.out_rowptr = (a.edge_rule || !a.low_degree) ? a.rowptr : nullptr;
     e.in_colptr = a.edge_rule ? a.colptr : nullptr;
     e.slot = slot;
     if (st.local)
@@ -794,6 +796,16 @@ __global__ __launch_bounds__(kThreads) void k_slab(const int32_t* ptr, const int
   }
 }
 
+// Largest row length of a CSR offset array (one atomic per block).
+__global__ __launch_bounds__(kThreads) void k_max_degree(const int32_t* ptr, int32_t V, uint32_t* out) {
+  uint32_t m = 0;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < V; i += stride)
+    m = max(m, uint32_t(ptr[i + 1] - ptr[i]));
+  m = block_max32(m);
+  if (threadIdx.x == 0 && m) atomicMax(out, m);
+}
+
 // Copies the state after a batch and the batch's level records into pinned
 // host memory, then publishes `seq` with a system-scope release.
 __global__ void k_report(const Ctrl* c, int32_t l_first, int32_t n, HostReport* host, uint32_t seq) {
@@ -904,6 +916,11 @@ hipError_t launch_nz_bits(hipStream_t s, const int32_t* ptr, int32_t V, uint32_t
 hipError_t launch_slab(hipStream_t s, const int32_t* ptr, const int32_t* ind, int32_t V, int4* slab) {
   hipLaunchKernelGGL(k_slab, dim3(grid_for(V, kThreads, 8192)), dim3(kThreads), 0, s, ptr, ind, V,
                      slab);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_degree(hipStream_t s, const int32_t* ptr, int32_t V, uint32_t* out) {
+  hipLaunchKernelGGL(k_max_degree, dim3(grid_for(V, kThreads, 1024)), dim3(kThreads), 0, s, ptr, V, out);
   return hipGetLastError();
 }
 
