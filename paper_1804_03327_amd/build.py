@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libdobfs.so")
-SOURCES = ["kernels.hip", "batch.hip", "api.hip", "serve.hip"]
+SOURCES = ["kernels.hip", "batch.hip", "sortpush.hip", "api.hip", "serve.hip"]
 ARCH = os.environ.get("DOBFS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

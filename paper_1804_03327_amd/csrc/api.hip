@@ -114,6 +114,33 @@ Layout plan(int32_t V, int64_t nnz) {
   return L;
 }
 
+// Workspace layout of the sort-based push: the common layout, then the
+// pair buffers of the sort (nnz keys and values, twice) and its scratch.
+struct SortLayout {
+  Layout base;
+  size_t kA, kB, vA, vB, tmp, tmp_bytes, total;
+};
+
+SortLayout plan_sort(int32_t V, int64_t nnz) {
+  SortLayout L{};
+  L.base = plan(V, nnz);
+  size_t cur = L.base.total;
+  auto take = [&](size_t bytes) {
+    size_t off = cur;
+    cur += align_up(bytes);
+    return off;
+  };
+  const size_t nb = size_t(std::max<int64_t>(nnz, 1)) * 4;
+  L.kA = take(nb);
+  L.kB = take(nb);
+  L.vA = take(nb);
+  L.vB = take(nb);
+  L.tmp_bytes = sort_push_bytes(nnz);
+  L.tmp = take(L.tmp_bytes);
+  L.total = cur;
+  return L;
+}
+
 // Workspace layout of a multi-source call with k sources.
 struct BatchLayout {
   size_t visA, visB, FA, FB, nzF, Q0, Q1, S, R, chunks, flagsA, flagsB, ctrl, lvl, total;
@@ -227,7 +254,7 @@ dobfs_options defaults() {
 }
 
 dobfs_status check_options(const dobfs_options& o) {
-  if (o.mode < DOBFS_MODE_FULL || o.mode > DOBFS_MODE_PULL_ONLY)
+  if (o.mode < DOBFS_MODE_FULL || o.mode > DOBFS_MODE_PUSH_SORT)
     return fail(DOBFS_ERR_INVALID_ARG, "unknown mode %d", o.mode);
   if (o.heuristic != DOBFS_HEUR_RATIO && o.heuristic != DOBFS_HEUR_EDGES)
     return fail(DOBFS_ERR_INVALID_ARG, "unknown heuristic %d", o.heuristic);
@@ -336,6 +363,48 @@ dobfs_status get_workspace(dobfs_graph g, void* workspace, size_t ws_bytes, size
 }
 
 
+// The argument block of a single-source traversal over workspace `ws`.
+BfsArgs bfs_args(dobfs_graph g, uint8_t* ws, const Layout& L, const dobfs_options& opt, int32_t* depth,
+                 int32_t* parent) {
+  BfsArgs a{};
+  a.V = g->V;
+  a.nwords = g->nwords;
+  a.nnz = g->nnz;
+  a.rowptr = g->rowptr;
+  a.colind = g->colind;
+  a.colptr = g->colptr;
+  a.rowind = g->rowind;
+  a.slab = g->slab;
+  a.nz_in = g->nz_in;
+  a.depth = depth;
+  a.parent = parent;
+  a.vis[0] = reinterpret_cast<uint32_t*>(ws + L.visA);
+  a.vis[1] = reinterpret_cast<uint32_t*>(ws + L.visB);
+  a.F[0] = reinterpret_cast<uint32_t*>(ws + L.FA);
+  a.F[1] = reinterpret_cast<uint32_t*>(ws + L.FB);
+  a.Q[0] = reinterpret_cast<int32_t*>(ws + L.Q0);
+  a.Q[1] = reinterpret_cast<int32_t*>(ws + L.Q1);
+  a.S = reinterpret_cast<int32_t*>(ws + L.S);
+  a.R = reinterpret_cast<int32_t*>(ws + L.R);
+  a.chunk_first = reinterpret_cast<int32_t*>(ws + L.chunks);
+  a.flagsA = reinterpret_cast<uint64_t*>(ws + L.flagsA);
+  a.flagsB = reinterpret_cast<uint64_t*>(ws + L.flagsB);
+  a.ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
+  a.mode = opt.mode;
+  a.heuristic = opt.heuristic;
+  a.alpha = double(opt.alpha);
+  a.beta = double(opt.beta);
+  a.reuse = (opt.mode == DOBFS_MODE_FULL || opt.mode == DOBFS_MODE_PULL_ONLY ||
+             opt.mode == DOBFS_MODE_PUSH_ONLY) ? 1 : 0;
+  a.early_exit = (opt.mode != DOBFS_MODE_PULL_MASKED && opt.mode != DOBFS_MODE_PULL_UNMASKED) ? 1 : 0;
+  a.mask_after = opt.mode == DOBFS_MODE_PULL_UNMASKED ? 1 : 0;
+  a.need_F = a.reuse ? 0 : 1;
+  a.edge_rule = opt.heuristic == DOBFS_HEUR_EDGES ? 1 : 0;
+  a.local_push = 1;
+  a.low_degree = g->max_outdeg <= uint32_t(kLocalDeg) ? 1 : 0;
+  return a;
+}
+
 // Result of a level loop.
 struct LoopResult {
   int64_t levels = 0;   // levels run (the last discovered nothing)
@@ -415,6 +484,95 @@ dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool t
     next_batch = std::min(2 * next_batch, kMaxBatch);
   }
   last_levels.store(int32_t(res->levels), std::memory_order_relaxed);
+  return DOBFS_OK;
+}
+
+// The sort-based push of Table 2's first row: push at every level with the
+// pairs gathered, radix-sorted by key and reduced to their first element
+// per key (Algorithm 3 as printed). The first kernel of each level (state +
+// frontier scan) is shared with the atomic push; the host reads the level's
+// state and edge count back before sizing the sort, as the paper's loop does.
+dobfs_status bfs_sort_push(dobfs_graph g, int32_t source, const dobfs_options& opt_in, int32_t* depth,
+                           int32_t* parent, void* workspace, size_t ws_bytes, void* stream,
+                           dobfs_stats* stats) {
+  const SortLayout SL = plan_sort(g->V, g->nnz);
+  std::unique_lock<std::mutex> lock;
+  uint8_t* ws = nullptr;
+  dobfs_status st = get_workspace(g, workspace, ws_bytes, SL.total, lock, &ws);
+  if (st != DOBFS_OK) return st;
+  hipEvent_t* ev = events_for(g->device);
+  if (!ev) return fail(DOBFS_ERR_DEVICE, "event creation failed");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  dobfs_options opt = opt_in;
+  opt.mode = DOBFS_MODE_PUSH_ONLY;  // the level state machine: push at every level
+  BfsArgs a = bfs_args(g, ws, SL.base, opt, depth, parent);
+  a.local_push = 0;  // the gather reads the frontier scan's chunk table
+  a.edge_rule = 0;
+  uint32_t* kA = reinterpret_cast<uint32_t*>(ws + SL.kA);
+  uint32_t* kB = reinterpret_cast<uint32_t*>(ws + SL.kB);
+  int32_t* vA = reinterpret_cast<int32_t*>(ws + SL.vA);
+  int32_t* vB = reinterpret_cast<int32_t*>(ws + SL.vB);
+  void* tmp = ws + SL.tmp;
+  int bits = 1;
+  while (bits < 32 && (int64_t(1) << bits) < int64_t(g->V)) ++bits;
+  Ctrl* c = a.ctrl;
+  Ctrl* hc = host_ctrl();
+  if (!hc) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
+
+  HIPCK(hipEventRecord(ev[kEvStart], s));
+  HIPCK(launch_bfs_init(s, a, source, DOBFS_DIR_PUSH));
+  int64_t levels = 0, reached = 1;
+  for (int32_t L = 0;; ++L) {
+    if (int64_t(L) > int64_t(g->V) + 1) return fail(DOBFS_ERR_INTERNAL, "level loop did not terminate");
+    HIPCK(launch_level_prep(s, a, L, -1));
+    HIPCK(hipMemcpyAsync(&hc->ring[0], &c->ring[L % kRing], sizeof(LevelState), hipMemcpyDeviceToHost, s));
+    HIPCK(hipMemcpyAsync(&hc->mf[0], &c->mf[L % kSlots], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    if (L >= 1)
+      HIPCK(hipMemcpyAsync(&hc->rec[0], &c->rec[(L - 1) % kRing], sizeof(LevelRecord), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    const LevelState stL = hc->ring[0];
+    if (L >= 1) {
+      const LevelRecord& r = hc->rec[0];
+      reached += r.n_new;
+      if (stats && L - 1 < stats->cap) {
+        dobfs_level_stats& ls = stats->level[L - 1];
+        ls.dir = r.dir;
+        ls.nf = r.nf;
+        ls.n_new = r.n_new;
+        ls.pad = 0;
+        ls.edges = r.edges;
+        ls.m_f = r.m_f;
+        ls.ms_main = 0.f;
+        ls.ms_aux = 0.f;
+      }
+    }
+    if (stL.done) {
+      levels = stL.levels;
+      break;
+    }
+    const uint32_t m = hc->mf[0];
+    if (m == 0) continue;  // nothing to gather: the next level's state sees no discovery
+    ExpandArgs e{};
+    e.Q = a.Q[L % 2];
+    e.nf = stL.nf;
+    e.S = a.S;
+    e.R = a.R;
+    e.chunk_first = a.chunk_first;
+    e.colind = a.colind;
+    e.m = m;
+    HIPCK(launch_sort_gather(s, e, kA, vA));
+    HIPCK(sort_pairs(s, tmp, SL.tmp_bytes, kA, kB, vA, vB, m, bits));
+    HIPCK(launch_sort_filter(s, kB, vB, m, a.vis[stL.vis_idx], depth, parent, L, a.Q[(L + 1) % 2],
+                             &c->qcount[L % kSlots], &c->slot[L % kSlots]));
+  }
+  HIPCK(hipEventRecord(ev[kEvEnd], s));
+  HIPCK(hipEventSynchronize(ev[kEvEnd]));
+  if (stats) {
+    stats->levels = int32_t(levels);
+    stats->ms_total = elapsed(ev[kEvStart], ev[kEvEnd]);
+    stats->ms_init = 0.f;
+    stats->reached = reached;
+  }
   return DOBFS_OK;
 }
 
@@ -574,9 +732,9 @@ dobfs_status dobfs_graph_info(dobfs_graph g, int32_t* V, int64_t* nnz, int32_t* 
 }
 
 dobfs_status dobfs_bfs_workspace_bytes(dobfs_graph g, const dobfs_options* opt, size_t* bytes) {
-  (void)opt;
   if (!g || !bytes) return fail(DOBFS_ERR_INVALID_ARG, "graph or bytes is NULL");
-  *bytes = plan(g->V, g->nnz).total;
+  *bytes = (opt && opt->mode == DOBFS_MODE_PUSH_SORT) ? plan_sort(g->V, g->nnz).total
+                                                       : plan(g->V, g->nnz).total;
   return DOBFS_OK;
 }
 
@@ -601,6 +759,8 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
 
   DeviceScope ds(g->device);
   if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice", __LINE__);
+  if (opt.mode == DOBFS_MODE_PUSH_SORT)
+    return bfs_sort_push(g, source, opt, depth, parent, workspace, ws_bytes, stream, stats);
   const Layout L = plan(g->V, g->nnz);
   std::unique_lock<std::mutex> lock;
   uint8_t* ws = nullptr;
@@ -610,42 +770,7 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   if (!ev) return fail(DOBFS_ERR_DEVICE, "event creation failed");
   hipStream_t s = static_cast<hipStream_t>(stream);
 
-  BfsArgs a{};
-  a.V = g->V;
-  a.nwords = g->nwords;
-  a.nnz = g->nnz;
-  a.rowptr = g->rowptr;
-  a.colind = g->colind;
-  a.colptr = g->colptr;
-  a.rowind = g->rowind;
-  a.slab = g->slab;
-  a.nz_in = g->nz_in;
-  a.depth = depth;
-  a.parent = parent;
-  a.vis[0] = reinterpret_cast<uint32_t*>(ws + L.visA);
-  a.vis[1] = reinterpret_cast<uint32_t*>(ws + L.visB);
-  a.F[0] = reinterpret_cast<uint32_t*>(ws + L.FA);
-  a.F[1] = reinterpret_cast<uint32_t*>(ws + L.FB);
-  a.Q[0] = reinterpret_cast<int32_t*>(ws + L.Q0);
-  a.Q[1] = reinterpret_cast<int32_t*>(ws + L.Q1);
-  a.S = reinterpret_cast<int32_t*>(ws + L.S);
-  a.R = reinterpret_cast<int32_t*>(ws + L.R);
-  a.chunk_first = reinterpret_cast<int32_t*>(ws + L.chunks);
-  a.flagsA = reinterpret_cast<uint64_t*>(ws + L.flagsA);
-  a.flagsB = reinterpret_cast<uint64_t*>(ws + L.flagsB);
-  a.ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
-  a.mode = opt.mode;
-  a.heuristic = opt.heuristic;
-  a.alpha = double(opt.alpha);
-  a.beta = double(opt.beta);
-  a.reuse = (opt.mode == DOBFS_MODE_FULL || opt.mode == DOBFS_MODE_PULL_ONLY ||
-             opt.mode == DOBFS_MODE_PUSH_ONLY) ? 1 : 0;
-  a.early_exit = (opt.mode != DOBFS_MODE_PULL_MASKED && opt.mode != DOBFS_MODE_PULL_UNMASKED) ? 1 : 0;
-  a.mask_after = opt.mode == DOBFS_MODE_PULL_UNMASKED ? 1 : 0;
-  a.need_F = a.reuse ? 0 : 1;
-  a.edge_rule = opt.heuristic == DOBFS_HEUR_EDGES ? 1 : 0;
-  a.local_push = 1;
-  a.low_degree = g->max_outdeg <= uint32_t(kLocalDeg) ? 1 : 0;
+  const BfsArgs a = bfs_args(g, ws, L, opt, depth, parent);
   auto forced = [&](int64_t l) -> int32_t {
     return l < opt.n_forced ? int32_t(opt.forced_dirs[l]) : -1;
   };

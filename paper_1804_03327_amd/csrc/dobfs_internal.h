@@ -308,6 +308,15 @@ hipError_t launch_check_offsets(hipStream_t s, const int32_t* ptr, int32_t V, in
 hipError_t launch_check_indices(hipStream_t s, const int32_t* idx, int64_t nnz, int32_t V,
                                 int32_t* err);
 
+// ---- sort-based push (sortpush.hip) ----
+size_t sort_push_bytes(int64_t nnz);  // radix-sort scratch for nnz pairs
+hipError_t launch_sort_gather(hipStream_t s, const ExpandArgs& a, uint32_t* keys, int32_t* vals);
+hipError_t sort_pairs(hipStream_t s, void* tmp, size_t tmp_bytes, const uint32_t* kin, uint32_t* kout,
+                      const int32_t* vin, int32_t* vout, uint32_t m, int bits);
+hipError_t launch_sort_filter(hipStream_t s, const uint32_t* keys, const int32_t* vals, uint32_t m, uint32_t* vis,
+                              int32_t* depth, int32_t* parent, int32_t level, int32_t* Qout, uint32_t* qcount,
+                              LevelSlot* slot);
+
 // ---- host runtime entry points shared between api.hip and serve.hip ----
 // Multi-source traversal writing source b's depths to rows.row[b].
 dobfs_status bfs_batch_rows(dobfs_graph g, const int32_t* sources, int32_t k, const dobfs_options* opt,

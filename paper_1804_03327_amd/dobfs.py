@@ -20,10 +20,10 @@ OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_WORKSPACE_TOO_SMALL, ERR
 UPLOAD_VALIDATE = 1
 DIR_PUSH, DIR_PULL = 0, 1
 MODE_FULL, MODE_PUSH_ONLY, MODE_PULL_UNMASKED, MODE_PULL_MASKED, MODE_PULL_MASKED_EE, \
-    MODE_PULL_ONLY = range(6)
+    MODE_PULL_ONLY, MODE_PUSH_SORT = range(7)
 MODES = {"full": MODE_FULL, "push_only": MODE_PUSH_ONLY, "pull_unmasked": MODE_PULL_UNMASKED,
          "pull_masked": MODE_PULL_MASKED, "pull_masked_ee": MODE_PULL_MASKED_EE,
-         "pull_only": MODE_PULL_ONLY}
+         "pull_only": MODE_PULL_ONLY, "push_sort": MODE_PUSH_SORT}
 HEUR_RATIO, HEUR_EDGES = 0, 1
 OPT_TIME_KERNELS = 1
 MXV_EARLY_EXIT, MXV_ACCUM_OR = 1, 2

@@ -101,6 +101,42 @@ def test_all_modes_match_oracle(graphs, name):
                 assert set(dirs) == {PULL}
 
 
+@pytest.mark.parametrize("name", ["rmat10", "rmat14", "directed100003", "lattice37", "grid61x53"])
+def test_push_sort_matches_oracle(graphs, name):
+    """Table 2's baseline row: gather, key-value radix sort, first of each key, mask filter
+    (Algorithm 3 as printed). Depths exact, parents valid, push at every level, the per-level
+    sizes of the oracle, and the gathered pairs of a level are exactly nnz(m_f^+)."""
+    hg, g = graphs[name]
+    outdeg = hg.out_degree()
+    opt = dobfs.make_options("push_sort")
+    need = dobfs.bfs_workspace_bytes(g, opt)
+    assert need > dobfs.bfs_workspace_bytes(g)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    depth = torch.empty(g.V, dtype=torch.int32, device="cuda")
+    parent = torch.empty(g.V, dtype=torch.int32, device="cuda")
+    st = dobfs.make_stats(4096)
+    for s in _sources(hg, 3, seed=2):
+        tag = "%s src=%d push_sort" % (name, s)
+        _say(tag)
+        want, _ = oracle.bfs(hg, s)
+        dobfs.bfs(g, s, depth, parent, opt, ws, stats=st)
+        d, p = depth.cpu().numpy(), parent.cpu().numpy()
+        assert np.array_equal(d, want), tag + ": depth mismatch"
+        code, bad = oracle.validate(hg, s, d, p)
+        assert code == 0, "%s: parent check %d failed at %d" % (tag, code, bad)
+        lv = dobfs.stats_levels(st)
+        sizes = oracle.level_sizes(want)
+        assert [r["nf"] for r in lv] == sizes, tag
+        assert set(r["dir"] for r in lv) == {PUSH}, tag
+        for L, r in enumerate(lv):
+            m_f = int(outdeg[want == L].sum())
+            assert r["m_f"] == m_f and r["edges"] == m_f, "%s level %d" % (tag, L)
+    # too small a workspace for this mode is refused
+    with pytest.raises(dobfs.DobfsError) as e:
+        dobfs.bfs(g, 0, depth, parent, opt, ws, ws_bytes=need - 256)
+    assert e.value.status == dobfs.ERR_WORKSPACE_TOO_SMALL
+
+
 @pytest.mark.parametrize("name", ["rmat14", "directed100003", "lattice37"])
 def test_work_counts_match_table1(graphs, name):
     """Edges touched per level: push reads nnz(m_f^+); pull with early exit checks exactly the
