@@ -105,3 +105,13 @@ def test_bit_packing_layout():
         i = np.arange(V)
         assert np.array_equal(((w[i >> 5] >> (i & 31)) & 1).astype(bool), m)
         assert np.array_equal(unpack_bits(w, V), m)
+
+
+def test_autotune_candidates_cover_both_rules():
+    from paper_1804_03327_amd import autotune, dobfs
+    c = autotune.candidates()
+    assert len(c) == len(set(c))
+    assert {h for h, _, _ in c} == {dobfs.HEUR_RATIO, dobfs.HEUR_EDGES}
+    assert (dobfs.HEUR_RATIO, 0.01, 0.01) in c  # the paper's constants
+    assert any(h == dobfs.HEUR_EDGES and abs(a - 1 / 14) < 1e-12 and abs(b - 1 / 24) < 1e-12 for h, a, b in c)
+    assert autotune.describe(dict(heuristic=dobfs.HEUR_RATIO, alpha=0.01, beta=0.01)) == "ratio alpha=0.01 beta=0.01"
