@@ -57,8 +57,14 @@ typedef struct dobfs_graph_s *dobfs_graph;
 
 /* ------------------------------------------------------------------ graphs */
 
-/* Accepted for compatibility; the checks below are always made. */
-enum { DOBFS_UPLOAD_VALIDATE = 1u };
+enum {
+  DOBFS_UPLOAD_VALIDATE = 1u,  /* accepted for compatibility; the checks below are always made */
+  DOBFS_UPLOAD_HUBS_FIRST = 2u /* keep every CSC(A) column (a row's in-neighbours) ordered by
+                                  decreasing out-degree of the neighbour, ties by id, in a copy
+                                  the graph owns: the pull's early exit (Section 5.3) then tends
+                                  to stop at the first entries. Depths are unchanged; a pull
+                                  reports the first hit in this order as the parent. */
+};
 
 /*
  * Copy a graph from host memory to device `device` (Section 6: the matrix is
@@ -69,7 +75,8 @@ enum { DOBFS_UPLOAD_VALIDATE = 1u };
  * index lies in [0, V) (O(V + nnz) on the host). flags: 0 or
  * DOBFS_UPLOAD_VALIDATE. Returns INVALID_ARG on a failed check, DEVICE /
  * OUT_OF_MEMORY on HIP failures; *out is set only on success. When the CSR
- * and CSC pointers are the same (an undirected graph), one copy is stored.
+ * and CSC pointers are the same (an undirected graph), one copy is stored
+ * (with DOBFS_UPLOAD_HUBS_FIRST the CSC side gets its own reordered copy).
  */
 dobfs_status dobfs_graph_upload(int32_t V, int64_t nnz, const int32_t *csr_rowptr,
                                 const int32_t *csr_colind, const int32_t *csc_colptr,

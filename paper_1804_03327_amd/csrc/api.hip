@@ -304,14 +304,11 @@ dobfs_status check_device(int32_t device) {
   return DOBFS_OK;
 }
 
-dobfs_status finish_graph(dobfs_graph g, hipStream_t s) {
+dobfs_status finish_graph(dobfs_graph g, hipStream_t s, uint32_t flags) {
   void* p = nullptr;
   HIPCK(hipMalloc(&p, size_t(std::max(g->nwords, 1)) * 4));
   g->nz_in = static_cast<uint32_t*>(p);
   HIPCK(launch_nz_bits(s, g->colptr, g->V, g->nz_in));
-  HIPCK(hipMalloc(&p, size_t(std::max(g->V, 1)) * sizeof(int4)));
-  g->slab = static_cast<int4*>(p);
-  HIPCK(launch_slab(s, g->colptr, g->rowind, g->V, g->slab));
   uint32_t* dmax = nullptr;
   HIPCK(hipMalloc(&p, sizeof(uint32_t)));
   dmax = static_cast<uint32_t*>(p);
@@ -321,6 +318,23 @@ dobfs_status finish_graph(dobfs_graph g, hipStream_t s) {
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(dmax);
   if (e != hipSuccess) return hip_fail(e, "max degree", __LINE__);
+  if ((flags & DOBFS_UPLOAD_HUBS_FIRST) && g->nnz > 0) {
+    // a reordered copy of CSC(A)'s indices, owned by the graph (the CSR side keeps its order)
+    HIPCK(hipMalloc(&p, size_t(g->nnz) * 4));
+    e = hubs_first(s, g->rowptr, g->colptr, g->rowind, static_cast<int32_t*>(p), g->V, g->nnz, g->max_outdeg);
+    if (e != hipSuccess) {
+      (void)hipFree(p);
+      return hip_fail(e, "in-neighbour reorder", __LINE__);
+    }
+    const bool own = g->owned[3] != nullptr && g->owned[3] == static_cast<const void*>(g->rowind);
+    if (own) (void)hipFree(g->owned[3]);
+    g->owned[3] = p;
+    g->rowind = static_cast<const int32_t*>(p);
+  }
+  HIPCK(hipMalloc(&p, size_t(std::max(g->V, 1)) * sizeof(int4)));
+  g->slab = static_cast<int4*>(p);
+  HIPCK(launch_slab(s, g->colptr, g->rowind, g->V, g->slab));
+  HIPCK(hipStreamSynchronize(s));
   return DOBFS_OK;
 }
 
@@ -618,7 +632,7 @@ dobfs_status dobfs_graph_upload(int32_t V, int64_t nnz, const int32_t* csr_rowpt
   t_last_error.clear();
   dobfs_status st = check_args(V, nnz, csr_rowptr, csr_colind, csc_colptr, csc_rowind, device, out);
   if (st != DOBFS_OK) return st;
-  if (flags & ~uint32_t(DOBFS_UPLOAD_VALIDATE))
+  if (flags & ~uint32_t(DOBFS_UPLOAD_VALIDATE | DOBFS_UPLOAD_HUBS_FIRST))
     return fail(DOBFS_ERR_INVALID_ARG, "unknown upload flags 0x%x", flags);
   if ((st = check_offsets_host(V, nnz, csr_rowptr, "csr_rowptr")) != DOBFS_OK) return st;
   if ((st = check_offsets_host(V, nnz, csc_colptr, "csc_colptr")) != DOBFS_OK) return st;
@@ -662,7 +676,7 @@ dobfs_status dobfs_graph_upload(int32_t V, int64_t nnz, const int32_t* csr_rowpt
     free_graph(g);
     return hip_fail(e == hipSuccess ? hipErrorOutOfMemory : e, "graph upload", __LINE__);
   }
-  if ((st = finish_graph(g, nullptr)) != DOBFS_OK) {
+  if ((st = finish_graph(g, nullptr, flags)) != DOBFS_OK) {
     free_graph(g);
     return st;
   }
@@ -677,7 +691,7 @@ dobfs_status dobfs_graph_wrap_device(int32_t V, int64_t nnz, const int32_t* csr_
   t_last_error.clear();
   dobfs_status st = check_args(V, nnz, csr_rowptr, csr_colind, csc_colptr, csc_rowind, device, out);
   if (st != DOBFS_OK) return st;
-  if (flags & ~uint32_t(DOBFS_UPLOAD_VALIDATE))
+  if (flags & ~uint32_t(DOBFS_UPLOAD_VALIDATE | DOBFS_UPLOAD_HUBS_FIRST))
     return fail(DOBFS_ERR_INVALID_ARG, "unknown upload flags 0x%x", flags);
   if ((st = check_device(device)) != DOBFS_OK) return st;
   DeviceScope ds(device);
@@ -707,7 +721,7 @@ dobfs_status dobfs_graph_wrap_device(int32_t V, int64_t nnz, const int32_t* csr_
   g->colind = csr_colind;
   g->colptr = csc_colptr;
   g->rowind = csc_rowind;
-  if ((st = finish_graph(g, s)) != DOBFS_OK) {
+  if ((st = finish_graph(g, s, flags)) != DOBFS_OK) {
     free_graph(g);
     return st;
   }

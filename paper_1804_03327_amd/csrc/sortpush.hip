@@ -14,6 +14,7 @@
 #include "device_common.h"
 
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_segmented_radix_sort.hpp>
 
 namespace dobfs {
 namespace {
@@ -126,7 +127,47 @@ __global__ __launch_bounds__(kThreads) void k_sort_filter(const uint32_t* keys, 
   if (tid == 0) stripe_add(slot, v[0], 0, uint64_t(i1 - i0), 0, 0);
 }
 
+// Sort key of CSC entry p: larger out-degree of its row first (maxdeg - deg).
+__global__ __launch_bounds__(kThreads) void k_hub_keys(const int32_t* rowind, const int32_t* rowptr, int64_t nnz,
+                                                       uint32_t maxdeg, uint32_t* keys) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < nnz; p += stride) {
+    const int32_t r = rowind[p];
+    keys[p] = maxdeg - uint32_t(rowptr[r + 1] - rowptr[r]);
+  }
+}
+
 }  // namespace
+
+hipError_t hubs_first(hipStream_t s, const int32_t* rowptr, const int32_t* colptr, const int32_t* rowind_in,
+                      int32_t* rowind_out, int32_t V, int64_t nnz, uint32_t maxdeg) {
+  if (nnz <= 0) return hipSuccess;
+  int bits = 1;
+  while (bits < 32 && (uint64_t(1) << bits) <= maxdeg) ++bits;
+  uint32_t *kin = nullptr, *kout = nullptr;
+  void* tmp = nullptr;
+  size_t tb = 0;
+  hipError_t e = hipMalloc(&kin, size_t(nnz) * 4);
+  if (e == hipSuccess) e = hipMalloc(&kout, size_t(nnz) * 4);
+  if (e == hipSuccess) {
+    const unsigned g = unsigned(std::min<int64_t>((nnz + kThreads - 1) / kThreads, 8192));
+    hipLaunchKernelGGL(k_hub_keys, dim3(g), dim3(kThreads), 0, s, rowind_in, rowptr, nnz, maxdeg, kin);
+    e = hipGetLastError();
+  }
+  // a stable sort within each column: equal degrees keep their stored (ascending id) order
+  if (e == hipSuccess)
+    e = rocprim::segmented_radix_sort_pairs(nullptr, tb, kin, kout, rowind_in, rowind_out, unsigned(nnz),
+                                            unsigned(V), colptr, colptr + 1, 0, unsigned(bits), s);
+  if (e == hipSuccess) e = hipMalloc(&tmp, std::max<size_t>(tb, 1));
+  if (e == hipSuccess)
+    e = rocprim::segmented_radix_sort_pairs(tmp, tb, kin, kout, rowind_in, rowind_out, unsigned(nnz),
+                                            unsigned(V), colptr, colptr + 1, 0, unsigned(bits), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (kin) (void)hipFree(kin);
+  if (kout) (void)hipFree(kout);
+  if (tmp) (void)hipFree(tmp);
+  return e;
+}
 
 size_t sort_push_bytes(int64_t nnz) {
   size_t tmp = 0;

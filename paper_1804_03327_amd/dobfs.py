@@ -18,6 +18,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "dobfs.h")
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_WORKSPACE_TOO_SMALL, ERR_UNSUPPORTED, \
     ERR_INTERNAL, ERR_TIMEOUT = range(8)
 UPLOAD_VALIDATE = 1
+UPLOAD_HUBS_FIRST = 2
 DIR_PUSH, DIR_PULL = 0, 1
 MODE_FULL, MODE_PUSH_ONLY, MODE_PULL_UNMASKED, MODE_PULL_MASKED, MODE_PULL_MASKED_EE, \
     MODE_PULL_ONLY, MODE_PUSH_SORT = range(7)

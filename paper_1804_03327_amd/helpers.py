@@ -23,10 +23,13 @@ def unpack_bits(words, V: int) -> np.ndarray:
     return np.unpackbits(w.view(np.uint8), bitorder="little")[:V].astype(bool)
 
 
-def upload(hg, device: int = 0, validate: bool = False) -> dobfs.Graph:
-    """Upload a host graph with CSR(A) (rowptr, colind) and CSC(A) (csc_colptr, csc_rowind)."""
+def upload(hg, device: int = 0, validate: bool = False, hubs_first: bool = False) -> dobfs.Graph:
+    """Upload a host graph with CSR(A) (rowptr, colind) and CSC(A) (csc_colptr, csc_rowind);
+    hubs_first keeps each row's in-neighbours ordered by decreasing out-degree on the device."""
+    flags = (dobfs.UPLOAD_VALIDATE if validate else 0) | (dobfs.UPLOAD_HUBS_FIRST if hubs_first else 0)
     return dobfs.graph_upload(hg.V, hg.nnz, hg.rowptr, hg.colind, hg.csc_colptr, hg.csc_rowind,
-                              device=device, flags=dobfs.UPLOAD_VALIDATE if validate else 0)
+                              device=device, flags=flags)
+
 
 
 class BfsRunner:

@@ -137,6 +137,44 @@ def test_push_sort_matches_oracle(graphs, name):
     assert e.value.status == dobfs.ERR_WORKSPACE_TOO_SMALL
 
 
+def _hubs_first_order(hg):
+    """Host copy of hg with every CSC column in the order DOBFS_UPLOAD_HUBS_FIRST gives it on the
+    device: decreasing out-degree of the in-neighbour, ties in stored order."""
+    import copy
+    deg = np.diff(hg.rowptr).astype(np.int64)
+    col = np.repeat(np.arange(hg.V, dtype=np.int64), np.diff(hg.csc_colptr))
+    order = np.lexsort((np.arange(hg.nnz), -deg[hg.csc_rowind], col))
+    out = copy.copy(hg)
+    out.csc_rowind = np.ascontiguousarray(hg.csc_rowind[order])
+    return out
+
+
+@pytest.mark.parametrize("name", ["rmat14", "directed100003", "lattice37"])
+def test_hubs_first_upload(name):
+    """In-neighbours reordered on the device by decreasing out-degree: depths unchanged, parents
+    valid, and a pull reports the first hit in the new order with the exact check count."""
+    hg = _graphs()[name]
+    g = upload(hg, hubs_first=True)
+    h2 = _hubs_first_order(hg)
+    r = BfsRunner(g)
+    for s in _sources(hg, 2, seed=4):
+        want, _ = oracle.bfs(hg, s)
+        fp2 = oracle.first_parent(h2, want, s)
+        for mode in ("full", "pull_only", "pull_masked_ee"):
+            tag = "%s hubs-first src=%d %s" % (name, s, mode)
+            r.run(s, mode=mode)
+            d, p = r.result()
+            assert np.array_equal(d, want), tag
+            assert oracle.validate(hg, s, d, p)[0] == 0, tag
+            for L, row in enumerate(r.levels()):
+                if row["dir"] != PULL:
+                    continue
+                lvl = want == L + 1
+                assert np.array_equal(p[lvl], fp2[lvl]), tag + ": level %d parents" % L
+                assert row["edges"] == oracle.pull_checks(h2, want, L), tag + ": level %d checks" % L
+    dobfs.graph_destroy(g)
+
+
 @pytest.mark.parametrize("name", ["rmat14", "directed100003", "lattice37"])
 def test_work_counts_match_table1(graphs, name):
     """Edges touched per level: push reads nnz(m_f^+); pull with early exit checks exactly the
