@@ -108,7 +108,7 @@ def measure_batched(args, heur, alpha, beta):
 
     hb = gen.rmat(args.batched_scale, args.edgefactor, seed=1)
     srcs = [int(x) for x in gen.sample_sources(hb, 64, seed=5)]
-    gb = upload(hb, device=0)
+    gb = upload(hb, device=0, hubs_first=not args.stored_order)
     stream = torch.cuda.current_stream()
     opt = dobfs.make_options("full", heur, alpha, beta)
     ws = torch.empty(dobfs.bfs_batch_workspace_bytes(gb, 64), dtype=torch.uint8, device="cuda")
@@ -183,7 +183,7 @@ def measure_serving(args, hg22, g22, heur, alpha, beta):
 
     specs = [("rmat16", gen.rmat(16, args.edgefactor, seed=1)), ("rmat20", gen.rmat(20, args.edgefactor, seed=1)),
              ("rmat22", hg22), ("grid2048", gen.grid2d(2048, 2048))]
-    gs = [g22 if h is hg22 else upload(h, device=0) for _, h in specs]
+    gs = [g22 if h is hg22 else upload(h, device=0, hubs_first=not args.stored_order) for _, h in specs]
     opt = dobfs.make_options("full", heur, alpha, beta)
     rng = np.random.default_rng(6)
     N = args.serve_queries
@@ -274,6 +274,8 @@ def main():
     ap.add_argument("--alpha", type=float, default=None)
     ap.add_argument("--beta", type=float, default=None)
     ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--stored-order", action="store_true",
+                    help="upload the graph without reordering in-neighbours (DOBFS_UPLOAD_HUBS_FIRST off)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the multi-source (64 sources per launch) RMAT-20 measurement")
     ap.add_argument("--no-autotune", action="store_true",
@@ -313,7 +315,7 @@ def main():
     if args.profile_batched:
         hb = gen.rmat(args.batched_scale, args.edgefactor, seed=1)
         srcs = [int(x) for x in gen.sample_sources(hb, 64, seed=5)]
-        gb = upload(hb, device=0)
+        gb = upload(hb, device=0, hubs_first=not args.stored_order)
         ws = torch.empty(dobfs.bfs_batch_workspace_bytes(gb, 64), dtype=torch.uint8, device="cuda")
         depth = torch.empty(64 * gb.V, dtype=torch.int32, device="cuda")
         heur_b = dobfs.HEUR_EDGES if args.heuristic == "edges" else dobfs.HEUR_RATIO
@@ -330,7 +332,9 @@ def main():
     log("generated rmat%d ef%d: V=%d nnz=%d in %.1fs" % (args.scale, args.edgefactor, hg.V, hg.nnz,
                                                           time.time() - t0))
     sources = [int(s) for s in gen.sample_sources(hg, args.sources, seed=2)]
-    g = upload(hg, device=0)
+    # in-neighbours by decreasing out-degree (DOBFS_UPLOAD_HUBS_FIRST), arranged once at upload
+    # like the CSR/CSC themselves and outside the timed region; --stored-order keeps the input order
+    g = upload(hg, device=0, hubs_first=not args.stored_order)
     outdeg = hg.out_degree()
     indeg_nz = hg.in_degree() > 0
     runner = BfsRunner(g, with_parent=True)
@@ -510,6 +514,22 @@ def main():
             ablation[mode] = round(sum(edges_g500[s] for s in sources) / dt / 1e9, 3)
         log("ablation GTEPS:", json.dumps(ablation))
 
+    # the same traversals on the graph in its stored in-neighbour order, for comparison
+    stored = None
+    if not args.stored_order and not args.no_ablation:
+        g_st = upload(hg, device=0)
+        for s in sources[:4]:
+            dobfs.bfs(g_st, s, runner.depth, runner.parent, opt_plain, runner.ws, stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(3):
+            for s in sources:
+                dobfs.bfs(g_st, s, runner.depth, runner.parent, opt_plain, runner.ws, stream=stream)
+        torch.cuda.synchronize()
+        stored = round(sum(edges_g500[s] for s in sources) / ((time.perf_counter() - t1) / 3) / 1e9, 3)
+        dobfs.graph_destroy(g_st)
+        log("stored in-neighbour order: %.2f GTEPS" % stored)
+
     # the other direction rule on the same workload, for comparison
     other = None
     if not args.no_ablation:
@@ -567,6 +587,7 @@ def main():
                    "directed_edges": hg.nnz, "sources_per_step": len(sources), "mode": "full",
                    "heuristic": "%s alpha=%.4g beta=%.4g" % (args.heuristic, alpha, beta),
                    "teps_edges": "graph500",
+                   "csc_order": "stored" if args.stored_order else "hubs_first",
                    "rmat_abcd": [0.57, 0.19, 0.19, 0.05], "graph_seed": 1, "source_seed": 2},
         "gteps_paper_convention": round(gteps_paper, 3),
         "bfs_ms_median": round(float(np.median(bfs_ms)), 4),
@@ -574,6 +595,7 @@ def main():
         "kernels": kernel_table,
         "cpu_baseline": cpu,
         "ablation_gteps": ablation,
+        "stored_order_gteps": stored,
         "other_direction_rule": other,
         "autotuned_direction_rule": autotuned,
         "validated": validated,
