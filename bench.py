@@ -413,9 +413,9 @@ def main():
     kinds = {k: {"ms": 0.0, "launches": 0, "bytes": 0.0} for k in
              ("level_prep", "level_main", "init", "main_push", "main_pull")}
 
-    def add(kind, ms, nbytes):
+    def add(kind, ms, nbytes, launches=1):
         kinds[kind]["ms"] += ms
-        kinds[kind]["launches"] += 1
+        kinds[kind]["launches"] += launches
         kinds[kind]["bytes"] += nbytes
 
     bfs_ms = []
@@ -427,6 +427,7 @@ def main():
             bfs_ms.append(st.ms_total)
             add("init", st.ms_init, bytes_init(hg.V))
             prev = dobfs.DIR_PUSH
+            prep_bytes = main_bytes = 0
             for L, lv in enumerate(dobfs.stats_levels(st)):
                 if lv["dir"] == dobfs.DIR_PUSH:
                     prep = bytes_push_scan(lv["nf"]) + (bytes_d2s(hg.V, lv["nf"]) if prev == dobfs.DIR_PULL else 0)
@@ -437,9 +438,14 @@ def main():
                     prep = 0
                     main = bytes_pull(hg.V, int(nc), lv["edges"], lv["n_new"])
                     add("main_pull", lv["ms_main"], main)
-                add("level_prep", lv["ms_aux"], prep)
-                add("level_main", lv["ms_main"], main)
+                prep_bytes += prep
+                main_bytes += main
                 prev = lv["dir"]
+            # every launch of the two level kernels, as a profiler counts them: the levels,
+            # the prep that finds the end, and the levels enqueued past the end (no work,
+            # no algorithmic bytes)
+            add("level_prep", st.ms_aux_all, prep_bytes, st.launches_aux)
+            add("level_main", st.ms_main_all, main_bytes, st.launches_main)
     dom = max(("level_prep", "level_main", "init"), key=lambda k: kinds[k]["ms"])
     kd = kinds[dom]
     avg_ms = kd["ms"] / max(1, kd["launches"])

@@ -167,7 +167,9 @@ typedef struct {
   int32_t dir;     /* direction of this level */
   int32_t nf;      /* frontier size entering the level, nnz(f) */
   int32_t n_new;   /* vertices discovered by the level */
-  int32_t pad;
+  int32_t variant; /* how a push level ran: 0 with a global scan of the frontier's degrees,
+                      1 block-local over the frontier list, 2 block-local over the bits the
+                      pull before it found; 0 for pull levels */
   int64_t edges;   /* push: nnz(m_f^+) adjacency entries read; pull: in-neighbours checked */
   int64_t m_f;     /* push: out-edges of the input frontier (0 on pull levels) */
   float ms_main;   /* execution time of the level's second kernel, the push expansion or the
@@ -184,6 +186,14 @@ typedef struct {
   float ms_total;           /* device time of the whole call (events) */
   float ms_init;            /* init kernel execution time (DOBFS_OPT_TIME_KERNELS) */
   int64_t reached;          /* vertices with depth >= 0 (multi-source: (vertex, source) pairs) */
+  /* Every launch of the two per-level kernels in the call, counted the way a kernel
+     profiler counts them: the `levels` levels, the first kernel of the level that finds
+     the end, and the levels enqueued past the end, which exit at once. The times need
+     DOBFS_OPT_TIME_KERNELS (else 0). The sort-based push mode leaves all four at 0. */
+  int32_t launches_main;    /* launches of the second kernel (push expansion / pull) */
+  int32_t launches_aux;     /* launches of the first kernel (direction + frontier scan) */
+  float ms_main_all;        /* their summed execution times */
+  float ms_aux_all;
 } dobfs_stats;
 
 /* ----------------------------------------------------------------- BFS */

@@ -12,6 +12,7 @@ What it computes (each function cites the passage it follows):
   complement and OR-accumulate (Equations 4-5, Section 3.2).
 * :func:`first_parent` -- the parent a first-hit pull reports (Section 5.3).
 * :func:`schedule` -- the push/pull direction sequence of the Section 6.3 rule.
+* :func:`schedule_edges` -- the same under Beamer's edge-count rule (Section 6.3).
 * :func:`level_work` -- per-level frontier sizes and the work of Table 1.
 
 Parity unpinned: parents chosen on push levels (any in-neighbour one level up
@@ -167,6 +168,36 @@ def schedule(sizes, V: int, alpha: float = 0.01, beta: float = 0.01, start: int 
             d = PULL
         elif d == PULL and nn < nf and nn < beta * V:
             d = PUSH
+    return dirs
+
+
+def schedule_edges(g, depth, alpha: float = 1 / 14, beta: float = 1 / 24, start: int = PUSH) -> list:
+    """Direction used at each level under Beamer's edge-count rule as Section 6.3 states it.
+
+    After level L (which found the vertices of depth L+1): in push, switch to pull when
+    nnz(m_f) > alpha * nnz(m_u), where m_f is the out-edges of the new frontier (depth L+1)
+    and m_u the in-edges of the vertices still unvisited (no depth yet, or depth > L+1); in
+    pull, switch back when nnz(f)/M < beta, f being the new frontier (M = number of rows).
+    alpha and beta are taken as float32 (the options store them so) and compared in double.
+    """
+    alpha, beta = float(np.float32(alpha)), float(np.float32(beta))
+    depth = np.asarray(depth)
+    sizes = level_sizes(depth)
+    outdeg = g.out_degree().astype(np.int64)
+    indeg = g.in_degree().astype(np.int64)
+    V = int(depth.size)
+    dirs = []
+    d = start
+    for L in range(len(sizes)):
+        dirs.append(d)
+        new = depth == L + 1
+        nn = int(new.sum())
+        m_f = int(outdeg[new].sum())
+        m_u = int(indeg[(depth < 0) | (depth > L + 1)].sum())
+        if d == PUSH:
+            d = PULL if float(m_f) > alpha * float(m_u) else PUSH
+        else:
+            d = PUSH if float(nn) < beta * float(V) else PULL
     return dirs
 
 

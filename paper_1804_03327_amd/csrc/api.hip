@@ -31,7 +31,9 @@ struct dobfs_graph_s {
   const int32_t* colptr = nullptr;  // CSC(A)
   const int32_t* rowind = nullptr;
   uint32_t* nz_in = nullptr;        // rows of CSC(A) with at least one entry
+  uint32_t* heavy = nullptr;        // rows of CSR(A) with more than kLocalDeg entries
   int4* slab = nullptr;             // first kSlab entries of every CSC(A) column (-1 past its end)
+  int32_t* head = nullptr;          // first entry of every CSC(A) column, complemented when more follow
   uint32_t max_outdeg = 0;          // largest CSR(A) row length
   std::atomic<int32_t> last_levels{8};  // level count of the previous BFS (first batch size)
   std::atomic<int32_t> last_levels_mb{8};  // the same for multi-source traversals
@@ -309,6 +311,9 @@ dobfs_status finish_graph(dobfs_graph g, hipStream_t s, uint32_t flags) {
   HIPCK(hipMalloc(&p, size_t(std::max(g->nwords, 1)) * 4));
   g->nz_in = static_cast<uint32_t*>(p);
   HIPCK(launch_nz_bits(s, g->colptr, g->V, g->nz_in));
+  HIPCK(hipMalloc(&p, size_t(std::max(g->nwords, 1)) * 4));
+  g->heavy = static_cast<uint32_t*>(p);
+  HIPCK(launch_nz_bits(s, g->rowptr, g->V, g->heavy, kLocalDeg));
   uint32_t* dmax = nullptr;
   HIPCK(hipMalloc(&p, sizeof(uint32_t)));
   dmax = static_cast<uint32_t*>(p);
@@ -333,7 +338,9 @@ dobfs_status finish_graph(dobfs_graph g, hipStream_t s, uint32_t flags) {
   }
   HIPCK(hipMalloc(&p, size_t(std::max(g->V, 1)) * sizeof(int4)));
   g->slab = static_cast<int4*>(p);
-  HIPCK(launch_slab(s, g->colptr, g->rowind, g->V, g->slab));
+  HIPCK(hipMalloc(&p, size_t(std::max(g->V, 1)) * sizeof(int32_t)));
+  g->head = static_cast<int32_t*>(p);
+  HIPCK(launch_slab(s, g->colptr, g->rowind, g->V, g->slab, g->head));
   HIPCK(hipStreamSynchronize(s));
   return DOBFS_OK;
 }
@@ -343,7 +350,9 @@ void free_graph(dobfs_graph g) {
   for (void* p : g->owned)
     if (p) (void)hipFree(p);
   if (g->nz_in) (void)hipFree(g->nz_in);
+  if (g->heavy) (void)hipFree(g->heavy);
   if (g->slab) (void)hipFree(g->slab);
+  if (g->head) (void)hipFree(g->head);
   if (g->ws) (void)hipFree(g->ws);
   delete g;
 }
@@ -389,7 +398,9 @@ BfsArgs bfs_args(dobfs_graph g, uint8_t* ws, const Layout& L, const dobfs_option
   a.colptr = g->colptr;
   a.rowind = g->rowind;
   a.slab = g->slab;
+  a.head = g->head;
   a.nz_in = g->nz_in;
+  a.heavy = g->heavy;
   a.depth = depth;
   a.parent = parent;
   a.vis[0] = reinterpret_cast<uint32_t*>(ws + L.visA);
@@ -425,6 +436,8 @@ struct LoopResult {
   int64_t sum_new = 0;  // vertices discovered over all levels
   int64_t sum_aux = 0;  // multi-source: (vertex, source) pairs discovered
   LevelState end{};     // state after the last level
+  int32_t n_main = 0, n_aux = 0;            // every launch of the two level kernels
+  float ms_main_all = 0.f, ms_aux_all = 0.f;  // their execution times (when timing)
 };
 
 // The level loop shared by the single- and multi-source traversals. Level l
@@ -452,6 +465,7 @@ dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool t
   float first_aux = 0.f;  // prep time of a batch's first level
   auto E = [&](int i) -> hipEvent_t { return timing ? ev[i] : nullptr; };
   HIPCK(prep(0, forced(0), E(ev_p0(0)), E(ev_p1(0))));
+  res->n_aux = 1;
   while (true) {
     if (lvl + batch > max_levels) batch = int32_t(max_levels - lvl);
     const int64_t l1 = lvl + batch - 1;
@@ -463,7 +477,17 @@ dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool t
     const uint32_t seq = ++report_seq;
     HIPCK(launch_report(s, ctrl, int32_t(lvl), batch, rep, seq));
     HIPCK(wait_report(rep, seq, s));
-    if (timing && lvl == 0) first_aux = elapsed(ev[ev_p0(0)], ev[ev_p1(0)]);
+    if (timing && lvl == 0) {
+      first_aux = elapsed(ev[ev_p0(0)], ev[ev_p1(0)]);
+      res->ms_aux_all += first_aux;
+    }
+    res->n_main += batch;
+    res->n_aux += batch;
+    if (timing)
+      for (int32_t k = 0; k < batch; ++k) {
+        res->ms_main_all += elapsed(ev[ev_m0(k)], ev[ev_m1(k)]);
+        res->ms_aux_all += elapsed(ev[ev_p0(k + 1)], ev[ev_p1(k + 1)]);
+      }
     const LevelState& end = rep->end;
     const int64_t last = end.done ? int64_t(end.levels) - 1 : l1;  // last level that ran
     for (int64_t l = lvl; l <= last; ++l) {
@@ -476,7 +500,7 @@ dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool t
         ls.dir = r.dir;
         ls.nf = r.nf;
         ls.n_new = r.n_new;
-        ls.pad = 0;
+        ls.variant = r.variant;
         ls.edges = r.edges;
         ls.m_f = r.m_f;
         ls.ms_aux = timing ? (k == 0 ? first_aux : elapsed(ev[ev_p0(k)], ev[ev_p1(k)])) : 0.f;
@@ -553,7 +577,7 @@ dobfs_status bfs_sort_push(dobfs_graph g, int32_t source, const dobfs_options& o
         ls.dir = r.dir;
         ls.nf = r.nf;
         ls.n_new = r.n_new;
-        ls.pad = 0;
+        ls.variant = 0;
         ls.edges = r.edges;
         ls.m_f = r.m_f;
         ls.ms_main = 0.f;
@@ -586,6 +610,8 @@ dobfs_status bfs_sort_push(dobfs_graph g, int32_t source, const dobfs_options& o
     stats->ms_total = elapsed(ev[kEvStart], ev[kEvEnd]);
     stats->ms_init = 0.f;
     stats->reached = reached;
+    stats->launches_main = stats->launches_aux = 0;
+    stats->ms_main_all = stats->ms_aux_all = 0.f;
   }
   return DOBFS_OK;
 }
@@ -809,6 +835,10 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
     stats->ms_total = elapsed(ev[kEvStart], ev[kEvEnd]);
     stats->ms_init = timing ? elapsed(ev[kEvInit0], ev[kEvInit1]) : 0.f;
     stats->reached = 1 + res.sum_new;
+    stats->launches_main = res.n_main;
+    stats->launches_aux = res.n_aux;
+    stats->ms_main_all = res.ms_main_all;
+    stats->ms_aux_all = res.ms_aux_all;
   }
   return DOBFS_OK;
 }
@@ -928,6 +958,10 @@ dobfs_status dobfs::bfs_batch_rows(dobfs_graph g, const int32_t* sources, int32_
     stats->ms_total = elapsed(ev[kEvStart], ev[kEvEnd]);
     stats->ms_init = timing ? elapsed(ev[kEvInit0], ev[kEvInit1]) : 0.f;
     stats->reached = k + res.sum_aux;  // (vertex, source) pairs, the sources included
+    stats->launches_main = res.n_main;
+    stats->launches_aux = res.n_aux;
+    stats->ms_main_all = res.ms_main_all;
+    stats->ms_aux_all = res.ms_aux_all;
   }
   return DOBFS_OK;
 }
@@ -994,6 +1028,7 @@ dobfs_status dobfs_mxv(dobfs_graph g, const uint32_t* x_bits, const int32_t* x_i
     pa.colptr = g->colptr;
     pa.rowind = g->rowind;
     pa.slab = g->slab;
+    pa.head = g->head;
     pa.x = x;
     pa.mask = mask_bits;
     pa.complement = complement ? 1 : 0;

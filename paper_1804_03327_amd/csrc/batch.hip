@@ -81,6 +81,7 @@ __global__ __launch_bounds__(kThreads) void k_mb_init(BatchArgs a, int32_t dir0,
       st.levels = 0;
       st.level = 0;
       st.local = 0;
+      st.share = 1;
       st.m_u = a.nnz;  // in-edges of vertices some source has not reached yet
       st.active = a.active;
       c->ring[0] = st;
@@ -410,7 +411,7 @@ __global__ __launch_bounds__(kThreads) void k_mb_prep(BatchArgs a, int32_t L, in
     scan_list(a.Q[L % 2], st.nf, a.rowptr, a.S, a.R, a.chunk_first, a.flagsA, uint32_t(2 * L + 1),
               &c->ticket[L % 2], mf_out);
   } else {
-    ScanBitsArgs sb;
+    ScanBitsArgs sb{};
     sb.a = a.nzF;
     sb.b_not = nullptr;
     sb.nwords = a.nwords;

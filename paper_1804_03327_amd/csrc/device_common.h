@@ -125,7 +125,9 @@ __device__ __forceinline__ void zero_stripe(Stripe& st) {
   st.mnew = 0;
   st.insub = 0;
   st.fbits = 0;
+  st.mu = 0;
   st.maxdeg = 0;
+  st.tilemax = 0;
 }
 
 // Raises a block's stripe's largest discovered out-degree (thread 0 only).
@@ -335,6 +337,21 @@ __device__ void scan_bits(const ScanBitsArgs& a) {
         }
       }
     }
+    if (a.mu_slot) {  // in-edges of the rows nobody has reached yet (m_u of the edge-count rule)
+      unsigned long long mu[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int k = 0; k < kBitsWPT; ++k) {
+        const int32_t w = wbase + k;
+        uint32_t u = w < a.nwords ? (a.unv_nz[w] & ~a.unv_vis[w] & valid_bits(w, a.V)) : 0u;
+        while (u) {
+          const int32_t v = w * 32 + __ffs(u) - 1;
+          mu[0] += uint64_t(a.colptr[v + 1] - a.colptr[v]);
+          u &= u - 1;
+        }
+      }
+      block_sum4(mu);
+      if (threadIdx.x == 0 && mu[0]) atomicAdd(&a.mu_slot->s[blockIdx.x % kStripes].mu, mu[0]);
+    }
     uint32_t agg_c, agg_d = 0;
     const uint32_t excl_c = block_excl_scan(c, &agg_c);
     uint32_t excl_d = 0;
@@ -375,6 +392,15 @@ __device__ __forceinline__ int32_t thread_search(const int32_t* S, int32_t lo, i
   return lo;
 }
 
+// Whether the scan of a push that follows a pull recounts m_u (see scan_bits):
+// the single-source traversal under the edge-count rule. Its pulls then skip
+// the in-degrees of the rows they find.
+__device__ __forceinline__ bool recounts_mu(const BfsArgs& a) { return a.edge_rule != 0; }
+__device__ __forceinline__ bool recounts_mu(const BatchArgs&) { return false; }
+// The multi-source traversal also needs the (vertex, source) pair counts and the source bits.
+__host__ __device__ constexpr bool is_batch(const BfsArgs&) { return false; }
+__host__ __device__ constexpr bool is_batch(const BatchArgs&) { return true; }
+
 // The state entering level L, from the state entering L-1 and the counters
 // L-1 left: the direction rule of Section 6.3 (or Beamer's edge form),
 // forced directions and mode overrides, buffer parities. Every thread
@@ -386,7 +412,7 @@ template <class Args>
 __device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, LevelTotals* tot_out,
                                   LevelState* prev_out) {
   const Ctrl* c = a.ctrl;
-  LevelTotals t{0, 0, 0, 0, 0};
+  LevelTotals t{0, 0, 0, 0, 0, 0};
   LevelState st;
   if (L == 0) {
     st = c->ring[0];
@@ -406,24 +432,31 @@ __device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, Leve
   const uint64_t v1 = mine ? sk->edges : 0ull, v2 = mine ? sk->mnew : 0ull, v3 = mine ? sk->insub : 0ull;
   const uint64_t v4 = mine ? sk->fbits : 0ull;
   const uint32_t v5 = mine ? sk->maxdeg : 0u;
+  const uint64_t v6 = mine ? sk->mu : 0ull;
+  const uint32_t v7 = mine ? sk->tilemax : 0u;
   const LevelState prev = c->ring[(L - 1) % kRing];
   *prev_out = prev;
   st = prev;
   st.level = L;
   if (!prev.done) {
-    const uint64_t lo = wave_sum64(v0 & 0xffffffffull), hi = wave_sum64(v0 >> 32);
-    const uint64_t fb = uniform64(wave_or64(v4));
-    t.count = uniform64(lo);
-    t.aux = uniform64(hi);
+    // each cross-lane reduction costs a few hundred cycles of a launch every level runs, so
+    // only the totals this traversal and level use are formed (the branches are uniform)
+    constexpr bool batch = is_batch(Args{});
+    t.count = uniform64(wave_sum64(v0 & 0xffffffffull));
     t.edges = uniform64(wave_sum64(v1));
     t.mnew = uniform64(wave_sum64(v2));
-    t.insub = uniform64(wave_sum64(v3));
+    if (batch) t.aux = uniform64(wave_sum64(v0 >> 32));
+    if (a.edge_rule) t.insub = uniform64(wave_sum64(v3));
     if (t.count == 0) {
       st.done = 1;
       st.levels = L;
     } else {
       const int64_t n_new = int64_t(t.count);
-      const int64_t m_u = prev.m_u - (a.edge_rule ? int64_t(t.insub) : 0);
+      // m_u loses the in-edges of each push level's winners; pulls leave it alone, and the
+      // scan of the push that follows a pull recounts it (single source)
+      const bool recounted = recounts_mu(a) && prev.dir == 0 && !prev.list_valid;
+      if (recounted) t.mu = uniform64(wave_sum64(v6));
+      const int64_t m_u = (recounted ? int64_t(t.mu) : prev.m_u) - (a.edge_rule ? int64_t(t.insub) : 0);
       int32_t next = next_direction_rule(a.heuristic, a.alpha, a.beta, prev.dir, a.V, prev.nf, n_new,
                                          int64_t(t.mnew), m_u);
       if (a.mode == 1) next = 0;  // push only
@@ -434,11 +467,30 @@ __device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, Leve
       st.list_valid = prev.dir == 0 ? 1 : 0;  // a push level appended its winners to Q[L % 2]
       st.vis_idx = prev.dir == 1 ? (prev.vis_idx ^ 1) : prev.vis_idx;
       st.m_u = m_u;
-      st.active = fb;
-      // a push after a push gets its frontier as a list; small degrees need no global scan
-      const uint32_t md = __builtin_amdgcn_readfirstlane(wave_max32(v5));
-      st.local = (a.local_push && next == 0 && prev.dir == 0 && (a.low_degree || md <= uint32_t(kLocalDeg)))
-                     ? 1 : 0;
+      st.active = batch ? uniform64(wave_or64(v4)) : 0ull;
+      // a push needs no global scan when its frontier's edges can be shared out inside
+      // blocks: a list from a push whose sizes local_fits() accepts (local 1), or the bits a
+      // pull left when no tile found more than kBitmapLocalRows rows and none of high
+      // out-degree (local 2: every block expands its own slice of the bitmap)
+      st.local = 0;
+      st.share = 1;
+      if (a.local_push && next == 0) {
+        if (prev.dir == 0) {
+          // a push's winners' out-degrees are tracked unless the graph is low-degree and the
+          // rule needs no m_f; then kLocalDeg bounds them
+          const bool tracked = a.edge_rule || !a.low_degree;
+          const int64_t mf_b = tracked ? int64_t(t.mnew) : INT64_MAX;
+          const int64_t md_b = tracked ? int64_t(__builtin_amdgcn_readfirstlane(wave_max32(v5))) : int64_t(kLocalDeg);
+          const int64_t G = main_blocks(a.nwords);
+          if (a.low_degree || local_fits(n_new, mf_b, md_b, G)) {
+            st.local = 1;
+            st.share = local_share(n_new, mf_b, md_b, G);
+          }
+        } else {
+          const uint32_t tm = __builtin_amdgcn_readfirstlane(wave_max32(v7));
+          st.local = tm <= uint32_t(kBitmapLocalRows) ? 2 : 0;
+        }
+      }
     }
   }
   *tot_out = t;
@@ -459,7 +511,7 @@ __device__ void publish_level(Ctrl* c, int32_t L, const LevelState& st, const Le
         r.dir = prev.dir;
         r.nf = prev.nf;
         r.n_new = int32_t(tot.count);
-        r.pad = 0;
+        r.variant = prev.dir == 0 ? prev.local : 0;
         r.edges = int64_t(tot.edges);
         // a scanned push level's m_f comes from its scan; a local one reads exactly its m_f edges
         r.m_f = prev.dir == 0 ? (prev.local ? int64_t(tot.edges) : int64_t(c->mf[(L - 1) % kSlots])) : 0;

@@ -24,7 +24,11 @@ struct alignas(128) Stripe {
   uint64_t insub;  // in-edges of the vertices discovered (edge-count rule only; multi-source:
                    // of the vertices every source has now reached)
   uint64_t fbits;  // multi-source: OR of the source bits discovered
+  uint64_t mu;     // edge-count rule, single source: in-edges of the vertices still unvisited
+                   // entering a push that follows a pull, recounted by that level's scan
   uint32_t maxdeg; // largest out-degree of the vertices a push level discovered
+  uint32_t tilemax; // pull levels: most rows found in one tile, or UINT32_MAX when a found row
+                    // has an out-degree above kLocalDeg
 };
 struct LevelSlot {
   Stripe s[kStripes];
@@ -40,14 +44,15 @@ struct alignas(64) LevelState {
   int32_t nf;          // frontier size entering the level
   int32_t levels;      // when done: number of levels run
   int32_t level;       // index of this level
-  int32_t local;       // push level whose frontier is a list of small out-degrees: expanded with
-                       // block-local load balancing, no global scan
+  int32_t local;       // push level expanded with block-local load balancing, no global scan:
+                       // 1 over the frontier list, 2 over the bits the previous pull found
+  int32_t share;       // local 1: blocks that share one unit's edge chunks (local_share)
   int64_t m_u;         // edge-count rule: in-edges of still-unvisited vertices
   uint64_t active;     // multi-source: sources whose frontier entering the level is non-empty
 };
 // Per-level statistics for the host, written by the next level's first kernel.
 struct LevelRecord {
-  int32_t dir, nf, n_new, pad;
+  int32_t dir, nf, n_new, variant;  // variant: dobfs_level_stats.variant
   int64_t edges, m_f;
   uint64_t mnew, insub;
   uint64_t aux;        // multi-source: (vertex, source) pairs discovered
@@ -72,16 +77,17 @@ static_assert(offsetof(Ctrl, slot) % 128 == 0, "slots start on a line");
 
 // Host-side totals of one level.
 struct LevelTotals {
-  uint64_t count, aux, edges, mnew, insub;
+  uint64_t count, aux, edges, mnew, insub, mu;
 };
 inline LevelTotals sum_slot(const LevelSlot& s) {
-  LevelTotals t{0, 0, 0, 0, 0};
+  LevelTotals t{0, 0, 0, 0, 0, 0};
   for (int k = 0; k < kStripes; ++k) {
     t.count += s.s[k].count;
     t.aux += s.s[k].aux;
     t.edges += s.s[k].edges;
     t.mnew += s.s[k].mnew;
     t.insub += s.s[k].insub;
+    t.mu += s.s[k].mu;
   }
   return t;
 }
@@ -105,14 +111,53 @@ constexpr int kSlab = 4;                             // in-neighbours per row ke
 constexpr int kPullFirst = kSlab;                    // pull phase 1 checks a row's slab entries
 constexpr int kPullMid = 32;                         // rows still open continue thread-per-row up to here
 constexpr int kPullStep = 4;                         // in-neighbours a thread loads at once past kPullFirst
-constexpr int kPullBatch = 4;                        // candidate rows a thread works on at once
-constexpr int kLocalDeg = 32;                        // local push: largest out-degree in the frontier
+constexpr int kPullBatch = 4;                        // open rows a thread works on at once (slab)
+constexpr int kPullHeadBatch = 8;                    // candidate rows a thread works on at once (head)
+constexpr int kLocalDeg = 32;                        // graphs with no out-degree above this always push locally
 constexpr int kLocalUnit = 128;                      // local push: frontier vertices a block takes at once
+constexpr int kLocalChunks = 4;                      // local push: most edge chunks one block may get
+constexpr int kBitmapLocalRows = 512;                // bitmap push: most frontier rows in one pull tile
 
 inline int32_t words_of(int64_t V) { return int32_t((V + 31) / 32); }
 inline int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 inline int64_t bits_tiles(int64_t nwords) { return (nwords + kBitsTile - 1) / kBitsTile; }
-inline int64_t pull_tiles(int64_t nwords) { return (nwords + kPullTileWords - 1) / kPullTileWords; }
+__host__ __device__ inline int64_t pull_tiles(int64_t nwords) {
+  return (nwords + kPullTileWords - 1) / kPullTileWords;
+}
+// Blocks of a level's second kernel: the pull's tiles, at least the push's expand grid.
+__host__ __device__ inline int64_t main_blocks(int64_t nwords) {
+  const int64_t t = pull_tiles(nwords);
+  return t > kExpandBlocks ? t : kExpandBlocks;
+}
+// Whether a push over a frontier list of nf vertices with m_f out-edges in all, none above
+// maxdeg, can balance its load inside blocks (no global degree scan): the list is cut into
+// units of kLocalUnit vertices, a unit holds at most min(m_f, kLocalUnit * maxdeg) edges, and
+// when there are fewer units than blocks each unit's edge chunks are shared by
+// blocks / units blocks. Local when no block gets more than kLocalChunks chunks of a unit.
+// (Every thread of a level's first kernel evaluates this: 32-bit arithmetic, one division.)
+__host__ __device__ inline uint32_t local_unit_chunks_bound(int64_t m_f, int64_t maxdeg) {
+  const int64_t cap = int64_t(kLocalUnit) * maxdeg;
+  const int64_t edges = m_f < cap ? m_f : cap;
+  const int64_t chunks = (edges + kExpandChunk - 1) >> 10;  // kExpandChunk = 1024
+  return chunks > 0xffffffffll ? 0xffffffffu : uint32_t(chunks);
+}
+__host__ __device__ inline uint32_t local_units(int64_t nf) { return uint32_t((nf + kLocalUnit - 1) >> 7); }
+__host__ __device__ inline bool local_fits(int64_t nf, int64_t m_f, int64_t maxdeg, int64_t blocks) {
+  static_assert(kExpandChunk == 1024 && kLocalUnit == 128, "shifts below");
+  const uint32_t units = local_units(nf);
+  if (units == 0) return true;
+  const uint32_t per_unit = units < uint32_t(blocks) ? uint32_t(blocks) / units : 1u;
+  return uint64_t(local_unit_chunks_bound(m_f, maxdeg)) <= uint64_t(kLocalChunks) * per_unit;
+}
+// Blocks that share each unit's chunks in a local push: as many as the unit's
+// chunks could need, at most blocks / units (so idle blocks exit at once).
+__host__ __device__ inline int32_t local_share(int64_t nf, int64_t m_f, int64_t maxdeg, int64_t blocks) {
+  const uint32_t units = local_units(nf);
+  if (units == 0 || units >= uint32_t(blocks)) return 1;
+  const uint32_t chunks = local_unit_chunks_bound(m_f, maxdeg);
+  const uint32_t most = uint32_t(blocks) / units;
+  return int32_t(chunks < 1u ? 1u : (chunks < most ? chunks : most));
+}
 inline int64_t max_chunks(int64_t nnz) { return nnz / kExpandChunk + 2; }
 inline int64_t flag_entries(int64_t V) {
   const int64_t a = scan_tiles(V), b = bits_tiles(words_of(V));
@@ -129,6 +174,7 @@ struct PullArgs {
   const int32_t* colptr;
   const int32_t* rowind;
   const int4* slab;          // first kSlab entries of every CSC column (-1 past its end)
+  const int32_t* head;       // first entry of every CSC column: j, or ~j when more follow
   const uint32_t* x;         // input vector bits
   const uint32_t* mask;      // nullable: rows that pass = mask XOR complement
   int32_t complement;
@@ -142,7 +188,7 @@ struct PullArgs {
   int32_t level;
   int32_t early_exit;
   int32_t count_out;         // 1: add popcount(out) to the stripes' aux (mxv)
-  int32_t edge_rule;         // 1: add in-degrees of the results to the stripes' insub
+  const uint32_t* heavy;     // nullable: rows of out-degree above kLocalDeg (tilemax bookkeeping)
   LevelSlot* slot;
 };
 
@@ -166,6 +212,13 @@ struct ExpandArgs {
   const int32_t* rowptr;     // CSR(A) offsets (local push: degrees of the frontier)
   const int32_t* out_rowptr; // nullable: out-degrees of winners -> mnew
   const int32_t* in_colptr;  // nullable: in-degrees of winners -> insub
+  // bitmap push (a frontier the previous pull left as bits): the frontier bits, the visited
+  // set before that pull, rows with in-edges, and where the recount of m_u goes (nullable)
+  int32_t share;             // local list push: blocks per unit (LevelState::share)
+  const uint32_t* front;
+  const uint32_t* vis_before;
+  const uint32_t* nz;
+  LevelSlot* mu_slot;
   LevelSlot* slot;
 };
 
@@ -179,7 +232,9 @@ struct BfsArgs {
   const int32_t* colptr;
   const int32_t* rowind;
   const int4* slab;          // first kSlab entries of every CSC column (-1 past its end)
+  const int32_t* head;       // first entry of every CSC column: j, or ~j when more follow
   const uint32_t* nz_in;
+  const uint32_t* heavy;     // vertices of out-degree above kLocalDeg
   int32_t* depth;
   int32_t* parent;
   uint32_t* vis[2];
@@ -257,6 +312,12 @@ struct ScanBitsArgs {
   unsigned long long* ticket;
   uint32_t* nf_out;          // list length
   uint32_t* mf_out;          // total degree (when rowptr)
+  // nullable: also add up the in-degrees of the rows set in unv_nz AND NOT unv_vis (the
+  // vertices still unvisited) into mu_slot's stripes
+  LevelSlot* mu_slot;
+  const uint32_t* unv_nz;
+  const uint32_t* unv_vis;
+  const int32_t* colptr;
 };
 
 // ---- launchers (kernels.hip, batch.hip); each returns hipGetLastError() ----
@@ -278,8 +339,10 @@ hipError_t launch_fill(hipStream_t s, uint32_t* p, int64_t n, uint32_t v);
 hipError_t launch_s2d(hipStream_t s, const int32_t* idx, int32_t n, int32_t V, uint32_t* bits);
 hipError_t launch_mxv_finalize(hipStream_t s, uint32_t* y, const uint32_t* r, int32_t nwords,
                                int32_t V, int accum, LevelSlot* slot);
-hipError_t launch_nz_bits(hipStream_t s, const int32_t* ptr, int32_t V, uint32_t* bits);
-hipError_t launch_slab(hipStream_t s, const int32_t* ptr, const int32_t* ind, int32_t V, int4* slab);
+// bit v set when row v of the offsets has more than min_len entries
+hipError_t launch_nz_bits(hipStream_t s, const int32_t* ptr, int32_t V, uint32_t* bits, int32_t min_len = 0);
+hipError_t launch_slab(hipStream_t s, const int32_t* ptr, const int32_t* ind, int32_t V, int4* slab,
+                       int32_t* head);
 hipError_t launch_max_degree(hipStream_t s, const int32_t* ptr, int32_t V, uint32_t* out);
 // What the host needs after a batch of levels: the state after the batch and
 // the records of its levels. Written into pinned host memory by one block,

@@ -166,116 +166,201 @@ __device__ void expand_body(const ExpandArgs& a, ExpandShared& sh) {
   }
 }
 
-// Push for a frontier list whose out-degrees are all at most kLocalDeg:
-// the load balancing of the column-based matvec is done inside each block,
-// so the level needs no global degree scan. A block takes kLocalUnit
-// frontier vertices at a time, scans their degrees in LDS and walks the unit's edges
-// 1024 at a time, each edge finding its vertex by a search over the unit's
-// prefix; the claim and the winners' bookkeeping are those of expand_body.
+// Pushes that need no global degree scan: the load balancing of the
+// column-based matvec is done inside each block. A block takes kLocalUnit
+// frontier vertices at a time (a unit), scans their degrees in LDS and walks
+// the unit's edges kExpandChunk at a time, each edge finding its vertex by a
+// search over the unit's prefix; the claim and the winners' bookkeeping are
+// those of expand_body.
 struct LocalShared {
   int32_t off[kThreads + 1], beg[kThreads], src[kThreads];
   int32_t buf[kExpandBuf];
+  uint16_t list[kPullTileV];  // bitmap push: the block's frontier rows (offsets in its slice)
   uint32_t nbuf, base;
 };
 
+struct LocalAcc {
+  unsigned long long won = 0, mnew = 0, insub = 0, edges = 0;
+  uint32_t maxdeg = 0;
+};
+
+// Appends the buffered winners to the next frontier list (all threads; the
+// callers are past a barrier).
+__device__ __forceinline__ void local_flush(const ExpandArgs& a, LocalShared& sh) {
+  const uint32_t nb = sh.nbuf;
+  if (nb == 0) return;
+  if (threadIdx.x == 0) sh.base = atomicAdd(a.qcount, nb);
+  __syncthreads();
+  const uint32_t b = sh.base;
+  for (uint32_t k = threadIdx.x; k < nb; k += kThreads) a.Qout[b + k] = sh.buf[k];
+  __syncthreads();
+  if (threadIdx.x == 0) sh.nbuf = 0;
+  __syncthreads();
+}
+
+// Loads unit vertex v (-1: none) of this thread, scans the unit's degrees
+// into sh.off / beg / src and returns the unit's edge count. The scan's
+// first barrier also orders the previous unit's LDS reads before the writes.
+__device__ __forceinline__ uint32_t local_unit_prefix(const ExpandArgs& a, LocalShared& sh, int32_t v) {
+  int32_t b = 0, d = 0;
+  if (v >= 0) {
+    b = a.rowptr[v];
+    d = a.rowptr[v + 1] - b;
+  }
+  uint32_t total;
+  const uint32_t ex = block_excl_scan(uint32_t(d), &total);
+  sh.off[threadIdx.x] = int32_t(ex);
+  sh.beg[threadIdx.x] = b;
+  sh.src[threadIdx.x] = v;
+  if (threadIdx.x == 0) sh.off[kThreads] = int32_t(total);
+  return total;
+}
+
+// The chunks first, first + step, ... of a unit of n vertices whose prefix
+// local_unit_prefix() wrote.
+__device__ __forceinline__ void local_unit_chunks(const ExpandArgs& a, LocalShared& sh, int32_t n, uint32_t total, uint32_t first,
+                                  uint32_t step, LocalAcc& acc) {
+  const int tid = threadIdx.x;
+  for (uint32_t e0 = first; e0 < total; e0 += step) {
+    __syncthreads();  // the unit's prefix is written, nbuf is settled
+    if (sh.nbuf + kExpandChunk > uint32_t(kExpandBuf)) local_flush(a, sh);
+    int32_t w[kExpandEPT], uu[kExpandEPT];
+    bool valid[kExpandEPT], won[kExpandEPT];
+#pragma unroll
+    for (int t = 0; t < kExpandEPT; ++t) {
+      const uint32_t e = e0 + uint32_t(t * kThreads + tid);
+      valid[t] = e < total;
+      w[t] = 0;
+      uu[t] = 0;
+      if (valid[t]) {
+        const int32_t k = thread_search(sh.off, 0, n, e);
+        uu[t] = sh.src[k];
+        w[t] = a.colind[sh.beg[k] + int32_t(e - uint32_t(sh.off[k]))];
+      }
+    }
+    uint32_t seen[kExpandEPT];
+#pragma unroll
+    for (int t = 0; t < kExpandEPT; ++t) seen[t] = valid[t] ? a.claim[w[t] >> 5] : 0xffffffffu;
+#pragma unroll
+    for (int t = 0; t < kExpandEPT; ++t) {
+      const uint32_t bit = 1u << (w[t] & 31);
+      won[t] = false;
+      if (valid[t] && !(seen[t] & bit)) won[t] = !(atomicOr(a.claim + (w[t] >> 5), bit) & bit);
+    }
+#pragma unroll
+    for (int t = 0; t < kExpandEPT; ++t) {
+      if (won[t]) {
+        ++acc.won;
+        a.depth[w[t]] = a.level + 1;
+        if (a.parent) a.parent[w[t]] = uu[t];
+        if (a.found_out) atomicOr(a.found_out + (w[t] >> 5), 1u << (w[t] & 31));
+        if (a.out_rowptr) {
+          const uint32_t dw = uint32_t(a.out_rowptr[w[t] + 1] - a.out_rowptr[w[t]]);
+          acc.mnew += dw;
+          acc.maxdeg = max(acc.maxdeg, dw);
+        }
+        if (a.in_colptr) acc.insub += uint64_t(a.in_colptr[w[t] + 1] - a.in_colptr[w[t]]);
+      }
+      const uint64_t bal = __ballot(won[t]);
+      if (bal) {
+        const int cnt = __popcll(bal);
+        const int leader = __ffsll((unsigned long long)bal) - 1;
+        uint32_t p = 0;
+        if (lane() == leader) p = atomicAdd(&sh.nbuf, uint32_t(cnt));
+        p = __shfl(p, leader, 64);
+        if (won[t]) sh.buf[p + __popcll(bal & lanemask_lt())] = w[t];
+      }
+    }
+  }
+}
+
+// A block's counters into the level's stripes (all threads).
+__device__ __forceinline__ void local_finish(const ExpandArgs& a, LocalShared& sh, LocalAcc& acc, unsigned long long mu) {
+  __syncthreads();
+  local_flush(a, sh);
+  unsigned long long vv[4] = {acc.won, acc.mnew, acc.insub, acc.edges};
+  block_sum4(vv);
+  unsigned long long vm[4] = {mu, 0, 0, 0};
+  if (a.mu_slot) block_sum4(vm);
+  const uint32_t maxdeg = block_max32(acc.maxdeg);
+  if (threadIdx.x == 0) {
+    stripe_add(a.slot, vv[0], 0, vv[3], vv[1], vv[2]);
+    stripe_max(a.slot, maxdeg);
+    if (vm[0]) atomicAdd(&a.mu_slot->s[blockIdx.x % kStripes].mu, vm[0]);
+  }
+}
+
+// Push over a frontier list whose sizes local_fits() accepts: with fewer
+// units than blocks, each unit gets a.share blocks (local_share: what its
+// chunks could need, at most gridDim / units), which all scan the unit's
+// degrees and take its chunks in turn; otherwise a block takes whole units.
 __device__ void local_expand_body(const ExpandArgs& a, LocalShared& sh) {
   const int32_t nf = a.nf;
   const int32_t nunits = (nf + kLocalUnit - 1) / kLocalUnit;
+  const int32_t G = int32_t(gridDim.x);
+  const int32_t per_unit = max(1, a.share);  // blocks sharing one unit's chunks (at most G / nunits)
+  const int32_t nwork = nunits * per_unit;     // (unit, share) pairs
+  if (int32_t(blockIdx.x) >= nwork) return;                // no work: no counters to add
   const int tid = threadIdx.x;
   if (tid == 0) sh.nbuf = 0;
-  unsigned long long won_total = 0, mnew = 0, insub = 0, edges = 0;
-  uint32_t maxdeg = 0;
-
-  auto flush = [&]() {  // all threads; callers are past a barrier
-    const uint32_t nb = sh.nbuf;
-    if (nb == 0) return;
-    if (tid == 0) sh.base = atomicAdd(a.qcount, nb);
-    __syncthreads();
-    const uint32_t b = sh.base;
-    for (uint32_t k = tid; k < nb; k += kThreads) a.Qout[b + k] = sh.buf[k];
-    __syncthreads();
-    if (tid == 0) sh.nbuf = 0;
-    __syncthreads();
-  };
-
-  for (int32_t u = blockIdx.x; u < nunits; u += gridDim.x) {
+  LocalAcc acc;
+  for (int32_t wi = blockIdx.x; wi < nwork; wi += G) {
+    const int32_t u = per_unit == 1 ? wi : wi / per_unit, share = per_unit == 1 ? 0 : wi - u * per_unit;
     const int32_t i = u * kLocalUnit + tid;
-    int32_t v = -1, b = 0, d = 0;
-    if (tid < kLocalUnit && i < nf) {
-      v = a.Q[i];
-      b = a.rowptr[v];
-      d = a.rowptr[v + 1] - b;
-    }
-    uint32_t total;
-    // the scan's first barrier also orders the previous unit's LDS reads before these writes
-    const uint32_t ex = block_excl_scan(uint32_t(d), &total);
-    sh.off[tid] = int32_t(ex);
-    sh.beg[tid] = b;
-    sh.src[tid] = v;
-    if (tid == 0) sh.off[kThreads] = int32_t(total);
-    const int32_t n = min(kLocalUnit, nf - u * kLocalUnit);
-    edges += tid == 0 ? total : 0;
-    for (uint32_t e0 = 0; e0 < total; e0 += kExpandChunk) {
-      __syncthreads();  // the unit's prefix is written, nbuf is settled
-      if (sh.nbuf + kExpandChunk > uint32_t(kExpandBuf)) flush();
-      int32_t w[kExpandEPT], uu[kExpandEPT];
-      bool valid[kExpandEPT], won[kExpandEPT];
-#pragma unroll
-      for (int t = 0; t < kExpandEPT; ++t) {
-        const uint32_t e = e0 + uint32_t(t * kThreads + tid);
-        valid[t] = e < total;
-        w[t] = 0;
-        uu[t] = 0;
-        if (valid[t]) {
-          const int32_t k = thread_search(sh.off, 0, n, e);
-          uu[t] = sh.src[k];
-          w[t] = a.colind[sh.beg[k] + int32_t(e - uint32_t(sh.off[k]))];
-        }
-      }
-      uint32_t seen[kExpandEPT];
-#pragma unroll
-      for (int t = 0; t < kExpandEPT; ++t) seen[t] = valid[t] ? a.claim[w[t] >> 5] : 0xffffffffu;
-#pragma unroll
-      for (int t = 0; t < kExpandEPT; ++t) {
-        const uint32_t bit = 1u << (w[t] & 31);
-        won[t] = false;
-        if (valid[t] && !(seen[t] & bit)) won[t] = !(atomicOr(a.claim + (w[t] >> 5), bit) & bit);
-      }
-#pragma unroll
-      for (int t = 0; t < kExpandEPT; ++t) {
-        if (won[t]) {
-          ++won_total;
-          a.depth[w[t]] = a.level + 1;
-          if (a.parent) a.parent[w[t]] = uu[t];
-          if (a.found_out) atomicOr(a.found_out + (w[t] >> 5), 1u << (w[t] & 31));
-          if (a.out_rowptr) {
-            const uint32_t dw = uint32_t(a.out_rowptr[w[t] + 1] - a.out_rowptr[w[t]]);
-            mnew += dw;
-            maxdeg = max(maxdeg, dw);
-          }
-          if (a.in_colptr) insub += uint64_t(a.in_colptr[w[t] + 1] - a.in_colptr[w[t]]);
-        }
-        const uint64_t bal = __ballot(won[t]);
-        if (bal) {
-          const int cnt = __popcll(bal);
-          const int leader = __ffsll((unsigned long long)bal) - 1;
-          uint32_t p = 0;
-          if (lane() == leader) p = atomicAdd(&sh.nbuf, uint32_t(cnt));
-          p = __shfl(p, leader, 64);
-          if (won[t]) sh.buf[p + __popcll(bal & lanemask_lt())] = w[t];
-        }
-      }
+    const uint32_t total = local_unit_prefix(a, sh, (tid < kLocalUnit && i < nf) ? a.Q[i] : -1);
+    acc.edges += (tid == 0 && share == 0) ? total : 0;  // each unit's edges counted once
+    local_unit_chunks(a, sh, min(kLocalUnit, nf - u * kLocalUnit), total, uint32_t(share) * kExpandChunk,
+                      uint32_t(per_unit) * kExpandChunk, acc);
+  }
+  local_finish(a, sh, acc, 0);
+}
+
+// Push over the frontier a pull left as bits (a.front), when no pull tile
+// found more than kBitmapLocalRows rows and none of high out-degree: block b
+// lists the frontier rows of its own slice of the bitmap (at most one pull
+// tile) in LDS and expands them unit by unit, so the level needs neither the
+// bitmap-to-list conversion nor the degree scan. Under the edge-count rule
+// the block also adds up the in-degrees of its slice's rows still unvisited
+// when the level started (m_u, which the pulls do not track).
+__device__ void bitmap_expand_body(const ExpandArgs& a, int32_t nwords, int32_t V, LocalShared& sh) {
+  const int32_t G = int32_t(gridDim.x);
+  const int32_t wpb = (nwords + G - 1) / G;  // words per block; at most kPullTileWords
+  const int32_t w0 = int32_t(blockIdx.x) * wpb;
+  if (w0 >= nwords) return;
+  const int32_t w1 = min(w0 + wpb, nwords);
+  const int tid = threadIdx.x;
+  if (tid == 0) sh.nbuf = 0;
+  const int32_t w = w0 + tid;
+  const bool mine = tid < wpb && w < w1;
+  const uint32_t fb = mine ? a.front[w] & valid_bits(w, V) : 0u;
+  unsigned long long mu = 0;
+  if (a.mu_slot && mine) {
+    uint32_t u = a.nz[w] & ~(a.vis_before[w] | fb) & valid_bits(w, V);
+    while (u) {
+      const int32_t v = w * 32 + __ffs(u) - 1;
+      mu += uint64_t(a.in_colptr[v + 1] - a.in_colptr[v]);
+      u &= u - 1;
     }
   }
-  __syncthreads();
-  flush();
-  unsigned long long vv[4] = {won_total, mnew, insub, edges};
-  block_sum4(vv);
-  maxdeg = block_max32(maxdeg);
-  if (tid == 0) {
-    stripe_add(a.slot, vv[0], 0, vv[3], vv[1], vv[2]);
-    stripe_max(a.slot, maxdeg);
+  uint32_t nfront;
+  const uint32_t pos = block_excl_scan(uint32_t(__popc(fb)), &nfront);
+  {
+    uint32_t b = fb, p = pos;
+    while (b) {
+      sh.list[p++] = uint16_t(tid * 32 + __ffs(b) - 1);
+      b &= b - 1;
+    }
   }
+  LocalAcc acc;
+  for (uint32_t u0 = 0; u0 < nfront; u0 += kLocalUnit) {
+    __syncthreads();  // the list is written (first unit) / the previous unit's chunks are done
+    const uint32_t i = u0 + uint32_t(tid);
+    const int32_t v = (tid < kLocalUnit && i < nfront) ? w0 * 32 + int32_t(sh.list[i]) : -1;
+    const uint32_t total = local_unit_prefix(a, sh, v);
+    acc.edges += tid == 0 ? total : 0;
+    local_unit_chunks(a, sh, int32_t(min(uint32_t(kLocalUnit), nfront - u0)), total, 0, kExpandChunk, acc);
+  }
+  local_finish(a, sh, acc, mu);
 }
 
 // ----------------------------------------------------------------- pull
@@ -284,7 +369,7 @@ struct PullShared {
   uint16_t mid[kPullTileV];
   uint16_t lng[kPullTileV];
   uint32_t found[kPullTileWords];
-  int32_t ncand, nmid, nlong;
+  int32_t ncand, nopen, nmid, nlong;
 };
 
 // Row-based masked matvec (Algorithm 2) over CSC(A) for the rows of one
@@ -340,74 +425,97 @@ __device__ void pull_body(const PullArgs& a, int32_t tile, PullShared& sh) {
     }
     if (tid == 63) {
       sh.ncand = incl;
+      sh.nopen = 0;
       sh.nmid = 0;
       sh.nlong = 0;
     }
   }
   __syncthreads();
   const int32_t ncand = sh.ncand;
-  unsigned long long checks = 0, insub = 0;
+  unsigned long long checks = 0;
 
-  auto record = [&](int32_t off, int32_t j, int32_t indeg) {
+  auto record = [&](int32_t off, int32_t j) {
     const int32_t i = v0 + off;
     if (a.mask_after && a.mask && !(get_bit(a.mask, i) ^ (cflip & 1u))) return;
     atomicOr(&sh.found[off >> 5], 1u << (off & 31));
     if (a.depth) a.depth[i] = a.level + 1;
     if (a.parent) a.parent[i] = j;
-    if (a.edge_rule) insub += uint64_t(indeg);
   };
 
-  // phase 1: the slab (first kSlab in-neighbours, one coalesced 16-byte read
-  // per row) of a batch of rows per thread; every bitmap word is loaded before
-  // any is tested so the loads overlap, and the first hit in stored order wins
-  for (int32_t base = 0; base < ncand; base += kPullBatch * kThreads) {
-    int32_t off[kPullBatch], beg[kPullBatch], end[kPullBatch], hitj[kPullBatch], cnt[kPullBatch];
+  // phase 1a: every candidate's first in-neighbour from the head array (4
+  // bytes per row, so a level touching few rows of a line reads little),
+  // kPullHeadBatch rows per thread with every load issued before any test.
+  // Rows with more in-neighbours that this does not settle are listed in
+  // sh.lng (free until phase 2) for the slab pass; the flag bit marks a row
+  // already found (no early exit: keep counting, do not record again).
+  for (int32_t base = 0; base < ncand; base += kPullHeadBatch * kThreads) {
+    int32_t idx[kPullHeadBatch], h[kPullHeadBatch];
+    uint32_t wd[kPullHeadBatch];
+#pragma unroll
+    for (int t = 0; t < kPullHeadBatch; ++t) {
+      idx[t] = base + t * kThreads + tid;
+      h[t] = idx[t] < ncand ? a.head[v0 + int32_t(sh.cand[idx[t]])] : 0;
+    }
+#pragma unroll
+    for (int t = 0; t < kPullHeadBatch; ++t) {
+      const int32_t j = h[t] < 0 ? ~h[t] : h[t];
+      wd[t] = idx[t] < ncand ? a.x[j >> 5] : 0u;
+    }
+#pragma unroll
+    for (int t = 0; t < kPullHeadBatch; ++t) {
+      if (idx[t] >= ncand) continue;
+      const int32_t j = h[t] < 0 ? ~h[t] : h[t];
+      const bool hit = ((wd[t] >> (j & 31)) & 1u) != 0;
+      ++checks;
+      if (hit) record(int32_t(sh.cand[idx[t]]), j);
+      if (h[t] < 0 && (!EE || !hit)) sh.lng[atomicAdd(&sh.nopen, 1)] = uint16_t(idx[t] | (hit ? 0x8000 : 0));
+    }
+  }
+  __syncthreads();
+
+  // phase 1b: rows still open read their slab (the first kSlab in-neighbours
+  // in one 16-byte load; position 0 was the head) and test positions 1..3 in
+  // order; a row with more in-neighbours than the slab holds goes on to phase 2
+  const int32_t nopen = sh.nopen;
+  for (int32_t base = 0; base < nopen; base += kPullBatch * kThreads) {
+    int32_t ent[kPullBatch], off[kPullBatch], hitj[kPullBatch];
     int4 hd[kPullBatch];
 #pragma unroll
     for (int t = 0; t < kPullBatch; ++t) {
-      const int32_t idx = base + t * kThreads + tid;
-      off[t] = idx < ncand ? int32_t(sh.cand[idx]) : -1;
+      const int32_t r = base + t * kThreads + tid;
+      ent[t] = r < nopen ? int32_t(sh.lng[r]) : -1;
+      off[t] = ent[t] >= 0 ? int32_t(sh.cand[ent[t] & 0x7fff]) : -1;
     }
 #pragma unroll
     for (int t = 0; t < kPullBatch; ++t) hd[t] = off[t] >= 0 ? a.slab[v0 + off[t]] : make_int4(-1, -1, -1, -1);
-    uint32_t wd[kPullBatch][kSlab];
+    uint32_t wd[kPullBatch][kSlab - 1];
 #pragma unroll
     for (int t = 0; t < kPullBatch; ++t) {
-      const int32_t e[kSlab] = {hd[t].x, hd[t].y, hd[t].z, hd[t].w};
+      const int32_t e[kSlab - 1] = {hd[t].y, hd[t].z, hd[t].w};
 #pragma unroll
-      for (int q = 0; q < kSlab; ++q) wd[t][q] = e[q] >= 0 ? a.x[e[q] >> 5] : 0u;
+      for (int q = 0; q < kSlab - 1; ++q) wd[t][q] = e[q] >= 0 ? a.x[e[q] >> 5] : 0u;
     }
 #pragma unroll
     for (int t = 0; t < kPullBatch; ++t) {
-      const int32_t e[kSlab] = {hd[t].x, hd[t].y, hd[t].z, hd[t].w};
       hitj[t] = -1;
-      cnt[t] = 0;
-#pragma unroll
-      for (int q = 0; q < kSlab; ++q) {
-        if (e[q] < 0 || (EE && hitj[t] >= 0)) continue;  // past the row's end / stopped at a hit
-        ++cnt[t];
-        if (hitj[t] < 0 && ((wd[t][q] >> (e[q] & 31)) & 1u)) hitj[t] = e[q];
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < kPullBatch; ++t) {
-      beg[t] = 0;
-      end[t] = 0;
-      // the extent is needed past a full slab (unless settled) and, for a
-      // found row, by the edge-count rule
-      const bool more = hd[t].w >= 0 && (hitj[t] < 0 || !EE);
-      if (off[t] >= 0 && (more || (a.edge_rule && hitj[t] >= 0))) {
-        beg[t] = a.colptr[v0 + off[t]];
-        end[t] = a.colptr[v0 + off[t] + 1];
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < kPullBatch; ++t) {
       if (off[t] < 0) continue;
-      checks += uint64_t(cnt[t]);
-      if (hitj[t] >= 0) record(off[t], hitj[t], end[t] - beg[t]);
-      if (end[t] > beg[t] + kSlab && (!EE || hitj[t] < 0))
-        sh.mid[atomicAdd(&sh.nmid, 1)] = uint16_t((base + t * kThreads + tid) | (hitj[t] >= 0 ? 0x8000 : 0));
+      const bool done = (ent[t] & 0x8000) != 0;
+      const int32_t e[kSlab - 1] = {hd[t].y, hd[t].z, hd[t].w};
+#pragma unroll
+      for (int q = 0; q < kSlab - 1; ++q) {
+        if (e[q] < 0 || (EE && hitj[t] >= 0)) continue;  // past the row's end / stopped at a hit
+        ++checks;
+        if (hitj[t] < 0 && !done && ((wd[t][q] >> (e[q] & 31)) & 1u)) hitj[t] = e[q];
+      }
+      if (hitj[t] >= 0) record(off[t], hitj[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < kPullBatch; ++t) {
+      // a full slab may hide more in-neighbours: the extent decides
+      if (off[t] < 0 || hd[t].w < 0 || (EE && hitj[t] >= 0)) continue;
+      const int32_t beg = a.colptr[v0 + off[t]], end = a.colptr[v0 + off[t] + 1];
+      if (end > beg + kSlab)
+        sh.mid[atomicAdd(&sh.nmid, 1)] = uint16_t((ent[t] & 0x7fff) | (((ent[t] & 0x8000) || hitj[t] >= 0) ? 0x8000 : 0));
     }
   }
   __syncthreads();
@@ -436,7 +544,7 @@ __device__ void pull_body(const PullArgs& a, int32_t tile, PullShared& sh) {
       }
     }
     checks += n;
-    if (hit >= 0) record(off, hit, end - beg0);
+    if (hit >= 0) record(off, hit);
     if (end > lim && (!EE || hit < 0))
       sh.lng[atomicAdd(&sh.nlong, 1)] = uint16_t((ent & 0x7fff) | ((done || hit >= 0) ? 0x8000 : 0));
   }
@@ -481,12 +589,12 @@ __device__ void pull_body(const PullArgs& a, int32_t tile, PullShared& sh) {
     }
     if (lane() == 0) {
       checks += n;
-      if (hit >= 0) record(off, hit, end - beg0);
+      if (hit >= 0) record(off, hit);
     }
   }
   __syncthreads();
 
-  unsigned long long nfound = 0, nout = 0;
+  unsigned long long nfound = 0, nout = 0, nheavy = 0;
   for (int lw = tid; lw < kPullTileWords; lw += kThreads) {
     const int32_t w = w0 + lw;
     if (w < a.nwords) {
@@ -496,11 +604,17 @@ __device__ void pull_body(const PullArgs& a, int32_t tile, PullShared& sh) {
       if (a.found_out) a.found_out[w] = f;
       nfound += __popc(f);
       nout += a.count_out ? __popc(o) : 0;
+      if (a.heavy && f) nheavy += __popc(f & a.heavy[w]);
     }
   }
-  unsigned long long v[4] = {nfound, nout, checks, insub};
+  unsigned long long v[4] = {nfound, nout, checks, nheavy};
   block_sum4(v);
-  if (tid == 0) stripe_add(a.slot, v[0], v[1], v[2], 0, v[3]);
+  if (tid == 0) {
+    stripe_add(a.slot, v[0], v[1], v[2], 0, 0);
+    // how a push over these results could share out its work (see bitmap_expand_body)
+    const uint32_t tm = v[3] ? 0xffffffffu : uint32_t(v[0]);
+    if (a.heavy && tm) atomicMax(&a.slot->s[blockIdx.x % kStripes].tilemax, tm);
+  }
 }
 
 // ----------------------------------------------------- BFS level kernels
@@ -572,7 +686,9 @@ __global__ __launch_bounds__(kThreads) void k_bfs_init(BfsArgs a, int32_t source
       st.level = 0;
       st.m_u = a.nnz - c->src_indeg;
       st.active = 0;
-      st.local = (a.local_push && dir0 == 0 && c->src_outdeg <= kLocalDeg) ? 1 : 0;
+      st.local = (a.local_push && dir0 == 0 &&
+                  local_fits(1, c->src_outdeg, c->src_outdeg, main_blocks(a.nwords))) ? 1 : 0;
+      st.share = local_share(1, c->src_outdeg, c->src_outdeg, main_blocks(a.nwords));
       c->ring[0] = st;
     }
   }
@@ -599,7 +715,7 @@ __global__ __launch_bounds__(kThreads) void k_level_prep(BfsArgs a, int32_t L, i
     scan_list(a.Q[L % 2], st.nf, a.rowptr, a.S, a.R, a.chunk_first, a.flagsA, uint32_t(2 * L + 1),
               &c->ticket[L % 2], mf_out);
   } else {
-    ScanBitsArgs sb;
+    ScanBitsArgs sb{};
     if (a.reuse) {  // discovered at the last pull = new visited AND NOT old visited
       sb.a = a.vis[st.vis_idx];
       sb.b_not = a.vis[st.vis_idx ^ 1];
@@ -621,6 +737,11 @@ __global__ __launch_bounds__(kThreads) void k_level_prep(BfsArgs a, int32_t L, i
     sb.ticket = &c->ticket[L % 2];
     sb.nf_out = &c->nf32;
     sb.mf_out = mf_out;
+    // edge-count rule: m_u afresh, since the pulls before did not track it
+    sb.mu_slot = a.edge_rule ? &c->slot[L % kSlots] : nullptr;
+    sb.unv_nz = a.nz_in;
+    sb.unv_vis = a.vis[st.vis_idx];
+    sb.colptr = a.colptr;
     scan_bits(sb);
   }
 }
@@ -664,10 +785,22 @@ __global__ __launch_bounds__(kThreads) void k_level_main(BfsArgs a, int32_t L) {
     e.out_rowptr = (a.edge_rule || !a.low_degree) ? a.rowptr : nullptr;
     e.in_colptr = a.edge_rule ? a.colptr : nullptr;
     e.slot = slot;
-    if (st.local)
+    e.share = st.share;
+    e.front = nullptr;
+    e.vis_before = nullptr;
+    e.nz = nullptr;
+    e.mu_slot = nullptr;
+    if (st.local == 2) {  // frontier = what the pull before found (written whole, untouched here)
+      e.front = a.F[L % 2];
+      e.vis_before = a.vis[st.vis_idx ^ 1];
+      e.nz = a.nz_in;
+      e.mu_slot = a.edge_rule ? slot : nullptr;  // m_u afresh: the pulls did not track it
+      bitmap_expand_body(e, a.nwords, a.V, sh.l);
+    } else if (st.local) {
       local_expand_body(e, sh.l);
-    else
+    } else {
       expand_body(e, sh.e);
+    }
   } else {
     const int32_t tiles = (a.nwords + kPullTileWords - 1) / kPullTileWords;
     if (int32_t(blockIdx.x) >= tiles) return;
@@ -677,6 +810,7 @@ __global__ __launch_bounds__(kThreads) void k_level_main(BfsArgs a, int32_t L) {
     p.colptr = a.colptr;
     p.rowind = a.rowind;
     p.slab = a.slab;
+    p.head = a.head;
     p.x = a.reuse ? a.vis[st.vis_idx] : a.F[L % 2];  // operand reuse: A^T v .* not(v) (Section 5.4)
     p.mask = a.vis[st.vis_idx];
     p.complement = 1;
@@ -684,13 +818,13 @@ __global__ __launch_bounds__(kThreads) void k_level_main(BfsArgs a, int32_t L) {
     p.nz = a.nz_in;
     p.out_base = a.vis[st.vis_idx];
     p.out = a.vis[st.vis_idx ^ 1];
-    p.found_out = a.need_F ? a.F[(L + 1) % 2] : nullptr;
+    p.found_out = (a.need_F || a.local_push) ? a.F[(L + 1) % 2] : nullptr;  // a bitmap push may read it
+    p.heavy = a.heavy;
     p.depth = a.depth;
     p.parent = a.parent;
     p.level = L;
     p.early_exit = EE;
     p.count_out = 0;
-    p.edge_rule = a.edge_rule;
     p.slot = slot;
     pull_body<EE>(p, int32_t(blockIdx.x), sh.p);
   }
@@ -772,14 +906,15 @@ __global__ __launch_bounds__(kThreads) void k_mxv_finalize(uint32_t* y, const ui
 }
 
 // Rows with a non-empty adjacency list, as a bit vector.
-__global__ __launch_bounds__(kThreads) void k_nz_bits(const int32_t* ptr, int32_t V, uint32_t* bits) {
+__global__ __launch_bounds__(kThreads) void k_nz_bits(const int32_t* ptr, int32_t V, uint32_t* bits,
+                                                      int32_t min_len) {
   const int32_t w = blockIdx.x * kThreads + threadIdx.x;
   const int32_t nwords = (V + 31) / 32;
   if (w >= nwords) return;
   uint32_t b = 0;
   for (int k = 0; k < 32; ++k) {
     const int32_t i = w * 32 + k;
-    if (i < V && ptr[i + 1] > ptr[i]) b |= 1u << k;
+    if (i < V && ptr[i + 1] - ptr[i] > min_len) b |= 1u << k;
   }
   bits[w] = b;
 }
@@ -787,12 +922,15 @@ __global__ __launch_bounds__(kThreads) void k_nz_bits(const int32_t* ptr, int32_
 // First entry of every CSC column (-1 for an empty column): the pull's
 // first check reads it densely.
 __global__ __launch_bounds__(kThreads) void k_slab(const int32_t* ptr, const int32_t* ind, int32_t V,
-                                                   int4* slab) {
+                                                   int4* slab, int32_t* head) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < V; i += stride) {
     const int32_t b = ptr[i], d = ptr[i + 1] - b;
     slab[i] = make_int4(d > 0 ? ind[b] : -1, d > 1 ? ind[b + 1] : -1, d > 2 ? ind[b + 2] : -1,
                         d > 3 ? ind[b + 3] : -1);
+    // the head: the first entry, complemented when more follow (0 for an empty
+    // column, which the pull never lists)
+    head[i] = d == 0 ? 0 : (d == 1 ? ind[b] : ~ind[b]);
   }
 }
 
@@ -857,7 +995,7 @@ hipError_t launch_level_prep(hipStream_t s, const BfsArgs& a, int32_t level, int
 }
 
 hipError_t launch_level_main(hipStream_t s, const BfsArgs& a, int32_t level, hipEvent_t t0, hipEvent_t t1) {
-  const dim3 g(unsigned(std::max<int64_t>(kExpandBlocks, pull_tiles(a.nwords))));
+  const dim3 g(unsigned(main_blocks(a.nwords)));
   if (a.early_exit) return launch_k(k_level_main<true>, g, s, t0, t1, a, level);
   return launch_k(k_level_main<false>, g, s, t0, t1, a, level);
 }
@@ -907,15 +1045,16 @@ hipError_t launch_mxv_finalize(hipStream_t s, uint32_t* y, const uint32_t* r, in
   return hipGetLastError();
 }
 
-hipError_t launch_nz_bits(hipStream_t s, const int32_t* ptr, int32_t V, uint32_t* bits) {
+hipError_t launch_nz_bits(hipStream_t s, const int32_t* ptr, int32_t V, uint32_t* bits, int32_t min_len) {
   hipLaunchKernelGGL(k_nz_bits, dim3(grid_for(words_of(V), kThreads, 1u << 30)), dim3(kThreads),
-                     0, s, ptr, V, bits);
+                     0, s, ptr, V, bits, min_len);
   return hipGetLastError();
 }
 
-hipError_t launch_slab(hipStream_t s, const int32_t* ptr, const int32_t* ind, int32_t V, int4* slab) {
+hipError_t launch_slab(hipStream_t s, const int32_t* ptr, const int32_t* ind, int32_t V, int4* slab,
+                       int32_t* head) {
   hipLaunchKernelGGL(k_slab, dim3(grid_for(V, kThreads, 8192)), dim3(kThreads), 0, s, ptr, ind, V,
-                     slab);
+                     slab, head);
   return hipGetLastError();
 }
 

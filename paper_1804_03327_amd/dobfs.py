@@ -39,14 +39,16 @@ class Options(ctypes.Structure):
 
 class LevelStats(ctypes.Structure):
     _fields_ = [("dir", ctypes.c_int32), ("nf", ctypes.c_int32), ("n_new", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("edges", ctypes.c_int64), ("m_f", ctypes.c_int64),
+                ("variant", ctypes.c_int32), ("edges", ctypes.c_int64), ("m_f", ctypes.c_int64),
                 ("ms_main", ctypes.c_float), ("ms_aux", ctypes.c_float)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("cap", ctypes.c_int32),
                 ("level", ctypes.POINTER(LevelStats)), ("ms_total", ctypes.c_float),
-                ("ms_init", ctypes.c_float), ("reached", ctypes.c_int64)]
+                ("ms_init", ctypes.c_float), ("reached", ctypes.c_int64),
+                ("launches_main", ctypes.c_int32), ("launches_aux", ctypes.c_int32),
+                ("ms_main_all", ctypes.c_float), ("ms_aux_all", ctypes.c_float)]
 
 
 class ServerOptions(ctypes.Structure):
@@ -274,7 +276,7 @@ def stats_levels(st: Stats) -> list:
     n = min(st.levels, st.cap)
     return [dict(dir=st.level[k].dir, nf=st.level[k].nf, n_new=st.level[k].n_new,
                  edges=st.level[k].edges, m_f=st.level[k].m_f, ms_main=st.level[k].ms_main,
-                 ms_aux=st.level[k].ms_aux) for k in range(n)]
+                 ms_aux=st.level[k].ms_aux, variant=st.level[k].variant) for k in range(n)]
 
 
 def bfs(g: Graph, source: int, depth, parent=None, opt=None, workspace=None, ws_bytes=None,

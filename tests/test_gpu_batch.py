@@ -85,6 +85,7 @@ def _check(hg, sources, d, st, tag):
     ecc = int(R.max())
     assert st.levels == ecc + 1, "%s: %d levels, oracle says %d" % (tag, st.levels, ecc + 1)
     assert st.reached == int((R >= 0).sum()), tag + ": reached pairs"
+    assert st.launches_main >= st.levels and st.launches_aux == st.launches_main + 1, tag + ": launch totals"
     lv = dobfs.stats_levels(st)
     for L, row in enumerate(lv):
         nf = int((R == L).any(axis=0).sum())

@@ -137,6 +137,32 @@ def test_push_sort_matches_oracle(graphs, name):
     assert e.value.status == dobfs.ERR_WORKSPACE_TOO_SMALL
 
 
+@pytest.mark.parametrize("name", ["rmat14", "lattice37"])
+def test_launch_totals(graphs, name):
+    """The whole-call launch totals count what a kernel profiler counts: one launch of each
+    level kernel per level, the prep that finds the end, and any levels enqueued past the
+    end; their times cover the per-level ones. A run in push_sort mode leaves them at 0."""
+    hg, g = graphs[name]
+    opt = dobfs.make_options("full", time_kernels=True)
+    ws = torch.empty(dobfs.bfs_workspace_bytes(g), dtype=torch.uint8, device="cuda")
+    depth = torch.empty(g.V, dtype=torch.int32, device="cuda")
+    parent = torch.empty(g.V, dtype=torch.int32, device="cuda")
+    st = dobfs.make_stats(4096)
+    for s in _sources(hg, 4, seed=8):
+        _say(name, "src", s)
+        dobfs.bfs(g, s, depth, parent, opt, ws, stats=st)
+        lv = dobfs.stats_levels(st)
+        assert st.launches_main >= st.levels == len(lv)
+        assert st.launches_aux == st.launches_main + 1
+        assert st.ms_main_all >= sum(r["ms_main"] for r in lv) * (1 - 1e-5) > 0
+        assert st.ms_aux_all >= sum(r["ms_aux"] for r in lv) * (1 - 1e-5) > 0
+        assert st.ms_main_all + st.ms_aux_all + st.ms_init <= st.ms_total * (1 + 1e-5)
+    opt = dobfs.make_options("push_sort", time_kernels=True)
+    ws = torch.empty(dobfs.bfs_workspace_bytes(g, opt), dtype=torch.uint8, device="cuda")
+    dobfs.bfs(g, 0, depth, parent, opt, ws, stats=st)
+    assert (st.launches_main, st.launches_aux, st.ms_main_all, st.ms_aux_all) == (0, 0, 0.0, 0.0)
+
+
 def _hubs_first_order(hg):
     """Host copy of hg with every CSC column in the order DOBFS_UPLOAD_HUBS_FIRST gives it on the
     device: decreasing out-degree of the in-neighbour, ties in stored order."""
@@ -219,6 +245,53 @@ def test_forced_schedules(graphs):
             assert [r["dir"] for r in runner.levels()] == [int(x) for x in sched][: runner.stats.levels]
 
 
+def test_push_variants(graphs):
+    """Push levels run one of three ways (stats variant): with the global degree scan (0),
+    block-local over the frontier list a push left (1), or block-local over the bits a pull
+    found (2, when no pull tile found more than 512 rows and none of out-degree above 32).
+    All give the oracle's depths, valid parents and exact per-level counts; each kind occurs."""
+    seen = set()
+    for name in ("rmat14", "directed100003", "lattice37", "grid61x53"):
+        hg, g = graphs[name]
+        runner = BfsRunner(g)
+        outdeg = hg.out_degree()
+        for s in _sources(hg, 3, seed=11):
+            want, _ = oracle.bfs(hg, s)
+            fp = oracle.first_parent(hg, want, s)
+            for heur, a, b in ((dobfs.HEUR_EDGES, 1 / 14, 1 / 24), (dobfs.HEUR_RATIO, 0.01, 0.01)):
+                tag = "%s src=%d heur=%d" % (name, s, heur)
+                runner.run(s, heuristic=heur, alpha=a, beta=b)
+                _check(hg, runner, s, "full", want, fp, tag)
+                lv = runner.levels()
+                for L, r in enumerate(lv):
+                    if r["dir"] == PULL:
+                        assert r["variant"] == 0, tag
+                        continue
+                    m_f = int(outdeg[want == L].sum())
+                    assert r["m_f"] == m_f and r["edges"] == m_f, "%s level %d" % (tag, L)
+                    after_pull = L > 0 and lv[L - 1]["dir"] == PULL
+                    assert r["variant"] in ((0, 2) if after_pull else (0, 1)), "%s level %d" % (tag, L)
+                    if after_pull and r["variant"] == 2:
+                        found = want == L  # what the pull before found: no heavy row
+                        assert outdeg[found].max(initial=0) <= 32, tag
+                    seen.add(r["variant"])
+    assert {1, 2} <= seen, seen  # the global scan (0) is forced below
+    # a push right after a pull that found high-degree rows must take the global scan
+    hg, g = graphs["rmat14"]
+    s = gen.max_degree_vertex(hg)
+    want, _ = oracle.bfs(hg, s)
+    runner = BfsRunner(g)
+    runner.run(s, forced_dirs=[PULL, PUSH, PUSH])
+    lv = runner.levels()
+    assert outdeg_max_at(hg, want, 1) > 32
+    assert [r["variant"] for r in lv[:2]] == [0, 0]
+    _check(hg, runner, s, "full", want, oracle.first_parent(hg, want, s), "forced pull-push")
+
+
+def outdeg_max_at(hg, depth, L):
+    return int(hg.out_degree()[depth == L].max(initial=0))
+
+
 def test_repeat_determinism(graphs):
     hg, g = graphs["rmat14"]
     runner = BfsRunner(g)
@@ -232,14 +305,21 @@ def test_repeat_determinism(graphs):
 
 
 def test_edges_heuristic(graphs):
-    for name in ("rmat14", "directed100003"):
+    """Beamer's edge-count rule: exact depths, valid parents, and the direction sequence the
+    oracle derives from m_f and m_u of its own depths (the device tracks m_u incrementally)."""
+    for name in ("rmat14", "directed100003", "lattice37"):
         hg, g = graphs[name]
         runner = BfsRunner(g)
-        for s in _sources(hg, 2, seed=4):
+        for s in _sources(hg, 3, seed=4):
             want, _ = oracle.bfs(hg, s)
             fp = oracle.first_parent(hg, want, s)
-            runner.run(s, heuristic=dobfs.HEUR_EDGES, alpha=1 / 14, beta=1 / 24)
-            _check(hg, runner, s, "edges", want, fp, "%s edges-rule" % name)
+            for a, b in ((1 / 14, 1 / 24), (1 / 40, 1 / 96), (1 / 3, 1 / 12)):
+                tag = "%s src=%d edges-rule %.4g %.4g" % (name, s, a, b)
+                _say(tag)
+                runner.run(s, heuristic=dobfs.HEUR_EDGES, alpha=a, beta=b)
+                _check(hg, runner, s, "edges", want, fp, tag)
+                dirs = [r["dir"] for r in runner.levels()]
+                assert dirs == oracle.schedule_edges(hg, want, a, b), tag
 
 
 def test_directed_orientation(tmp_path):

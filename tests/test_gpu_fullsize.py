@@ -1,9 +1,10 @@
 """GPU parity at the full sizes of the benchmarked and configured workloads, in the launch
-configuration the benchmark times (mode full, edge-count rule with alpha = 1/14, beta = 1/24,
-library-owned workspace, current stream).
+configuration the benchmark times (in-neighbours uploaded hubs-first, mode full, edge-count
+rule with alpha = 1/14, beta = 1/24, library-owned workspace, current stream).
 
 Every depth vector is compared with the oracle's over all vertices and every parent vector
-passes the validator; the multi-source launch is checked on sampled rows."""
+passes the validator; under the edge-count rule the direction sequence is the oracle's; the
+multi-source launch is checked on sampled rows."""
 import sys
 
 import numpy as np
@@ -30,8 +31,8 @@ def _say(*a):
 BENCH_OPT = dict(mode="full", heuristic=dobfs.HEUR_EDGES, alpha=1 / 14, beta=1 / 24)
 
 
-def _single(hg, sources, opts):
-    g = upload(hg)
+def _single(hg, sources, opts, hubs_first=False):
+    g = upload(hg, hubs_first=hubs_first)
     r = BfsRunner(g)
     for s in sources:
         want, _ = oracle.bfs(hg, s)
@@ -44,13 +45,17 @@ def _single(hg, sources, opts):
             assert bad == 0, "%s: %d depths differ" % (tag, bad)
             code, at = oracle.validate(hg, s, d, p)
             assert code == 0, "%s: parent check %d failed at %d" % (tag, code, at)
+            if o.get("heuristic") == dobfs.HEUR_EDGES:
+                dirs = [x["dir"] for x in r.levels()]
+                assert dirs == oracle.schedule_edges(hg, want, o["alpha"], o["beta"]), tag
     dobfs.graph_destroy(g)
 
 
 def test_rmat22_single_source():
     hg = gen.rmat(22, 16, seed=1)
     srcs = [int(x) for x in gen.sample_sources(hg, 64, seed=2)]
-    _single(hg, [srcs[0], srcs[63]], [BENCH_OPT, dict(mode="full")])
+    _single(hg, [srcs[0], srcs[63]], [BENCH_OPT, dict(mode="full")], hubs_first=True)
+    _single(hg, [srcs[1]], [BENCH_OPT])
 
 
 def test_lattice256_single_source():

@@ -367,6 +367,36 @@ def test_schedule_needs_trend():
     assert oracle.schedule([1, 50, 60, 5, 0], V) == [P, Q, Q, P, P]
 
 
+def test_schedule_edges_hand_example():
+    """Beamer's rule of Section 6.3 on a star 0-{1..8} with a tail 8-9 (undirected, 18
+    entries), from vertex 0. Level 0 finds 1..8: m_f = 7*1 + 2 = 9 out-edges, and only vertex
+    9 stays unvisited, m_u = 1. Level 1 finds 9 (nnz(f) = 1), level 2 nothing."""
+    hg = gen.from_edges(10, [0] * 8 + [8], list(range(1, 9)) + [9])
+    d, _ = oracle.bfs(hg, 0)
+    assert d.tolist() == [0] + [1] * 8 + [2]
+    P, Q = oracle.PUSH, oracle.PULL
+    # 9 > alpha * 1 switches to pull; 1 < beta * 10 needs beta > 0.1, 0 < beta * 10 any beta > 0
+    assert oracle.schedule_edges(hg, d, alpha=1 / 14, beta=1 / 24) == [P, Q, Q]
+    assert oracle.schedule_edges(hg, d, alpha=1 / 14, beta=0.2) == [P, Q, P]
+    # alpha = 10: 9 > 10 fails; after level 1, m_f = outdeg(9) = 1 > 10 * m_u = 0: pull
+    assert oracle.schedule_edges(hg, d, alpha=10.0, beta=1 / 24) == [P, P, Q]
+    # alpha = 9 exactly: 9 > 9 fails (strict)
+    assert oracle.schedule_edges(hg, d, alpha=9.0, beta=1 / 24) == [P, P, Q]
+    assert oracle.schedule_edges(hg, d, alpha=8.99, beta=1 / 24)[:2] == [P, Q]
+
+
+def test_schedule_edges_directed_counts():
+    """On a directed graph m_f counts out-edges and m_u in-edges: 0->1, 0->2, 1->3, 2->3,
+    4->3, 4->1 (vertex 4 unreachable from 0). Level 0 finds {1, 2}: m_f = 2; unvisited
+    {3, 4}, m_u = indeg 3 + indeg 0 = 3. Level 1 finds {3}: m_f = 0, m_u = 0."""
+    hg = gen.from_edges(5, [0, 0, 1, 2, 4, 4], [1, 2, 3, 3, 3, 1], directed=True)
+    d, _ = oracle.bfs(hg, 0)
+    assert d.tolist() == [0, 1, 1, 2, -1]
+    P, Q = oracle.PUSH, oracle.PULL
+    assert oracle.schedule_edges(hg, d, alpha=0.66, beta=0.01) == [P, Q, Q]   # 2 > 1.98
+    assert oracle.schedule_edges(hg, d, alpha=0.67, beta=0.01) == [P, P, P]   # 2 > 2.01 fails; 0 > 0 fails
+
+
 # ------------------------------------------------------------------- TEPS
 def test_teps_convention_matches_printed_figures():
     """The paper's MTEPS equal nnz(A) of the symmetrized graph divided by the runtime."""
