@@ -70,6 +70,14 @@ def bytes_d2s(V, n):
     return 2 * V / 8 + 4 * n
 
 
+def bytes_local_expand(nf, m_f, n_new):
+    return 12 * nf + 4 * m_f + 12 * n_new  # (id, offset pair) per vertex, adjacency, depth/parent/queue
+
+
+def bytes_mu_recount(V):
+    return 2 * V / 8  # nz and visited words (edge-count rule, first push after a pull)
+
+
 def bytes_init(V):
     return 8 * V + V / 8
 
@@ -430,8 +438,17 @@ def main():
             prep_bytes = main_bytes = 0
             for L, lv in enumerate(dobfs.stats_levels(st)):
                 if lv["dir"] == dobfs.DIR_PUSH:
-                    prep = bytes_push_scan(lv["nf"]) + (bytes_d2s(hg.V, lv["nf"]) if prev == dobfs.DIR_PULL else 0)
-                    main = bytes_push_expand(lv["nf"], lv["m_f"], lv["n_new"])
+                    after_pull = prev == dobfs.DIR_PULL
+                    mu = bytes_mu_recount(hg.V) if (after_pull and heur == dobfs.HEUR_EDGES) else 0
+                    if lv["variant"] == 0:  # global degree scan in the prep
+                        prep = bytes_push_scan(lv["nf"]) + (bytes_d2s(hg.V, lv["nf"]) + mu if after_pull else 0)
+                        main = bytes_push_expand(lv["nf"], lv["m_f"], lv["n_new"])
+                    elif lv["variant"] == 1:  # block-local over the frontier list
+                        prep = 0
+                        main = bytes_local_expand(lv["nf"], lv["m_f"], lv["n_new"])
+                    else:  # block-local over the bits the pull found
+                        prep = 0
+                        main = hg.V / 8 + mu + bytes_local_expand(lv["nf"], lv["m_f"], lv["n_new"]) - 4 * lv["nf"]
                     add("main_push", lv["ms_main"], main)
                 else:
                     nc = cand_tables[s][L] if L < len(cand_tables[s]) else cand_tables[s][-1]

@@ -29,27 +29,61 @@ __device__ __forceinline__ uint32_t valid_bits(int32_t w, int32_t V) {
   return (1u << (V - lo)) - 1u;
 }
 
-__device__ __forceinline__ int wave_incl_scan(int v) {
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    int t = __shfl_up(v, d, 64);
-    if (lane() >= d) v += t;
-  }
+// Cross-lane steps by DPP (GFX9 data-parallel primitives: shift right within
+// a row of 16 lanes, broadcast lane 15 / 31 to the next rows), a few cycles
+// each, where a lane shuffle goes through the LDS crossbar. The sequence is
+// the wave's inclusive scan; lane 63 ends with the whole wave's total. A
+// lane reading outside its row, or a row the mask leaves out, adds the
+// identity 0 (the values are unsigned). Every lane of the wave must be active.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kCtrl, kRowMask, 0xf, false));
+}
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+  return uint64_t(dpp32<kCtrl, kRowMask>(uint32_t(v))) | (uint64_t(dpp32<kCtrl, kRowMask>(uint32_t(v >> 32))) << 32);
+}
+struct OpAdd {
+  template <class T> __device__ __forceinline__ T operator()(T a, T b) const { return a + b; }
+};
+struct OpMax {
+  template <class T> __device__ __forceinline__ T operator()(T a, T b) const { return a > b ? a : b; }
+};
+struct OpOr {
+  template <class T> __device__ __forceinline__ T operator()(T a, T b) const { return a | b; }
+};
+template <class Op>
+__device__ __forceinline__ uint32_t wave_scan_dpp(uint32_t v, Op op) {
+  v = op(v, dpp32<kDppRowShr1, 0xf>(v));
+  v = op(v, dpp32<kDppRowShr2, 0xf>(v));
+  v = op(v, dpp32<kDppRowShr4, 0xf>(v));
+  v = op(v, dpp32<kDppRowShr8, 0xf>(v));
+  v = op(v, dpp32<kDppRowBcast15, 0xa>(v));
+  v = op(v, dpp32<kDppRowBcast31, 0xc>(v));
   return v;
 }
-
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+template <class Op>
+__device__ __forceinline__ uint64_t wave_scan_dpp(uint64_t v, Op op) {
+  v = op(v, dpp64<kDppRowShr1, 0xf>(v));
+  v = op(v, dpp64<kDppRowShr2, 0xf>(v));
+  v = op(v, dpp64<kDppRowShr4, 0xf>(v));
+  v = op(v, dpp64<kDppRowShr8, 0xf>(v));
+  v = op(v, dpp64<kDppRowBcast15, 0xa>(v));
+  v = op(v, dpp64<kDppRowBcast31, 0xc>(v));
   return v;
 }
+__device__ __forceinline__ uint32_t lane63(uint32_t v) { return uint32_t(__builtin_amdgcn_readlane(int(v), 63)); }
+__device__ __forceinline__ uint64_t lane63(uint64_t v) {
+  return uint64_t(lane63(uint32_t(v))) | (uint64_t(lane63(uint32_t(v >> 32))) << 32);
+}
 
+__device__ __forceinline__ int wave_incl_scan(int v) { return int(wave_scan_dpp(uint32_t(v), OpAdd{})); }
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return lane63(wave_scan_dpp(v, OpAdd{})); }
 __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-  return v;
+  return lane63(wave_scan_dpp(uint64_t(v), OpAdd{}));
 }
-
 // Launch with optional kernel start / end events (hipExtLaunchKernel).
 template <class K, class... Args>
 hipError_t launch_k(K kernel, dim3 grid, hipStream_t s, hipEvent_t t0, hipEvent_t t1, Args... args) {
@@ -135,12 +169,7 @@ __device__ __forceinline__ void stripe_max(LevelSlot* slot, uint32_t deg) {
   if (deg) atomicMax(&slot->s[blockIdx.x % kStripes].maxdeg, deg);
 }
 
-__device__ __forceinline__ uint32_t wave_max32(uint32_t v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v = max(v, uint32_t(__shfl_xor(int(v), d, 64)));
-  return v;
-}
-
+__device__ __forceinline__ uint32_t wave_max32(uint32_t v) { return lane63(wave_scan_dpp(v, OpMax{})); }
 // Largest value over the 256 threads of a block (every thread gets it).
 __device__ __forceinline__ uint32_t block_max32(uint32_t v) {
   __shared__ uint32_t s_m[kThreads / 64];
@@ -154,12 +183,7 @@ __device__ __forceinline__ uint32_t block_max32(uint32_t v) {
   return t;
 }
 
-__device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v |= __shfl_xor(v, d, 64);
-  return v;
-}
-
+__device__ __forceinline__ uint64_t wave_or64(uint64_t v) { return lane63(wave_scan_dpp(v, OpOr{})); }
 // OR over the 256 threads of a block (every thread gets the result).
 __device__ __forceinline__ uint64_t block_or64(uint64_t v) {
   __shared__ uint64_t s_o[kThreads / 64];

@@ -131,12 +131,14 @@ __device__ void expand_body(const ExpandArgs& a, ExpandShared& sh) {
         if (a.depth) a.depth[w[t]] = a.level + 1;
         if (a.parent) a.parent[w[t]] = u[t];
         if (a.found_out) atomicOr(a.found_out + (w[t] >> 5), 1u << (w[t] & 31));
+        uint32_t dw = 0;
         if (a.out_rowptr) {
-          const uint32_t dw = uint32_t(a.out_rowptr[w[t] + 1] - a.out_rowptr[w[t]]);
+          dw = uint32_t(a.out_rowptr[w[t] + 1] - a.out_rowptr[w[t]]);
           mnew += dw;
           maxdeg = max(maxdeg, dw);
         }
-        if (a.in_colptr) insub += uint64_t(a.in_colptr[w[t] + 1] - a.in_colptr[w[t]]);
+        if (a.in_colptr)  // an undirected graph keeps one offset array for both directions
+          insub += a.in_colptr == a.out_rowptr ? uint64_t(dw) : uint64_t(a.in_colptr[w[t] + 1] - a.in_colptr[w[t]]);
       }
       if (a.Qout) {
         const uint64_t bal = __ballot(won[t]);
@@ -254,12 +256,14 @@ __device__ __forceinline__ void local_unit_chunks(const ExpandArgs& a, LocalShar
         a.depth[w[t]] = a.level + 1;
         if (a.parent) a.parent[w[t]] = uu[t];
         if (a.found_out) atomicOr(a.found_out + (w[t] >> 5), 1u << (w[t] & 31));
+        uint32_t dw = 0;
         if (a.out_rowptr) {
-          const uint32_t dw = uint32_t(a.out_rowptr[w[t] + 1] - a.out_rowptr[w[t]]);
+          dw = uint32_t(a.out_rowptr[w[t] + 1] - a.out_rowptr[w[t]]);
           acc.mnew += dw;
           acc.maxdeg = max(acc.maxdeg, dw);
         }
-        if (a.in_colptr) acc.insub += uint64_t(a.in_colptr[w[t] + 1] - a.in_colptr[w[t]]);
+        if (a.in_colptr)
+          acc.insub += a.in_colptr == a.out_rowptr ? uint64_t(dw) : uint64_t(a.in_colptr[w[t] + 1] - a.in_colptr[w[t]]);
       }
       const uint64_t bal = __ballot(won[t]);
       if (bal) {
@@ -375,12 +379,13 @@ struct PullShared {
 // Row-based masked matvec (Algorithm 2) over CSC(A) for the rows of one
 // tile of kPullTileWords bitmap words: list the rows the mask lets through
 // (output sparsity, Section 5.2) and check each row's in-neighbours in stored
-// order, stopping at the first hit (early exit, Section 5.3). Three phases
-// keep many loads in flight: the slab (first kSlab in-neighbours, one 16-byte
-// read per row) of kPullBatch rows per thread at once; then rows still open,
-// one per thread, kPullStep positions per load round, up to kPullMid; then
-// what is left, one row per wave, 64 in-neighbours per step with the lowest
-// hitting lane kept. Every phase scans positions in
+// order, stopping at the first hit (early exit, Section 5.3). The phases
+// keep many loads in flight: every candidate's first in-neighbour from the
+// head array (kPullHeadBatch rows per thread at once); the slab (in-neighbours
+// 1..3, one 16-byte read) of the rows still open, kPullBatch per thread; then
+// rows still open, one per thread, kPullStep positions per load round, up to
+// kPullMid; then what is left, one row per wave, 64 in-neighbours per step
+// with the lowest hitting lane kept. Every phase scans positions in
 // order and keeps the first hit, so the reported parent is always the first
 // in stored order. Results gather in LDS and the tile's words of the output
 // vector are written whole, so no atomics touch the output bitmap. `x` (the
@@ -393,38 +398,28 @@ __device__ void pull_body(const PullArgs& a, int32_t tile, PullShared& sh) {
   const int32_t v0 = w0 * 32;
   const uint32_t cflip = a.complement ? 0xffffffffu : 0u;
 
-  // wave 0 lists the candidate rows of the tile in order, each lane taking
-  // kWPL consecutive words
-  constexpr int kWPL = kPullTileWords > 64 ? kPullTileWords / 64 : 1;
-  static_assert(kPullTileWords <= 64 || kPullTileWords % 64 == 0, "whole words per lane");
-  if (tid < 64) {
-    uint32_t cw[kWPL];
-    int c = 0;
-#pragma unroll
-    for (int k = 0; k < kWPL; ++k) {
-      const int lw = tid * kWPL + k;  // word within the tile
-      const int32_t w = w0 + lw;
-      cw[k] = 0;
-      if (lw < kPullTileWords) sh.found[lw] = 0;
-      if (lw < kPullTileWords && w < a.nwords) {
-        const uint32_t pass = a.mask ? (a.mask[w] ^ cflip) : 0xffffffffu;
-        cw[k] = (a.mask_after ? 0xffffffffu : pass) & a.nz[w] & valid_bits(w, a.V);
-      }
-      c += __popc(cw[k]);
+  // the tile's candidate rows (mask passed, in-degree > 0) listed in order:
+  // two threads per bitmap word, sixteen bits each, placed by a block scan
+  {
+    static_assert(kPullTileWords * 2 == kThreads, "two threads per tile word");
+    const int lw = tid >> 1, half = tid & 1;
+    const int32_t w = w0 + lw;
+    if (half == 0) sh.found[lw] = 0;
+    uint32_t cw = 0;
+    if (w < a.nwords) {
+      const uint32_t pass = a.mask ? (a.mask[w] ^ cflip) : 0xffffffffu;
+      cw = (a.mask_after ? 0xffffffffu : pass) & a.nz[w] & valid_bits(w, a.V);
+      cw = half ? (cw >> 16) : (cw & 0xffffu);
     }
-    const int incl = wave_incl_scan(c);
-    int pos = incl - c;
-#pragma unroll
-    for (int k = 0; k < kWPL; ++k) {
-      uint32_t bits = cw[k];
-      while (bits) {
-        const int b = __ffs(bits) - 1;
-        sh.cand[pos++] = uint16_t((tid * kWPL + k) * 32 + b);
-        bits &= bits - 1;
-      }
+    uint32_t total;
+    uint32_t pos = block_excl_scan(uint32_t(__popc(cw)), &total);
+    const int base_bit = lw * 32 + half * 16;
+    while (cw) {
+      sh.cand[pos++] = uint16_t(base_bit + __ffs(cw) - 1);
+      cw &= cw - 1;
     }
-    if (tid == 63) {
-      sh.ncand = incl;
+    if (tid == 0) {
+      sh.ncand = int32_t(total);
       sh.nopen = 0;
       sh.nmid = 0;
       sh.nlong = 0;
