@@ -416,10 +416,11 @@ def main():
     torch.cuda.synchronize()
     t_ev = time.perf_counter() - t_ev
 
-    # GPU kernels: k_bfs_init, k_level_prep (direction + frontier scan), k_level_main
-    # (push expand or pull); the push / pull split of level_main is reported beside them
+    # GPU kernels: k_bfs_init and k_step (one launch per level, two for a push level that
+    # needs the global degree scan); the push / pull split of the steps' time (scan steps
+    # apart) is reported beside them
     kinds = {k: {"ms": 0.0, "launches": 0, "bytes": 0.0} for k in
-             ("level_prep", "level_main", "init", "main_push", "main_pull")}
+             ("step", "init", "push", "push_scan", "pull")}
 
     def add(kind, ms, nbytes, launches=1):
         kinds[kind]["ms"] += ms
@@ -435,35 +436,31 @@ def main():
             bfs_ms.append(st.ms_total)
             add("init", st.ms_init, bytes_init(hg.V))
             prev = dobfs.DIR_PUSH
-            prep_bytes = main_bytes = 0
+            step_bytes = 0
             for L, lv in enumerate(dobfs.stats_levels(st)):
                 if lv["dir"] == dobfs.DIR_PUSH:
                     after_pull = prev == dobfs.DIR_PULL
                     mu = bytes_mu_recount(hg.V) if (after_pull and heur == dobfs.HEUR_EDGES) else 0
-                    if lv["variant"] == 0:  # global degree scan in the prep
-                        prep = bytes_push_scan(lv["nf"]) + (bytes_d2s(hg.V, lv["nf"]) + mu if after_pull else 0)
+                    if lv["variant"] == 0:  # scan step, then expansion step
+                        scan = bytes_push_scan(lv["nf"]) + (bytes_d2s(hg.V, lv["nf"]) + mu if after_pull else 0)
                         main = bytes_push_expand(lv["nf"], lv["m_f"], lv["n_new"])
+                        add("push_scan", lv["ms_aux"], scan)
+                        step_bytes += scan
                     elif lv["variant"] == 1:  # block-local over the frontier list
-                        prep = 0
                         main = bytes_local_expand(lv["nf"], lv["m_f"], lv["n_new"])
                     else:  # block-local over the bits the pull found
-                        prep = 0
                         main = hg.V / 8 + mu + bytes_local_expand(lv["nf"], lv["m_f"], lv["n_new"]) - 4 * lv["nf"]
-                    add("main_push", lv["ms_main"], main)
+                    add("push", lv["ms_main"], main)
                 else:
                     nc = cand_tables[s][L] if L < len(cand_tables[s]) else cand_tables[s][-1]
-                    prep = 0
                     main = bytes_pull(hg.V, int(nc), lv["edges"], lv["n_new"])
-                    add("main_pull", lv["ms_main"], main)
-                prep_bytes += prep
-                main_bytes += main
+                    add("pull", lv["ms_main"], main)
+                step_bytes += main
                 prev = lv["dir"]
-            # every launch of the two level kernels, as a profiler counts them: the levels,
-            # the prep that finds the end, and the levels enqueued past the end (no work,
-            # no algorithmic bytes)
-            add("level_prep", st.ms_aux_all, prep_bytes, st.launches_aux)
-            add("level_main", st.ms_main_all, main_bytes, st.launches_main)
-    dom = max(("level_prep", "level_main", "init"), key=lambda k: kinds[k]["ms"])
+            # every launch of the step kernel, as a profiler counts them: the levels' steps,
+            # the step that finds the end and those enqueued past it (no work, no bytes)
+            add("step", st.ms_main_all, step_bytes, st.launches_main)
+    dom = max(("step", "init"), key=lambda k: kinds[k]["ms"])
     kd = kinds[dom]
     avg_ms = kd["ms"] / max(1, kd["launches"])
     per_launch = kd["bytes"] / max(1, kd["launches"])

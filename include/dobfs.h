@@ -172,11 +172,13 @@ typedef struct {
                       pull before it found; 0 for pull levels */
   int64_t edges;   /* push: nnz(m_f^+) adjacency entries read; pull: in-neighbours checked */
   int64_t m_f;     /* push: out-edges of the input frontier (0 on pull levels) */
-  float ms_main;   /* execution time of the level's second kernel, the push expansion or the
-                      pull (DOBFS_OPT_TIME_KERNELS), else 0 */
-  float ms_aux;    /* execution time of the level's first kernel: the direction decision and,
-                      for push, the frontier scan (with the bitmap-to-list conversion after a
-                      pull level), else 0 */
+  float ms_main;   /* execution time (DOBFS_OPT_TIME_KERNELS, else 0) of the level's pull or
+                      push: single source, the step that decides and runs the level (the
+                      expansion step after a scan); multi-source, the level's second kernel */
+  float ms_aux;    /* single source: the scan step of a push level that needs the global
+                      degree scan (with the bitmap-to-list conversion after a pull level), 0
+                      otherwise; multi-source: the level's first kernel (direction decision,
+                      frontier scan) */
 } dobfs_level_stats;
 
 typedef struct {
@@ -186,13 +188,17 @@ typedef struct {
   float ms_total;           /* device time of the whole call (events) */
   float ms_init;            /* init kernel execution time (DOBFS_OPT_TIME_KERNELS) */
   int64_t reached;          /* vertices with depth >= 0 (multi-source: (vertex, source) pairs) */
-  /* Every launch of the two per-level kernels in the call, counted the way a kernel
-     profiler counts them: the `levels` levels, the first kernel of the level that finds
-     the end, and the levels enqueued past the end, which exit at once. The times need
-     DOBFS_OPT_TIME_KERNELS (else 0). The sort-based push mode leaves all four at 0. */
-  int32_t launches_main;    /* launches of the second kernel (push expansion / pull) */
-  int32_t launches_aux;     /* launches of the first kernel (direction + frontier scan) */
-  float ms_main_all;        /* their summed execution times */
+  /* Every launch of the per-level kernels in the call, counted the way a kernel profiler
+     counts them, with their summed execution times (DOBFS_OPT_TIME_KERNELS, else 0).
+     Single source: one step kernel, launched once per level, twice for a push level that
+     needs the global degree scan, once more for the step that finds the end, and for any
+     steps enqueued past the end (they exit at once); launches_aux and ms_aux_all are 0.
+     Multi-source: the levels' second kernels (main) and first kernels (aux, one more: the
+     one that finds the end), levels enqueued past the end included. The sort-based push
+     mode leaves all four at 0. */
+  int32_t launches_main;
+  int32_t launches_aux;
+  float ms_main_all;
   float ms_aux_all;
 } dobfs_stats;
 

@@ -36,6 +36,7 @@ struct dobfs_graph_s {
   int32_t* head = nullptr;          // first entry of every CSC(A) column, complemented when more follow
   uint32_t max_outdeg = 0;          // largest CSR(A) row length
   std::atomic<int32_t> last_levels{8};  // level count of the previous BFS (first batch size)
+  std::atomic<int32_t> last_steps{8};   // step count of the previous single-source BFS
   std::atomic<int32_t> last_levels_mb{8};  // the same for multi-source traversals
   void* owned[4] = {nullptr, nullptr, nullptr, nullptr};
   std::mutex mu;                    // guards the internal workspace
@@ -425,7 +426,7 @@ BfsArgs bfs_args(dobfs_graph g, uint8_t* ws, const Layout& L, const dobfs_option
   a.mask_after = opt.mode == DOBFS_MODE_PULL_UNMASKED ? 1 : 0;
   a.need_F = a.reuse ? 0 : 1;
   a.edge_rule = opt.heuristic == DOBFS_HEUR_EDGES ? 1 : 0;
-  a.local_push = 1;
+  a.local_push = a.need_F ? 0 : 1;  // (the frontier bitmap a push writes is cleared by its scan step)
   a.low_degree = g->max_outdeg <= uint32_t(kLocalDeg) ? 1 : 0;
   return a;
 }
@@ -522,6 +523,76 @@ dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool t
     next_batch = std::min(2 * next_batch, kMaxBatch);
   }
   last_levels.store(int32_t(res->levels), std::memory_order_relaxed);
+  return DOBFS_OK;
+}
+
+// The single-source level loop: the host enqueues steps (k_step, one launch
+// each) in batches and reads back, once per batch, the state every step
+// published and the records of the levels that are complete; steps enqueued
+// past the end exit at once. The first batch is one step longer than the
+// previous traversal of the graph needed; later batches start at 4 and
+// double. When timing, step k of a batch has events ev_m0(k) / ev_m1(k); a
+// level's scan step counts as its ms_aux, its other step as its ms_main.
+dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool timing, hipEvent_t* ev,
+                       const BfsArgs& a, int64_t max_steps, dobfs_stats* stats, LoopResult* res) {
+  HostReport* rep = host_report();
+  if (!rep) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
+  thread_local uint32_t report_seq = 0;
+  int64_t s0 = 0;
+  int32_t rec_first = 0;
+  int32_t batch = std::min(std::max(last_steps.load(std::memory_order_relaxed) + 1, 2), kMaxBatch);
+  int32_t next_batch = 4;
+  auto E = [&](int i) -> hipEvent_t { return timing ? ev[i] : nullptr; };
+  while (true) {
+    if (s0 + batch > max_steps) batch = int32_t(max_steps - s0);
+    for (int32_t k = 0; k < batch; ++k) HIPCK(launch_step(s, a, int32_t(s0 + k), E(ev_m0(k)), E(ev_m1(k))));
+    const uint32_t seq = ++report_seq;
+    HIPCK(launch_step_report(s, a.ctrl, int32_t(s0), batch, rec_first, rep, seq));
+    HIPCK(wait_report(rep, seq, s));
+    res->n_main += batch;
+    for (int32_t k = 0; k < batch; ++k) {  // step times, by level
+      const float t = timing ? elapsed(ev[ev_m0(k)], ev[ev_m1(k)]) : 0.f;
+      res->ms_main_all += t;
+      const LevelState& st = rep->steps[k];
+      if (st.done || !stats || st.level >= stats->cap) continue;
+      dobfs_level_stats& ls = stats->level[st.level];
+      if (st.phase != kPhaseExpand) ls.ms_aux = ls.ms_main = 0.f;  // the level's first step
+      if (st.phase == kPhaseScan) ls.ms_aux = t; else ls.ms_main += t;
+    }
+    for (int32_t k = 0; k < rep->nrec; ++k) {  // records of the levels now complete
+      const LevelRecord& r = rep->rec[k];
+      const int32_t l = rec_first + k;
+      res->sum_new += r.n_new;
+      res->sum_aux += int64_t(r.aux);
+      if (stats && l < stats->cap) {
+        dobfs_level_stats& ls = stats->level[l];
+        ls.dir = r.dir;
+        ls.nf = r.nf;
+        ls.n_new = r.n_new;
+        ls.variant = r.variant;
+        ls.edges = r.edges;
+        ls.m_f = r.m_f;
+      }
+    }
+    rec_first += rep->nrec;
+    const LevelState& end = rep->end;
+    if (end.done) {
+      res->levels = end.levels;
+      res->end = end;
+      break;
+    }
+    if (s0 + batch >= max_steps) {
+      (void)hipStreamSynchronize(s);
+      return fail(DOBFS_ERR_INTERNAL, "traversal needs more than %lld steps", (long long)max_steps);
+    }
+    s0 += batch;
+    batch = next_batch;
+    next_batch = std::min(2 * next_batch, kMaxBatch);
+  }
+  // steps the traversal used, up to the one that found the end (the batch before ended short of it)
+  int32_t k_end = 0;
+  while (k_end + 1 < batch && !rep->steps[k_end].done) ++k_end;
+  last_steps.store(int32_t(s0) + k_end + 1, std::memory_order_relaxed);
   return DOBFS_OK;
 }
 
@@ -810,23 +881,19 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   if (!ev) return fail(DOBFS_ERR_DEVICE, "event creation failed");
   hipStream_t s = static_cast<hipStream_t>(stream);
 
-  const BfsArgs a = bfs_args(g, ws, L, opt, depth, parent);
-  auto forced = [&](int64_t l) -> int32_t {
-    return l < opt.n_forced ? int32_t(opt.forced_dirs[l]) : -1;
-  };
-  const int32_t dir0 = forced(0) >= 0 ? forced(0)
-                                      : (opt.mode == DOBFS_MODE_PULL_ONLY ? DOBFS_DIR_PULL : DOBFS_DIR_PUSH);
+  BfsArgs a = bfs_args(g, ws, L, opt, depth, parent);
+  const int32_t dir0 = opt.n_forced > 0 ? int32_t(opt.forced_dirs[0])
+                                        : (opt.mode == DOBFS_MODE_PULL_ONLY ? DOBFS_DIR_PULL : DOBFS_DIR_PUSH);
+  a.n_forced = std::min<int32_t>(opt.n_forced, kRing);  // later levels follow the rule
+  if (a.n_forced > 0)
+    HIPCK(hipMemcpyAsync(a.ctrl->forced, opt.forced_dirs, size_t(a.n_forced), hipMemcpyHostToDevice, s));
 
   HIPCK(hipEventRecord(ev[kEvStart], s));
   HIPCK(launch_bfs_init(s, a, source, dir0, timing ? ev[kEvInit0] : nullptr,
                         timing ? ev[kEvInit1] : nullptr));
   LoopResult res;
-  st = run_levels(
-      g->last_levels, s, timing, ev, forced,
-      [&](int32_t l, int32_t f, hipEvent_t t0, hipEvent_t t1) { return launch_level_prep(s, a, l, f, t0, t1); },
-      [&](int32_t l, hipEvent_t t0, hipEvent_t t1) { return launch_level_main(s, a, l, t0, t1); },
-      a.ctrl, int64_t(g->V) + 2,
-      DOBFS_ERR_INTERNAL, stats, &res);
+  // a level takes at most two steps
+  st = run_steps(g->last_steps, s, timing, ev, a, 2 * (int64_t(g->V) + 2), stats, &res);
   if (st != DOBFS_OK) return st;
   HIPCK(hipEventRecord(ev[kEvEnd], s));
   HIPCK(hipEventSynchronize(ev[kEvEnd]));

@@ -432,54 +432,55 @@ __host__ __device__ constexpr bool is_batch(const BatchArgs&) { return true; }
 // loads; this measured several microseconds faster per launch than one wave
 // computing it and broadcasting it through LDS. All blocks of a level_prep
 // compute the same state.
-template <class Args>
-__device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, LevelTotals* tot_out,
-                                  LevelState* prev_out) {
-  const Ctrl* c = a.ctrl;
-  LevelTotals t{0, 0, 0, 0, 0, 0};
-  LevelState st;
-  if (L == 0) {
-    st = c->ring[0];
-    if (forced >= 0) st.dir = forced;
-    *tot_out = t;
-    *prev_out = st;
-    return st;
-  }
-  // the previous state and the counters are loaded together (one round
-  // trip): lane k reads stripe k and the wave adds them up; the totals are
-  // uniform, so they go back to scalar registers
-  const LevelSlot& sl = c->slot[(L - 1) % kSlots];
+// The counters one level left, one stripe per lane (lanes past kStripes read nothing).
+struct StripeLanes {
+  uint64_t v0, v1, v2, v3, v4, v6;  // count | aux << 32, edges, mnew, insub, fbits, mu
+  uint32_t v5, v7;                  // maxdeg, tilemax
+};
+__device__ __forceinline__ StripeLanes load_stripes(const LevelSlot& sl) {
   const int k = lane();
   const Stripe* sk = &sl.s[k & (kStripes - 1)];
   const bool mine = k < kStripes;
-  const uint64_t v0 = mine ? uint64_t(sk->count) | (uint64_t(sk->aux) << 32) : 0ull;
-  const uint64_t v1 = mine ? sk->edges : 0ull, v2 = mine ? sk->mnew : 0ull, v3 = mine ? sk->insub : 0ull;
-  const uint64_t v4 = mine ? sk->fbits : 0ull;
-  const uint32_t v5 = mine ? sk->maxdeg : 0u;
-  const uint64_t v6 = mine ? sk->mu : 0ull;
-  const uint32_t v7 = mine ? sk->tilemax : 0u;
-  const LevelState prev = c->ring[(L - 1) % kRing];
-  *prev_out = prev;
-  st = prev;
+  StripeLanes x;
+  x.v0 = mine ? uint64_t(sk->count) | (uint64_t(sk->aux) << 32) : 0ull;
+  x.v1 = mine ? sk->edges : 0ull;
+  x.v2 = mine ? sk->mnew : 0ull;
+  x.v3 = mine ? sk->insub : 0ull;
+  x.v4 = mine ? sk->fbits : 0ull;
+  x.v5 = mine ? sk->maxdeg : 0u;
+  x.v6 = mine ? sk->mu : 0ull;
+  x.v7 = mine ? sk->tilemax : 0u;
+  return x;
+}
+
+// The state entering level L from the state entering L-1 (prev) and the
+// counters L-1 left (x): the direction rule of Section 6.3 (or Beamer's edge
+// form), forced directions and mode overrides, buffer parities, and whether
+// a push can share out its own work.
+template <class Args>
+__device__ LevelState next_state(const Args& a, int32_t L, int32_t forced, const LevelState& prev,
+                                 const StripeLanes& x, LevelTotals* tot_out) {
+  LevelTotals t{0, 0, 0, 0, 0, 0};
+  LevelState st = prev;
   st.level = L;
   if (!prev.done) {
     // each cross-lane reduction costs a few hundred cycles of a launch every level runs, so
     // only the totals this traversal and level use are formed (the branches are uniform)
     constexpr bool batch = is_batch(Args{});
-    t.count = uniform64(wave_sum64(v0 & 0xffffffffull));
-    t.edges = uniform64(wave_sum64(v1));
-    t.mnew = uniform64(wave_sum64(v2));
-    if (batch) t.aux = uniform64(wave_sum64(v0 >> 32));
-    if (a.edge_rule) t.insub = uniform64(wave_sum64(v3));
+    t.count = uniform64(wave_sum64(x.v0 & 0xffffffffull));
+    t.edges = uniform64(wave_sum64(x.v1));
+    t.mnew = uniform64(wave_sum64(x.v2));
+    if (batch) t.aux = uniform64(wave_sum64(x.v0 >> 32));
+    if (a.edge_rule) t.insub = uniform64(wave_sum64(x.v3));
     if (t.count == 0) {
       st.done = 1;
       st.levels = L;
     } else {
       const int64_t n_new = int64_t(t.count);
       // m_u loses the in-edges of each push level's winners; pulls leave it alone, and the
-      // scan of the push that follows a pull recounts it (single source)
+      // push that follows a pull recounts it (single source)
       const bool recounted = recounts_mu(a) && prev.dir == 0 && !prev.list_valid;
-      if (recounted) t.mu = uniform64(wave_sum64(v6));
+      if (recounted) t.mu = uniform64(wave_sum64(x.v6));
       const int64_t m_u = (recounted ? int64_t(t.mu) : prev.m_u) - (a.edge_rule ? int64_t(t.insub) : 0);
       int32_t next = next_direction_rule(a.heuristic, a.alpha, a.beta, prev.dir, a.V, prev.nf, n_new,
                                          int64_t(t.mnew), m_u);
@@ -491,7 +492,7 @@ __device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, Leve
       st.list_valid = prev.dir == 0 ? 1 : 0;  // a push level appended its winners to Q[L % 2]
       st.vis_idx = prev.dir == 1 ? (prev.vis_idx ^ 1) : prev.vis_idx;
       st.m_u = m_u;
-      st.active = batch ? uniform64(wave_or64(v4)) : 0ull;
+      st.active = batch ? uniform64(wave_or64(x.v4)) : 0ull;
       // a push needs no global scan when its frontier's edges can be shared out inside
       // blocks: a list from a push whose sizes local_fits() accepts (local 1), or the bits a
       // pull left when no tile found more than kBitmapLocalRows rows and none of high
@@ -504,21 +505,43 @@ __device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, Leve
           // rule needs no m_f; then kLocalDeg bounds them
           const bool tracked = a.edge_rule || !a.low_degree;
           const int64_t mf_b = tracked ? int64_t(t.mnew) : INT64_MAX;
-          const int64_t md_b = tracked ? int64_t(__builtin_amdgcn_readfirstlane(wave_max32(v5))) : int64_t(kLocalDeg);
+          const int64_t md_b = tracked ? int64_t(__builtin_amdgcn_readfirstlane(wave_max32(x.v5))) : int64_t(kLocalDeg);
           const int64_t G = main_blocks(a.nwords);
           if (a.low_degree || local_fits(n_new, mf_b, md_b, G)) {
             st.local = 1;
             st.share = local_share(n_new, mf_b, md_b, G);
           }
         } else {
-          const uint32_t tm = __builtin_amdgcn_readfirstlane(wave_max32(v7));
+          const uint32_t tm = __builtin_amdgcn_readfirstlane(wave_max32(x.v7));
           st.local = tm <= uint32_t(kBitmapLocalRows) ? 2 : 0;
         }
       }
+      st.phase = (next == 0 && !st.local) ? kPhaseScan : kPhaseWhole;
     }
   }
   *tot_out = t;
   return st;
+}
+
+// The state entering level L (level loops with one slot per level): every
+// thread computes it from uniform addresses, which the compiler serves with
+// scalar loads; the previous state and the counters come in one round trip.
+// All blocks of a launch compute the same state.
+template <class Args>
+__device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, LevelTotals* tot_out,
+                                  LevelState* prev_out) {
+  const Ctrl* c = a.ctrl;
+  if (L == 0) {
+    LevelState st = c->ring[0];
+    if (forced >= 0) st.dir = forced;
+    *tot_out = LevelTotals{0, 0, 0, 0, 0, 0};
+    *prev_out = st;
+    return st;
+  }
+  const StripeLanes x = load_stripes(c->slot[(L - 1) % kSlots]);
+  const LevelState prev = c->ring[(L - 1) % kRing];
+  *prev_out = prev;
+  return next_state(a, L, forced, prev, x, tot_out);
 }
 
 // Block 0 of level L's first kernel: publish the level's state and the

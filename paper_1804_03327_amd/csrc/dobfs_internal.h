@@ -47,9 +47,14 @@ struct alignas(64) LevelState {
   int32_t local;       // push level expanded with block-local load balancing, no global scan:
                        // 1 over the frontier list, 2 over the bits the previous pull found
   int32_t share;       // local 1: blocks that share one unit's edge chunks (local_share)
+  int32_t phase;       // single-source step loop: kPhaseWhole, kPhaseScan or kPhaseExpand
   int64_t m_u;         // edge-count rule: in-edges of still-unvisited vertices
   uint64_t active;     // multi-source: sources whose frontier entering the level is non-empty
 };
+// What one step of the single-source loop does for its level: all of it
+// (a pull, or a push that shares out its own work), or one of the two steps of
+// a push that needs the global degree scan.
+constexpr int32_t kPhaseWhole = 0, kPhaseScan = 1, kPhaseExpand = 2;
 // Per-level statistics for the host, written by the next level's first kernel.
 struct LevelRecord {
   int32_t dir, nf, n_new, variant;  // variant: dobfs_level_stats.variant
@@ -71,6 +76,7 @@ struct Ctrl {
   LevelSlot slot[kSlots];
   LevelState ring[kRing];
   LevelRecord rec[kRing];
+  int8_t forced[kRing];          // single source: forced direction of levels 0 .. n_forced-1
 };
 static_assert(sizeof(Stripe) == 128, "stripe layout");
 static_assert(offsetof(Ctrl, slot) % 128 == 0, "slots start on a line");
@@ -256,6 +262,7 @@ struct BfsArgs {
   int32_t edge_rule;
   int32_t local_push;        // push levels of small out-degree may skip the global scan
   int32_t low_degree;        // every out-degree of the graph is <= kLocalDeg
+  int32_t n_forced;          // levels whose direction Ctrl::forced fixes
 };
 
 // ---- multi-source BFS: up to 64 sources, one bit of a uint64 per source ----
@@ -328,8 +335,6 @@ hipError_t launch_bfs_init(hipStream_t s, const BfsArgs& a, int32_t source, int3
                           hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_level_prep(hipStream_t s, const BfsArgs& a, int32_t level, int32_t forced_dir,
                             hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
-hipError_t launch_level_main(hipStream_t s, const BfsArgs& a, int32_t level, hipEvent_t t0 = nullptr,
-                            hipEvent_t t1 = nullptr);
 hipError_t launch_ctrl_init(hipStream_t s, Ctrl* ctrl, uint64_t* flags, int64_t nflags);
 hipError_t launch_scan_bits(hipStream_t s, const ScanBitsArgs& a);
 hipError_t launch_expand(hipStream_t s, const ExpandArgs& a, const uint32_t* m_dev,
@@ -351,8 +356,15 @@ constexpr int kMaxBatch = 64;
 struct HostReport {
   LevelState end;
   LevelRecord rec[kMaxBatch];
+  LevelState steps[kMaxBatch];  // single source: the state each step of the batch published
+  int32_t nrec;                 // single source: records in rec (levels rec_first ..)
   uint32_t seq;
 };
+// single-source step loop (kernels.hip)
+hipError_t launch_step(hipStream_t s, const BfsArgs& a, int32_t step, hipEvent_t t0 = nullptr,
+                       hipEvent_t t1 = nullptr);
+hipError_t launch_step_report(hipStream_t s, const Ctrl* ctrl, int32_t s_first, int32_t n, int32_t rec_first,
+                              HostReport* host, uint32_t seq);
 hipError_t launch_report(hipStream_t s, const Ctrl* ctrl, int32_t l_first, int32_t n,
                          HostReport* host, uint32_t seq);
 hipError_t launch_mb_init(hipStream_t s, const BatchArgs& a, int32_t dir0, int64_t nflags,

@@ -48,7 +48,7 @@ struct ExpandShared {
 // makes any winner exact), which both deduplicates and applies the mask
 // not(v). Winners are buffered in LDS and appended to the next frontier list
 // with one atomic per flush.
-__device__ void expand_body(const ExpandArgs& a, ExpandShared& sh) {
+__device__ __forceinline__ void expand_body(const ExpandArgs& a, ExpandShared& sh) {
   const int32_t nf = a.nf;
   const uint32_t m = a.m;
   if (nf <= 0 || m == 0) return;
@@ -298,7 +298,7 @@ __device__ __forceinline__ void local_finish(const ExpandArgs& a, LocalShared& s
 // units than blocks, each unit gets a.share blocks (local_share: what its
 // chunks could need, at most gridDim / units), which all scan the unit's
 // degrees and take its chunks in turn; otherwise a block takes whole units.
-__device__ void local_expand_body(const ExpandArgs& a, LocalShared& sh) {
+__device__ __forceinline__ void local_expand_body(const ExpandArgs& a, LocalShared& sh) {
   const int32_t nf = a.nf;
   const int32_t nunits = (nf + kLocalUnit - 1) / kLocalUnit;
   const int32_t G = int32_t(gridDim.x);
@@ -326,7 +326,7 @@ __device__ void local_expand_body(const ExpandArgs& a, LocalShared& sh) {
 // bitmap-to-list conversion nor the degree scan. Under the edge-count rule
 // the block also adds up the in-degrees of its slice's rows still unvisited
 // when the level started (m_u, which the pulls do not track).
-__device__ void bitmap_expand_body(const ExpandArgs& a, int32_t nwords, int32_t V, LocalShared& sh) {
+__device__ __forceinline__ void bitmap_expand_body(const ExpandArgs& a, int32_t nwords, int32_t V, LocalShared& sh) {
   const int32_t G = int32_t(gridDim.x);
   const int32_t wpb = (nwords + G - 1) / G;  // words per block; at most kPullTileWords
   const int32_t w0 = int32_t(blockIdx.x) * wpb;
@@ -392,7 +392,7 @@ struct PullShared {
 // input vector) is never written here, which keeps the visited snapshot exact
 // when x = visited (operand reuse, Section 5.4).
 template <bool EE>
-__device__ void pull_body(const PullArgs& a, int32_t tile, PullShared& sh) {
+__device__ __forceinline__ void pull_body(const PullArgs& a, int32_t tile, PullShared& sh) {
   const int tid = threadIdx.x;
   const int32_t w0 = tile * kPullTileWords;
   const int32_t v0 = w0 * 32;
@@ -684,6 +684,7 @@ __global__ __launch_bounds__(kThreads) void k_bfs_init(BfsArgs a, int32_t source
       st.local = (a.local_push && dir0 == 0 &&
                   local_fits(1, c->src_outdeg, c->src_outdeg, main_blocks(a.nwords))) ? 1 : 0;
       st.share = local_share(1, c->src_outdeg, c->src_outdeg, main_blocks(a.nwords));
+      st.phase = (dir0 == 0 && !st.local) ? kPhaseScan : kPhaseWhole;
       c->ring[0] = st;
     }
   }
@@ -747,54 +748,179 @@ union LevelShared {
   PullShared p;
 };
 
-// Second kernel of level L: the push expansion or the pull, as level_prep
-// decided.
+// ------------------------------------------------- single-source step loop
+// One launch per step: a level is one step (a pull, or a push that shares
+// out its own work), or two when its push needs the global degree scan (the
+// scan step, then the expansion step). Every block derives the step's state
+// from the state the previous step published and the counters it left (one
+// round trip), so no kernel of its own decides the level. The counters of
+// step s gather in slot s % kSlots; step s clears slot (s + 2) % kSlots, which
+// nothing reads or writes until step s + 2.
+
+__device__ __forceinline__ LevelState step_state(const BfsArgs& a, int32_t s, LevelTotals* tot, LevelState* prev_out,
+                                 bool* new_level) {
+  const Ctrl* c = a.ctrl;
+  *new_level = false;
+  *tot = LevelTotals{0, 0, 0, 0, 0, 0};
+  if (s == 0) {  // level 0 as the init kernel left it
+    const LevelState st = c->ring[0];
+    *prev_out = st;
+    return st;
+  }
+  const StripeLanes x = load_stripes(c->slot[(s - 1) % kSlots]);
+  const LevelState prev = c->ring[(s - 1) % kRing];
+  *prev_out = prev;
+  if (prev.done) return prev;  // past the end
+  if (prev.phase == kPhaseScan) {  // the expansion the scan step prepared
+    LevelState st = prev;
+    st.phase = kPhaseExpand;
+    return st;
+  }
+  const int32_t L = prev.level + 1;
+  const int32_t forced = L < a.n_forced ? int32_t(c->forced[L]) : -1;
+  *new_level = true;
+  return next_state(a, L, forced, prev, x, tot);
+}
+
+// Block 0: publish step s's state and, when it starts a level, the record of
+// the level before; clear what step s + 2 will count into.
+__device__ __forceinline__ void publish_step(Ctrl* c, int32_t s, const LevelState& st, const LevelState& prev,
+                             const LevelTotals& tot, bool new_level) {
+  if (threadIdx.x == 0) {
+    c->ring[s % kRing] = st;
+    if (new_level) {
+      LevelRecord r;
+      r.dir = prev.dir;
+      r.nf = prev.nf;
+      r.n_new = int32_t(tot.count);
+      r.variant = prev.dir == 0 ? prev.local : 0;
+      r.edges = int64_t(tot.edges);
+      // a scanned push level's m_f comes from its scan; a local one reads exactly its m_f edges
+      r.m_f = prev.dir == 0 ? (prev.local ? int64_t(tot.edges) : int64_t(c->mf[(s - 1) % kSlots])) : 0;
+      r.mnew = tot.mnew;
+      r.insub = tot.insub;
+      r.aux = tot.aux;
+      c->rec[(st.level - 1) % kRing] = r;
+    }
+    c->qcount[(s + 2) % kSlots] = 0;
+    c->ticket[(s + 1) % 2] = 0;
+  }
+  for (int k = threadIdx.x; k < kStripes; k += blockDim.x) zero_stripe(c->slot[(s + 2) % kSlots].s[k]);
+}
+
+// The scan step of a push level: its frontier list with the degree prefix
+// and chunk table (Section 6.2), from the list the push before left or from
+// the bits the pull before found. Its m_f goes where the expansion step reads it.
+__device__ __forceinline__ void step_scan(const BfsArgs& a, const LevelState& st, int32_t s) {
+  Ctrl* c = a.ctrl;
+  const int32_t L = st.level;
+  uint32_t* mf_out = &c->mf[(s + 1) % kSlots];
+  if (a.need_F) {  // winners of this push level will be set in F[(L+1)%2]
+    uint32_t* fn = a.F[(L + 1) % 2];
+    for (int32_t w = blockIdx.x * kThreads + threadIdx.x; w < a.nwords; w += gridDim.x * kThreads) fn[w] = 0;
+  }
+  if (st.list_valid) {
+    scan_list(a.Q[L % 2], st.nf, a.rowptr, a.S, a.R, a.chunk_first, a.flagsA, uint32_t(2 * s + 1),
+              &c->ticket[s % 2], mf_out);
+  } else {
+    ScanBitsArgs sb{};
+    if (a.reuse) {  // discovered at the last pull = new visited AND NOT old visited
+      sb.a = a.vis[st.vis_idx];
+      sb.b_not = a.vis[st.vis_idx ^ 1];
+    } else {
+      sb.a = a.F[L % 2];
+      sb.b_not = nullptr;
+    }
+    sb.nwords = a.nwords;
+    sb.V = a.V;
+    sb.rowptr = a.rowptr;
+    sb.Qout = a.Q[L % 2];
+    sb.S = a.S;
+    sb.R = a.R;
+    sb.chunk_first = a.chunk_first;
+    sb.flagsA = a.flagsA;
+    sb.flagsB = a.flagsB;
+    sb.epochA = uint32_t(2 * s + 1);
+    sb.epochB = uint32_t(2 * s + 2);
+    sb.ticket = &c->ticket[s % 2];
+    sb.nf_out = &c->nf32;
+    sb.mf_out = mf_out;
+    // edge-count rule: m_u afresh, since the pulls before did not track it; the
+    // expansion step's slot, which the next level reads
+    sb.mu_slot = a.edge_rule ? &c->slot[(s + 1) % kSlots] : nullptr;
+    sb.unv_nz = a.nz_in;
+    sb.unv_vis = a.vis[st.vis_idx];
+    sb.colptr = a.colptr;
+    scan_bits(sb);
+  }
+}
+
+// The argument block of step s's push (level st.level).
+__device__ __forceinline__ ExpandArgs step_expand_args(const BfsArgs& a, const LevelState& st, int32_t s,
+                                                       uint32_t m, const uint32_t* front,
+                                                       const uint32_t* vis_before, LevelSlot* mu_slot) {
+  Ctrl* c = a.ctrl;
+  const int32_t L = st.level;
+  ExpandArgs e;
+  e.Q = a.Q[L % 2];
+  e.nf = st.nf;
+  e.S = a.S;
+  e.R = a.R;
+  e.chunk_first = a.chunk_first;
+  e.colind = a.colind;
+  e.m = m;
+  e.claim = a.vis[st.vis_idx];
+  e.mask = nullptr;
+  e.complement = 0;
+  e.depth = a.depth;
+  e.parent = a.parent;
+  e.level = L;
+  e.Qout = a.Q[(L + 1) % 2];
+  e.qcount = &c->qcount[s % kSlots];
+  e.found_out = a.need_F ? a.F[(L + 1) % 2] : nullptr;
+  e.rowptr = a.rowptr;
+  // winners' out-degrees: the next level's m_f (edge-count rule) and its largest degree
+  // (whether it can skip the scan; known for all levels when the whole graph has low degree)
+  e.out_rowptr = (a.edge_rule || !a.low_degree) ? a.rowptr : nullptr;
+  e.in_colptr = a.edge_rule ? a.colptr : nullptr;
+  e.slot = &c->slot[s % kSlots];
+  e.share = st.share;
+  e.front = front;
+  e.vis_before = vis_before;
+  e.nz = a.nz_in;
+  e.mu_slot = mu_slot;
+  return e;
+}
+
 template <bool EE>
-__global__ __launch_bounds__(kThreads) void k_level_main(BfsArgs a, int32_t L) {
+__global__ __launch_bounds__(kThreads) void k_step(BfsArgs a, int32_t s) {
   __shared__ LevelShared sh;
   Ctrl* c = a.ctrl;
-  const LevelState st = c->ring[L % kRing];
+  LevelTotals tot;
+  LevelState prev;
+  bool new_level;
+  const LevelState st = step_state(a, s, &tot, &prev, &new_level);
+  if (blockIdx.x == 0) publish_step(c, s, st, prev, tot, new_level);
   if (st.done) return;
-  LevelSlot* slot = &c->slot[L % kSlots];
+  if (st.phase == kPhaseScan) {
+    step_scan(a, st, s);
+    return;
+  }
+  const int32_t L = st.level;
+  LevelSlot* slot = &c->slot[s % kSlots];
   if (st.dir == 0) {
-    ExpandArgs e;
-    e.Q = a.Q[L % 2];
-    e.nf = st.nf;
-    e.S = a.S;
-    e.R = a.R;
-    e.chunk_first = a.chunk_first;
-    e.colind = a.colind;
-    e.m = uint32_t(c->mf[L % kSlots]);
-    e.claim = a.vis[st.vis_idx];
-    e.mask = nullptr;
-    e.complement = 0;
-    e.depth = a.depth;
-    e.parent = a.parent;
-    e.level = L;
-    e.Qout = a.Q[(L + 1) % 2];
-    e.qcount = &c->qcount[L % kSlots];
-    e.found_out = a.need_F ? a.F[(L + 1) % 2] : nullptr;
-    e.rowptr = a.rowptr;
-    // winners' out-degrees: the next level's m_f (edge-count rule) and its largest degree
-    // (whether it can skip the scan; known for all levels when the whole graph has low degree)
-    e.out_rowptr = (a.edge_rule || !a.low_degree) ? a.rowptr : nullptr;
-    e.in_colptr = a.edge_rule ? a.colptr : nullptr;
-    e.slot = slot;
-    e.share = st.share;
-    e.front = nullptr;
-    e.vis_before = nullptr;
-    e.nz = nullptr;
-    e.mu_slot = nullptr;
-    if (st.local == 2) {  // frontier = what the pull before found (written whole, untouched here)
-      e.front = a.F[L % 2];
-      e.vis_before = a.vis[st.vis_idx ^ 1];
-      e.nz = a.nz_in;
-      e.mu_slot = a.edge_rule ? slot : nullptr;  // m_u afresh: the pulls did not track it
-      bitmap_expand_body(e, a.nwords, a.V, sh.l);
-    } else if (st.local) {
-      local_expand_body(e, sh.l);
-    } else {
+    // each push body gets its own argument block, built whole, so the compiler keeps it in
+    // registers (one block modified across branches went to scratch memory)
+    if (st.phase == kPhaseExpand) {
+      const ExpandArgs e = step_expand_args(a, st, s, c->mf[s % kSlots], nullptr, nullptr, nullptr);
       expand_body(e, sh.e);
+    } else if (st.local == 2) {  // frontier = what the pull before found (written whole, untouched here)
+      const ExpandArgs e = step_expand_args(a, st, s, 0u, a.F[L % 2], a.vis[st.vis_idx ^ 1],
+                                            a.edge_rule ? slot : nullptr);  // m_u afresh: pulls skip it
+      bitmap_expand_body(e, a.nwords, a.V, sh.l);
+    } else {
+      const ExpandArgs e = step_expand_args(a, st, s, 0u, nullptr, nullptr, nullptr);
+      local_expand_body(e, sh.l);
     }
   } else {
     const int32_t tiles = (a.nwords + kPullTileWords - 1) / kPullTileWords;
@@ -822,6 +948,27 @@ __global__ __launch_bounds__(kThreads) void k_level_main(BfsArgs a, int32_t L) {
     p.count_out = 0;
     p.slot = slot;
     pull_body<EE>(p, int32_t(blockIdx.x), sh.p);
+  }
+}
+
+// Copies the states the steps s_first .. s_first + n - 1 published, and the
+// records of the levels that are complete after them from rec_first on, into
+// pinned host memory; then publishes `seq` with a system-scope release.
+__global__ void k_step_report(const Ctrl* c, int32_t s_first, int32_t n, int32_t rec_first, HostReport* host,
+                              uint32_t seq) {
+  for (int k = threadIdx.x; k < n; k += blockDim.x) host->steps[k] = c->ring[(s_first + k) % kRing];
+  const LevelState end = c->ring[(s_first + n - 1) % kRing];
+  const int32_t upto = end.done ? end.levels : end.level;  // records exist for levels < upto
+  const int32_t nrec = max(0, min(upto - rec_first, kMaxBatch));
+  for (int k = threadIdx.x; k < nrec; k += blockDim.x) host->rec[k] = c->rec[(rec_first + k) % kRing];
+  if (threadIdx.x == 0) {
+    host->end = end;
+    host->nrec = nrec;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence_system();
+    __hip_atomic_store(&host->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -989,10 +1136,16 @@ hipError_t launch_level_prep(hipStream_t s, const BfsArgs& a, int32_t level, int
   return launch_k(k_level_prep, dim3(unsigned(scan_grid(a.V))), s, t0, t1, a, level, forced_dir);
 }
 
-hipError_t launch_level_main(hipStream_t s, const BfsArgs& a, int32_t level, hipEvent_t t0, hipEvent_t t1) {
+hipError_t launch_step(hipStream_t s, const BfsArgs& a, int32_t step, hipEvent_t t0, hipEvent_t t1) {
   const dim3 g(unsigned(main_blocks(a.nwords)));
-  if (a.early_exit) return launch_k(k_level_main<true>, g, s, t0, t1, a, level);
-  return launch_k(k_level_main<false>, g, s, t0, t1, a, level);
+  if (a.early_exit) return launch_k(k_step<true>, g, s, t0, t1, a, step);
+  return launch_k(k_step<false>, g, s, t0, t1, a, step);
+}
+
+hipError_t launch_step_report(hipStream_t s, const Ctrl* ctrl, int32_t s_first, int32_t n, int32_t rec_first,
+                              HostReport* host, uint32_t seq) {
+  hipLaunchKernelGGL(k_step_report, dim3(1), dim3(64), 0, s, ctrl, s_first, n, rec_first, host, seq);
+  return hipGetLastError();
 }
 
 hipError_t launch_ctrl_init(hipStream_t s, Ctrl* ctrl, uint64_t* flags, int64_t nflags) {

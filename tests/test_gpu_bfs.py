@@ -139,9 +139,9 @@ def test_push_sort_matches_oracle(graphs, name):
 
 @pytest.mark.parametrize("name", ["rmat14", "lattice37"])
 def test_launch_totals(graphs, name):
-    """The whole-call launch totals count what a kernel profiler counts: one launch of each
-    level kernel per level, the prep that finds the end, and any levels enqueued past the
-    end; their times cover the per-level ones. A run in push_sort mode leaves them at 0."""
+    """The whole-call launch totals count what a kernel profiler counts: every launch of the
+    step kernel (one or two per level, the step that finds the end, any enqueued past it);
+    their time covers the per-level times. A run in push_sort mode leaves them at 0."""
     hg, g = graphs[name]
     opt = dobfs.make_options("full", time_kernels=True)
     ws = torch.empty(dobfs.bfs_workspace_bytes(g), dtype=torch.uint8, device="cuda")
@@ -152,11 +152,13 @@ def test_launch_totals(graphs, name):
         _say(name, "src", s)
         dobfs.bfs(g, s, depth, parent, opt, ws, stats=st)
         lv = dobfs.stats_levels(st)
-        assert st.launches_main >= st.levels == len(lv)
-        assert st.launches_aux == st.launches_main + 1
-        assert st.ms_main_all >= sum(r["ms_main"] for r in lv) * (1 - 1e-5) > 0
-        assert st.ms_aux_all >= sum(r["ms_aux"] for r in lv) * (1 - 1e-5) > 0
-        assert st.ms_main_all + st.ms_aux_all + st.ms_init <= st.ms_total * (1 + 1e-5)
+        scanned = sum(1 for r in lv if r["dir"] == PUSH and r["variant"] == 0)
+        assert st.launches_main >= st.levels + scanned + 1 and st.levels == len(lv)
+        assert st.launches_aux == 0 and st.ms_aux_all == 0
+        assert all(r["ms_main"] > 0 for r in lv)
+        assert all((r["ms_aux"] > 0) == (r["dir"] == PUSH and r["variant"] == 0) for r in lv)
+        assert st.ms_main_all >= sum(r["ms_main"] + r["ms_aux"] for r in lv) * (1 - 1e-5) > 0
+        assert st.ms_main_all + st.ms_init <= st.ms_total * (1 + 1e-5)
     opt = dobfs.make_options("push_sort", time_kernels=True)
     ws = torch.empty(dobfs.bfs_workspace_bytes(g, opt), dtype=torch.uint8, device="cuda")
     dobfs.bfs(g, 0, depth, parent, opt, ws, stats=st)
