@@ -892,8 +892,9 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   HIPCK(launch_bfs_init(s, a, source, dir0, timing ? ev[kEvInit0] : nullptr,
                         timing ? ev[kEvInit1] : nullptr));
   LoopResult res;
-  // a level takes at most two steps
-  st = run_steps(g->last_steps, s, timing, ev, a, 2 * (int64_t(g->V) + 2), stats, &res);
+  // a level takes at most two steps; scan tile flags carry 2 * step + 2 in 30 bits
+  const int64_t max_steps = std::min<int64_t>(2 * (int64_t(g->V) + 2), (int64_t(1) << 29) - 2);
+  st = run_steps(g->last_steps, s, timing, ev, a, max_steps, stats, &res);
   if (st != DOBFS_OK) return st;
   HIPCK(hipEventRecord(ev[kEvEnd], s));
   HIPCK(hipEventSynchronize(ev[kEvEnd]));
