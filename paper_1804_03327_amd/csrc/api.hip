@@ -203,6 +203,13 @@ HostReport* host_report() {
   return p;
 }
 
+// Sequence numbers of the reports a thread waits for: one counter for every
+// loop that shares the thread's pinned buffer, so a stale number never matches.
+uint32_t next_report_seq() {
+  thread_local uint32_t n = 0;
+  return ++n;
+}
+
 // Wait until the report with sequence number `seq` has landed: spin on the
 // pinned word for a short while (a kernel-to-host write takes ~6 us where a
 // stream synchronisation takes ~15 us), then block on the stream, which also
@@ -459,7 +466,6 @@ dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool t
                         dobfs_status too_deep, dobfs_stats* stats, LoopResult* res) {
   HostReport* rep = host_report();
   if (!rep) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
-  thread_local uint32_t report_seq = 0;
   int64_t lvl = 0;
   int32_t batch = std::min(std::max(last_levels.load(std::memory_order_relaxed) + 1, 2), kMaxBatch);
   int32_t next_batch = 4;
@@ -475,7 +481,7 @@ dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool t
       HIPCK(main(int32_t(l), E(ev_m0(k)), E(ev_m1(k))));
       HIPCK(prep(int32_t(l + 1), forced(l + 1), E(ev_p0(k + 1)), E(ev_p1(k + 1))));
     }
-    const uint32_t seq = ++report_seq;
+    const uint32_t seq = next_report_seq();
     HIPCK(launch_report(s, ctrl, int32_t(lvl), batch, rep, seq));
     HIPCK(wait_report(rep, seq, s));
     if (timing && lvl == 0) {
@@ -537,7 +543,6 @@ dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool tim
                        const BfsArgs& a, int64_t max_steps, dobfs_stats* stats, LoopResult* res) {
   HostReport* rep = host_report();
   if (!rep) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
-  thread_local uint32_t report_seq = 0;
   int64_t s0 = 0;
   int32_t rec_first = 0;
   int32_t batch = std::min(std::max(last_steps.load(std::memory_order_relaxed) + 1, 2), kMaxBatch);
@@ -546,7 +551,7 @@ dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool tim
   while (true) {
     if (s0 + batch > max_steps) batch = int32_t(max_steps - s0);
     for (int32_t k = 0; k < batch; ++k) HIPCK(launch_step(s, a, int32_t(s0 + k), E(ev_m0(k)), E(ev_m1(k))));
-    const uint32_t seq = ++report_seq;
+    const uint32_t seq = next_report_seq();
     HIPCK(launch_step_report(s, a.ctrl, int32_t(s0), batch, rec_first, rep, seq));
     HIPCK(wait_report(rep, seq, s));
     res->n_main += batch;
@@ -888,7 +893,9 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   if (a.n_forced > 0)
     HIPCK(hipMemcpyAsync(a.ctrl->forced, opt.forced_dirs, size_t(a.n_forced), hipMemcpyHostToDevice, s));
 
-  HIPCK(hipEventRecord(ev[kEvStart], s));
+  // the whole-call interval only when asked for: the last batch's report already tells the
+  // host that every kernel of the traversal has finished, so no further wait is needed
+  if (stats) HIPCK(hipEventRecord(ev[kEvStart], s));
   HIPCK(launch_bfs_init(s, a, source, dir0, timing ? ev[kEvInit0] : nullptr,
                         timing ? ev[kEvInit1] : nullptr));
   LoopResult res;
@@ -896,9 +903,9 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   const int64_t max_steps = std::min<int64_t>(2 * (int64_t(g->V) + 2), (int64_t(1) << 29) - 2);
   st = run_steps(g->last_steps, s, timing, ev, a, max_steps, stats, &res);
   if (st != DOBFS_OK) return st;
-  HIPCK(hipEventRecord(ev[kEvEnd], s));
-  HIPCK(hipEventSynchronize(ev[kEvEnd]));
   if (stats) {
+    HIPCK(hipEventRecord(ev[kEvEnd], s));
+    HIPCK(hipEventSynchronize(ev[kEvEnd]));
     stats->levels = int32_t(res.levels);
     stats->ms_total = elapsed(ev[kEvStart], ev[kEvEnd]);
     stats->ms_init = timing ? elapsed(ev[kEvInit0], ev[kEvInit1]) : 0.f;
@@ -1008,7 +1015,7 @@ dobfs_status dobfs::bfs_batch_rows(dobfs_graph g, const int32_t* sources, int32_
   // levels are kept as uint16 (level L stamps L + 1)
   const int64_t cap = std::min<int64_t>(int64_t(g->V) + 2, 0xfffe);
 
-  HIPCK(hipEventRecord(ev[kEvStart], s));
+  if (stats) HIPCK(hipEventRecord(ev[kEvStart], s));
   HIPCK(launch_mb_init(s, a, dir0, L.nflags, timing ? ev[kEvInit0] : nullptr,
                        timing ? ev[kEvInit1] : nullptr));
   LoopResult res;
@@ -1019,9 +1026,17 @@ dobfs_status dobfs::bfs_batch_rows(dobfs_graph g, const int32_t* sources, int32_
       cap < int64_t(g->V) + 2 ? DOBFS_ERR_UNSUPPORTED : DOBFS_ERR_INTERNAL, stats, &res);
   if (st != DOBFS_OK) return st;
   HIPCK(launch_mb_depth(s, a, a.vis[res.end.vis_idx], rows));
+  if (!stats) {  // the depth rows are final once a report behind them lands in pinned memory
+    HostReport* rep = host_report();
+    if (!rep) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
+    const uint32_t seq = next_report_seq();
+    HIPCK(launch_report(s, a.ctrl, 0, 0, rep, seq));
+    HIPCK(wait_report(rep, seq, s));
+    return DOBFS_OK;
+  }
   HIPCK(hipEventRecord(ev[kEvEnd], s));
   HIPCK(hipEventSynchronize(ev[kEvEnd]));
-  if (stats) {
+  {
     stats->levels = int32_t(res.levels);
     stats->ms_total = elapsed(ev[kEvStart], ev[kEvEnd]);
     stats->ms_init = timing ? elapsed(ev[kEvInit0], ev[kEvInit1]) : 0.f;

@@ -20,7 +20,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 from paper_1804_03327_amd import dobfs  # noqa: E402
-from paper_1804_03327_amd.helpers import upload  # noqa: E402
+from paper_1804_03327_amd.helpers import BfsRunner, upload  # noqa: E402
 
 PUSH, PULL = dobfs.DIR_PUSH, dobfs.DIR_PULL
 
@@ -199,3 +199,28 @@ def test_batch_errors(graphs):
         dobfs.bfs_batch(g, [0, 1], depth, workspace=ws)
     assert e.value.status == dobfs.ERR_WORKSPACE_TOO_SMALL
     assert dobfs.bfs_batch_workspace_bytes(g, 64) > dobfs.bfs_batch_workspace_bytes(g, 1)
+
+
+def test_interleaved_with_single_source_reports():
+    """Single-source and multi-source traversals share the thread's pinned report buffer: many
+    calls of each, interleaved on one thread, each answer checked (a report sequence number left
+    by one loop must never satisfy the other's wait)."""
+    hg = gen.rmat(10, 16, seed=1)
+    g = upload(hg)
+    runner = BfsRunner(g, with_parent=False)
+    srcs = _sources(hg, 8, seed=12)
+    refs = {s: _ref(hg, s) for s in srcs}
+    for rnd in range(3):
+        for i in range(250):
+            s = srcs[i % len(srcs)]
+            runner.run(s)
+            if i % 25 == 0:
+                assert np.array_equal(runner.result()[0], refs[s]), "single source %d, round %d" % (s, rnd)
+        for i in range(250):
+            b = srcs[i % 4: i % 4 + 4]
+            d, _ = _run(g, b)
+            if i % 25 == 0:
+                for row, s in zip(d, b):
+                    assert np.array_equal(row, refs[s]), "batch row of source %d, round %d" % (s, rnd)
+        _say("interleaved round", rnd, "ok")
+
