@@ -42,7 +42,8 @@ __global__ __launch_bounds__(kThreads) void k_mb_init(BatchArgs a, int32_t dir0,
   const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   for (int64_t v = t0; v < a.V; v += stride) {
     uint64_t m = 0;
-    for (int b = 0; b < a.k; ++b) m |= (a.src[b] == v) ? (1ull << b) : 0ull;
+    if ((a.src_filter[(v >> 6) & 15] >> (v & 63)) & 1ull)  // almost no vertex passes the filter
+      for (int b = 0; b < a.k; ++b) m |= (a.src[b] == v) ? (1ull << b) : 0ull;
     a.vis[0][v] = m;
     a.F[0][v] = m;
     a.F[1][v] = 0;
@@ -453,24 +454,53 @@ __global__ __launch_bounds__(kThreads) void k_mb_main(BatchArgs a, int32_t L) {
 }
 
 // rows.row[b][v] = level at which source b reached v, or -1: 64 vertices per
-// block step, read as whole [v][k] rows of the level table and written as
-// coalesced runs of each depth row.
+// block step, read as whole [v][k] rows of the level table (16-byte pieces,
+// and only for vertices some source reached) and written as coalesced runs of
+// each depth row, four vertices per 16-byte store.
 constexpr int kMbDepthV = 64;
 __global__ __launch_bounds__(kThreads) void k_mb_depth(BatchArgs a, const uint64_t* vis, DepthRows rows) {
-  __shared__ uint16_t s_l[kMbDepthV * kMaxSources];
+  __shared__ __align__(16) uint16_t s_l[kMbDepthV * kMaxSources];
   __shared__ uint64_t s_v[kMbDepthV];
   const int32_t k = a.k;
   const int64_t nblk = (int64_t(a.V) + kMbDepthV - 1) / kMbDepthV;
+  const bool wide = (k % 8) == 0;  // level-table rows are whole 16-byte pieces
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
     const int64_t v0 = blk * kMbDepthV;
     const int32_t nv = int32_t(min(int64_t(kMbDepthV), int64_t(a.V) - v0));
     __syncthreads();
-    for (int32_t i = threadIdx.x; i < nv * k; i += kThreads) s_l[i] = a.lvl[v0 * k + i];
     if (threadIdx.x < nv) s_v[threadIdx.x] = vis[v0 + threadIdx.x];
     __syncthreads();
-    for (int32_t i = threadIdx.x; i < nv * k; i += kThreads) {
-      const int32_t b = i / nv, j = i - b * nv;
-      rows.row[b][v0 + j] = ((s_v[j] >> b) & 1ull) ? int32_t(s_l[j * k + b]) : -1;
+    if (wide) {  // only the rows of vertices some source reached (the rest is never read)
+      const int32_t per = k / 8;
+      const uint4* src = reinterpret_cast<const uint4*>(a.lvl + v0 * k);
+      uint4* dst = reinterpret_cast<uint4*>(s_l);
+      for (int32_t i = threadIdx.x; i < nv * per; i += kThreads)
+        if (s_v[i / per]) dst[i] = src[i];
+    } else {
+      for (int32_t i = threadIdx.x; i < nv * k; i += kThreads) s_l[i] = a.lvl[v0 * k + i];
+    }
+    __syncthreads();
+    if (nv == kMbDepthV) {
+      // four consecutive vertices of one depth row per item: one 16-byte store where the row allows
+      constexpr int kQ = kMbDepthV / 4;
+      for (int32_t it = threadIdx.x; it < k * kQ; it += kThreads) {
+        const int32_t b = it / kQ, j = (it % kQ) * 4;
+        int32_t d[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d[q] = ((s_v[j + q] >> b) & 1ull) ? int32_t(s_l[(j + q) * k + b]) : -1;
+        int32_t* out = rows.row[b] + v0 + j;
+        if ((reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+          *reinterpret_cast<int4*>(out) = make_int4(d[0], d[1], d[2], d[3]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) out[q] = d[q];
+        }
+      }
+    } else {
+      for (int32_t i = threadIdx.x; i < nv * k; i += kThreads) {
+        const int32_t b = i / nv, j = i - b * nv;
+        rows.row[b][v0 + j] = ((s_v[j] >> b) & 1ull) ? int32_t(s_l[j * k + b]) : -1;
+      }
     }
   }
 }

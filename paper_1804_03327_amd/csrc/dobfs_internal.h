@@ -298,6 +298,7 @@ struct BatchArgs {
   int32_t low_degree;        // unused here
   int32_t src[kMaxSources];  // source of bit b
   int32_t uniq[kMaxSources]; // the distinct sources: the first frontier list
+  uint64_t src_filter[16];   // bit (v & 1023) set when some source v' has v' & 1023 == v & 1023
 };
 constexpr int kMbTileWords = 8;                 // multi-source pull: bitmap words of rows per block
 constexpr int kMbTileV = kMbTileWords * 32;     // 256 rows, one per thread: a tile's rows all run at once
