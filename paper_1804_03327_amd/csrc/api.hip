@@ -460,10 +460,10 @@ struct LoopResult {
 // timing, every kernel gets start / end events of its own execution: the
 // k-th level of a batch uses prep slot k and main slot k, and the prep that
 // opens the next batch uses prep slot `batch`.
-template <class Prep, class Main, class Forced>
+template <class Prep, class Main, class Forced, class Before>
 dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool timing, hipEvent_t* ev,
-                        Forced forced, Prep prep, Main main, const Ctrl* ctrl, int64_t max_levels,
-                        dobfs_status too_deep, dobfs_stats* stats, LoopResult* res) {
+                        Forced forced, Prep prep, Main main, Before before_report, const Ctrl* ctrl,
+                        int64_t max_levels, dobfs_status too_deep, dobfs_stats* stats, LoopResult* res) {
   HostReport* rep = host_report();
   if (!rep) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
   int64_t lvl = 0;
@@ -482,6 +482,7 @@ dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool t
       HIPCK(prep(int32_t(l + 1), forced(l + 1), E(ev_p0(k + 1)), E(ev_p1(k + 1))));
     }
     const uint32_t seq = next_report_seq();
+    HIPCK(before_report(int32_t(l1 + 1)));  // sees the state level l1 + 1 would start from
     HIPCK(launch_report(s, ctrl, int32_t(lvl), batch, rep, seq));
     HIPCK(wait_report(rep, seq, s));
     if (timing && lvl == 0) {
@@ -1023,18 +1024,14 @@ dobfs_status dobfs::bfs_batch_rows(dobfs_graph g, const int32_t* sources, int32_
   st = run_levels(
       g->last_levels_mb, s, timing, ev, forced,
       [&](int32_t l, int32_t f, hipEvent_t t0, hipEvent_t t1) { return launch_mb_prep(s, a, l, f, t0, t1); },
-      [&](int32_t l, hipEvent_t t0, hipEvent_t t1) { return launch_mb_main(s, a, l, t0, t1); }, a.ctrl, cap,
+      [&](int32_t l, hipEvent_t t0, hipEvent_t t1) { return launch_mb_main(s, a, l, t0, t1); },
+      // the depth rows ahead of each report: a transpose that exits at once unless the state
+      // level l would start from says the traversal is over, so the last report already
+      // finds the rows final
+      [&](int32_t l) { return launch_mb_depth(s, a, l, rows); }, a.ctrl, cap,
       cap < int64_t(g->V) + 2 ? DOBFS_ERR_UNSUPPORTED : DOBFS_ERR_INTERNAL, stats, &res);
   if (st != DOBFS_OK) return st;
-  HIPCK(launch_mb_depth(s, a, a.vis[res.end.vis_idx], rows));
-  if (!stats) {  // the depth rows are final once a report behind them lands in pinned memory
-    HostReport* rep = host_report();
-    if (!rep) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
-    const uint32_t seq = next_report_seq();
-    HIPCK(launch_report(s, a.ctrl, 0, 0, rep, seq));
-    HIPCK(wait_report(rep, seq, s));
-    return DOBFS_OK;
-  }
+  if (!stats) return DOBFS_OK;
   HIPCK(hipEventRecord(ev[kEvEnd], s));
   HIPCK(hipEventSynchronize(ev[kEvEnd]));
   {

@@ -458,9 +458,12 @@ __global__ __launch_bounds__(kThreads) void k_mb_main(BatchArgs a, int32_t L) {
 // and only for vertices some source reached) and written as coalesced runs of
 // each depth row, four vertices per 16-byte store.
 constexpr int kMbDepthV = 64;
-__global__ __launch_bounds__(kThreads) void k_mb_depth(BatchArgs a, const uint64_t* vis, DepthRows rows) {
+__global__ __launch_bounds__(kThreads) void k_mb_depth(BatchArgs a, int32_t level, DepthRows rows) {
   __shared__ __align__(16) uint16_t s_l[kMbDepthV * kMaxSources];
   __shared__ uint64_t s_v[kMbDepthV];
+  const LevelState end = a.ctrl->ring[level % kRing];
+  if (!end.done) return;  // not over yet: a later batch's transpose writes the rows
+  const uint64_t* vis = a.vis[end.vis_idx];
   const int32_t k = a.k;
   const int64_t nblk = (int64_t(a.V) + kMbDepthV - 1) / kMbDepthV;
   const bool wide = (k % 8) == 0;  // level-table rows are whole 16-byte pieces
@@ -525,10 +528,10 @@ hipError_t launch_mb_main(hipStream_t s, const BatchArgs& a, int32_t level, hipE
   return launch_k(k_mb_main, g, s, t0, t1, a, level);
 }
 
-hipError_t launch_mb_depth(hipStream_t s, const BatchArgs& a, const uint64_t* vis, const DepthRows& rows) {
+hipError_t launch_mb_depth(hipStream_t s, const BatchArgs& a, int32_t level, const DepthRows& rows) {
   const int64_t nblk = (int64_t(a.V) + kMbDepthV - 1) / kMbDepthV;
   const unsigned g = unsigned(std::min<int64_t>(nblk, 4096));
-  hipLaunchKernelGGL(k_mb_depth, dim3(g > 0 ? g : 1), dim3(kThreads), 0, s, a, vis, rows);
+  hipLaunchKernelGGL(k_mb_depth, dim3(g > 0 ? g : 1), dim3(kThreads), 0, s, a, level, rows);
   return hipGetLastError();
 }
 

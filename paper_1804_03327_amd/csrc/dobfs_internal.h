@@ -378,7 +378,9 @@ hipError_t launch_mb_main(hipStream_t s, const BatchArgs& a, int32_t level, hipE
 struct DepthRows {
   int32_t* row[kMaxSources];
 };
-hipError_t launch_mb_depth(hipStream_t s, const BatchArgs& a, const uint64_t* vis, const DepthRows& rows);
+// depth rows from the level table, when ring state `level` says the traversal
+// is over (its vis_idx names the final visited words); otherwise nothing
+hipError_t launch_mb_depth(hipStream_t s, const BatchArgs& a, int32_t level, const DepthRows& rows);
 hipError_t launch_check_offsets(hipStream_t s, const int32_t* ptr, int32_t V, int64_t nnz,
                                 int32_t* err);
 hipError_t launch_check_indices(hipStream_t s, const int32_t* idx, int64_t nnz, int32_t V,
