@@ -39,13 +39,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# the sources the single-source kernels (k_bfs_init, k_step) are compiled from: kernels.hip and
+# the headers it includes (the multi-source, sort and host files do not change them)
+SINGLE_SOURCE_KERNEL_FILES = ("kernels.hip", "device_common.h", "dobfs_internal.h", "dobfs.h")
+
+
 def kernel_source_hash() -> str:
-    """SHA-256 (16 hex digits) over the device sources: the kernels and the headers they include."""
+    """SHA-256 (16 hex digits) over the sources of the single-source kernels."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(KERNEL_DIR)):
-        if name.endswith((".hip", ".h")) and name != "api.hip":
-            with open(os.path.join(KERNEL_DIR, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in SINGLE_SOURCE_KERNEL_FILES:
+        path = os.path.join(KERNEL_DIR, name)
+        if not os.path.exists(path):
+            path = os.path.join(ROOT, "include", name)
+        with open(path, "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
 
 
