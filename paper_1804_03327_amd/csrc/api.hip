@@ -551,9 +551,14 @@ dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool tim
   auto E = [&](int i) -> hipEvent_t { return timing ? ev[i] : nullptr; };
   while (true) {
     if (s0 + batch > max_steps) batch = int32_t(max_steps - s0);
-    for (int32_t k = 0; k < batch; ++k) HIPCK(launch_step(s, a, int32_t(s0 + k), E(ev_m0(k)), E(ev_m1(k))));
     const uint32_t seq = next_report_seq();
-    HIPCK(launch_step_report(s, a.ctrl, int32_t(s0), batch, rec_first, rep, seq));
+    // untimed, the batch's last step writes the report; timed, a report kernel follows the
+    // steps so that every step's end event has completed when the host reads it
+    const StepReportArgs rp{rep, seq, int32_t(s0), rec_first};
+    for (int32_t k = 0; k < batch; ++k)
+      HIPCK(launch_step(s, a, int32_t(s0 + k), E(ev_m0(k)), E(ev_m1(k)),
+                        (!timing && k == batch - 1) ? &rp : nullptr));
+    if (timing) HIPCK(launch_step_report(s, a.ctrl, int32_t(s0), batch, rec_first, rep, seq));
     HIPCK(wait_report(rep, seq, s));
     res->n_main += batch;
     for (int32_t k = 0; k < batch; ++k) {  // step times, by level

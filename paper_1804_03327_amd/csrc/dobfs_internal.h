@@ -361,9 +361,15 @@ struct HostReport {
   int32_t nrec;                 // single source: records in rec (levels rec_first ..)
   uint32_t seq;
 };
-// single-source step loop (kernels.hip)
+// single-source step loop (kernels.hip); a step given report arguments also
+// writes the report of the batch it ends (block 0, after publishing its state)
+struct StepReportArgs {
+  HostReport* host;  // nullptr: no report
+  uint32_t seq;
+  int32_t s_first, rec_first;
+};
 hipError_t launch_step(hipStream_t s, const BfsArgs& a, int32_t step, hipEvent_t t0 = nullptr,
-                       hipEvent_t t1 = nullptr);
+                       hipEvent_t t1 = nullptr, const StepReportArgs* rp = nullptr);
 hipError_t launch_step_report(hipStream_t s, const Ctrl* ctrl, int32_t s_first, int32_t n, int32_t rec_first,
                               HostReport* host, uint32_t seq);
 hipError_t launch_report(hipStream_t s, const Ctrl* ctrl, int32_t l_first, int32_t n,

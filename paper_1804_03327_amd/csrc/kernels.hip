@@ -782,26 +782,60 @@ __device__ __forceinline__ LevelState step_state(const BfsArgs& a, int32_t s, Le
   return next_state(a, L, forced, prev, x, tot);
 }
 
+// The record of the level before the one step s starts (prev is that level's state).
+__device__ __forceinline__ LevelRecord step_record(const Ctrl* c, int32_t s, const LevelState& prev,
+                                                   const LevelTotals& tot) {
+  LevelRecord r;
+  r.dir = prev.dir;
+  r.nf = prev.nf;
+  r.n_new = int32_t(tot.count);
+  r.variant = prev.dir == 0 ? prev.local : 0;
+  r.edges = int64_t(tot.edges);
+  // a scanned push level's m_f comes from its scan; a local one reads exactly its m_f edges
+  r.m_f = prev.dir == 0 ? (prev.local ? int64_t(tot.edges) : int64_t(c->mf[(s - 1) % kSlots])) : 0;
+  r.mnew = tot.mnew;
+  r.insub = tot.insub;
+  r.aux = tot.aux;
+  return r;
+}
+
+// The last step of a batch writes the batch's report itself (block 0, right
+// after publishing): the states the batch's steps published (its own from
+// registers), the records of the levels complete by now (the one it has just
+// written from registers too), then the sequence number with a system-scope
+// release. When the traversal is over this step has no work of its own, so
+// the report lands after every kernel of the traversal has finished.
+__device__ __forceinline__ void step_report(const Ctrl* c, const StepReportArgs& rp, int32_t s,
+                                            const LevelState& st, const LevelState& prev,
+                                            const LevelTotals& tot, bool new_level) {
+  HostReport* host = rp.host;
+  const int32_t n = s - rp.s_first + 1;
+  for (int k = threadIdx.x; k < n - 1; k += blockDim.x) host->steps[k] = c->ring[(rp.s_first + k) % kRing];
+  const int32_t upto = st.done ? st.levels : st.level;  // records exist for levels < upto
+  const int32_t nrec = max(0, min(upto - rp.rec_first, kMaxBatch));
+  for (int k = threadIdx.x; k < nrec; k += blockDim.x) {
+    const int32_t l = rp.rec_first + k;
+    host->rec[k] = (new_level && l == st.level - 1) ? step_record(c, s, prev, tot) : c->rec[l % kRing];
+  }
+  if (threadIdx.x == 0) {
+    host->steps[n - 1] = st;
+    host->end = st;
+    host->nrec = nrec;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence_system();
+    __hip_atomic_store(&host->seq, rp.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 // Block 0: publish step s's state and, when it starts a level, the record of
 // the level before; clear what step s + 2 will count into.
 __device__ __forceinline__ void publish_step(Ctrl* c, int32_t s, const LevelState& st, const LevelState& prev,
                              const LevelTotals& tot, bool new_level) {
   if (threadIdx.x == 0) {
     c->ring[s % kRing] = st;
-    if (new_level) {
-      LevelRecord r;
-      r.dir = prev.dir;
-      r.nf = prev.nf;
-      r.n_new = int32_t(tot.count);
-      r.variant = prev.dir == 0 ? prev.local : 0;
-      r.edges = int64_t(tot.edges);
-      // a scanned push level's m_f comes from its scan; a local one reads exactly its m_f edges
-      r.m_f = prev.dir == 0 ? (prev.local ? int64_t(tot.edges) : int64_t(c->mf[(s - 1) % kSlots])) : 0;
-      r.mnew = tot.mnew;
-      r.insub = tot.insub;
-      r.aux = tot.aux;
-      c->rec[(st.level - 1) % kRing] = r;
-    }
+    if (new_level) c->rec[(st.level - 1) % kRing] = step_record(c, s, prev, tot);
     c->qcount[(s + 2) % kSlots] = 0;
     c->ticket[(s + 1) % 2] = 0;
   }
@@ -893,14 +927,17 @@ __device__ __forceinline__ ExpandArgs step_expand_args(const BfsArgs& a, const L
 }
 
 template <bool EE>
-__global__ __launch_bounds__(kThreads) void k_step(BfsArgs a, int32_t s) {
+__global__ __launch_bounds__(kThreads) void k_step(BfsArgs a, int32_t s, StepReportArgs rp) {
   __shared__ LevelShared sh;
   Ctrl* c = a.ctrl;
   LevelTotals tot;
   LevelState prev;
   bool new_level;
   const LevelState st = step_state(a, s, &tot, &prev, &new_level);
-  if (blockIdx.x == 0) publish_step(c, s, st, prev, tot, new_level);
+  if (blockIdx.x == 0) {
+    publish_step(c, s, st, prev, tot, new_level);
+    if (rp.host) step_report(c, rp, s, st, prev, tot, new_level);
+  }
   if (st.done) return;
   if (st.phase == kPhaseScan) {
     step_scan(a, st, s);
@@ -1136,10 +1173,12 @@ hipError_t launch_level_prep(hipStream_t s, const BfsArgs& a, int32_t level, int
   return launch_k(k_level_prep, dim3(unsigned(scan_grid(a.V))), s, t0, t1, a, level, forced_dir);
 }
 
-hipError_t launch_step(hipStream_t s, const BfsArgs& a, int32_t step, hipEvent_t t0, hipEvent_t t1) {
+hipError_t launch_step(hipStream_t s, const BfsArgs& a, int32_t step, hipEvent_t t0, hipEvent_t t1,
+                       const StepReportArgs* rp) {
   const dim3 g(unsigned(main_blocks(a.nwords)));
-  if (a.early_exit) return launch_k(k_step<true>, g, s, t0, t1, a, step);
-  return launch_k(k_step<false>, g, s, t0, t1, a, step);
+  const StepReportArgs r = rp ? *rp : StepReportArgs{nullptr, 0u, 0, 0};
+  if (a.early_exit) return launch_k(k_step<true>, g, s, t0, t1, a, step, r);
+  return launch_k(k_step<false>, g, s, t0, t1, a, step, r);
 }
 
 hipError_t launch_step_report(hipStream_t s, const Ctrl* ctrl, int32_t s_first, int32_t n, int32_t rec_first,
