@@ -146,7 +146,7 @@ SortLayout plan_sort(int32_t V, int64_t nnz) {
 
 // Workspace layout of a multi-source call with k sources.
 struct BatchLayout {
-  size_t visA, visB, FA, FB, nzF, Q0, Q1, S, R, chunks, flagsA, flagsB, ctrl, lvl, total;
+  size_t visA, visB, F, nzF, Q0, Q1, S, R, chunks, flagsA, flagsB, ctrl, lvl, total;
   int64_t nflags, nchunks;
 };
 
@@ -163,8 +163,7 @@ BatchLayout plan_batch(int32_t V, int64_t nnz, int32_t k) {
   };
   L.visA = take(qb);
   L.visB = take(qb);
-  L.FA = take(qb);
-  L.FB = take(qb);
+  L.F = take(qb * size_t(kMbSnap + 2));  // frontier words: kMbSnap kept levels and two alternating
   L.nzF = take(wb);
   L.Q0 = take(vb);
   L.Q1 = take(vb);
@@ -990,8 +989,7 @@ dobfs_status dobfs::bfs_batch_rows(dobfs_graph g, const int32_t* sources, int32_
   a.active = k == 64 ? ~0ull : ((1ull << k) - 1ull);
   a.vis[0] = reinterpret_cast<uint64_t*>(ws + L.visA);
   a.vis[1] = reinterpret_cast<uint64_t*>(ws + L.visB);
-  a.F[0] = reinterpret_cast<uint64_t*>(ws + L.FA);
-  a.F[1] = reinterpret_cast<uint64_t*>(ws + L.FB);
+  a.Fs = reinterpret_cast<uint64_t*>(ws + L.F);
   a.nzF = reinterpret_cast<uint32_t*>(ws + L.nzF);
   a.Q[0] = reinterpret_cast<int32_t*>(ws + L.Q0);
   a.Q[1] = reinterpret_cast<int32_t*>(ws + L.Q1);

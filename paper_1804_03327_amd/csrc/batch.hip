@@ -22,9 +22,15 @@
 namespace dobfs {
 namespace {
 
-// Level L+1 for every source bit in `bits` of vertex v.
+__device__ __forceinline__ uint64_t* mb_frontier(const BatchArgs& a, int32_t L) {
+  return a.Fs + int64_t(mb_frontier_slot(L)) * a.V;
+}
+
+// Level L+1 for every source bit in `bits` of vertex v, where level L+1's
+// frontier is not kept (its words are the record of the levels below kMbSnap).
 __device__ __forceinline__ void stamp_levels(uint16_t* lvl, int32_t k, int32_t v, uint64_t bits,
                                              int32_t level) {
+  if (level + 1 < kMbSnap) return;
   uint16_t* row = lvl + int64_t(v) * k;
   while (bits) {
     const int b = __ffsll((unsigned long long)bits) - 1;
@@ -34,8 +40,8 @@ __device__ __forceinline__ void stamp_levels(uint16_t* lvl, int32_t k, int32_t v
 }
 
 // ----------------------------------------------------------------- init
-// Visited and frontier words hold the source bits, the spare frontier
-// buffer is cleared, the level of every source is 0, and the control block
+// Visited and level-0 frontier words hold the source bits (the frontier of
+// level 0 records that every source is at depth 0), and the control block
 // starts a push level whose list is the distinct sources.
 __global__ __launch_bounds__(kThreads) void k_mb_init(BatchArgs a, int32_t dir0, int64_t nflags) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
@@ -45,13 +51,7 @@ __global__ __launch_bounds__(kThreads) void k_mb_init(BatchArgs a, int32_t dir0,
     if ((a.src_filter[(v >> 6) & 15] >> (v & 63)) & 1ull)  // almost no vertex passes the filter
       for (int b = 0; b < a.k; ++b) m |= (a.src[b] == v) ? (1ull << b) : 0ull;
     a.vis[0][v] = m;
-    a.F[0][v] = m;
-    a.F[1][v] = 0;
-    if (m) {
-      uint16_t* row = a.lvl + v * a.k;
-      for (int b = 0; b < a.k; ++b)
-        if ((m >> b) & 1ull) row[b] = 0;
-    }
+    a.Fs[v] = m;  // mb_frontier(a, 0)
   }
   for (int64_t k = t0; k < nflags; k += stride) {
     a.flagsA[k] = 0;
@@ -112,8 +112,8 @@ __device__ void mb_expand_body(const BatchArgs& a, int32_t L, const LevelState& 
   if (blockIdx.x >= nchunks) return;
   const int32_t* Q = a.Q[L % 2];
   int32_t* Qout = a.Q[(L + 1) % 2];
-  const uint64_t* Fc = a.F[L % 2];
-  uint64_t* Fn = a.F[(L + 1) % 2];
+  const uint64_t* Fc = mb_frontier(a, L);
+  uint64_t* Fn = mb_frontier(a, L + 1);
   uint64_t* vis = a.vis[st.vis_idx];
   uint32_t* qcount = &a.ctrl->qcount[(L + 1) % kSlots];
   const uint64_t active = a.active;
@@ -248,7 +248,7 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
   const int32_t v0 = w0 * 32;
   const uint64_t* vin = a.vis[st.vis_idx];
   uint64_t* vout = a.vis[st.vis_idx ^ 1];
-  uint64_t* Fn = a.F[(L + 1) % 2];
+  uint64_t* Fn = mb_frontier(a, L + 1);
   const uint64_t active = st.active;  // a source with an empty frontier finds nothing more
   if (tid < kMbTileWords) sh.nzf[tid] = 0;
   if (tid == 0) {
@@ -386,9 +386,9 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
 // First kernel of level L: the state (direction rule on vertex counts and
 // edge counts of the whole batch), the previous level's record, and for a
 // push level the frontier list with its degree prefix. Before a push level
-// adds into the next frontier buffer, the entries the buffer still holds from
-// two levels back are cleared: sparsely through that level's list when it has
-// one, else densely.
+// adds into the next frontier buffer, the buffer is cleared: densely when it
+// is one of this traversal's fresh buffers, else (it holds the frontier of
+// two levels back) sparsely through that level's list when it has one.
 __global__ __launch_bounds__(kThreads) void k_mb_prep(BatchArgs a, int32_t L, int32_t forced) {
   Ctrl* c = a.ctrl;
   LevelTotals tot;
@@ -396,11 +396,12 @@ __global__ __launch_bounds__(kThreads) void k_mb_prep(BatchArgs a, int32_t L, in
   const LevelState st = level_state(a, L, forced, &tot, &prev);
   publish_level(c, L, st, prev, tot);
   if (st.done || st.dir != 0) return;
-  uint64_t* Fn = a.F[(L + 1) % 2];
-  if (L >= 1) {
+  uint64_t* Fn = mb_frontier(a, L + 1);
+  {
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (prev.list_valid || prev.dir == 0) {  // a push level always had its frontier as a list
+    if (mb_frontier_recycled(L + 1) && (prev.list_valid || prev.dir == 0)) {
+      // a push level always had its frontier as a list
       const int32_t* Qp = a.Q[(L + 1) % 2];
       for (int64_t i = t0; i < prev.nf; i += stride) Fn[Qp[i]] = 0;
     } else {
@@ -454,44 +455,101 @@ __global__ __launch_bounds__(kThreads) void k_mb_main(BatchArgs a, int32_t L) {
 }
 
 // rows.row[b][v] = level at which source b reached v, or -1: 64 vertices per
-// block step, read as whole [v][k] rows of the level table (16-byte pieces,
-// and only for vertices some source reached) and written as coalesced runs of
-// each depth row, four vertices per 16-byte store.
+// block step. The kept frontier words of levels below kMbSnap give those
+// depths: bit b of level L's word. Four threads per vertex fold the vertex's
+// kept words into bit planes of the depth (plane i = OR of the words of the
+// levels with bit i set; each reached pair sits in exactly one level's word)
+// and write 16 entries each of the block's [v][k] level table in LDS, 0xffff
+// where the source never reached the vertex; the level table in memory is
+// read only for pairs first reached at level kMbSnap or later. The depth
+// rows are then written as coalesced runs, four vertices per 16-byte store.
 constexpr int kMbDepthV = 64;
+static_assert(kMbSnap <= 16, "depths of the kept levels are folded into four bit planes");
+static_assert(kThreads == 4 * kMbDepthV, "four threads per vertex of a block step");
 __global__ __launch_bounds__(kThreads) void k_mb_depth(BatchArgs a, int32_t level, DepthRows rows) {
   __shared__ __align__(16) uint16_t s_l[kMbDepthV * kMaxSources];
-  __shared__ uint64_t s_v[kMbDepthV];
   const LevelState end = a.ctrl->ring[level % kRing];
   if (!end.done) return;  // not over yet: a later batch's transpose writes the rows
   const uint64_t* vis = a.vis[end.vis_idx];
   const int32_t k = a.k;
+  const int32_t nsnap = min(end.levels, kMbSnap);  // kept frontiers: levels 0 .. nsnap-1
   const int64_t nblk = (int64_t(a.V) + kMbDepthV - 1) / kMbDepthV;
-  const bool wide = (k % 8) == 0;  // level-table rows are whole 16-byte pieces
+  const int32_t j = threadIdx.x >> 2, b0 = (threadIdx.x & 3) * 16;
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
     const int64_t v0 = blk * kMbDepthV;
     const int32_t nv = int32_t(min(int64_t(kMbDepthV), int64_t(a.V) - v0));
-    __syncthreads();
-    if (threadIdx.x < nv) s_v[threadIdx.x] = vis[v0 + threadIdx.x];
-    __syncthreads();
-    if (wide) {  // only the rows of vertices some source reached (the rest is never read)
-      const int32_t per = k / 8;
-      const uint4* src = reinterpret_cast<const uint4*>(a.lvl + v0 * k);
-      uint4* dst = reinterpret_cast<uint4*>(s_l);
-      for (int32_t i = threadIdx.x; i < nv * per; i += kThreads)
-        if (s_v[i / per]) dst[i] = src[i];
-    } else {
-      for (int32_t i = threadIdx.x; i < nv * k; i += kThreads) s_l[i] = a.lvl[v0 * k + i];
+    __syncthreads();  // the previous step's table is no longer read
+    if (j < nv && b0 < k) {
+      const int64_t v = v0 + j;
+      const uint64_t reached = vis[v];
+      uint64_t kept = 0, p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+#pragma unroll
+      for (int32_t L = 0; L < kMbSnap; ++L) {
+        if (L < nsnap) {
+          const uint64_t f = a.Fs[int64_t(L) * a.V + v];  // mb_frontier(a, L)
+          kept |= f;
+          if (L & 1) p0 |= f;
+          if (L & 2) p1 |= f;
+          if (L & 4) p2 |= f;
+          if (L & 8) p3 |= f;
+        }
+      }
+      const uint64_t deep = reached & ~kept;
+      const int32_t nb = min(16, k - b0);
+      const bool vec = nb == 16 && (k % 8) == 0;  // this thread's 16 entries are one aligned 32-byte piece
+      union Piece {
+        uint4 x[2];
+        uint16_t h[16];
+      };
+      Piece lv, d;
+      lv.x[0] = lv.x[1] = make_uint4(0u, 0u, 0u, 0u);
+      const uint16_t* lrow = a.lvl + v * k + b0;
+      if ((deep >> b0) & 0xffffull) {  // some of these pairs were reached at a level >= kMbSnap
+        if (vec) {
+          lv.x[0] = reinterpret_cast<const uint4*>(lrow)[0];
+          lv.x[1] = reinterpret_cast<const uint4*>(lrow)[1];
+        } else {
+#pragma unroll
+          for (int32_t q = 0; q < 16; ++q)
+            if (q < nb) lv.h[q] = lrow[q];
+        }
+      }
+#pragma unroll
+      for (int32_t q = 0; q < 16; ++q) {
+        const int32_t b = b0 + q;
+        uint16_t x = 0xffff;
+        if ((deep >> b) & 1ull) {
+          x = lv.h[q];
+        } else if ((reached >> b) & 1ull) {
+          x = uint16_t(((p0 >> b) & 1ull) | (((p1 >> b) & 1ull) << 1) | (((p2 >> b) & 1ull) << 2) |
+                       (((p3 >> b) & 1ull) << 3));
+        }
+        d.h[q] = x;
+      }
+      uint16_t* dst = s_l + j * k + b0;
+      if (vec) {
+        reinterpret_cast<uint4*>(dst)[0] = d.x[0];
+        reinterpret_cast<uint4*>(dst)[1] = d.x[1];
+      } else {
+#pragma unroll
+        for (int32_t q = 0; q < 16; ++q)
+          if (q < nb) dst[q] = d.h[q];
+      }
     }
     __syncthreads();
+    auto depth_at = [&](int32_t i) -> int32_t {
+      const uint16_t d = s_l[i];
+      return d == 0xffff ? -1 : int32_t(d);
+    };
     if (nv == kMbDepthV) {
       // four consecutive vertices of one depth row per item: one 16-byte store where the row allows
       constexpr int kQ = kMbDepthV / 4;
       for (int32_t it = threadIdx.x; it < k * kQ; it += kThreads) {
-        const int32_t b = it / kQ, j = (it % kQ) * 4;
+        const int32_t b = it / kQ, jj = (it % kQ) * 4;
         int32_t d[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) d[q] = ((s_v[j + q] >> b) & 1ull) ? int32_t(s_l[(j + q) * k + b]) : -1;
-        int32_t* out = rows.row[b] + v0 + j;
+        for (int q = 0; q < 4; ++q) d[q] = depth_at((jj + q) * k + b);
+        int32_t* out = rows.row[b] + v0 + jj;
         if ((reinterpret_cast<uintptr_t>(out) & 15) == 0) {
           *reinterpret_cast<int4*>(out) = make_int4(d[0], d[1], d[2], d[3]);
         } else {
@@ -501,8 +559,8 @@ __global__ __launch_bounds__(kThreads) void k_mb_depth(BatchArgs a, int32_t leve
       }
     } else {
       for (int32_t i = threadIdx.x; i < nv * k; i += kThreads) {
-        const int32_t b = i / nv, j = i - b * nv;
-        rows.row[b][v0 + j] = ((s_v[j] >> b) & 1ull) ? int32_t(s_l[j * k + b]) : -1;
+        const int32_t b = i / nv, jj = i - b * nv;
+        rows.row[b][v0 + jj] = depth_at(jj * k + b);
       }
     }
   }

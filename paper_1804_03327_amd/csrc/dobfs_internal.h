@@ -276,12 +276,12 @@ struct BatchArgs {
   const int32_t* rowind;
   const uint32_t* nz_in;
   const int4* slab;          // first kSlab entries of every CSC column (-1 past its end)
-  uint16_t* lvl;             // [V][k]: level at which source b reached v (valid where vis bit b is set)
+  uint16_t* lvl;             // [V][k]: level at which source b reached v, for levels >= kMbSnap only
   int32_t k;                 // sources
   int32_t nuniq;             // distinct sources
   uint64_t active;           // the k source bits
   uint64_t* vis[2];          // per vertex: sources that reached it
-  uint64_t* F[2];            // per vertex: sources whose frontier holds it; level L reads F[L % 2]
+  uint64_t* Fs;              // kMbSnap + 2 buffers of V words; level L's frontier in mb_frontier(a, L)
   uint32_t* nzF;             // one bit per vertex: its next-frontier word is nonzero (pull output)
   int32_t* Q[2];
   int32_t* S;
@@ -300,6 +300,15 @@ struct BatchArgs {
   int32_t uniq[kMaxSources]; // the distinct sources: the first frontier list
   uint64_t src_filter[16];   // bit (v & 1023) set when some source v' has v' & 1023 == v & 1023
 };
+// Multi-source frontier words: per vertex, the sources whose frontier holds it.
+// The frontier of level L is exactly the set of (vertex, source) pairs first
+// reached at level L, so the frontiers of levels below kMbSnap are kept, one
+// buffer each, and stand in for those levels' depths; later levels alternate
+// between two more buffers and record their depths in the level table.
+constexpr int kMbSnap = 16;
+__host__ __device__ inline int32_t mb_frontier_slot(int32_t L) { return L < kMbSnap ? L : kMbSnap + (L & 1); }
+// whether level L's frontier buffer held the frontier of level L - 2 in this traversal
+__host__ __device__ inline bool mb_frontier_recycled(int32_t L) { return L >= kMbSnap + 2; }
 constexpr int kMbTileWords = 8;                 // multi-source pull: bitmap words of rows per block
 constexpr int kMbTileV = kMbTileWords * 32;     // 256 rows, one per thread: a tile's rows all run at once
 constexpr int kMbMid = 32;                      // multi-source pull: in-neighbours a thread scans before a wave takes over

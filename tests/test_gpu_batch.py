@@ -178,6 +178,36 @@ def test_batch_small_graphs():
                 _check(hg, srcs, d, st, "%s %s k=%d" % (name, mode, len(srcs)))
 
 
+@pytest.mark.parametrize("V", [15, 16, 17, 18, 19, 40])
+def test_batch_kept_level_boundary(V):
+    """Paths whose eccentricities straddle the number of levels whose frontier words are kept
+    (16): depths below it come from those words, deeper ones from the level table, and the
+    two alternating frontier buffers past it start out holding a previous call's words."""
+    hg = gen.from_edges(V, np.arange(V - 1), np.arange(1, V), directed=False, name="path%d" % V)
+    g = upload(hg)
+    rng = np.random.default_rng(V)
+    for k in (33, 64):
+        srcs = [0, V - 1, V // 2, 1] + [int(x) for x in rng.integers(0, V, k - 4)]
+        for mode in ["full", "push_only", "pull_only"]:
+            d, st = _run(g, srcs, dobfs.make_options(mode))
+            _check(hg, srcs, d, st, "path%d %s k=%d" % (V, mode, k))
+
+
+def test_batch_forced_schedules_deep(graphs):
+    """Push and pull alternating over a traversal far deeper than the kept frontier levels: a
+    push after a pull must clear a recycled frontier buffer densely, a push after a push
+    through the earlier push's list."""
+    hg, g = graphs["grid61x53"]
+    srcs = [0] + _sources(hg, 32, 41)
+    for sc in ([PUSH, PULL] * 70, [PULL, PULL, PUSH] * 50, [PUSH, PUSH, PULL] * 50):
+        tag = "grid forced %s..." % "".join(str(int(x)) for x in sc[:6])
+        _say(tag)
+        d, st = _run(g, srcs, dobfs.make_options("full", forced_dirs=[int(x) for x in sc]))
+        _check(hg, srcs, d, st, tag)
+        dirs = [x["dir"] for x in dobfs.stats_levels(st)]
+        assert dirs == [int(x) for x in sc[: len(dirs)]], tag
+
+
 def test_batch_errors(graphs):
     hg, g = graphs["rmat10"]
     depth = torch.zeros(64 * g.V, dtype=torch.int32, device="cuda")
