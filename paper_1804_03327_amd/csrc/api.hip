@@ -163,7 +163,8 @@ BatchLayout plan_batch(int32_t V, int64_t nnz, int32_t k) {
   };
   L.visA = take(qb);
   L.visB = take(qb);
-  L.F = take(qb * size_t(kMbSnap + 2));  // frontier words: kMbSnap kept levels and two alternating
+  // frontier words: kMbSnap kept levels and two alternating, each buffer 256-byte aligned
+  L.F = take(size_t(mb_fstride(V)) * 8 * size_t(kMbSnap + 2));
   L.nzF = take(wb);
   L.Q0 = take(vb);
   L.Q1 = take(vb);
@@ -990,6 +991,7 @@ dobfs_status dobfs::bfs_batch_rows(dobfs_graph g, const int32_t* sources, int32_
   a.vis[0] = reinterpret_cast<uint64_t*>(ws + L.visA);
   a.vis[1] = reinterpret_cast<uint64_t*>(ws + L.visB);
   a.Fs = reinterpret_cast<uint64_t*>(ws + L.F);
+  a.fstride = mb_fstride(g->V);
   a.nzF = reinterpret_cast<uint32_t*>(ws + L.nzF);
   a.Q[0] = reinterpret_cast<int32_t*>(ws + L.Q0);
   a.Q[1] = reinterpret_cast<int32_t*>(ws + L.Q1);

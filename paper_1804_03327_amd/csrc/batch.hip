@@ -23,7 +23,7 @@ namespace dobfs {
 namespace {
 
 __device__ __forceinline__ uint64_t* mb_frontier(const BatchArgs& a, int32_t L) {
-  return a.Fs + int64_t(mb_frontier_slot(L)) * a.V;
+  return a.Fs + int64_t(mb_frontier_slot(L)) * a.fstride;
 }
 
 // Level L+1 for every source bit in `bits` of vertex v, where level L+1's
@@ -41,8 +41,9 @@ __device__ __forceinline__ void stamp_levels(uint16_t* lvl, int32_t k, int32_t v
 
 // ----------------------------------------------------------------- init
 // Visited and level-0 frontier words hold the source bits (the frontier of
-// level 0 records that every source is at depth 0), and the control block
-// starts a push level whose list is the distinct sources.
+// level 0 records that every source is at depth 0), level 1's frontier
+// buffer is cleared for the first push, and the control block starts a push
+// level whose list is the distinct sources.
 __global__ __launch_bounds__(kThreads) void k_mb_init(BatchArgs a, int32_t dir0, int64_t nflags) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -51,7 +52,8 @@ __global__ __launch_bounds__(kThreads) void k_mb_init(BatchArgs a, int32_t dir0,
     if ((a.src_filter[(v >> 6) & 15] >> (v & 63)) & 1ull)  // almost no vertex passes the filter
       for (int b = 0; b < a.k; ++b) m |= (a.src[b] == v) ? (1ull << b) : 0ull;
     a.vis[0][v] = m;
-    a.Fs[v] = m;  // mb_frontier(a, 0)
+    a.Fs[v] = m;              // mb_frontier(a, 0)
+    a.Fs[a.fstride + v] = 0;  // mb_frontier(a, 1)
   }
   for (int64_t k = t0; k < nflags; k += stride) {
     a.flagsA[k] = 0;
@@ -98,12 +100,13 @@ struct MbExpandShared {
 };
 
 // Column-based product: every edge u -> w of the frontier's concatenated
-// adjacency carries F[u]'s source bits to w. The bits w has not seen are
-// claimed with one 64-bit atomicOr on Vis[w]; the bits a thread newly set are
-// its own, so it stamps their level and adds them to the next frontier word
-// of w. The thread whose add made that word nonzero lists w for the next
-// level. The chunked, load-balanced walk over the edges is the one of the
-// single-source expansion.
+// adjacency carries F[u]'s source bits to w. The bits w had not seen when the
+// level began are claimed with one 64-bit atomicOr on w's next-frontier word
+// (Vis is not written during the level: the next frontier is exactly what it
+// gains, merged in by the next level's prep); the bits a thread newly set are
+// its own to count, and the thread whose add made the word nonzero lists w
+// for the next level. The chunked, load-balanced walk over the edges is the
+// one of the single-source expansion.
 __device__ void mb_expand_body(const BatchArgs& a, int32_t L, const LevelState& st, MbExpandShared& sh) {
   const int32_t nf = st.nf;
   const uint32_t m = a.ctrl->mf[L % kSlots];
@@ -170,20 +173,24 @@ __device__ void mb_expand_body(const BatchArgs& a, int32_t L, const LevelState& 
         pos[t] = rs + int32_t(e - uint32_t(s));
       }
     }
-    uint64_t x[kExpandEPT];
+    uint64_t x[kExpandEPT], seen[kExpandEPT];
 #pragma unroll
     for (int t = 0; t < kExpandEPT; ++t) w[t] = valid[t] ? a.colind[pos[t]] : 0;
 #pragma unroll
-    for (int t = 0; t < kExpandEPT; ++t) x[t] = valid[t] ? (Fc[u[t]] & active & ~vis[w[t]]) : 0ull;
+    for (int t = 0; t < kExpandEPT; ++t) {
+      seen[t] = valid[t] ? vis[w[t]] : ~0ull;
+      x[t] = valid[t] ? (Fc[u[t]] & active & ~seen[t]) : 0ull;
+    }
     bool listed[kExpandEPT];
 #pragma unroll
     for (int t = 0; t < kExpandEPT; ++t) {
       listed[t] = false;
       if (x[t]) {
-        const uint64_t old = atomicOr((unsigned long long*)(vis + w[t]), (unsigned long long)x[t]);
-        const uint64_t nb = x[t] & ~old;
+        // the next frontier word collects exactly the bits w gains at this level, so it is the
+        // only word claimed here; the visited words take them in the next level's prep
+        const uint64_t oldf = atomicOr((unsigned long long*)(Fn + w[t]), (unsigned long long)x[t]);
+        const uint64_t nb = x[t] & ~oldf;
         if (nb) {
-          const uint64_t oldf = atomicOr((unsigned long long*)(Fn + w[t]), (unsigned long long)nb);
           stamp_levels(a.lvl, a.k, w[t], nb, L);
           nbits += uint64_t(__popcll(nb));
           fbits |= nb;
@@ -192,7 +199,7 @@ __device__ void mb_expand_body(const BatchArgs& a, int32_t L, const LevelState& 
             ++nvert;
             if (a.edge_rule) mnew += uint64_t(a.rowptr[w[t] + 1] - a.rowptr[w[t]]);
           }
-          if (a.edge_rule && ((old | nb) & active) == active)  // this claim completed w
+          if (a.edge_rule && ((seen[t] | oldf | nb) & active) == active)  // this claim completed w
             insub += uint64_t(a.colptr[w[t] + 1] - a.colptr[w[t]]);
         }
       }
@@ -395,17 +402,42 @@ __global__ __launch_bounds__(kThreads) void k_mb_prep(BatchArgs a, int32_t L, in
   LevelState prev;
   const LevelState st = level_state(a, L, forced, &tot, &prev);
   publish_level(c, L, st, prev, tot);
+  if (L >= 1 && !st.done && prev.dir == 0) {
+    // a push leaves Vis as the level began: merge in what it found, through its list
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int32_t* Qc = a.Q[L % 2];
+    const uint64_t* Fc = mb_frontier(a, L);
+    uint64_t* vis = a.vis[st.vis_idx];
+    constexpr int kU = 4;  // independent entries per thread in flight
+    for (int64_t i0 = t0; i0 < st.nf; i0 += stride * kU) {
+      int32_t v[kU];
+      uint64_t f[kU], m[kU];
+#pragma unroll
+      for (int q = 0; q < kU; ++q) v[q] = i0 + q * stride < st.nf ? Qc[i0 + q * stride] : -1;
+#pragma unroll
+      for (int q = 0; q < kU; ++q) {
+        f[q] = v[q] >= 0 ? Fc[v[q]] : 0ull;
+        m[q] = v[q] >= 0 ? vis[v[q]] : 0ull;
+      }
+#pragma unroll
+      for (int q = 0; q < kU; ++q)
+        if (v[q] >= 0) vis[v[q]] = m[q] | f[q];
+    }
+  }
   if (st.done || st.dir != 0) return;
   uint64_t* Fn = mb_frontier(a, L + 1);
-  {
+  if (L >= 1) {  // level 1's buffer is cleared by the init kernel
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (mb_frontier_recycled(L + 1) && (prev.list_valid || prev.dir == 0)) {
       // a push level always had its frontier as a list
       const int32_t* Qp = a.Q[(L + 1) % 2];
       for (int64_t i = t0; i < prev.nf; i += stride) Fn[Qp[i]] = 0;
-    } else {
-      for (int64_t v = t0; v < a.V; v += stride) Fn[v] = 0;
+    } else {  // 16-byte stores: the buffer is 256-byte aligned and padded to an even length
+      ulonglong2* F2 = reinterpret_cast<ulonglong2*>(Fn);
+      const ulonglong2 z = make_ulonglong2(0ull, 0ull);
+      for (int64_t i = t0; i < (int64_t(a.V) + 1) / 2; i += stride) F2[i] = z;
     }
   }
   uint32_t* mf_out = &c->mf[L % kSlots];
@@ -454,113 +486,100 @@ __global__ __launch_bounds__(kThreads) void k_mb_main(BatchArgs a, int32_t L) {
   }
 }
 
-// rows.row[b][v] = level at which source b reached v, or -1: 64 vertices per
-// block step. The kept frontier words of levels below kMbSnap give those
-// depths: bit b of level L's word. Four threads per vertex fold the vertex's
-// kept words into bit planes of the depth (plane i = OR of the words of the
-// levels with bit i set; each reached pair sits in exactly one level's word)
-// and write 16 entries each of the block's [v][k] level table in LDS, 0xffff
-// where the source never reached the vertex; the level table in memory is
-// read only for pairs first reached at level kMbSnap or later. The depth
-// rows are then written as coalesced runs, four vertices per 16-byte store.
-constexpr int kMbDepthV = 64;
+// rows.row[b][v] = level at which source b reached v, or -1. A thread takes
+// four consecutive vertices and folds their kept frontier words (levels below
+// kMbSnap: bit b of level L's word) into bit planes of the depth, plane i
+// being the OR of the words of the levels with bit i set (each reached pair
+// sits in exactly one level's word). It then walks the sources, writing each
+// depth row's four entries with one 16-byte store, so a wave writes 1 KB
+// runs of a row. The level table in memory is read, eight entries at a time,
+// only where a pair was first reached at level kMbSnap or later.
+constexpr int kMbDepthVPT = 4;
 static_assert(kMbSnap <= 16, "depths of the kept levels are folded into four bit planes");
-static_assert(kThreads == 4 * kMbDepthV, "four threads per vertex of a block step");
 __global__ __launch_bounds__(kThreads) void k_mb_depth(BatchArgs a, int32_t level, DepthRows rows) {
-  __shared__ __align__(16) uint16_t s_l[kMbDepthV * kMaxSources];
   const LevelState end = a.ctrl->ring[level % kRing];
   if (!end.done) return;  // not over yet: a later batch's transpose writes the rows
   const uint64_t* vis = a.vis[end.vis_idx];
   const int32_t k = a.k;
   const int32_t nsnap = min(end.levels, kMbSnap);  // kept frontiers: levels 0 .. nsnap-1
-  const int64_t nblk = (int64_t(a.V) + kMbDepthV - 1) / kMbDepthV;
-  const int32_t j = threadIdx.x >> 2, b0 = (threadIdx.x & 3) * 16;
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const int64_t v0 = blk * kMbDepthV;
-    const int32_t nv = int32_t(min(int64_t(kMbDepthV), int64_t(a.V) - v0));
-    __syncthreads();  // the previous step's table is no longer read
-    if (j < nv && b0 < k) {
-      const int64_t v = v0 + j;
-      const uint64_t reached = vis[v];
-      uint64_t kept = 0, p0 = 0, p1 = 0, p2 = 0, p3 = 0;
-#pragma unroll
-      for (int32_t L = 0; L < kMbSnap; ++L) {
-        if (L < nsnap) {
-          const uint64_t f = a.Fs[int64_t(L) * a.V + v];  // mb_frontier(a, L)
-          kept |= f;
-          if (L & 1) p0 |= f;
-          if (L & 2) p1 |= f;
-          if (L & 4) p2 |= f;
-          if (L & 8) p3 |= f;
-        }
-      }
-      const uint64_t deep = reached & ~kept;
-      const int32_t nb = min(16, k - b0);
-      const bool vec = nb == 16 && (k % 8) == 0;  // this thread's 16 entries are one aligned 32-byte piece
-      union Piece {
-        uint4 x[2];
-        uint16_t h[16];
-      };
-      Piece lv, d;
-      lv.x[0] = lv.x[1] = make_uint4(0u, 0u, 0u, 0u);
-      const uint16_t* lrow = a.lvl + v * k + b0;
-      if ((deep >> b0) & 0xffffull) {  // some of these pairs were reached at a level >= kMbSnap
-        if (vec) {
-          lv.x[0] = reinterpret_cast<const uint4*>(lrow)[0];
-          lv.x[1] = reinterpret_cast<const uint4*>(lrow)[1];
-        } else {
-#pragma unroll
-          for (int32_t q = 0; q < 16; ++q)
-            if (q < nb) lv.h[q] = lrow[q];
-        }
-      }
-#pragma unroll
-      for (int32_t q = 0; q < 16; ++q) {
-        const int32_t b = b0 + q;
-        uint16_t x = 0xffff;
-        if ((deep >> b) & 1ull) {
-          x = lv.h[q];
-        } else if ((reached >> b) & 1ull) {
-          x = uint16_t(((p0 >> b) & 1ull) | (((p1 >> b) & 1ull) << 1) | (((p2 >> b) & 1ull) << 2) |
-                       (((p3 >> b) & 1ull) << 3));
-        }
-        d.h[q] = x;
-      }
-      uint16_t* dst = s_l + j * k + b0;
-      if (vec) {
-        reinterpret_cast<uint4*>(dst)[0] = d.x[0];
-        reinterpret_cast<uint4*>(dst)[1] = d.x[1];
+  const int64_t ngroups = (int64_t(a.V) + kMbDepthVPT - 1) / kMbDepthVPT;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < ngroups; g += stride) {
+    const int64_t v0 = g * kMbDepthVPT;
+    const int32_t nv = int32_t(min(int64_t(kMbDepthVPT), int64_t(a.V) - v0));
+    uint64_t reached[4], kept[4], p0[4], p1[4], p2[4], p3[4];
+    // v0 is a multiple of 4 and every word array is 256-byte aligned: two 16-byte loads each
+    auto load4 = [&](const uint64_t* base, uint64_t out[4]) {
+      if (nv == 4) {
+        const ulonglong2 x = reinterpret_cast<const ulonglong2*>(base + v0)[0];
+        const ulonglong2 y = reinterpret_cast<const ulonglong2*>(base + v0)[1];
+        out[0] = x.x; out[1] = x.y; out[2] = y.x; out[3] = y.y;
       } else {
 #pragma unroll
-        for (int32_t q = 0; q < 16; ++q)
-          if (q < nb) dst[q] = d.h[q];
+        for (int q = 0; q < 4; ++q) out[q] = q < nv ? base[v0 + q] : 0ull;
+      }
+    };
+    load4(vis, reached);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) kept[q] = p0[q] = p1[q] = p2[q] = p3[q] = 0ull;
+#pragma unroll
+    for (int32_t L = 0; L < kMbSnap; ++L) {
+      if (L < nsnap) {
+        uint64_t f[4];
+        load4(a.Fs + int64_t(L) * a.fstride, f);  // mb_frontier(a, L)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          kept[q] |= f[q];
+          if (L & 1) p0[q] |= f[q];
+          if (L & 2) p1[q] |= f[q];
+          if (L & 4) p2[q] |= f[q];
+          if (L & 8) p3[q] |= f[q];
+        }
       }
     }
-    __syncthreads();
-    auto depth_at = [&](int32_t i) -> int32_t {
-      const uint16_t d = s_l[i];
-      return d == 0xffff ? -1 : int32_t(d);
-    };
-    if (nv == kMbDepthV) {
-      // four consecutive vertices of one depth row per item: one 16-byte store where the row allows
-      constexpr int kQ = kMbDepthV / 4;
-      for (int32_t it = threadIdx.x; it < k * kQ; it += kThreads) {
-        const int32_t b = it / kQ, jj = (it % kQ) * 4;
+    uint64_t deep[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) deep[q] = reached[q] & ~kept[q];
+    const bool any_deep = (deep[0] | deep[1] | deep[2] | deep[3]) != 0ull;
+    for (int32_t b8 = 0; b8 < k; b8 += 8) {
+      union Piece {
+        uint4 x;
+        uint16_t h[8];
+      };
+      Piece lv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        lv[q].x = make_uint4(0u, 0u, 0u, 0u);
+        if (any_deep && ((deep[q] >> b8) & 0xffull)) {  // some pair reached at a level >= kMbSnap
+          const uint16_t* row = a.lvl + (v0 + q) * k + b8;
+          if ((k % 8) == 0) {
+            lv[q].x = *reinterpret_cast<const uint4*>(row);
+          } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+              if (b8 + j < k) lv[q].h[j] = row[j];
+          }
+        }
+      }
+#pragma unroll
+      for (int32_t j = 0; j < 8; ++j) {
+        const int32_t b = b8 + j;
+        if (b >= k) break;
         int32_t d[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) d[q] = depth_at((jj + q) * k + b);
-        int32_t* out = rows.row[b] + v0 + jj;
-        if ((reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t plane = uint32_t((p0[q] >> b) & 1ull) | (uint32_t((p1[q] >> b) & 1ull) << 1) |
+                                 (uint32_t((p2[q] >> b) & 1ull) << 2) | (uint32_t((p3[q] >> b) & 1ull) << 3);
+          d[q] = !((reached[q] >> b) & 1ull) ? -1 : (((deep[q] >> b) & 1ull) ? int32_t(lv[q].h[j]) : int32_t(plane));
+        }
+        int32_t* out = rows.row[b] + v0;
+        if (nv == 4 && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
           *reinterpret_cast<int4*>(out) = make_int4(d[0], d[1], d[2], d[3]);
         } else {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) out[q] = d[q];
+          for (int q = 0; q < 4; ++q)
+            if (q < nv) out[q] = d[q];
         }
-      }
-    } else {
-      for (int32_t i = threadIdx.x; i < nv * k; i += kThreads) {
-        const int32_t b = i / nv, jj = i - b * nv;
-        rows.row[b][v0 + jj] = depth_at(jj * k + b);
       }
     }
   }
@@ -587,8 +606,8 @@ hipError_t launch_mb_main(hipStream_t s, const BatchArgs& a, int32_t level, hipE
 }
 
 hipError_t launch_mb_depth(hipStream_t s, const BatchArgs& a, int32_t level, const DepthRows& rows) {
-  const int64_t nblk = (int64_t(a.V) + kMbDepthV - 1) / kMbDepthV;
-  const unsigned g = unsigned(std::min<int64_t>(nblk, 4096));
+  const int64_t groups = (int64_t(a.V) + kMbDepthVPT - 1) / kMbDepthVPT;
+  const unsigned g = unsigned(std::min<int64_t>((groups + kThreads - 1) / kThreads, 4096));
   hipLaunchKernelGGL(k_mb_depth, dim3(g > 0 ? g : 1), dim3(kThreads), 0, s, a, level, rows);
   return hipGetLastError();
 }

@@ -281,7 +281,8 @@ struct BatchArgs {
   int32_t nuniq;             // distinct sources
   uint64_t active;           // the k source bits
   uint64_t* vis[2];          // per vertex: sources that reached it
-  uint64_t* Fs;              // kMbSnap + 2 buffers of V words; level L's frontier in mb_frontier(a, L)
+  uint64_t* Fs;              // kMbSnap + 2 buffers of fstride words; level L's frontier in mb_frontier(a, L)
+  int64_t fstride;           // V rounded up to a multiple of 32 (every buffer 256-byte aligned)
   uint32_t* nzF;             // one bit per vertex: its next-frontier word is nonzero (pull output)
   int32_t* Q[2];
   int32_t* S;
@@ -307,6 +308,7 @@ struct BatchArgs {
 // between two more buffers and record their depths in the level table.
 constexpr int kMbSnap = 16;
 __host__ __device__ inline int32_t mb_frontier_slot(int32_t L) { return L < kMbSnap ? L : kMbSnap + (L & 1); }
+__host__ __device__ inline int64_t mb_fstride(int64_t V) { return (V + 31) / 32 * 32; }
 // whether level L's frontier buffer held the frontier of level L - 2 in this traversal
 __host__ __device__ inline bool mb_frontier_recycled(int32_t L) { return L >= kMbSnap + 2; }
 constexpr int kMbTileWords = 8;                 // multi-source pull: bitmap words of rows per block
