@@ -403,26 +403,43 @@ __global__ __launch_bounds__(kThreads) void k_mb_prep(BatchArgs a, int32_t L, in
   const LevelState st = level_state(a, L, forced, &tot, &prev);
   publish_level(c, L, st, prev, tot);
   if (L >= 1 && !st.done && prev.dir == 0) {
-    // a push leaves Vis as the level began: merge in what it found, through its list
+    // a push leaves Vis as the level began: merge in what it found, through its list when that
+    // is short, else in one dense pass (random lines of two arrays cost more than a sweep)
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int32_t* Qc = a.Q[L % 2];
     const uint64_t* Fc = mb_frontier(a, L);
     uint64_t* vis = a.vis[st.vis_idx];
-    constexpr int kU = 4;  // independent entries per thread in flight
-    for (int64_t i0 = t0; i0 < st.nf; i0 += stride * kU) {
-      int32_t v[kU];
-      uint64_t f[kU], m[kU];
-#pragma unroll
-      for (int q = 0; q < kU; ++q) v[q] = i0 + q * stride < st.nf ? Qc[i0 + q * stride] : -1;
-#pragma unroll
-      for (int q = 0; q < kU; ++q) {
-        f[q] = v[q] >= 0 ? Fc[v[q]] : 0ull;
-        m[q] = v[q] >= 0 ? vis[v[q]] : 0ull;
+    if (int64_t(st.nf) * kMbDenseMerge >= int64_t(a.V)) {
+      const ulonglong2* F2 = reinterpret_cast<const ulonglong2*>(Fc);
+      ulonglong2* V2 = reinterpret_cast<ulonglong2*>(vis);
+      const int64_t n2 = int64_t(a.V) / 2;
+      for (int64_t i = t0; i < n2; i += stride) {
+        const ulonglong2 f = F2[i];
+        if (f.x | f.y) {
+          ulonglong2 m = V2[i];
+          m.x |= f.x;
+          m.y |= f.y;
+          V2[i] = m;
+        }
       }
+      if ((a.V & 1) && t0 == 0) vis[a.V - 1] |= Fc[a.V - 1];
+    } else {
+      constexpr int kU = 4;  // independent entries per thread in flight
+      for (int64_t i0 = t0; i0 < st.nf; i0 += stride * kU) {
+        int32_t v[kU];
+        uint64_t f[kU], m[kU];
 #pragma unroll
-      for (int q = 0; q < kU; ++q)
-        if (v[q] >= 0) vis[v[q]] = m[q] | f[q];
+        for (int q = 0; q < kU; ++q) v[q] = i0 + q * stride < st.nf ? Qc[i0 + q * stride] : -1;
+#pragma unroll
+        for (int q = 0; q < kU; ++q) {
+          f[q] = v[q] >= 0 ? Fc[v[q]] : 0ull;
+          m[q] = v[q] >= 0 ? vis[v[q]] : 0ull;
+        }
+#pragma unroll
+        for (int q = 0; q < kU; ++q)
+          if (v[q] >= 0) vis[v[q]] = m[q] | f[q];
+      }
     }
   }
   if (st.done || st.dir != 0) return;

@@ -311,6 +311,7 @@ __host__ __device__ inline int32_t mb_frontier_slot(int32_t L) { return L < kMbS
 __host__ __device__ inline int64_t mb_fstride(int64_t V) { return (V + 31) / 32 * 32; }
 // whether level L's frontier buffer held the frontier of level L - 2 in this traversal
 __host__ __device__ inline bool mb_frontier_recycled(int32_t L) { return L >= kMbSnap + 2; }
+constexpr int kMbDenseMerge = 16;  // a push's winners merge into Vis densely once they are V/16 or more
 constexpr int kMbTileWords = 8;                 // multi-source pull: bitmap words of rows per block
 constexpr int kMbTileV = kMbTileWords * 32;     // 256 rows, one per thread: a tile's rows all run at once
 constexpr int kMbMid = 32;                      // multi-source pull: in-neighbours a thread scans before a wave takes over
