@@ -234,7 +234,9 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options *opt, 
 /* ------------------------------------------------------ multi-source BFS */
 
 /* Device bytes of workspace a dobfs_bfs_batch call with k sources needs
- * (k in [1, 64]; it grows by 2*k bytes per vertex for the level table). */
+ * (k in [1, 64]): about 168 bytes per vertex for the visited and frontier
+ * words (the frontiers of the first 16 levels are kept as their depth
+ * record), plus 2*k bytes per vertex for the level table of deeper levels. */
 dobfs_status dobfs_bfs_batch_workspace_bytes(dobfs_graph g, int32_t k, size_t *bytes);
 
 /*

@@ -146,7 +146,7 @@ SortLayout plan_sort(int32_t V, int64_t nnz) {
 
 // Workspace layout of a multi-source call with k sources.
 struct BatchLayout {
-  size_t visA, visB, F, nzF, Q0, Q1, S, R, chunks, flagsA, flagsB, ctrl, lvl, total;
+  size_t visA, visB, F, nzF0, nzF1, Q0, Q1, S, R, chunks, flagsA, flagsB, ctrl, lvl, total;
   int64_t nflags, nchunks;
 };
 
@@ -165,7 +165,8 @@ BatchLayout plan_batch(int32_t V, int64_t nnz, int32_t k) {
   L.visB = take(qb);
   // frontier words: kMbSnap kept levels and two alternating, each buffer 256-byte aligned
   L.F = take(size_t(mb_fstride(V)) * 8 * size_t(kMbSnap + 2));
-  L.nzF = take(wb);
+  L.nzF0 = take(wb);
+  L.nzF1 = take(wb);
   L.Q0 = take(vb);
   L.Q1 = take(vb);
   L.S = take(vb);
@@ -992,7 +993,8 @@ dobfs_status dobfs::bfs_batch_rows(dobfs_graph g, const int32_t* sources, int32_
   a.vis[1] = reinterpret_cast<uint64_t*>(ws + L.visB);
   a.Fs = reinterpret_cast<uint64_t*>(ws + L.F);
   a.fstride = mb_fstride(g->V);
-  a.nzF = reinterpret_cast<uint32_t*>(ws + L.nzF);
+  a.nzF[0] = reinterpret_cast<uint32_t*>(ws + L.nzF0);
+  a.nzF[1] = reinterpret_cast<uint32_t*>(ws + L.nzF1);
   a.Q[0] = reinterpret_cast<int32_t*>(ws + L.Q0);
   a.Q[1] = reinterpret_cast<int32_t*>(ws + L.Q1);
   a.S = reinterpret_cast<int32_t*>(ws + L.S);

@@ -119,6 +119,8 @@ __device__ void mb_expand_body(const BatchArgs& a, int32_t L, const LevelState& 
   uint64_t* Fn = mb_frontier(a, L + 1);
   uint64_t* vis = a.vis[st.vis_idx];
   uint32_t* qcount = &a.ctrl->qcount[(L + 1) % kSlots];
+  uint32_t* nzn = a.nzF[(L + 1) % 2];
+  const bool marks = mb_push_marks(m);  // winners go to the non-zero bitmap, not the list
   const uint64_t active = a.active;
   if (threadIdx.x == 0) sh.nbuf = 0;
   unsigned long long nvert = 0, nbits = 0, mnew = 0, insub = 0;
@@ -144,7 +146,7 @@ __device__ void mb_expand_body(const BatchArgs& a, int32_t L, const LevelState& 
     const int32_t n = k1 - k0 + 1;
     const bool in_lds = n <= kExpandWin;
     __syncthreads();
-    if (sh.nbuf + kExpandChunk > kExpandBuf) flush();
+    if (!marks && sh.nbuf + kExpandChunk > kExpandBuf) flush();
     if (in_lds) {
       for (int32_t i = threadIdx.x; i < n; i += kThreads) {
         sh.sS[i] = a.S[k0 + i];
@@ -195,7 +197,8 @@ __device__ void mb_expand_body(const BatchArgs& a, int32_t L, const LevelState& 
           nbits += uint64_t(__popcll(nb));
           fbits |= nb;
           if (oldf == 0) {
-            listed[t] = true;
+            listed[t] = !marks;
+            if (marks) atomicOr(nzn + (w[t] >> 5), 1u << (w[t] & 31));
             ++nvert;
             if (a.edge_rule) mnew += uint64_t(a.rowptr[w[t] + 1] - a.rowptr[w[t]]);
           }
@@ -218,7 +221,7 @@ __device__ void mb_expand_body(const BatchArgs& a, int32_t L, const LevelState& 
     }
   }
   __syncthreads();
-  flush();
+  if (!marks) flush();
   unsigned long long v4[4] = {nvert, nbits, mnew, insub};
   block_sum4(v4);
   fbits = block_or64(fbits);
@@ -377,7 +380,7 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
     }
   }
   __syncthreads();
-  if (tid < kMbTileWords && w0 + tid < a.nwords) a.nzF[w0 + tid] = sh.nzf[tid];
+  if (tid < kMbTileWords && w0 + tid < a.nwords) a.nzF[(L + 1) % 2][w0 + tid] = sh.nzf[tid];
   unsigned long long v4[4] = {nvert, nbits, checks, mnew};
   block_sum4(v4);
   unsigned long long i4[4] = {insub, 0, 0, 0};
@@ -403,14 +406,14 @@ __global__ __launch_bounds__(kThreads) void k_mb_prep(BatchArgs a, int32_t L, in
   const LevelState st = level_state(a, L, forced, &tot, &prev);
   publish_level(c, L, st, prev, tot);
   if (L >= 1 && !st.done && prev.dir == 0) {
-    // a push leaves Vis as the level began: merge in what it found, through its list when that
-    // is short, else in one dense pass (random lines of two arrays cost more than a sweep)
+    // a push leaves Vis as the level began: merge in what it found, through its list when it
+    // made a short one, else in one dense pass (random lines of two arrays cost more than a sweep)
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int32_t* Qc = a.Q[L % 2];
     const uint64_t* Fc = mb_frontier(a, L);
     uint64_t* vis = a.vis[st.vis_idx];
-    if (int64_t(st.nf) * kMbDenseMerge >= int64_t(a.V)) {
+    if (!st.list_valid || int64_t(st.nf) * kMbDenseMerge >= int64_t(a.V)) {
       const ulonglong2* F2 = reinterpret_cast<const ulonglong2*>(Fc);
       ulonglong2* V2 = reinterpret_cast<ulonglong2*>(vis);
       const int64_t n2 = int64_t(a.V) / 2;
@@ -443,6 +446,10 @@ __global__ __launch_bounds__(kThreads) void k_mb_prep(BatchArgs a, int32_t L, in
     }
   }
   if (st.done || st.dir != 0) return;
+  {  // the non-zero bitmap of the next frontier, in case this push marks its winners there
+    uint32_t* nzn = a.nzF[(L + 1) % 2];
+    for (int32_t w = blockIdx.x * kThreads + threadIdx.x; w < a.nwords; w += gridDim.x * kThreads) nzn[w] = 0;
+  }
   uint64_t* Fn = mb_frontier(a, L + 1);
   if (L >= 1) {  // level 1's buffer is cleared by the init kernel
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
@@ -463,7 +470,7 @@ __global__ __launch_bounds__(kThreads) void k_mb_prep(BatchArgs a, int32_t L, in
               &c->ticket[L % 2], mf_out);
   } else {
     ScanBitsArgs sb{};
-    sb.a = a.nzF;
+    sb.a = a.nzF[L % 2];
     sb.b_not = nullptr;
     sb.nwords = a.nwords;
     sb.V = a.V;

@@ -489,7 +489,8 @@ __device__ LevelState next_state(const Args& a, int32_t L, int32_t forced, const
       if (forced >= 0) next = forced;
       st.dir = next;
       st.nf = int32_t(n_new);
-      st.list_valid = prev.dir == 0 ? 1 : 0;  // a push level appended its winners to Q[L % 2]
+      // a push level appended its winners to Q[L % 2], unless (multi-source) it marked them
+      st.list_valid = (prev.dir == 0 && !(batch && mb_push_marks(a.ctrl->mf[(L - 1) % kSlots]))) ? 1 : 0;
       st.vis_idx = prev.dir == 1 ? (prev.vis_idx ^ 1) : prev.vis_idx;
       st.m_u = m_u;
       st.active = batch ? uniform64(wave_or64(x.v4)) : 0ull;

@@ -283,7 +283,8 @@ struct BatchArgs {
   uint64_t* vis[2];          // per vertex: sources that reached it
   uint64_t* Fs;              // kMbSnap + 2 buffers of fstride words; level L's frontier in mb_frontier(a, L)
   int64_t fstride;           // V rounded up to a multiple of 32 (every buffer 256-byte aligned)
-  uint32_t* nzF;             // one bit per vertex: its next-frontier word is nonzero (pull output)
+  uint32_t* nzF[2];          // one bit per vertex: its frontier word is nonzero; level L reads nzF[L % 2]
+                             // (written by a pull, or by a push that marks instead of listing)
   int32_t* Q[2];
   int32_t* S;
   int32_t* R;
@@ -311,6 +312,13 @@ __host__ __device__ inline int32_t mb_frontier_slot(int32_t L) { return L < kMbS
 __host__ __device__ inline int64_t mb_fstride(int64_t V) { return (V + 31) / 32 * 32; }
 // whether level L's frontier buffer held the frontier of level L - 2 in this traversal
 __host__ __device__ inline bool mb_frontier_recycled(int32_t L) { return L >= kMbSnap + 2; }
+// A multi-source push over more edges than this marks its winners in the
+// next frontier's non-zero bitmap (non-returning atomics) instead of listing
+// them: every block reserving list space with one returning atomic on a single
+// counter serialises a wide push. The next level lists the bitmap only if it
+// pushes too.
+constexpr uint32_t kMbMarkEdges = 64u * kExpandChunk;
+__host__ __device__ inline bool mb_push_marks(uint32_t m) { return m > kMbMarkEdges; }
 constexpr int kMbDenseMerge = 16;  // a push's winners merge into Vis densely once they are V/16 or more
 constexpr int kMbTileWords = 8;                 // multi-source pull: bitmap words of rows per block
 constexpr int kMbTileV = kMbTileWords * 32;     // 256 rows, one per thread: a tile's rows all run at once

@@ -208,6 +208,34 @@ def test_batch_forced_schedules_deep(graphs):
         assert dirs == [int(x) for x in sc[: len(dirs)]], tag
 
 
+def test_batch_wide_pushes_deep():
+    """Consecutive layers of 200 vertices joined completely, 24 layers: every push level reads
+    more than 64 Ki edges, so its winners are marked in the non-zero bitmap rather than listed,
+    the next push lists them from that bitmap, and past the kept frontier levels the recycled
+    buffers are cleared through those lists."""
+    W, D = 200, 24
+    src, dst = [], []
+    for l in range(D - 1):
+        a = np.arange(l * W, (l + 1) * W)
+        b = np.arange((l + 1) * W, (l + 2) * W)
+        src.append(np.repeat(a, W))
+        dst.append(np.tile(b, W))
+    hg = gen.from_edges(W * D, np.concatenate(src), np.concatenate(dst), directed=False, name="layers")
+    g = upload(hg)
+    rng = np.random.default_rng(5)
+    srcs = [0, 1, W * D - 1] + [int(x) for x in rng.integers(0, W * D, 61)]
+    for mode in ["push_only", "full"]:
+        for sc in (None, [PUSH, PUSH, PULL] * 10):
+            tag = "layers %s %s" % (mode, "forced" if sc else "rule")
+            _say(tag)
+            opt = dobfs.make_options(mode, forced_dirs=sc) if sc else dobfs.make_options(mode)
+            d, st = _run(g, srcs, opt)
+            _check(hg, srcs, d, st, tag)
+            if mode == "push_only" or sc:  # the rule itself may pull the wide levels
+                lv = dobfs.stats_levels(st)
+                assert max(x["edges"] for x in lv if x["dir"] == PUSH) > 64 * 1024, tag
+
+
 def test_batch_errors(graphs):
     hg, g = graphs["rmat10"]
     depth = torch.zeros(64 * g.V, dtype=torch.int32, device="cuda")
