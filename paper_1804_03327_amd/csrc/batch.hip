@@ -515,8 +515,8 @@ __global__ __launch_bounds__(kThreads) void k_mb_main(BatchArgs a, int32_t L) {
 // kMbSnap: bit b of level L's word) into bit planes of the depth, plane i
 // being the OR of the words of the levels with bit i set (each reached pair
 // sits in exactly one level's word). It then walks the sources, writing each
-// depth row's four entries with one 16-byte store, so a wave writes 1 KB
-// runs of a row. The level table in memory is read, eight entries at a time,
+// depth row's four entries with one 16-byte non-temporal store, so a wave
+// writes 1 KB runs of a row. The level table in memory is read, eight entries at a time,
 // only where a pair was first reached at level kMbSnap or later.
 constexpr int kMbDepthVPT = 4;
 static_assert(kMbSnap <= 16, "depths of the kept levels are folded into four bit planes");
@@ -598,7 +598,11 @@ __global__ __launch_bounds__(kThreads) void k_mb_depth(BatchArgs a, int32_t leve
         }
         int32_t* out = rows.row[b] + v0;
         if (nv == 4 && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
-          *reinterpret_cast<int4*>(out) = make_int4(d[0], d[1], d[2], d[3]);
+          // non-temporal: the rows are the call's output, not read again on the device, and
+          // 256 MB of them left in the caches would evict what the next traversal works on
+          typedef int32_t v4i __attribute__((ext_vector_type(4)));
+          const v4i x = {d[0], d[1], d[2], d[3]};
+          __builtin_nontemporal_store(x, reinterpret_cast<v4i*>(out));
         } else {
 #pragma unroll
           for (int q = 0; q < 4; ++q)
