@@ -1014,7 +1014,6 @@ dobfs_status dobfs::bfs_batch_rows(dobfs_graph g, const int32_t* sources, int32_
     bool seen = false;
     for (int32_t c = 0; c < a.nuniq; ++c) seen = seen || a.uniq[c] == sources[b];
     if (!seen) a.uniq[a.nuniq++] = sources[b];
-    a.src_filter[(sources[b] >> 6) & 15] |= 1ull << (sources[b] & 63);
   }
   auto forced = [&](int64_t l) -> int32_t {
     return l < opt.n_forced ? int32_t(opt.forced_dirs[l]) : -1;

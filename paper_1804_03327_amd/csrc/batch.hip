@@ -40,20 +40,27 @@ __device__ __forceinline__ void stamp_levels(uint16_t* lvl, int32_t k, int32_t v
 }
 
 // ----------------------------------------------------------------- init
-// Visited and level-0 frontier words hold the source bits (the frontier of
-// level 0 records that every source is at depth 0), level 1's frontier
-// buffer is cleared for the first push, and the control block starts a push
+// Visited and level-0/1 frontier words start cleared (16-byte stores; the
+// level-0 prep then sets the source bits, after this kernel, so no store here
+// needs to know where the sources are), and the control block starts a push
 // level whose list is the distinct sources.
 __global__ __launch_bounds__(kThreads) void k_mb_init(BatchArgs a, int32_t dir0, int64_t nflags) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  for (int64_t v = t0; v < a.V; v += stride) {
-    uint64_t m = 0;
-    if ((a.src_filter[(v >> 6) & 15] >> (v & 63)) & 1ull)  // almost no vertex passes the filter
-      for (int b = 0; b < a.k; ++b) m |= (a.src[b] == v) ? (1ull << b) : 0ull;
-    a.vis[0][v] = m;
-    a.Fs[v] = m;              // mb_frontier(a, 0)
-    a.Fs[a.fstride + v] = 0;  // mb_frontier(a, 1)
+  const ulonglong2 z = make_ulonglong2(0ull, 0ull);
+  ulonglong2* vis2 = reinterpret_cast<ulonglong2*>(a.vis[0]);
+  ulonglong2* f0 = reinterpret_cast<ulonglong2*>(a.Fs);              // mb_frontier(a, 0)
+  ulonglong2* f1 = reinterpret_cast<ulonglong2*>(a.Fs + a.fstride);  // mb_frontier(a, 1)
+  const int64_t npair = int64_t(a.V) / 2;
+  for (int64_t i = t0; i < npair; i += stride) {
+    vis2[i] = z;
+    f0[i] = z;
+    f1[i] = z;
+  }
+  if ((a.V & 1) && t0 == 0) {
+    a.vis[0][a.V - 1] = 0ull;
+    a.Fs[a.V - 1] = 0ull;
+    a.Fs[a.fstride + a.V - 1] = 0ull;
   }
   for (int64_t k = t0; k < nflags; k += stride) {
     a.flagsA[k] = 0;
@@ -405,6 +412,13 @@ __global__ __launch_bounds__(kThreads) void k_mb_prep(BatchArgs a, int32_t L, in
   LevelState prev;
   const LevelState st = level_state(a, L, forced, &tot, &prev);
   publish_level(c, L, st, prev, tot);
+  if (L == 0 && blockIdx.x == 0 && int32_t(threadIdx.x) < a.k) {
+    // the sources: bit b of Vis and of level 0's frontier at sources[b] (depth 0)
+    const int32_t v = a.src[threadIdx.x];
+    const unsigned long long bit = 1ull << threadIdx.x;
+    atomicOr(reinterpret_cast<unsigned long long*>(a.vis[0] + v), bit);
+    atomicOr(reinterpret_cast<unsigned long long*>(a.Fs + v), bit);
+  }
   if (L >= 1 && !st.done && prev.dir == 0) {
     // a push leaves Vis as the level began: merge in what it found, through its list when it
     // made a short one, else in one dense pass (random lines of two arrays cost more than a sweep)
@@ -617,7 +631,7 @@ __global__ __launch_bounds__(kThreads) void k_mb_depth(BatchArgs a, int32_t leve
 
 hipError_t launch_mb_init(hipStream_t s, const BatchArgs& a, int32_t dir0, int64_t nflags, hipEvent_t t0,
                          hipEvent_t t1) {
-  const int64_t n = std::max<int64_t>(a.V, nflags);
+  const int64_t n = std::max<int64_t>(int64_t(a.V) / 2 + 1, nflags);
   const unsigned g = unsigned(std::min<int64_t>((n + kThreads - 1) / kThreads, 8192));
   return launch_k(k_mb_init, dim3(g > 0 ? g : 1), s, t0, t1, a, dir0, nflags);
 }

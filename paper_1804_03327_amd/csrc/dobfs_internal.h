@@ -300,7 +300,6 @@ struct BatchArgs {
   int32_t low_degree;        // unused here
   int32_t src[kMaxSources];  // source of bit b
   int32_t uniq[kMaxSources]; // the distinct sources: the first frontier list
-  uint64_t src_filter[16];   // bit (v & 1023) set when some source v' has v' & 1023 == v & 1023
 };
 // Multi-source frontier words: per vertex, the sources whose frontier holds it.
 // The frontier of level L is exactly the set of (vertex, source) pairs first
