@@ -12,10 +12,11 @@
 //
 // Levels are laid out as in the single-source path: mb_prep decides the
 // direction on the device and, for push, lists the frontier vertices with
-// their degree prefix; mb_main runs the expansion or the pull. Levels of
-// discovery are kept vertex-major ([V][k] uint16, one 128-byte line per
-// vertex at k = 64) so a vertex's new bits land in one line; mb_depth turns
-// them into the [k][V] int32 depth rows at the end.
+// their degree prefix; mb_main runs the expansion or the pull. The frontier
+// words of a level are exactly the (vertex, source) pairs first reached at
+// that level, so those of the first kMbSnap levels are kept and are the depth
+// record; deeper levels stamp a vertex-major [V][k] uint16 level table.
+// mb_depth turns both into the [k][V] int32 depth rows at the end.
 
 #include "device_common.h"
 
