@@ -10,7 +10,7 @@ average execution time, from each kernel's own start/end events in a repeat of t
 steps), the CPU oracle on a bounded sample of the same workload, the Table 2 ablation modes,
 the other direction rule, the multi-source measurement (64 sources per launch on RMAT-20
 against the same 64 queries run one at a time) and the query server (four graphs, Poisson
-arrivals at 1x and 2x the sequential capacity, p50/p99 latency against first-in first-out plain
+arrivals at 0.5x, 1x and 2x the sequential capacity, p50/p99 latency against first-in first-out plain
 DOBFS).
 
 --profile-steps / --profile-batched run only the BFS launches (for rocprofv3); --copy-mb adds
@@ -192,7 +192,7 @@ def measure_batched(args, heur, alpha, beta):
 def measure_serving(args, hg22, g22, heur, alpha, beta):
     """The query server on four device-resident graphs (RMAT-16, RMAT-20, RMAT-22, a 2048x2048
     grid): single-source queries with a uniformly drawn graph and source (degree > 0, seed 6)
-    arrive as a Poisson stream at 1x and 2x the sequential capacity. Compared with the same
+    arrive as a Poisson stream at 0.5x, 1x and 2x the sequential capacity. Compared with the same
     arrival sequence served first-in first-out by plain single-source DOBFS, one query at a
     time, using each query's own measured service time (host gaps between queries ignored,
     which favours the baseline). Latency = arrival to depth final in device memory."""
@@ -226,7 +226,7 @@ def measure_serving(args, hg22, g22, heur, alpha, beta):
     cap = 1.0 / float(svc.mean())
     del runners
     points = []
-    for mult in (1.0, 2.0):
+    for mult in (0.5, 1.0, 2.0):
         lam = mult * cap
         arrivals = np.cumsum(rng.exponential(1.0 / lam, N))
         # FIFO, one query at a time (Lindley recursion on the measured service times)

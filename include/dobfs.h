@@ -273,7 +273,8 @@ dobfs_status dobfs_bfs_batch(dobfs_graph g, const int32_t *sources, int32_t k,
  * arrive one at a time (dobfs_server_submit) and are answered by
  * multi-source traversals (dobfs_bfs_batch semantics) that take up to
  * max_batch queued queries of one graph at once, the graph whose oldest
- * query has waited longest first. `slots` batches run at the same time,
+ * query has waited longest first; a batch of one runs dobfs_bfs (depths
+ * only, its own smaller workspace). `slots` batches run at the same time,
  * each on a host thread and HIP stream of its own, so queries that arrive
  * while a batch is on the GPU are admitted into the next free slot and run
  * beside it (continuous batching, not a single queue). A batch starts only

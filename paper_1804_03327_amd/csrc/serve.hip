@@ -6,9 +6,12 @@
 // up to max_batch queued queries of that graph in arrival order, waits until
 // its workspace bytes fit in the memory budget beside the batches already
 // running, and runs them as one multi-source traversal whose depth rows are
-// written straight into the callers' buffers. Queries that arrive while a
-// batch is on the GPU go to the next free slot, so their traversal overlaps
-// the running one on the device.
+// written straight into the callers' buffers. A batch of one runs the
+// single-source traversal instead (depths only): one kernel per level and a
+// smaller workspace, where the multi-source loop takes two kernels per level,
+// which tells on deep graphs. Queries that arrive while a batch is on the GPU
+// go to the next free slot, so their traversal overlaps the running one on
+// the device.
 
 #include "dobfs.h"
 #include "dobfs_internal.h"
@@ -77,6 +80,13 @@ size_t batch_bytes(dobfs_graph g, int32_t k) {
   return b;
 }
 
+// Workspace of a batch of k queries: the single-source call's for k = 1.
+size_t run_bytes(dobfs_graph g, const dobfs_options& opt, int32_t k) {
+  size_t b = 0;
+  if (k == 1) return dobfs_bfs_workspace_bytes(g, &opt, &b) == DOBFS_OK ? b : SIZE_MAX;
+  return batch_bytes(g, k);
+}
+
 void worker(dobfs_server s, int slot) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
@@ -96,10 +106,10 @@ void worker(dobfs_server s, int slot) {
     }
     // admission by memory: the batch's workspace must fit beside the running ones
     int32_t k = int32_t(take.size());
-    while (k > 1 && batch_bytes(s->graphs[gi], k) > s->budget) --k;
+    while (k > 1 && run_bytes(s->graphs[gi], s->opt.opt, k) > s->budget) --k;
     for (size_t q = take.size(); q > size_t(k); --q) s->pending.push_front(take[q - 1]);  // back to the head, in order
     take.resize(size_t(k));
-    const size_t need = batch_bytes(s->graphs[gi], k);
+    const size_t need = run_bytes(s->graphs[gi], s->opt.opt, k);
     if (need > s->budget) {  // not even one source fits
       const double t = s->now_ms();
       for (uint64_t id : take) {
@@ -124,9 +134,12 @@ void worker(dobfs_server s, int slot) {
       q.t_start = t_start;
     }
     lk.unlock();
-    const dobfs_status st = bfs_batch_rows(s->graphs[gi], src.data(), k, &s->opt.opt, rows,
-                                           s->ws[size_t(slot)], s->ws_bytes, s->streams[size_t(slot)],
-                                           nullptr);  // returns once the depth rows are final
+    // both calls return once the depth rows are final
+    const dobfs_status st =
+        k == 1 ? dobfs_bfs(s->graphs[gi], src[0], &s->opt.opt, rows.row[0], nullptr, s->ws[size_t(slot)],
+                           s->ws_bytes, s->streams[size_t(slot)], nullptr)
+               : bfs_batch_rows(s->graphs[gi], src.data(), k, &s->opt.opt, rows, s->ws[size_t(slot)],
+                                s->ws_bytes, s->streams[size_t(slot)], nullptr);
     lk.lock();
     s->in_use -= need;
     const double t_done = s->now_ms();
@@ -208,7 +221,7 @@ dobfs_status dobfs_server_create(const dobfs_graph* graphs, int32_t n_graphs, co
     }
     s->graphs.push_back(graphs[i]);
     s->info.push_back(gi);
-    largest = std::max(largest, batch_bytes(graphs[i], o.max_batch));
+    largest = std::max(largest, std::max(run_bytes(graphs[i], o.opt, 1), run_bytes(graphs[i], o.opt, o.max_batch)));
   }
   s->ws_bytes = largest;
   s->budget = o.mem_budget ? o.mem_budget : largest * size_t(o.slots);

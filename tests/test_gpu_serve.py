@@ -92,10 +92,17 @@ def test_server_mix_equals_alone(graphs):
     assert overlap, "no two batches were in flight at once"
 
 
+def _run_bytes(g, k):
+    """Workspace a server batch of k takes: a batch of one runs the single-source call."""
+    return dobfs.bfs_workspace_bytes(g) if k == 1 else dobfs.bfs_batch_workspace_bytes(g, k)
+
+
 def test_server_memory_budget(graphs):
     hg, g = graphs[1]
     need8 = dobfs.bfs_batch_workspace_bytes(g, 8)
-    # room for one 8-source batch: batches are cut to 8 and run one at a time
+    # room for one 8-source batch: batches are cut to 8, and the batches in flight at any time
+    # never hold more workspace than the budget (a lone query's smaller one may run beside
+    # another)
     srv = dobfs.Server([g], slots=3, max_batch=64, mem_budget=need8)
     qs = []
     for n in range(120):
@@ -106,8 +113,10 @@ def test_server_memory_budget(graphs):
     srv.close()
     b = _batches(infos)
     assert max(len(v) for v in b.values()) <= 8
-    spans = sorted((k[1], k[2]) for k in b)
-    assert all(spans[i + 1][0] >= spans[i][1] for i in range(len(spans) - 1)), "batches overlapped"
+    spans = sorted((k[1], k[2], _run_bytes(g, len(v))) for k, v in b.items())
+    for t0, _, _ in spans:  # the bytes in flight at every batch start
+        held = sum(nb for s0, s1, nb in spans if s0 <= t0 < s1)
+        assert held <= need8, "batches in flight hold %d bytes, budget %d" % (held, need8)
     for s, depth, _ in qs:
         assert np.array_equal(depth.cpu().numpy(), _alone(g, s))
 
