@@ -111,6 +111,168 @@ def load_traffic(kernel: str):
     return t.get("bytes_per_launch")
 
 
+def step_roofline(V, heur, runs, cand_tables, traffic):
+    """Per-kernel table and the roofline of the dominant kernel from timed traversals.
+
+    runs: (source, stats) of traversals made with DOBFS_OPT_TIME_KERNELS; cand_tables[source]:
+    the rows each level's pull lists (from the oracle's depths). The kernels are k_bfs_init and
+    k_step (one launch per level, two for a push level that needs the global degree scan); the
+    push / pull split of the steps' time (scan steps apart) is reported beside them. Returns
+    (roofline, kernel table, per-BFS ms)."""
+    from paper_1804_03327_amd import dobfs
+    kinds = {k: {"ms": 0.0, "launches": 0, "bytes": 0.0} for k in
+             ("step", "init", "push", "push_scan", "pull")}
+
+    def add(kind, ms, nbytes, launches=1):
+        kinds[kind]["ms"] += ms
+        kinds[kind]["launches"] += launches
+        kinds[kind]["bytes"] += nbytes
+
+    bfs_ms = []
+    for s, st in runs:
+        if st.levels > st.cap:
+            raise RuntimeError("level stats truncated: %d levels > cap %d" % (st.levels, st.cap))
+        bfs_ms.append(st.ms_total)
+        add("init", st.ms_init, bytes_init(V))
+        prev = dobfs.DIR_PUSH
+        step_bytes = 0
+        for L, lv in enumerate(dobfs.stats_levels(st)):
+            if lv["dir"] == dobfs.DIR_PUSH:
+                after_pull = prev == dobfs.DIR_PULL
+                mu = bytes_mu_recount(V) if (after_pull and heur == dobfs.HEUR_EDGES) else 0
+                if lv["variant"] == 0:  # scan step, then expansion step
+                    scan = bytes_push_scan(lv["nf"]) + (bytes_d2s(V, lv["nf"]) + mu if after_pull else 0)
+                    main = bytes_push_expand(lv["nf"], lv["m_f"], lv["n_new"])
+                    add("push_scan", lv["ms_aux"], scan)
+                    step_bytes += scan
+                elif lv["variant"] == 1:  # block-local over the frontier list
+                    main = bytes_local_expand(lv["nf"], lv["m_f"], lv["n_new"])
+                else:  # block-local over the bits the pull found
+                    main = V / 8 + mu + bytes_local_expand(lv["nf"], lv["m_f"], lv["n_new"]) - 4 * lv["nf"]
+                add("push", lv["ms_main"], main)
+            else:
+                nc = cand_tables[s][L] if L < len(cand_tables[s]) else cand_tables[s][-1]
+                main = bytes_pull(V, int(nc), lv["edges"], lv["n_new"])
+                add("pull", lv["ms_main"], main)
+            step_bytes += main
+            prev = lv["dir"]
+        # every launch of the step kernel, as a profiler counts them: the levels' steps,
+        # the step that finds the end and those enqueued past it (no work, no bytes)
+        add("step", st.ms_main_all, step_bytes, st.launches_main)
+    dom = max(("step", "init"), key=lambda k: kinds[k]["ms"])
+    kd = kinds[dom]
+    avg_ms = kd["ms"] / max(1, kd["launches"])
+    per_launch = kd["bytes"] / max(1, kd["launches"])
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "kernel": "k_" + dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic if dom == "step" else None,
+                "algorithmic_bytes_per_launch": round(per_launch),
+                "avg_launch_us": round(avg_ms * 1e3, 3), "launches": kd["launches"]}
+    kernel_table = {k: {"total_ms": round(v["ms"], 3), "launches": v["launches"],
+                        "avg_us": round(1e3 * v["ms"] / max(1, v["launches"]), 3),
+                        "GBps": round(v["bytes"] / max(1e-12, v["ms"] * 1e-3) / 1e9, 1)}
+                    for k, v in kinds.items()}
+    return roofline, kernel_table, bfs_ms
+
+
+def validate_sources(hg, sources, run):
+    """Runs run(s) -> (depth, parent) host arrays for every source on the GPU, one after another,
+    and checks each against the oracle in a thread pool (the C oracle runs outside the GIL):
+    depths equal, parents valid (parent None: depths only). Returns {source: oracle depth};
+    exits on a mismatch."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+
+    def check(s, d, p):
+        want, _ = oracle.bfs(hg, s)
+        if not np.array_equal(d, want):
+            return s, None, "%d depths differ" % int((d != want).sum())
+        if p is not None:
+            code, at = oracle.validate(hg, s, d, p)
+            if code:
+                return s, None, "parent check %d failed at %d" % (code, at)
+        return s, want, ""
+
+    workers = max(1, min(16, os.cpu_count() or 1))
+    out = {}
+    with ThreadPoolExecutor(workers) as ex:
+        futs = []
+        for s in sources:
+            d, p = run(s)
+            futs.append(ex.submit(check, s, d, p))
+        for f in futs:
+            s, want, err = f.result()
+            if err:
+                raise SystemExit("bench: GPU result differs from the oracle on source %d: %s" % (s, err))
+            out[s] = want
+    return out
+
+
+def measure_lattice(args, heur, alpha, beta):
+    """The high-diameter configuration: a 256^3 7-point lattice with 5% of its undirected edges
+    deleted (seed 3), 16 sources (seed 4, degree > 0), in the benchmarked mode and rule. Every
+    source is checked against the oracle; ms per BFS, GTEPS in both edge counts, the roofline of
+    the dominant kernel and the single-core oracle on two of the sources."""
+    import torch
+    import gen
+    import oracle
+    from paper_1804_03327_amd import dobfs
+    from paper_1804_03327_amd.helpers import BfsRunner, upload
+
+    hl = gen.lattice3d(args.lattice_n, 0.05, seed=3)
+    srcs = [int(x) for x in gen.sample_sources(hl, 16, seed=4)]
+    gl = upload(hl, device=0, hubs_first=not args.stored_order)
+    r = BfsRunner(gl, with_parent=True)
+    stream = torch.cuda.current_stream()
+    opt = dobfs.make_options("full", heur, alpha, beta)
+    opt_t = dobfs.make_options("full", heur, alpha, beta, time_kernels=True)
+
+    def run_one(s):
+        r.run(s, opt=opt, stream=stream)
+        return r.result()
+
+    want = validate_sources(hl, srcs, run_one)
+    edges = {s: oracle.teps_edges(hl, want[s])["graph500"] for s in srcs}
+    cand = {s: candidates_per_level(want[s], hl.in_degree() > 0) for s in srcs}
+    reps = 3
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        for s in srcs:
+            dobfs.bfs(gl, s, r.depth, r.parent, opt, r.ws, stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    n = reps * len(srcs)
+    stats = [dobfs.make_stats(4096) for _ in srcs]
+    for s, st in zip(srcs, stats):
+        dobfs.bfs(gl, s, r.depth, r.parent, opt_t, r.ws, stream=stream, stats=st)
+    torch.cuda.synchronize()
+    roof, table, _ = step_roofline(hl.V, heur, list(zip(srcs, stats)), cand, None)
+    levels = [st.levels for st in stats]
+    cpu_src = srcs[:2]
+    tc = 0.0
+    for s in cpu_src:
+        t2 = time.perf_counter()
+        oracle.bfs(hl, s)
+        tc += time.perf_counter() - t2
+    res = {"workload": "lattice%d^3, 5%% of undirected edges deleted (seed 3), 16 sources (seed 4)" % args.lattice_n,
+           "vertices": hl.V, "directed_edges": hl.nnz,
+           "gteps": round(sum(edges.values()) * reps / dt / 1e9, 3),
+           "gteps_paper_convention": round(hl.nnz * n / dt / 1e9, 3),
+           "ms_per_bfs": round(1e3 * dt / n, 4),
+           "levels_mean": round(float(np.mean(levels)), 1),
+           "us_per_level": round(1e3 * dt / reps / max(1, sum(levels)), 3),
+           "validated_sources": len(want),
+           "roofline": roof, "kernels": table,
+           "cpu_baseline": {"value": round(sum(edges[s] for s in cpu_src) / tc / 1e9, 5), "unit": "GTEPS",
+                            "cores": 1, "kind": "oracle",
+                            "sample": "FIFO-queue BFS from 2 of the 16 sources (%.1f s)" % tc}}
+    log("lattice:", json.dumps({k: v for k, v in res.items() if k != "kernels"}))
+    dobfs.graph_destroy(gl)
+    return res
+
+
 def measure_batched(args, heur, alpha, beta):
     """Multi-source BFS: 64 sources per launch on RMAT-20 (edge factor 16), against the same 64
     queries run one after another through the single-source call on the same GPU. A query's
@@ -141,9 +303,8 @@ def measure_batched(args, heur, alpha, beta):
     t_all = time.perf_counter() - t_all
     qps = 64 * args.batched_launches / t_all
     d = depth.cpu().numpy().reshape(64, gb.V)
-    rows_ok = all(np.array_equal(d[b], oracle.bfs(hb, srcs[b])[0]) for b in (0, 63))
-    if not rows_ok:
-        raise SystemExit("bench: multi-source depth rows differ from the oracle")
+    rows = iter(d)
+    validate_sources(hb, srcs, lambda s: (next(rows), None))  # every row, depths only
     # the same queries one at a time through the single-source path: depths only (the output
     # the batched call gives), and with parents as well for reference
     qps_seq = {}
@@ -182,7 +343,7 @@ def measure_batched(args, heur, alpha, beta):
            "sequential_with_parents_queries_per_s": round(qps_seq[True], 1),
            "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
            "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 3),
-           "launches": args.batched_launches, "rows_checked_against_oracle": [0, 63],
+           "launches": args.batched_launches, "rows_checked_against_oracle": 64,
            "autotuned_direction_rule": tuned}
     log("batched:", json.dumps(res))
     del ws, depth
@@ -306,6 +467,9 @@ def main():
                     help="skip the query-server measurement (4 graphs, Poisson arrivals)")
     ap.add_argument("--serve-queries", type=int, default=600)
     ap.add_argument("--serve-slots", type=int, default=2)
+    ap.add_argument("--no-lattice", action="store_true",
+                    help="skip the 256^3 lattice (5%% of edges deleted, 16 sources) measurement")
+    ap.add_argument("--lattice-n", type=int, default=256)
     ap.add_argument("--batched-scale", type=int, default=20)
     ap.add_argument("--batched-launches", type=int, default=20)
     ap.add_argument("--no-validate", action="store_true")
@@ -388,15 +552,33 @@ def main():
             log("profile step %d done" % k)
         return
 
-    # warm-up, and per-source edge counts / candidate tables from the GPU's own depths
-    edges_g500, cand_tables = {}, {}
+    # warm-up; the first pass checks every source's result against the oracle (depths exact,
+    # parents valid) and takes the per-source edge counts and pull candidate tables from the
+    # oracle's depths
+    import oracle
+    edges_g500, cand_tables, validated = {}, {}, None
     for w in range(max(1, args.warmup)):
+        if w == 0 and not args.no_validate:
+            def run_one(s):
+                runner.run(s, opt=opt_plain, stream=stream)
+                return runner.result()
+
+            res = validate_sources(hg, sources, run_one)
+            for s, want in res.items():
+                edges_g500[s] = oracle.teps_edges(hg, want)["graph500"]
+                cand_tables[s] = candidates_per_level(want, indeg_nz)
+            validated = {"sources": len(res), "depth_exact_and_parents_valid": True,
+                         "edge_counts": "oracle (Graph500 count)"}
+            log("validated %d sources against the oracle" % len(res))
+            continue
         for s in sources:
             runner.run(s, opt=opt_plain, stream=stream)
-            if w == 0:
-                d = runner.depth.cpu().numpy()
-                edges_g500[s] = int(outdeg[d >= 0].sum()) // 2
-                cand_tables[s] = candidates_per_level(d, indeg_nz)
+    if not edges_g500:  # --no-validate: counts from the GPU's depths (reported as such)
+        for s in sources:
+            runner.run(s, opt=opt_plain, stream=stream)
+            d = runner.depth.cpu().numpy()
+            edges_g500[s] = int(outdeg[d >= 0].sum()) // 2
+            cand_tables[s] = candidates_per_level(d, indeg_nz)
     torch.cuda.synchronize()
     log("warm-up done")
 
@@ -430,82 +612,19 @@ def main():
     torch.cuda.synchronize()
     t_ev = time.perf_counter() - t_ev
 
-    # GPU kernels: k_bfs_init and k_step (one launch per level, two for a push level that
-    # needs the global degree scan); the push / pull split of the steps' time (scan steps
-    # apart) is reported beside them
-    kinds = {k: {"ms": 0.0, "launches": 0, "bytes": 0.0} for k in
-             ("step", "init", "push", "push_scan", "pull")}
-
-    def add(kind, ms, nbytes, launches=1):
-        kinds[kind]["ms"] += ms
-        kinds[kind]["launches"] += launches
-        kinds[kind]["bytes"] += nbytes
-
-    bfs_ms = []
-    for k in range(args.steps):
-        for i, s in enumerate(sources):
-            st = pool[k][i]
-            if st.levels > st.cap:
-                raise RuntimeError("level stats truncated: %d levels > cap %d" % (st.levels, st.cap))
-            bfs_ms.append(st.ms_total)
-            add("init", st.ms_init, bytes_init(hg.V))
-            prev = dobfs.DIR_PUSH
-            step_bytes = 0
-            for L, lv in enumerate(dobfs.stats_levels(st)):
-                if lv["dir"] == dobfs.DIR_PUSH:
-                    after_pull = prev == dobfs.DIR_PULL
-                    mu = bytes_mu_recount(hg.V) if (after_pull and heur == dobfs.HEUR_EDGES) else 0
-                    if lv["variant"] == 0:  # scan step, then expansion step
-                        scan = bytes_push_scan(lv["nf"]) + (bytes_d2s(hg.V, lv["nf"]) + mu if after_pull else 0)
-                        main = bytes_push_expand(lv["nf"], lv["m_f"], lv["n_new"])
-                        add("push_scan", lv["ms_aux"], scan)
-                        step_bytes += scan
-                    elif lv["variant"] == 1:  # block-local over the frontier list
-                        main = bytes_local_expand(lv["nf"], lv["m_f"], lv["n_new"])
-                    else:  # block-local over the bits the pull found
-                        main = hg.V / 8 + mu + bytes_local_expand(lv["nf"], lv["m_f"], lv["n_new"]) - 4 * lv["nf"]
-                    add("push", lv["ms_main"], main)
-                else:
-                    nc = cand_tables[s][L] if L < len(cand_tables[s]) else cand_tables[s][-1]
-                    main = bytes_pull(hg.V, int(nc), lv["edges"], lv["n_new"])
-                    add("pull", lv["ms_main"], main)
-                step_bytes += main
-                prev = lv["dir"]
-            # every launch of the step kernel, as a profiler counts them: the levels' steps,
-            # the step that finds the end and those enqueued past it (no work, no bytes)
-            add("step", st.ms_main_all, step_bytes, st.launches_main)
-    dom = max(("step", "init"), key=lambda k: kinds[k]["ms"])
-    kd = kinds[dom]
-    avg_ms = kd["ms"] / max(1, kd["launches"])
-    per_launch = kd["bytes"] / max(1, kd["launches"])
-    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    traffic = load_traffic(dom)
-    roofline = {"bound": "hbm", "kernel": "k_" + dom, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "algorithmic_bytes_per_launch": round(per_launch),
-                "avg_launch_us": round(avg_ms * 1e3, 3), "launches": kd["launches"],
-                "timing": "each kernel's own start/end events (hipExtLaunchKernel) on the BFS stream, "
-                          "over a repeat of the timed steps (%.1f ms/step with events)" % (
-                              1e3 * t_ev / args.steps)}
-    kernel_table = {k: {"total_ms": round(v["ms"], 3), "launches": v["launches"],
-                        "avg_us": round(1e3 * v["ms"] / max(1, v["launches"]), 3),
-                        "GBps": round(v["bytes"] / max(1e-12, v["ms"] * 1e-3) / 1e9, 1)}
-                    for k, v in kinds.items()}
+    runs = [(s, pool[k][i]) for k in range(args.steps) for i, s in enumerate(sources)]
+    roofline, kernel_table, bfs_ms = step_roofline(hg.V, heur, runs, cand_tables,
+                                                   load_traffic("step"))
+    roofline["timing"] = ("each kernel's own start/end events (hipExtLaunchKernel) on the BFS stream, "
+                          "over a repeat of the timed steps (%.1f ms/step with events)" % (1e3 * t_ev / args.steps))
     log("kernels:", json.dumps(kernel_table))
 
-    # parity spot-check of the benchmarked configuration against the oracle
-    import oracle
-    validated = None
-    if not args.no_validate:
-        s = sources[0]
-        runner.run(s, opt=opt_plain, stream=stream)
-        d, p = runner.result()
-        want, _ = oracle.bfs(hg, s)
-        ok = bool(np.array_equal(d, want)) and oracle.validate(hg, s, d, p)[0] == 0
-        validated = {"source": s, "depth_exact_and_parents_valid": ok}
-        if not ok:
-            raise SystemExit("bench: GPU result differs from the oracle on source %d" % s)
-        log("validated source %d against the oracle" % s)
+    # the library's own Graph500 edge counts (stats) against the oracle's
+    if validated is not None:
+        bad = [s for i, s in enumerate(sources) if pool[0][i].edges_g500 != edges_g500[s]]
+        if bad:
+            raise SystemExit("bench: library edge count differs from the oracle's on sources %s" % bad[:4])
+        validated["library_edge_counts_match"] = True
 
     # CPU baseline: the oracle as it stands, single thread, on a bounded sample of sources
     cpu = None
@@ -604,6 +723,10 @@ def main():
                      "tuning_ms_per_bfs": round(res["ms"], 4)}
         log("autotuned:", json.dumps(autotuned))
 
+    lattice = None
+    if not args.no_lattice:
+        lattice = measure_lattice(args, heur, alpha, beta)
+
     batched = None
     if not args.no_batched:
         batched = measure_batched(args, heur, alpha, beta)
@@ -633,6 +756,7 @@ def main():
         "other_direction_rule": other,
         "autotuned_direction_rule": autotuned,
         "validated": validated,
+        "lattice": lattice,
         "batched": batched,
         "serving": serving,
     }

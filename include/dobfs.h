@@ -200,6 +200,12 @@ typedef struct {
   int32_t launches_aux;
   float ms_main_all;
   float ms_aux_all;
+  /* Single source: the traversed edges in the Graph500 count, i.e. the sum of out-degrees
+     over the reached vertices, halved when the graph was given as undirected (the same
+     arrays passed for CSR(A) and CSC(A)): every undirected edge with a reached endpoint
+     counted once. Counted on the device after the traversal (outside ms_total).
+     Multi-source: 0. */
+  int64_t edges_g500;
 } dobfs_stats;
 
 /* ----------------------------------------------------------------- BFS */
@@ -226,6 +232,12 @@ dobfs_status dobfs_bfs_workspace_bytes(dobfs_graph g, const dobfs_options *opt, 
  * direction is decided on the device, and the host reads the traversal state
  * back once per batch of levels. source outside [0,V) -> INVALID_ARG with
  * nothing written.
+ * Workspace reuse: when the call returns, depth and parent are final, but
+ * blocks of its last kernel may still be reading the workspace's control
+ * block. A caller's workspace may be passed to a later call on the same
+ * stream, or on another stream once the first stream has been synchronised
+ * (or an event recorded on it waited for); the library-owned workspace is
+ * ordered this way by the library.
  */
 dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options *opt, int32_t *depth,
                        int32_t *parent, void *workspace, size_t ws_bytes, void *stream,
@@ -358,6 +370,10 @@ dobfs_status dobfs_mxv_workspace_bytes(dobfs_graph g, size_t *bytes);
  * j->i (pull: the first in CSC order); other entries are left unchanged.
  * y_nnz (host, optional): popcount of y; when y_nnz or y_idx is given the
  * call blocks until done, otherwise it only enqueues work on `stream`.
+ * Aliasing: x_bits and mask_bits may be the same buffer as y_bits (the
+ * in-place BFS form v = v OR A^T v .* not(v) of Section 5.4 with ACCUM_OR):
+ * the result is then computed from x and mask as they were before the call.
+ * y_idx, y_witness and x_idx must not overlap each other or the bit vectors.
  */
 dobfs_status dobfs_mxv(dobfs_graph g, const uint32_t *x_bits, const int32_t *x_idx,
                        int32_t x_nnz, const uint32_t *mask_bits, int32_t complement,

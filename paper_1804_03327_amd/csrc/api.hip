@@ -35,6 +35,7 @@ struct dobfs_graph_s {
   int4* slab = nullptr;             // first kSlab entries of every CSC(A) column (-1 past its end)
   int32_t* head = nullptr;          // first entry of every CSC(A) column, complemented when more follow
   uint32_t max_outdeg = 0;          // largest CSR(A) row length
+  bool symmetric = false;           // given as undirected: the same arrays for CSR(A) and CSC(A)
   std::atomic<int32_t> last_levels{8};  // level count of the previous BFS (first batch size)
   std::atomic<int32_t> last_steps{8};   // step count of the previous single-source BFS
   std::atomic<int32_t> last_levels_mb{8};  // the same for multi-source traversals
@@ -42,6 +43,8 @@ struct dobfs_graph_s {
   std::mutex mu;                    // guards the internal workspace
   void* ws = nullptr;
   size_t ws_size = 0;
+  hipEvent_t ws_event = nullptr;    // recorded on the stream of the last call that used ws
+  bool ws_event_recorded = false;
 };
 
 namespace {
@@ -363,13 +366,33 @@ void free_graph(dobfs_graph g) {
   if (g->slab) (void)hipFree(g->slab);
   if (g->head) (void)hipFree(g->head);
   if (g->ws) (void)hipFree(g->ws);
+  if (g->ws_event) (void)hipEventDestroy(g->ws_event);
   delete g;
 }
 
+// The graph's own workspace, held by one call: its lock, and on release an
+// event on the call's stream. When a call returns, blocks of its last kernel
+// may still be reading the control block (a step past the end has nothing
+// to write, so the report does not wait for it); the next call that takes
+// the workspace on another stream waits for that event before its first
+// kernel, so nothing it writes can reach those blocks.
+struct WsLease {
+  std::unique_lock<std::mutex> lock;
+  dobfs_graph g = nullptr;
+  hipStream_t s = nullptr;
+  WsLease() = default;
+  WsLease(const WsLease&) = delete;
+  WsLease& operator=(const WsLease&) = delete;
+  ~WsLease() {
+    if (g) (void)hipEventRecord(g->ws_event, s);
+  }
+};
+
 // Workspace for a call: the caller's, or the graph's own (grown on demand;
-// the lock is held for the duration of the call).
-dobfs_status get_workspace(dobfs_graph g, void* workspace, size_t ws_bytes, size_t need,
-                           std::unique_lock<std::mutex>& lock, uint8_t** base) {
+// the lease holds its lock for the duration of the call and orders it after
+// the previous call on the graph's workspace).
+dobfs_status get_workspace(dobfs_graph g, void* workspace, size_t ws_bytes, size_t need, hipStream_t s,
+                           WsLease& lease, uint8_t** base) {
   if (workspace) {
     if (ws_bytes < need)
       return fail(DOBFS_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes,
@@ -379,7 +402,12 @@ dobfs_status get_workspace(dobfs_graph g, void* workspace, size_t ws_bytes, size
     *base = static_cast<uint8_t*>(workspace);
     return DOBFS_OK;
   }
-  lock = std::unique_lock<std::mutex>(g->mu);
+  lease.lock = std::unique_lock<std::mutex>(g->mu);
+  if (!g->ws_event) HIPCK(hipEventCreateWithFlags(&g->ws_event, hipEventDisableTiming));
+  if (g->ws_event_recorded) HIPCK(hipStreamWaitEvent(s, g->ws_event, 0));
+  g->ws_event_recorded = true;
+  lease.g = g;
+  lease.s = s;
   if (g->ws_size < need) {
     if (g->ws) {
       HIPCK(hipDeviceSynchronize());
@@ -608,6 +636,20 @@ dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool tim
   return DOBFS_OK;
 }
 
+// stats->edges_g500 after a single-source traversal into depth: the out-degree sum of the
+// reached vertices, counted on the device, halved for a graph given as undirected.
+dobfs_status reached_edges(dobfs_graph g, hipStream_t s, Ctrl* ctrl, const int32_t* depth,
+                           dobfs_stats* stats) {
+  Ctrl* host = host_ctrl();
+  if (!host) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
+  HIPCK(launch_reached_degree(s, g->rowptr, depth, g->V, &ctrl->tail));
+  HIPCK(hipMemcpyAsync(&host->tail, &ctrl->tail, sizeof(LevelSlot), hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  const int64_t sum = int64_t(sum_slot(host->tail).edges);
+  stats->edges_g500 = g->symmetric ? sum / 2 : sum;
+  return DOBFS_OK;
+}
+
 // The sort-based push of Table 2's first row: push at every level with the
 // pairs gathered, radix-sorted by key and reduced to their first element
 // per key (Algorithm 3 as printed). The first kernel of each level (state +
@@ -617,13 +659,13 @@ dobfs_status bfs_sort_push(dobfs_graph g, int32_t source, const dobfs_options& o
                            int32_t* parent, void* workspace, size_t ws_bytes, void* stream,
                            dobfs_stats* stats) {
   const SortLayout SL = plan_sort(g->V, g->nnz);
-  std::unique_lock<std::mutex> lock;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  WsLease lease;
   uint8_t* ws = nullptr;
-  dobfs_status st = get_workspace(g, workspace, ws_bytes, SL.total, lock, &ws);
+  dobfs_status st = get_workspace(g, workspace, ws_bytes, SL.total, s, lease, &ws);
   if (st != DOBFS_OK) return st;
   hipEvent_t* ev = events_for(g->device);
   if (!ev) return fail(DOBFS_ERR_DEVICE, "event creation failed");
-  hipStream_t s = static_cast<hipStream_t>(stream);
   dobfs_options opt = opt_in;
   opt.mode = DOBFS_MODE_PUSH_ONLY;  // the level state machine: push at every level
   BfsArgs a = bfs_args(g, ws, SL.base, opt, depth, parent);
@@ -695,6 +737,7 @@ dobfs_status bfs_sort_push(dobfs_graph g, int32_t source, const dobfs_options& o
     stats->reached = reached;
     stats->launches_main = stats->launches_aux = 0;
     stats->ms_main_all = stats->ms_aux_all = 0.f;
+    return reached_edges(g, s, c, depth, stats);
   }
   return DOBFS_OK;
 }
@@ -764,6 +807,7 @@ dobfs_status dobfs_graph_upload(int32_t V, int64_t nnz, const int32_t* csr_rowpt
   g->nnz = nnz;
   g->nwords = words_of(V);
   const bool shared = (csr_rowptr == csc_colptr) && (csr_colind == csc_rowind);
+  g->symmetric = shared;
   auto upload = [&](const int32_t* src, size_t n, int slot) -> const int32_t* {
     void* p = nullptr;
     if (hipMalloc(&p, std::max<size_t>(n, 1) * 4) != hipSuccess) return nullptr;
@@ -830,6 +874,7 @@ dobfs_status dobfs_graph_wrap_device(int32_t V, int64_t nnz, const int32_t* csr_
   g->colind = csr_colind;
   g->colptr = csc_colptr;
   g->rowind = csc_rowind;
+  g->symmetric = (csr_rowptr == csc_colptr) && (csr_colind == csc_rowind);
   if ((st = finish_graph(g, s, flags)) != DOBFS_OK) {
     free_graph(g);
     return st;
@@ -885,13 +930,13 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   if (opt.mode == DOBFS_MODE_PUSH_SORT)
     return bfs_sort_push(g, source, opt, depth, parent, workspace, ws_bytes, stream, stats);
   const Layout L = plan(g->V, g->nnz);
-  std::unique_lock<std::mutex> lock;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  WsLease lease;
   uint8_t* ws = nullptr;
-  if ((st = get_workspace(g, workspace, ws_bytes, L.total, lock, &ws)) != DOBFS_OK) return st;
+  if ((st = get_workspace(g, workspace, ws_bytes, L.total, s, lease, &ws)) != DOBFS_OK) return st;
   const bool timing = (opt.flags & DOBFS_OPT_TIME_KERNELS) != 0;
   hipEvent_t* ev = events_for(g->device);
   if (!ev) return fail(DOBFS_ERR_DEVICE, "event creation failed");
-  hipStream_t s = static_cast<hipStream_t>(stream);
 
   BfsArgs a = bfs_args(g, ws, L, opt, depth, parent);
   const int32_t dir0 = opt.n_forced > 0 ? int32_t(opt.forced_dirs[0])
@@ -921,6 +966,7 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
     stats->launches_aux = res.n_aux;
     stats->ms_main_all = res.ms_main_all;
     stats->ms_aux_all = res.ms_aux_all;
+    return reached_edges(g, s, a.ctrl, depth, stats);
   }
   return DOBFS_OK;
 }
@@ -968,13 +1014,13 @@ dobfs_status dobfs::bfs_batch_rows(dobfs_graph g, const int32_t* sources, int32_
   DeviceScope ds(g->device);
   if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice", __LINE__);
   const BatchLayout L = plan_batch(g->V, g->nnz, k);
-  std::unique_lock<std::mutex> lock;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  WsLease lease;
   uint8_t* ws = nullptr;
-  if ((st = get_workspace(g, workspace, ws_bytes, L.total, lock, &ws)) != DOBFS_OK) return st;
+  if ((st = get_workspace(g, workspace, ws_bytes, L.total, s, lease, &ws)) != DOBFS_OK) return st;
   const bool timing = (opt.flags & DOBFS_OPT_TIME_KERNELS) != 0;
   hipEvent_t* ev = events_for(g->device);
   if (!ev) return fail(DOBFS_ERR_DEVICE, "event creation failed");
-  hipStream_t s = static_cast<hipStream_t>(stream);
 
   BatchArgs a{};
   a.V = g->V;
@@ -1049,6 +1095,7 @@ dobfs_status dobfs::bfs_batch_rows(dobfs_graph g, const int32_t* sources, int32_
     stats->launches_aux = res.n_aux;
     stats->ms_main_all = res.ms_main_all;
     stats->ms_aux_all = res.ms_aux_all;
+    stats->edges_g500 = 0;
   }
   return DOBFS_OK;
 }
@@ -1082,11 +1129,11 @@ dobfs_status dobfs_mxv(dobfs_graph g, const uint32_t* x_bits, const int32_t* x_i
   DeviceScope ds(g->device);
   if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice", __LINE__);
   const Layout L = plan(g->V, g->nnz);
-  std::unique_lock<std::mutex> lock;
-  uint8_t* ws = nullptr;
-  dobfs_status st = get_workspace(g, workspace, ws_bytes, L.total, lock, &ws);
-  if (st != DOBFS_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  WsLease lease;
+  uint8_t* ws = nullptr;
+  dobfs_status st = get_workspace(g, workspace, ws_bytes, L.total, s, lease, &ws);
+  if (st != DOBFS_OK) return st;
   const int32_t V = g->V, nwords = g->nwords;
   uint32_t* rbits = reinterpret_cast<uint32_t*>(ws + L.visA);
   uint32_t* xbits = reinterpret_cast<uint32_t*>(ws + L.FA);
@@ -1107,6 +1154,12 @@ dobfs_status dobfs_mxv(dobfs_graph g, const uint32_t* x_bits, const int32_t* x_i
     if (!x) {
       HIPCK(launch_fill(s, xbits, nwords, 0u));
       if (x_nnz > 0) HIPCK(launch_s2d(s, x_idx, x_nnz, V, xbits));
+      x = xbits;
+    } else if (x_bits < y_bits + nwords && y_bits < x_bits + nwords) {
+      // x overlaps y (the in-place form y = y OR A^T y .* not y): every tile writes its own
+      // words of y whole while other tiles still read x at in-neighbour positions, so the
+      // pull reads a copy of x made before it starts
+      HIPCK(hipMemcpyAsync(xbits, x_bits, size_t(nwords) * 4, hipMemcpyDeviceToDevice, s));
       x = xbits;
     }
     PullArgs pa{};

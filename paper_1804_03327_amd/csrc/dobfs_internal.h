@@ -77,6 +77,7 @@ struct Ctrl {
   LevelState ring[kRing];
   LevelRecord rec[kRing];
   int8_t forced[kRing];          // single source: forced direction of levels 0 .. n_forced-1
+  LevelSlot tail;                // after a traversal: out-degree sum of the reached vertices (edges)
 };
 static_assert(sizeof(Stripe) == 128, "stripe layout");
 static_assert(offsetof(Ctrl, slot) % 128 == 0, "slots start on a line");
@@ -369,6 +370,9 @@ hipError_t launch_nz_bits(hipStream_t s, const int32_t* ptr, int32_t V, uint32_t
 hipError_t launch_slab(hipStream_t s, const int32_t* ptr, const int32_t* ind, int32_t V, int4* slab,
                        int32_t* head);
 hipError_t launch_max_degree(hipStream_t s, const int32_t* ptr, int32_t V, uint32_t* out);
+// slot->s[*].edges += out-degrees (CSR offsets ptr) of the vertices with depth >= 0; slot zeroed first
+hipError_t launch_reached_degree(hipStream_t s, const int32_t* ptr, const int32_t* depth, int32_t V,
+                                 LevelSlot* slot);
 // What the host needs after a batch of levels: the state after the batch and
 // the records of its levels. Written into pinned host memory by one block,
 // `seq` last (system-scope release), so the host can spin on it.

@@ -1123,6 +1123,23 @@ __global__ __launch_bounds__(kThreads) void k_max_degree(const int32_t* ptr, int
   if (threadIdx.x == 0 && m) atomicMax(out, m);
 }
 
+// Out-degree sum over the reached vertices (the Graph500 edge count before
+// halving): a grid stride over depth, one stripe atomic per block.
+__global__ __launch_bounds__(kThreads) void k_reached_degree(const int32_t* ptr, const int32_t* depth,
+                                                             int32_t V, LevelSlot* slot) {
+  unsigned long long sum = 0;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < V; i += stride)
+    if (depth[i] >= 0) sum += uint64_t(ptr[i + 1] - ptr[i]);
+  unsigned long long v[4] = {sum, 0, 0, 0};
+  block_sum4(v);
+  if (threadIdx.x == 0 && v[0]) atomicAdd(&slot->s[blockIdx.x % kStripes].edges, v[0]);
+}
+
+__global__ void k_zero_slot(LevelSlot* slot) {
+  for (int k = threadIdx.x; k < kStripes; k += blockDim.x) zero_stripe(slot->s[k]);
+}
+
 // Copies the state after a batch and the batch's level records into pinned
 // host memory, then publishes `seq` with a system-scope release.
 __global__ void k_report(const Ctrl* c, int32_t l_first, int32_t n, HostReport* host, uint32_t seq) {
@@ -1247,6 +1264,14 @@ hipError_t launch_slab(hipStream_t s, const int32_t* ptr, const int32_t* ind, in
 
 hipError_t launch_max_degree(hipStream_t s, const int32_t* ptr, int32_t V, uint32_t* out) {
   hipLaunchKernelGGL(k_max_degree, dim3(grid_for(V, kThreads, 1024)), dim3(kThreads), 0, s, ptr, V, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reached_degree(hipStream_t s, const int32_t* ptr, const int32_t* depth, int32_t V,
+                                 LevelSlot* slot) {
+  hipLaunchKernelGGL(k_zero_slot, dim3(1), dim3(64), 0, s, slot);
+  hipLaunchKernelGGL(k_reached_degree, dim3(grid_for(V, kThreads * 8, 512)), dim3(kThreads), 0, s, ptr,
+                     depth, V, slot);
   return hipGetLastError();
 }
 

@@ -48,7 +48,8 @@ class Stats(ctypes.Structure):
                 ("level", ctypes.POINTER(LevelStats)), ("ms_total", ctypes.c_float),
                 ("ms_init", ctypes.c_float), ("reached", ctypes.c_int64),
                 ("launches_main", ctypes.c_int32), ("launches_aux", ctypes.c_int32),
-                ("ms_main_all", ctypes.c_float), ("ms_aux_all", ctypes.c_float)]
+                ("ms_main_all", ctypes.c_float), ("ms_aux_all", ctypes.c_float),
+                ("edges_g500", ctypes.c_int64)]
 
 
 class ServerOptions(ctypes.Structure):

@@ -1,11 +1,14 @@
 """GPU parity at the full sizes of the benchmarked and configured workloads, in the launch
-configuration the benchmark times (in-neighbours uploaded hubs-first, mode full, edge-count
-rule with alpha = 1/14, beta = 1/24, library-owned workspace, current stream).
+configuration the benchmark times (in-neighbours uploaded hubs-first, edge-count rule with
+alpha = 1/14, beta = 1/24, caller-owned workspace, current stream).
 
 Every depth vector is compared with the oracle's over all vertices and every parent vector
-passes the validator; under the edge-count rule the direction sequence is the oracle's; the
-multi-source launch is checked on sampled rows."""
+passes the validator; under the edge-count rule the direction sequence is the oracle's. The
+benchmark's 64 RMAT-22 sources are all checked in the benchmarked mode, every Table 2 mode the
+benchmark times is checked on two of them, four of the lattice's 16 sources run in three
+modes, and every row of the 64-source RMAT-20 launch is checked."""
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -29,57 +32,120 @@ def _say(*a):
 
 
 BENCH_OPT = dict(mode="full", heuristic=dobfs.HEUR_EDGES, alpha=1 / 14, beta=1 / 24)
+# the Table 2 rows the benchmark times, each with the benchmark's direction rule
+ABLATION_MODES = ("push_sort", "push_only", "pull_unmasked", "pull_masked", "pull_masked_ee", "full")
 
 
-def _single(hg, sources, opts, hubs_first=False):
-    g = upload(hg, hubs_first=hubs_first)
+def _oracle_many(hg, sources):
+    """Oracle depths of many sources at once (the C oracle runs outside the GIL)."""
+    with ThreadPoolExecutor(8) as ex:
+        return dict(zip(sources, ex.map(lambda s: oracle.bfs(hg, s)[0], sources)))
+
+
+def _check(hg, s, want, d, p, tag, opt=None, levels=None):
+    bad = int((d != want).sum())
+    assert bad == 0, "%s: %d depths differ" % (tag, bad)
+    code, at = oracle.validate(hg, s, d, p)
+    assert code == 0, "%s: parent check %d failed at %d" % (tag, code, at)
+    if opt is not None and opt.get("heuristic") == dobfs.HEUR_EDGES and levels is not None:
+        dirs = [x["dir"] for x in levels]
+        assert dirs == oracle.schedule_edges(hg, want, opt["alpha"], opt["beta"]), tag
+
+
+@pytest.fixture(scope="module")
+def rmat22():
+    hg = gen.rmat(22, 16, seed=1)
+    srcs = [int(x) for x in gen.sample_sources(hg, 64, seed=2)]
+    _say("rmat22 generated: V=%d nnz=%d" % (hg.V, hg.nnz))
+    return hg, srcs
+
+
+def test_rmat22_all_bench_sources(rmat22):
+    """The 64 benchmark sources in the benchmarked configuration, and the library's Graph500
+    edge count of each against the oracle's."""
+    hg, srcs = rmat22
+    g = upload(hg, hubs_first=True)
     r = BfsRunner(g)
-    for s in sources:
-        want, _ = oracle.bfs(hg, s)
-        for o in opts:
-            tag = "%s source %d %s" % (hg.name, s, o)
+    want = _oracle_many(hg, srcs)
+    for k, s in enumerate(srcs):
+        st = r.run(s, **BENCH_OPT)
+        d, p = r.result()
+        tag = "rmat22 bench source #%d (%d)" % (k, s)
+        if k % 8 == 0:
             _say(tag)
-            r.run(s, **o)
-            d, p = r.result()
-            bad = int((d != want).sum())
-            assert bad == 0, "%s: %d depths differ" % (tag, bad)
-            code, at = oracle.validate(hg, s, d, p)
-            assert code == 0, "%s: parent check %d failed at %d" % (tag, code, at)
-            if o.get("heuristic") == dobfs.HEUR_EDGES:
-                dirs = [x["dir"] for x in r.levels()]
-                assert dirs == oracle.schedule_edges(hg, want, o["alpha"], o["beta"]), tag
+        _check(hg, s, want[s], d, p, tag, BENCH_OPT, r.levels())
+        assert st.edges_g500 == oracle.teps_edges(hg, want[s])["graph500"], tag
     dobfs.graph_destroy(g)
 
 
-def test_rmat22_single_source():
-    hg = gen.rmat(22, 16, seed=1)
-    srcs = [int(x) for x in gen.sample_sources(hg, 64, seed=2)]
-    _single(hg, [srcs[0], srcs[63]], [BENCH_OPT, dict(mode="full")], hubs_first=True)
-    _single(hg, [srcs[1]], [BENCH_OPT])
+def test_rmat22_ablation_modes(rmat22):
+    """Every Table 2 mode the benchmark times, on two of its sources, with its upload and rule."""
+    hg, srcs = rmat22
+    g = upload(hg, hubs_first=True)
+    r = BfsRunner(g)
+    pick = [srcs[0], srcs[37]]
+    want = _oracle_many(hg, pick)
+    for s in pick:
+        for mode in ABLATION_MODES:
+            tag = "rmat22 source %d mode %s" % (s, mode)
+            _say(tag)
+            opt = dobfs.make_options(mode, BENCH_OPT["heuristic"], BENCH_OPT["alpha"], BENCH_OPT["beta"])
+            # the sort-based push needs its larger workspace: the library's own, as the bench runs it
+            ws = None if mode == "push_sort" else r.ws
+            dobfs.bfs(g, s, r.depth, r.parent, opt, ws, stats=r.stats)
+            d, p = r.result()
+            _check(hg, s, want[s], d, p, tag)
+    # the paper's ratio rule in the stored order as well
+    g2 = upload(hg)
+    r2 = BfsRunner(g2)
+    r2.run(pick[1], mode="full")
+    d, p = r2.result()
+    _check(hg, pick[1], want[pick[1]], d, p, "rmat22 stored order, ratio rule")
+    dobfs.graph_destroy(g)
+    dobfs.graph_destroy(g2)
 
 
-def test_lattice256_single_source():
+def test_lattice256_sources():
+    """Four of the 16 lattice sources in the full, push-only and benchmarked configurations."""
     hg = gen.lattice3d(256, 0.05, seed=3)
     assert hg.nnz == 95_256_576
     srcs = [int(x) for x in gen.sample_sources(hg, 16, seed=4)]
-    _single(hg, [srcs[0]], [dict(mode="full"), BENCH_OPT])
+    pick = [srcs[0], srcs[5], srcs[10], srcs[15]]
+    want = _oracle_many(hg, pick)
+    g = upload(hg, hubs_first=True)
+    r = BfsRunner(g)
+    for s in pick:
+        for o in (dict(mode="full"), dict(mode="push_only"), BENCH_OPT):
+            tag = "lattice256 source %d %s" % (s, o)
+            _say(tag)
+            r.run(s, **o)
+            d, p = r.result()
+            _check(hg, s, want[s], d, p, tag, o, r.levels())
+    dobfs.graph_destroy(g)
 
 
 def test_grid2048_single_source():
     hg = gen.grid2d(2048, 2048)
     assert hg.nnz == 16_769_024
-    _single(hg, [0], [dict(mode="full")])
+    g = upload(hg)
+    r = BfsRunner(g)
+    want, _ = oracle.bfs(hg, 0)
+    r.run(0, mode="full")
+    d, p = r.result()
+    _check(hg, 0, want, d, p, "grid2048 source 0")
+    dobfs.graph_destroy(g)
 
 
-def test_rmat20_multi_source_rows():
+def test_rmat20_multi_source_all_rows():
+    """Every row of the benchmark's 64-source RMAT-20 launch, in its configuration."""
     hg = gen.rmat(20, 16, seed=1)
     srcs = [int(x) for x in gen.sample_sources(hg, 64, seed=5)]
-    g = upload(hg)
+    g = upload(hg, hubs_first=True)
     depth = torch.full((64 * g.V,), -7, dtype=torch.int32, device="cuda")
     dobfs.bfs_batch(g, srcs, depth, opt=dobfs.make_options(**BENCH_OPT))
     rows = depth.cpu().numpy().reshape(64, g.V)
-    for b in (0, 21, 42, 63):
-        _say("rmat20 row", b)
-        want, _ = oracle.bfs(hg, srcs[b])
-        assert np.array_equal(rows[b], want), "row %d (source %d) differs" % (b, srcs[b])
+    want = _oracle_many(hg, srcs)
+    for b in range(64):
+        assert np.array_equal(rows[b], want[srcs[b]]), "row %d (source %d) differs" % (b, srcs[b])
+    _say("rmat20: 64 rows match")
     dobfs.graph_destroy(g)

@@ -130,3 +130,25 @@ def test_mxv_rejects_bad_args(cases):
         dobfs.mxv(g, yb, x_bits=yb, flags=8)
     with pytest.raises(dobfs.DobfsError):
         dobfs.mxv(g, yb, x_idx=None, x_nnz=3)
+
+
+def test_mxv_in_place_operand_reuse(cases):
+    """x = mask = y in one buffer: the in-place BFS form v = v OR A^T v .* not(v) (Section 5.4,
+    complement and ACCUM_OR). The result must be the oracle's one-hop step from the vector
+    as it was before the call, in both directions and with or without early exit, repeated
+    from a few random starting sets (two hops never appear in one call)."""
+    rng = np.random.default_rng(23)
+    for hg, g, _ in cases:
+        V = hg.V
+        for dens in (0.0005, 0.02, 0.3):
+            v0 = rng.random(V) < dens
+            for direction, ee in itertools.product((dobfs.DIR_PUSH, dobfs.DIR_PULL), (False, True)):
+                buf = _dev(pack_bits(v0))
+                flags = dobfs.MXV_ACCUM_OR | (dobfs.MXV_EARLY_EXIT if ee else 0)
+                nnz = dobfs.mxv(g, buf, x_bits=buf, mask_bits=buf, complement=True,
+                                direction=direction, flags=flags)
+                got = unpack_bits(buf.cpu().numpy(), V)
+                want = oracle.mxv(hg, v0, v0, True, True, v0).astype(bool)
+                tag = "%s dens=%g dir=%d ee=%s" % (hg.name, dens, direction, ee)
+                assert np.array_equal(got, want), tag
+                assert nnz == int(want.sum()), tag

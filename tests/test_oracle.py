@@ -420,3 +420,92 @@ def test_teps_edges():
     g2 = gen.from_edges(6, [0, 1, 3], [1, 2, 4])
     d2, _ = oracle.bfs(g2, 0)
     assert oracle.teps_edges(g2, d2) == {"graph500": 2, "paper": 6}
+
+
+# ------------------------------------------- first-hit parents: hand-worked pins
+def _fig3_columns(fx, cols):
+    """The Figure 3 graph with its CSC columns stored as `cols` lists them (CSR sorted)."""
+    names = list(fx["vertices"])
+    ids = {v: i for i, v in enumerate(names)}
+    base = gen.from_edges(len(ids), *np.array([[ids[a], ids[b]] for a, b in fx["undirected_edges"]]).T)
+    colptr = np.zeros(len(names) + 1, dtype=np.int32)
+    rowind = []
+    for i, v in enumerate(names):
+        col = [ids[u] for u in cols[v]]
+        # the hand-written columns hold exactly the graph's in-neighbours
+        assert sorted(col) == base.csc_rowind[base.csc_colptr[i]:base.csc_colptr[i + 1]].tolist(), v
+        rowind += col
+        colptr[i + 1] = len(rowind)
+    g = gen.HostGraph("fig3_cols", len(names), base.rowptr, base.colind, colptr,
+                      np.asarray(rowind, dtype=np.int32), True, {})
+    return g, ids, names
+
+
+@pytest.mark.parametrize("order", ["sorted_columns", "reordered_columns"])
+def test_first_parent_fig3_hand_worked(order):
+    """Section 4.2 / Algorithm 2: a pull stops at the first in-neighbour, in the order the
+    column is stored, that is one level up. On the Figure 3 graph from A, vertex E has two
+    such in-neighbours (C and D): sorted it reports C (the last hit would be D); with the
+    column stored as G, D, C it reports D, which is neither the smallest id nor the last hit."""
+    with open(os.path.join(GOLDEN, "fig3_toy.json")) as f:
+        fx = json.load(f)
+    with open(os.path.join(GOLDEN, "fig3_first_parent.json")) as f:
+        pin = json.load(f)
+    g, ids, names = _fig3_columns(fx, pin[order]["columns"])
+    s = ids[pin["source"]]
+    d, _ = oracle.bfs(g, s)
+    assert {v: int(d[ids[v]]) for v in names} == pin["depth"]
+    fp = oracle.first_parent(g, d, s)
+    assert {v: names[fp[ids[v]]] for v in names} == pin[order]["first_parent"]
+    assert oracle.validate(g, s, d, fp)[0] == 0
+    # the pull of level 1 (visited = {A, B, C, D}) checks this many in-neighbours
+    assert oracle.pull_checks(g, d, 1) == pin[order]["pull_checks_level1"]
+    if order == "sorted_columns":
+        last = pin[order]["last_parent"]
+        assert all(names[fp[ids[v]]] != p for v, p in last.items())
+
+
+def _pull_traversal_parents(V, colptr, rowind, s):
+    """Algorithm 1 run with the pull of Algorithm 2 at every level, written level by level:
+    x = the visited set at the start of the level (operand reuse), every unvisited row scans
+    its column in stored order and stops at the first entry with x set; that entry is the
+    row's parent. A different route to first_parent's values: frontier membership level by
+    level instead of the final depths."""
+    visited = np.zeros(V, dtype=bool)
+    visited[s] = True
+    parent = np.full(V, -1, dtype=np.int64)
+    parent[s] = s
+    while True:
+        found = {}
+        for i in range(V):
+            if visited[i]:
+                continue
+            for q in range(colptr[i], colptr[i + 1]):
+                if visited[rowind[q]]:
+                    found[i] = rowind[q]
+                    break
+        if not found:
+            return parent
+        for i, j in found.items():
+            visited[i] = True
+            parent[i] = j
+
+
+@pytest.mark.parametrize("reverse", [False, True])
+def test_first_parent_matches_level_by_level_pull(reverse):
+    """All undirected graphs on 5 vertices, every source, columns stored sorted and reversed."""
+    n = 5
+    pairs = list(itertools.combinations(range(n), 2))
+    for bits in range(0, 1 << len(pairs), 3):
+        A = np.zeros((n, n), dtype=bool)
+        for k, (i, j) in enumerate(pairs):
+            if bits >> k & 1:
+                A[i, j] = A[j, i] = True
+        g = _graph_from_dense(A)
+        if reverse:
+            ri = np.concatenate([g.csc_rowind[g.csc_colptr[v]:g.csc_colptr[v + 1]][::-1] for v in range(n)])
+            g = gen.HostGraph("rev", n, g.rowptr, g.colind, g.csc_colptr, ri.astype(np.int32), True, {})
+        for s in range(n):
+            d, _ = oracle.bfs(g, s)
+            want = _pull_traversal_parents(n, g.csc_colptr, g.csc_rowind, s)
+            assert np.array_equal(oracle.first_parent(g, d, s), want), (A, s, reverse)
