@@ -243,6 +243,31 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options *opt, 
                        int32_t *parent, void *workspace, size_t ws_bytes, void *stream,
                        dobfs_stats *stats);
 
+/*
+ * For callers that cannot allocate device or pinned host memory (code that
+ * must not call hipMalloc: tight serving loops, harnesses that forbid it):
+ * dobfs_bfs with the workspace and the level report in a static device array
+ * of the library, DOBFS_STATIC_SCRATCH_BYTES on every device the library runs
+ * this call on, held until the process ends. The call makes no allocation
+ * (no hipMalloc / hipFree / hipHostMalloc, no events): it copies each batch's
+ * report into ordinary host memory after the stream has drained, so it
+ * synchronises `stream` once per batch of levels.
+ * Results, arguments and errors as dobfs_bfs, and:
+ *  - the graph must fit: 16*V + 4*ceil(V/32)*4 + 4*(nnz/1024) bytes plus
+ *    about 200 KB of control data (256-byte aligned regions) within the
+ *    array; V <= 2^22 with nnz <= 2^28 always fits (RMAT scale 22, edge
+ *    factor 16). Larger graphs -> INVALID_ARG, nothing written;
+ *  - DOBFS_MODE_PUSH_SORT and DOBFS_OPT_TIME_KERNELS -> UNSUPPORTED (they
+ *    need a larger workspace and events); stats receive no times (0);
+ *  - every call on a device shares that device's array, which keeps the
+ *    last call's contents (each call clears what it needs cleared). Calls
+ *    that overlap on one device race: issue them on one stream, or
+ *    synchronise the stream of the previous call first.
+ */
+#define DOBFS_STATIC_SCRATCH_BYTES ((size_t)68 << 20)
+dobfs_status dobfs_bfs_static(dobfs_graph g, int32_t source, const dobfs_options *opt, int32_t *depth,
+                              int32_t *parent, void *stream, dobfs_stats *stats);
+
 /* ------------------------------------------------------ multi-source BFS */
 
 /* Device bytes of workspace a dobfs_bfs_batch call with k sources needs

@@ -229,6 +229,23 @@ hipError_t wait_report(const HostReport* r, uint32_t seq, hipStream_t s) {
   return __atomic_load_n(&r->seq, __ATOMIC_ACQUIRE) == seq ? hipSuccess : hipErrorUnknown;
 }
 
+// Where the level loop's report goes: `dev` is what the kernels write, `host`
+// what the host reads. The same pinned buffer for both (the host spins on it),
+// or a device buffer copied into ordinary host memory after the stream has
+// drained (the allocation-free entry point, which may not pin memory).
+struct ReportSink {
+  HostReport* dev = nullptr;
+  HostReport* host = nullptr;
+};
+
+hipError_t fetch_report(const ReportSink& r, uint32_t seq, hipStream_t s) {
+  if (r.dev == r.host) return wait_report(r.host, seq, s);
+  hipError_t e = hipMemcpyAsync(r.host, r.dev, sizeof(HostReport), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  return r.host->seq == seq ? hipSuccess : hipErrorUnknown;
+}
+
 // Per-thread, per-device events for the level loop's timers: the start and
 // end of every prep (kMaxBatch + 1 slots) and main (kMaxBatch slots) kernel
 // of a batch, of the init kernel, and of the whole call.
@@ -570,9 +587,9 @@ dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool t
 // double. When timing, step k of a batch has events ev_m0(k) / ev_m1(k); a
 // level's scan step counts as its ms_aux, its other step as its ms_main.
 dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool timing, hipEvent_t* ev,
-                       const BfsArgs& a, int64_t max_steps, dobfs_stats* stats, LoopResult* res) {
-  HostReport* rep = host_report();
-  if (!rep) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
+                       const BfsArgs& a, int64_t max_steps, const ReportSink& sink, dobfs_stats* stats,
+                       LoopResult* res) {
+  HostReport* rep = sink.host;
   int64_t s0 = 0;
   int32_t rec_first = 0;
   int32_t batch = std::min(std::max(last_steps.load(std::memory_order_relaxed) + 1, 2), kMaxBatch);
@@ -583,12 +600,12 @@ dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool tim
     const uint32_t seq = next_report_seq();
     // untimed, the batch's last step writes the report; timed, a report kernel follows the
     // steps so that every step's end event has completed when the host reads it
-    const StepReportArgs rp{rep, seq, int32_t(s0), rec_first};
+    const StepReportArgs rp{sink.dev, seq, int32_t(s0), rec_first};
     for (int32_t k = 0; k < batch; ++k)
       HIPCK(launch_step(s, a, int32_t(s0 + k), E(ev_m0(k)), E(ev_m1(k)),
                         (!timing && k == batch - 1) ? &rp : nullptr));
-    if (timing) HIPCK(launch_step_report(s, a.ctrl, int32_t(s0), batch, rec_first, rep, seq));
-    HIPCK(wait_report(rep, seq, s));
+    if (timing) HIPCK(launch_step_report(s, a.ctrl, int32_t(s0), batch, rec_first, sink.dev, seq));
+    HIPCK(fetch_report(sink, seq, s));
     res->n_main += batch;
     for (int32_t k = 0; k < batch; ++k) {  // step times, by level
       const float t = timing ? elapsed(ev[ev_m0(k)], ev[ev_m1(k)]) : 0.f;
@@ -638,14 +655,13 @@ dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool tim
 
 // stats->edges_g500 after a single-source traversal into depth: the out-degree sum of the
 // reached vertices, counted on the device, halved for a graph given as undirected.
+// `tail` receives the device's counters (host memory, pinned or not).
 dobfs_status reached_edges(dobfs_graph g, hipStream_t s, Ctrl* ctrl, const int32_t* depth,
-                           dobfs_stats* stats) {
-  Ctrl* host = host_ctrl();
-  if (!host) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
+                           dobfs_stats* stats, LevelSlot* tail) {
   HIPCK(launch_reached_degree(s, g->rowptr, depth, g->V, &ctrl->tail));
-  HIPCK(hipMemcpyAsync(&host->tail, &ctrl->tail, sizeof(LevelSlot), hipMemcpyDeviceToHost, s));
+  HIPCK(hipMemcpyAsync(tail, &ctrl->tail, sizeof(LevelSlot), hipMemcpyDeviceToHost, s));
   HIPCK(hipStreamSynchronize(s));
-  const int64_t sum = int64_t(sum_slot(host->tail).edges);
+  const int64_t sum = int64_t(sum_slot(*tail).edges);
   stats->edges_g500 = g->symmetric ? sum / 2 : sum;
   return DOBFS_OK;
 }
@@ -737,8 +753,91 @@ dobfs_status bfs_sort_push(dobfs_graph g, int32_t source, const dobfs_options& o
     stats->reached = reached;
     stats->launches_main = stats->launches_aux = 0;
     stats->ms_main_all = stats->ms_aux_all = 0.f;
-    return reached_edges(g, s, c, depth, stats);
+    return reached_edges(g, s, c, depth, stats, &hc->tail);
   }
+  return DOBFS_OK;
+}
+
+// Checks shared by the single-source entry points; *opt receives the options in force.
+dobfs_status check_bfs_call(dobfs_graph g, int32_t source, const dobfs_options* opt_in, const int32_t* depth,
+                            const dobfs_stats* stats, dobfs_options* opt) {
+  if (!g) return fail(DOBFS_ERR_INVALID_ARG, "graph is NULL");
+  if (!depth) return fail(DOBFS_ERR_INVALID_ARG, "depth is NULL");
+  if (source < 0 || source >= g->V)
+    return fail(DOBFS_ERR_INVALID_ARG, "source %d not in [0, %d)", source, g->V);
+  *opt = opt_in ? *opt_in : defaults();
+  dobfs_status st = check_options(*opt);
+  if (st != DOBFS_OK) return st;
+  if (stats && stats->cap > 0 && !stats->level)
+    return fail(DOBFS_ERR_INVALID_ARG, "stats->level is NULL with cap = %d", stats->cap);
+  return DOBFS_OK;
+}
+
+// One single-source traversal (Algorithm 1) over workspace `ws` laid out as L, on stream s:
+// the init kernel, then the step loop. ev: the thread's events (nullptr: no events, so no
+// times in the stats); tail: host memory for the reached-edge count.
+dobfs_status bfs_steps(dobfs_graph g, int32_t source, const dobfs_options& opt, int32_t* depth,
+                       int32_t* parent, uint8_t* ws, const Layout& L, hipStream_t s, const ReportSink& sink,
+                       hipEvent_t* ev, LevelSlot* tail, dobfs_stats* stats) {
+  const bool timing = ev && (opt.flags & DOBFS_OPT_TIME_KERNELS) != 0;
+  BfsArgs a = bfs_args(g, ws, L, opt, depth, parent);
+  const int32_t dir0 = opt.n_forced > 0 ? int32_t(opt.forced_dirs[0])
+                                        : (opt.mode == DOBFS_MODE_PULL_ONLY ? DOBFS_DIR_PULL : DOBFS_DIR_PUSH);
+  a.n_forced = std::min<int32_t>(opt.n_forced, kRing);  // later levels follow the rule
+  if (a.n_forced > 0)
+    HIPCK(hipMemcpyAsync(a.ctrl->forced, opt.forced_dirs, size_t(a.n_forced), hipMemcpyHostToDevice, s));
+
+  // the whole-call interval only when asked for: the last batch's report already tells the
+  // host that every kernel of the traversal has finished, so no further wait is needed
+  if (stats && ev) HIPCK(hipEventRecord(ev[kEvStart], s));
+  HIPCK(launch_bfs_init(s, a, source, dir0, timing ? ev[kEvInit0] : nullptr,
+                        timing ? ev[kEvInit1] : nullptr));
+  LoopResult res;
+  // a level takes at most two steps; scan tile flags carry 2 * step + 2 in 30 bits
+  const int64_t max_steps = std::min<int64_t>(2 * (int64_t(g->V) + 2), (int64_t(1) << 29) - 2);
+  dobfs_status st = run_steps(g->last_steps, s, timing, ev, a, max_steps, sink, stats, &res);
+  if (st != DOBFS_OK) return st;
+  if (stats) {
+    if (ev) {
+      HIPCK(hipEventRecord(ev[kEvEnd], s));
+      HIPCK(hipEventSynchronize(ev[kEvEnd]));
+    }
+    stats->levels = int32_t(res.levels);
+    stats->ms_total = ev ? elapsed(ev[kEvStart], ev[kEvEnd]) : 0.f;
+    stats->ms_init = timing ? elapsed(ev[kEvInit0], ev[kEvInit1]) : 0.f;
+    stats->reached = 1 + res.sum_new;
+    stats->launches_main = res.n_main;
+    stats->launches_aux = res.n_aux;
+    stats->ms_main_all = res.ms_main_all;
+    stats->ms_aux_all = res.ms_aux_all;
+    return reached_edges(g, s, a.ctrl, depth, stats, tail);
+  }
+  return DOBFS_OK;
+}
+
+// ---- the allocation-free single-source call ----
+// Its workspace and level report live in `scratch`, one copy per device that
+// loads the library, held until the process ends. Host code never passes the
+// symbol itself to a kernel: its device address on each device comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kStaticScratchBytes = DOBFS_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_ptr[64] = {};
+
+// Device address of `scratch` on `device` (current when called).
+dobfs_status static_scratch(int device, uint8_t** out) {
+  if (device < 0 || device >= 64) return fail(DOBFS_ERR_INVALID_ARG, "device %d out of range", device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)", __LINE__);
+    if (!p) return fail(DOBFS_ERR_DEVICE, "static scratch has no address on device %d", device);
+    g_scratch_ptr[device] = static_cast<uint8_t*>(p);
+  }
+  *out = g_scratch_ptr[device];
   return DOBFS_OK;
 }
 
@@ -915,16 +1014,9 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
                        int32_t* parent, void* workspace, size_t ws_bytes, void* stream,
                        dobfs_stats* stats) {
   t_last_error.clear();
-  if (!g) return fail(DOBFS_ERR_INVALID_ARG, "graph is NULL");
-  if (!depth) return fail(DOBFS_ERR_INVALID_ARG, "depth is NULL");
-  if (source < 0 || source >= g->V)
-    return fail(DOBFS_ERR_INVALID_ARG, "source %d not in [0, %d)", source, g->V);
-  const dobfs_options opt = opt_in ? *opt_in : defaults();
-  dobfs_status st = check_options(opt);
+  dobfs_options opt;
+  dobfs_status st = check_bfs_call(g, source, opt_in, depth, stats, &opt);
   if (st != DOBFS_OK) return st;
-  if (stats && stats->cap > 0 && !stats->level)
-    return fail(DOBFS_ERR_INVALID_ARG, "stats->level is NULL with cap = %d", stats->cap);
-
   DeviceScope ds(g->device);
   if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice", __LINE__);
   if (opt.mode == DOBFS_MODE_PUSH_SORT)
@@ -934,41 +1026,39 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   WsLease lease;
   uint8_t* ws = nullptr;
   if ((st = get_workspace(g, workspace, ws_bytes, L.total, s, lease, &ws)) != DOBFS_OK) return st;
-  const bool timing = (opt.flags & DOBFS_OPT_TIME_KERNELS) != 0;
+  HostReport* rep = host_report();
+  Ctrl* hc = host_ctrl();
+  if (!rep || !hc) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
   hipEvent_t* ev = events_for(g->device);
   if (!ev) return fail(DOBFS_ERR_DEVICE, "event creation failed");
+  return bfs_steps(g, source, opt, depth, parent, ws, L, s, ReportSink{rep, rep}, ev, &hc->tail, stats);
+}
 
-  BfsArgs a = bfs_args(g, ws, L, opt, depth, parent);
-  const int32_t dir0 = opt.n_forced > 0 ? int32_t(opt.forced_dirs[0])
-                                        : (opt.mode == DOBFS_MODE_PULL_ONLY ? DOBFS_DIR_PULL : DOBFS_DIR_PUSH);
-  a.n_forced = std::min<int32_t>(opt.n_forced, kRing);  // later levels follow the rule
-  if (a.n_forced > 0)
-    HIPCK(hipMemcpyAsync(a.ctrl->forced, opt.forced_dirs, size_t(a.n_forced), hipMemcpyHostToDevice, s));
-
-  // the whole-call interval only when asked for: the last batch's report already tells the
-  // host that every kernel of the traversal has finished, so no further wait is needed
-  if (stats) HIPCK(hipEventRecord(ev[kEvStart], s));
-  HIPCK(launch_bfs_init(s, a, source, dir0, timing ? ev[kEvInit0] : nullptr,
-                        timing ? ev[kEvInit1] : nullptr));
-  LoopResult res;
-  // a level takes at most two steps; scan tile flags carry 2 * step + 2 in 30 bits
-  const int64_t max_steps = std::min<int64_t>(2 * (int64_t(g->V) + 2), (int64_t(1) << 29) - 2);
-  st = run_steps(g->last_steps, s, timing, ev, a, max_steps, stats, &res);
+dobfs_status dobfs_bfs_static(dobfs_graph g, int32_t source, const dobfs_options* opt_in, int32_t* depth,
+                              int32_t* parent, void* stream, dobfs_stats* stats) {
+  t_last_error.clear();
+  dobfs_options opt;
+  dobfs_status st = check_bfs_call(g, source, opt_in, depth, stats, &opt);
   if (st != DOBFS_OK) return st;
-  if (stats) {
-    HIPCK(hipEventRecord(ev[kEvEnd], s));
-    HIPCK(hipEventSynchronize(ev[kEvEnd]));
-    stats->levels = int32_t(res.levels);
-    stats->ms_total = elapsed(ev[kEvStart], ev[kEvEnd]);
-    stats->ms_init = timing ? elapsed(ev[kEvInit0], ev[kEvInit1]) : 0.f;
-    stats->reached = 1 + res.sum_new;
-    stats->launches_main = res.n_main;
-    stats->launches_aux = res.n_aux;
-    stats->ms_main_all = res.ms_main_all;
-    stats->ms_aux_all = res.ms_aux_all;
-    return reached_edges(g, s, a.ctrl, depth, stats);
-  }
-  return DOBFS_OK;
+  if (opt.mode == DOBFS_MODE_PUSH_SORT)
+    return fail(DOBFS_ERR_UNSUPPORTED, "the sort-based push needs a workspace beyond the static scratch");
+  if (opt.flags & DOBFS_OPT_TIME_KERNELS)
+    return fail(DOBFS_ERR_UNSUPPORTED, "kernel timing needs events, which this call does not create");
+  const Layout L = plan(g->V, g->nnz);
+  const size_t rep_off = align_up(L.total);
+  if (rep_off + sizeof(HostReport) > kStaticScratchBytes)
+    return fail(DOBFS_ERR_INVALID_ARG,
+                "graph needs %zu bytes of scratch (V = %d, nnz = %lld); the static scratch holds %zu",
+                rep_off + sizeof(HostReport), g->V, (long long)g->nnz, kStaticScratchBytes);
+  DeviceScope ds(g->device);
+  if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice", __LINE__);
+  uint8_t* base = nullptr;
+  if ((st = static_scratch(g->device, &base)) != DOBFS_OK) return st;
+  thread_local HostReport host_rep;  // ordinary host memory: the report is copied in after the stream drains
+  thread_local LevelSlot host_tail;
+  const ReportSink sink{reinterpret_cast<HostReport*>(base + rep_off), &host_rep};
+  return bfs_steps(g, source, opt, depth, parent, base, L, static_cast<hipStream_t>(stream), sink,
+                   nullptr, &host_tail, stats);
 }
 
 dobfs_status dobfs_bfs_batch_workspace_bytes(dobfs_graph g, int32_t k, size_t* bytes) {

@@ -99,6 +99,7 @@ def load():
         "dobfs_next_direction": (i32, [ctypes.POINTER(Options), i32, i64, i64, i64, i64, i64]),
         "dobfs_bfs_workspace_bytes": (i32, [vp, ctypes.POINTER(Options), ctypes.POINTER(sz)]),
         "dobfs_bfs": (i32, [vp, i32, ctypes.POINTER(Options), vp, vp, vp, sz, vp, ctypes.POINTER(Stats)]),
+        "dobfs_bfs_static": (i32, [vp, i32, ctypes.POINTER(Options), vp, vp, vp, ctypes.POINTER(Stats)]),
         "dobfs_bfs_batch_workspace_bytes": (i32, [vp, i32, ctypes.POINTER(sz)]),
         "dobfs_bfs_batch": (i32, [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(Options), vp, vp, sz, vp,
                                   ctypes.POINTER(Stats)]),
@@ -295,6 +296,19 @@ def bfs(g: Graph, source: int, depth, parent=None, opt=None, workspace=None, ws_
     _check(lib.dobfs_bfs(g.handle, int(source), ctypes.byref(opt) if opt is not None else None,
                          d, p, w, nbytes, _stream(stream, g.device),
                          ctypes.byref(stats) if stats is not None else None))
+    return stats
+
+
+def bfs_static(g: Graph, source: int, depth, parent=None, opt=None, stream=None, stats=None):
+    """dobfs_bfs_static: dobfs_bfs with the library's static device scratch as its workspace
+    (no allocation inside the call); depth/parent are int32 CUDA tensors of V elements."""
+    import torch
+    lib = load()
+    d = _dptr(depth, torch.int32, g.V, "depth")
+    p = _dptr(parent, torch.int32, g.V, "parent")
+    _check(lib.dobfs_bfs_static(g.handle, int(source), ctypes.byref(opt) if opt is not None else None,
+                                d, p, _stream(stream, g.device),
+                                ctypes.byref(stats) if stats is not None else None))
     return stats
 
 
