@@ -129,8 +129,20 @@ enum {
 };
 
 enum {
-  DOBFS_OPT_TIME_KERNELS = 1u /* every kernel launch records its own start and end (HIP
-                                 extended-launch events); fills the *_ms stats */
+  DOBFS_OPT_TIME_KERNELS = 1u, /* every kernel launch records its own start and end (HIP
+                                  extended-launch events); fills the *_ms stats. In the
+                                  persistent loop a level's time is the difference of the
+                                  device clock at the starts of consecutive steps */
+  DOBFS_OPT_PERSISTENT = 2u /* single source: run the level loop as a persistent kernel (one
+                               launch runs up to 64 steps, co-resident blocks sized by the
+                               occupancy query, a grid barrier between steps) instead of one
+                               launch per step. Same results. On MI355X the barrier needs an
+                               agent-scope L2 write-back and invalidate per block (the XCDs' L2
+                               caches are not coherent), which costs more than a kernel
+                               boundary, so this is off by default. The environment variable
+                               DOBFS_SPIN_LIMIT bounds every barrier wait (polls; exceeded ->
+                               DOBFS_ERR_INTERNAL, every block leaves); DOBFS_PERSIST_BLOCKS
+                               caps the grid */
 };
 
 typedef struct {

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -297,7 +298,7 @@ dobfs_status check_options(const dobfs_options& o) {
     if (o.forced_dirs[k] != DOBFS_DIR_PUSH && o.forced_dirs[k] != DOBFS_DIR_PULL)
       return fail(DOBFS_ERR_INVALID_ARG, "forced_dirs[%d] = %d is not a direction", k,
                   int(o.forced_dirs[k]));
-  if (o.flags & ~uint32_t(DOBFS_OPT_TIME_KERNELS))
+  if (o.flags & ~uint32_t(DOBFS_OPT_TIME_KERNELS | DOBFS_OPT_PERSISTENT))
     return fail(DOBFS_ERR_INVALID_ARG, "unknown option flags 0x%x", o.flags);
   return DOBFS_OK;
 }
@@ -579,6 +580,41 @@ dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool t
   return DOBFS_OK;
 }
 
+// The persistent step loop on one device: how many of its blocks fit at once
+// (its grid), the wall-clock rate, and a lock held from one of its launches
+// until that launch's report is in. A launch waits at its barriers only
+// until its report is written, so with the lock no two launches of the loop
+// ever wait on each other for room on the device.
+struct PersistentDevice {
+  std::mutex mu;
+  std::once_flag once;
+  int32_t capacity = 0;       // 0: the persistent loop is not available
+  double ticks_per_ms = 0.0;  // device wall clock
+};
+PersistentDevice g_persistent[64];
+
+PersistentDevice* persistent_device(int device) {
+  if (device < 0 || device >= 64) return nullptr;
+  PersistentDevice* d = &g_persistent[device];
+  std::call_once(d->once, [d, device]() {
+    int32_t cap = 0;
+    int khz = 0;
+    if (persistent_capacity(&cap) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0) {
+      d->capacity = cap;
+      d->ticks_per_ms = double(khz);
+    }
+  });
+  return d->capacity > 0 ? d : nullptr;
+}
+
+uint32_t env_u32(const char* name, uint32_t dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  const unsigned long long x = std::strtoull(v, nullptr, 10);
+  return x > 0xffffffffull ? 0xffffffffu : uint32_t(x);
+}
+
 // The single-source level loop: the host enqueues steps (k_step, one launch
 // each) in batches and reads back, once per batch, the state every step
 // published and the records of the levels that are complete; steps enqueued
@@ -586,30 +622,61 @@ dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool t
 // previous traversal of the graph needed; later batches start at 4 and
 // double. When timing, step k of a batch has events ev_m0(k) / ev_m1(k); a
 // level's scan step counts as its ms_aux, its other step as its ms_main.
+// With `pd` (persistent loop on that device) a batch is one launch of
+// k_steps running the batch's steps, with the same report; per-step times
+// then come from the device clock at each step's start (and the launch's end).
 dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool timing, hipEvent_t* ev,
-                       const BfsArgs& a, int64_t max_steps, const ReportSink& sink, dobfs_stats* stats,
-                       LoopResult* res) {
+                       const BfsArgs& a, int64_t max_steps, const ReportSink& sink, PersistentDevice* pd,
+                       dobfs_stats* stats, LoopResult* res) {
   HostReport* rep = sink.host;
   int64_t s0 = 0;
   int32_t rec_first = 0;
   int32_t batch = std::min(std::max(last_steps.load(std::memory_order_relaxed) + 1, 2), kMaxBatch);
   int32_t next_batch = 4;
   auto E = [&](int i) -> hipEvent_t { return timing ? ev[i] : nullptr; };
+  const int32_t blocks = pd ? int32_t(std::min<int64_t>(main_blocks(a.nwords),
+                                                        int64_t(env_u32("DOBFS_PERSIST_BLOCKS", uint32_t(pd->capacity)))))
+                            : 0;
+  const uint32_t spin_limit = env_u32("DOBFS_SPIN_LIMIT", 1u << 22);
+  if (pd && (blocks < 1 || blocks > pd->capacity))
+    return fail(DOBFS_ERR_INVALID_ARG, "persistent grid of %d blocks (1 .. %d fit)", blocks, pd->capacity);
+  if (pd) batch = next_batch = kMaxBatch;  // a launch ends with the traversal: no steps past the end
   while (true) {
     if (s0 + batch > max_steps) batch = int32_t(max_steps - s0);
     const uint32_t seq = next_report_seq();
     // untimed, the batch's last step writes the report; timed, a report kernel follows the
     // steps so that every step's end event has completed when the host reads it
     const StepReportArgs rp{sink.dev, seq, int32_t(s0), rec_first};
-    for (int32_t k = 0; k < batch; ++k)
-      HIPCK(launch_step(s, a, int32_t(s0 + k), E(ev_m0(k)), E(ev_m1(k)),
-                        (!timing && k == batch - 1) ? &rp : nullptr));
-    if (timing) HIPCK(launch_step_report(s, a.ctrl, int32_t(s0), batch, rec_first, sink.dev, seq));
-    HIPCK(fetch_report(sink, seq, s));
-    res->n_main += batch;
+    if (pd) {
+      std::lock_guard<std::mutex> lk(pd->mu);
+      HIPCK(launch_steps(s, a, int32_t(s0), batch, blocks, spin_limit, timing,
+                         timing ? StepReportArgs{nullptr, 0u, 0, 0} : rp, E(ev_m0(0)), E(ev_m1(0))));
+      if (timing) HIPCK(launch_step_report(s, a.ctrl, int32_t(s0), batch, rec_first, sink.dev, seq));
+      HIPCK(fetch_report(sink, seq, s));
+    } else {
+      for (int32_t k = 0; k < batch; ++k)
+        HIPCK(launch_step(s, a, int32_t(s0 + k), E(ev_m0(k)), E(ev_m1(k)),
+                          (!timing && k == batch - 1) ? &rp : nullptr));
+      if (timing) HIPCK(launch_step_report(s, a.ctrl, int32_t(s0), batch, rec_first, sink.dev, seq));
+      HIPCK(fetch_report(sink, seq, s));
+    }
+    if (rep->error) {
+      (void)hipStreamSynchronize(s);
+      return fail(DOBFS_ERR_INTERNAL, "a grid barrier wait of the persistent level loop gave up "
+                                      "(spin limit %u polls)", spin_limit);
+    }
+    res->n_main += pd ? 1 : batch;
+    if (pd && timing) res->ms_main_all += elapsed(ev[ev_m0(0)], ev[ev_m1(0)]);
     for (int32_t k = 0; k < batch; ++k) {  // step times, by level
-      const float t = timing ? elapsed(ev[ev_m0(k)], ev[ev_m1(k)]) : 0.f;
-      res->ms_main_all += t;
+      float t = 0.f;
+      if (timing && !pd) {
+        t = elapsed(ev[ev_m0(k)], ev[ev_m1(k)]);
+        res->ms_main_all += t;
+      } else if (timing && !rep->steps[k].done) {  // to the next step's start, or the launch's end
+        const unsigned long long t1 =
+            (k + 1 < batch && !rep->steps[k + 1].done) ? rep->steps[k + 1].t0 : rep->t_end;
+        t = float(double(t1 - rep->steps[k].t0) / pd->ticks_per_ms);
+      }
       const LevelState& st = rep->steps[k];
       if (st.done || !stats || st.level >= stats->cap) continue;
       dobfs_level_stats& ls = stats->level[st.level];
@@ -795,7 +862,12 @@ dobfs_status bfs_steps(dobfs_graph g, int32_t source, const dobfs_options& opt, 
   LoopResult res;
   // a level takes at most two steps; scan tile flags carry 2 * step + 2 in 30 bits
   const int64_t max_steps = std::min<int64_t>(2 * (int64_t(g->V) + 2), (int64_t(1) << 29) - 2);
-  dobfs_status st = run_steps(g->last_steps, s, timing, ev, a, max_steps, sink, stats, &res);
+  PersistentDevice* pd = nullptr;
+  if (opt.flags & DOBFS_OPT_PERSISTENT) {
+    pd = persistent_device(g->device);
+    if (!pd) return fail(DOBFS_ERR_UNSUPPORTED, "the persistent level loop is not available on device %d", g->device);
+  }
+  dobfs_status st = run_steps(g->last_steps, s, timing, ev, a, max_steps, sink, pd, stats, &res);
   if (st != DOBFS_OK) return st;
   if (stats) {
     if (ev) {

@@ -50,7 +50,9 @@ struct alignas(64) LevelState {
   int32_t phase;       // single-source step loop: kPhaseWhole, kPhaseScan or kPhaseExpand
   int64_t m_u;         // edge-count rule: in-edges of still-unvisited vertices
   uint64_t active;     // multi-source: sources whose frontier entering the level is non-empty
+  uint64_t t0;         // single source, persistent loop: device clock when the step started
 };
+static_assert(sizeof(LevelState) == 64, "one state per 64-byte line");
 // What one step of the single-source loop does for its level: all of it
 // (a pull, or a push that shares out its own work), or one of the two steps of
 // a push that needs the global degree scan.
@@ -63,6 +65,26 @@ struct LevelRecord {
   uint64_t aux;        // multi-source: (vertex, source) pairs discovered
 };
 constexpr int kRing = 1024;  // levels of state / records kept on the device
+
+// Grid barrier of the persistent step loop. Blocks arrive on one of
+// kBarGroups counters (each on its own line, so arrivals on different
+// counters do not serialise), the last arrival of a group on `top`, and the
+// last group's arrival publishes the next generation, which every block
+// waits for. Counters only grow during a traversal (the init kernel zeroes
+// them): a group's last arrival is the one that makes its count a multiple
+// of the group's size. `abort` is raised by a block whose wait exceeded the
+// spin limit; every waiting block then leaves.
+constexpr int kBarGroups = 16;
+struct alignas(128) BarCounter {
+  unsigned long long n;
+};
+struct GridBar {
+  BarCounter group[kBarGroups];
+  BarCounter top;
+  alignas(128) uint32_t gen;
+  alignas(128) uint32_t abort;
+  alignas(128) unsigned long long t_end;  // timing: latest block end of the last launch (device clock)
+};
 
 struct Ctrl {
   unsigned long long ticket[2];  // scan tile tickets, one counter per level parity
@@ -78,6 +100,7 @@ struct Ctrl {
   LevelRecord rec[kRing];
   int8_t forced[kRing];          // single source: forced direction of levels 0 .. n_forced-1
   LevelSlot tail;                // after a traversal: out-degree sum of the reached vertices (edges)
+  GridBar bar;                   // single source: the persistent loop's grid barrier
 };
 static_assert(sizeof(Stripe) == 128, "stripe layout");
 static_assert(offsetof(Ctrl, slot) % 128 == 0, "slots start on a line");
@@ -382,6 +405,8 @@ struct HostReport {
   LevelRecord rec[kMaxBatch];
   LevelState steps[kMaxBatch];  // single source: the state each step of the batch published
   int32_t nrec;                 // single source: records in rec (levels rec_first ..)
+  int32_t error;                // persistent loop: 1 when a grid barrier wait gave up
+  unsigned long long t_end;     // persistent loop, timed: device clock when its last block ended
   uint32_t seq;
 };
 // single-source step loop (kernels.hip); a step given report arguments also
@@ -395,6 +420,16 @@ hipError_t launch_step(hipStream_t s, const BfsArgs& a, int32_t step, hipEvent_t
                        hipEvent_t t1 = nullptr, const StepReportArgs* rp = nullptr);
 hipError_t launch_step_report(hipStream_t s, const Ctrl* ctrl, int32_t s_first, int32_t n, int32_t rec_first,
                               HostReport* host, uint32_t seq);
+// The persistent form of the step loop: one launch runs steps s_first .. s_first + n - 1 with a
+// grid barrier between steps (over `blocks` co-resident blocks, each looping over the virtual
+// blocks of one step launch), the report written as the step loop's last step writes it.
+// spin_limit bounds every barrier wait (polls); timing: per-step start times in the published
+// states and the launch's end in ctrl->bar.t_end.
+hipError_t launch_steps(hipStream_t s, const BfsArgs& a, int32_t s_first, int32_t n, int32_t blocks,
+                        uint32_t spin_limit, bool timing, const StepReportArgs& rp, hipEvent_t t0 = nullptr,
+                        hipEvent_t t1 = nullptr);
+// Blocks of the persistent step loop that fit on the current device at once.
+hipError_t persistent_capacity(int32_t* blocks);
 hipError_t launch_report(hipStream_t s, const Ctrl* ctrl, int32_t l_first, int32_t n,
                          HostReport* host, uint32_t seq);
 hipError_t launch_mb_init(hipStream_t s, const BatchArgs& a, int32_t dir0, int64_t nflags,

@@ -48,12 +48,12 @@ struct ExpandShared {
 // makes any winner exact), which both deduplicates and applies the mask
 // not(v). Winners are buffered in LDS and appended to the next frontier list
 // with one atomic per flush.
-__device__ __forceinline__ void expand_body(const ExpandArgs& a, ExpandShared& sh) {
+__device__ __forceinline__ void expand_body(const ExpandArgs& a, ExpandShared& sh, uint32_t bid, uint32_t nblk) {
   const int32_t nf = a.nf;
   const uint32_t m = a.m;
   if (nf <= 0 || m == 0) return;
   const uint32_t nchunks = (m + kExpandChunk - 1) / kExpandChunk;
-  if (blockIdx.x >= nchunks) return;
+  if (bid >= nchunks) return;
   if (threadIdx.x == 0) sh.nbuf = 0;
   unsigned long long won_total = 0, mnew = 0, insub = 0;
   uint32_t maxdeg = 0;
@@ -71,7 +71,7 @@ __device__ __forceinline__ void expand_body(const ExpandArgs& a, ExpandShared& s
     __syncthreads();
   };
 
-  for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+  for (uint32_t c = bid; c < nchunks; c += nblk) {
     const uint32_t e0 = c * kExpandChunk;
     const uint32_t e1 = min(e0 + uint32_t(kExpandChunk), m);
     const int32_t k0 = a.chunk_first[c];
@@ -161,7 +161,7 @@ __device__ __forceinline__ void expand_body(const ExpandArgs& a, ExpandShared& s
   if (threadIdx.x == 0) {
     // every edge of a chunk is read exactly once; the block's chunks sum to its edges
     unsigned long long edges = 0;
-    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x)
+    for (uint32_t c = bid; c < nchunks; c += nblk)
       edges += min(uint32_t(kExpandChunk), m - c * kExpandChunk);
     stripe_add(a.slot, v[0], 0, edges, v[1], v[2]);
     stripe_max(a.slot, maxdeg);
@@ -298,17 +298,17 @@ __device__ __forceinline__ void local_finish(const ExpandArgs& a, LocalShared& s
 // units than blocks, each unit gets a.share blocks (local_share: what its
 // chunks could need, at most gridDim / units), which all scan the unit's
 // degrees and take its chunks in turn; otherwise a block takes whole units.
-__device__ __forceinline__ void local_expand_body(const ExpandArgs& a, LocalShared& sh) {
+__device__ __forceinline__ void local_expand_body(const ExpandArgs& a, LocalShared& sh, int32_t bid, int32_t nblk) {
   const int32_t nf = a.nf;
   const int32_t nunits = (nf + kLocalUnit - 1) / kLocalUnit;
-  const int32_t G = int32_t(gridDim.x);
+  const int32_t G = nblk;
   const int32_t per_unit = max(1, a.share);  // blocks sharing one unit's chunks (at most G / nunits)
   const int32_t nwork = nunits * per_unit;     // (unit, share) pairs
-  if (int32_t(blockIdx.x) >= nwork) return;                // no work: no counters to add
+  if (bid >= nwork) return;                // no work: no counters to add
   const int tid = threadIdx.x;
   if (tid == 0) sh.nbuf = 0;
   LocalAcc acc;
-  for (int32_t wi = blockIdx.x; wi < nwork; wi += G) {
+  for (int32_t wi = bid; wi < nwork; wi += G) {
     const int32_t u = per_unit == 1 ? wi : wi / per_unit, share = per_unit == 1 ? 0 : wi - u * per_unit;
     const int32_t i = u * kLocalUnit + tid;
     const uint32_t total = local_unit_prefix(a, sh, (tid < kLocalUnit && i < nf) ? a.Q[i] : -1);
@@ -326,10 +326,11 @@ __device__ __forceinline__ void local_expand_body(const ExpandArgs& a, LocalShar
 // bitmap-to-list conversion nor the degree scan. Under the edge-count rule
 // the block also adds up the in-degrees of its slice's rows still unvisited
 // when the level started (m_u, which the pulls do not track).
-__device__ __forceinline__ void bitmap_expand_body(const ExpandArgs& a, int32_t nwords, int32_t V, LocalShared& sh) {
-  const int32_t G = int32_t(gridDim.x);
+__device__ __forceinline__ void bitmap_expand_body(const ExpandArgs& a, int32_t nwords, int32_t V, LocalShared& sh,
+                                                   int32_t bid, int32_t nblk) {
+  const int32_t G = nblk;
   const int32_t wpb = (nwords + G - 1) / G;  // words per block; at most kPullTileWords
-  const int32_t w0 = int32_t(blockIdx.x) * wpb;
+  const int32_t w0 = bid * wpb;
   if (w0 >= nwords) return;
   const int32_t w1 = min(w0 + wpb, nwords);
   const int tid = threadIdx.x;
@@ -659,7 +660,12 @@ __global__ __launch_bounds__(kThreads) void k_bfs_init(BfsArgs a, int32_t source
     Ctrl* c = a.ctrl;
     for (int k = threadIdx.x; k < kSlots * kStripes; k += blockDim.x)
       zero_stripe(c->slot[k / kStripes].s[k % kStripes]);
+    if (threadIdx.x < kBarGroups) c->bar.group[threadIdx.x].n = 0;
     if (threadIdx.x == 0) {
+      c->bar.top.n = 0;
+      c->bar.gen = 0;
+      c->bar.abort = 0;
+      c->bar.t_end = 0;
       a.Q[0][0] = source;
       c->ticket[0] = 0;
       c->ticket[1] = 0;
@@ -805,11 +811,14 @@ __device__ __forceinline__ LevelRecord step_record(const Ctrl* c, int32_t s, con
 // written from registers too), then the sequence number with a system-scope
 // release. When the traversal is over this step has no work of its own, so
 // the report lands after every kernel of the traversal has finished.
+// n_steps: steps the report covers (the persistent loop reports the whole launch's range when
+// the traversal ends early, the states past the end being copies of the final one).
 __device__ __forceinline__ void step_report(const Ctrl* c, const StepReportArgs& rp, int32_t s,
                                             const LevelState& st, const LevelState& prev,
-                                            const LevelTotals& tot, bool new_level) {
+                                            const LevelTotals& tot, bool new_level, int32_t error,
+                                            int32_t n_steps = -1) {
   HostReport* host = rp.host;
-  const int32_t n = s - rp.s_first + 1;
+  const int32_t n = n_steps > 0 ? n_steps : s - rp.s_first + 1;
   for (int k = threadIdx.x; k < n - 1; k += blockDim.x) host->steps[k] = c->ring[(rp.s_first + k) % kRing];
   const int32_t upto = st.done ? st.levels : st.level;  // records exist for levels < upto
   const int32_t nrec = max(0, min(upto - rp.rec_first, kMaxBatch));
@@ -821,6 +830,7 @@ __device__ __forceinline__ void step_report(const Ctrl* c, const StepReportArgs&
     host->steps[n - 1] = st;
     host->end = st;
     host->nrec = nrec;
+    host->error = error;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -926,19 +936,13 @@ __device__ __forceinline__ ExpandArgs step_expand_args(const BfsArgs& a, const L
   return e;
 }
 
+// The work of step s (state st) that virtual block bid of nblk does: the step's launch has
+// nblk = main_blocks(nwords) blocks; the persistent loop runs several virtual blocks per block.
+// The scan step's tiles go by ticket, so there every block calls it once (bid = blockIdx.x).
 template <bool EE>
-__global__ __launch_bounds__(kThreads) void k_step(BfsArgs a, int32_t s, StepReportArgs rp) {
-  __shared__ LevelShared sh;
+__device__ __forceinline__ void step_body(const BfsArgs& a, const LevelState& st, int32_t s, LevelShared& sh,
+                                          int32_t bid, int32_t nblk) {
   Ctrl* c = a.ctrl;
-  LevelTotals tot;
-  LevelState prev;
-  bool new_level;
-  const LevelState st = step_state(a, s, &tot, &prev, &new_level);
-  if (blockIdx.x == 0) {
-    publish_step(c, s, st, prev, tot, new_level);
-    if (rp.host) step_report(c, rp, s, st, prev, tot, new_level);
-  }
-  if (st.done) return;
   if (st.phase == kPhaseScan) {
     step_scan(a, st, s);
     return;
@@ -950,18 +954,18 @@ __global__ __launch_bounds__(kThreads) void k_step(BfsArgs a, int32_t s, StepRep
     // registers (one block modified across branches went to scratch memory)
     if (st.phase == kPhaseExpand) {
       const ExpandArgs e = step_expand_args(a, st, s, c->mf[s % kSlots], nullptr, nullptr, nullptr);
-      expand_body(e, sh.e);
+      expand_body(e, sh.e, uint32_t(bid), uint32_t(nblk));
     } else if (st.local == 2) {  // frontier = what the pull before found (written whole, untouched here)
       const ExpandArgs e = step_expand_args(a, st, s, 0u, a.F[L % 2], a.vis[st.vis_idx ^ 1],
                                             a.edge_rule ? slot : nullptr);  // m_u afresh: pulls skip it
-      bitmap_expand_body(e, a.nwords, a.V, sh.l);
+      bitmap_expand_body(e, a.nwords, a.V, sh.l, bid, nblk);
     } else {
       const ExpandArgs e = step_expand_args(a, st, s, 0u, nullptr, nullptr, nullptr);
-      local_expand_body(e, sh.l);
+      local_expand_body(e, sh.l, bid, nblk);
     }
   } else {
     const int32_t tiles = (a.nwords + kPullTileWords - 1) / kPullTileWords;
-    if (int32_t(blockIdx.x) >= tiles) return;
+    if (bid >= tiles) return;
     PullArgs p;
     p.V = a.V;
     p.nwords = a.nwords;
@@ -984,7 +988,124 @@ __global__ __launch_bounds__(kThreads) void k_step(BfsArgs a, int32_t s, StepRep
     p.early_exit = EE;
     p.count_out = 0;
     p.slot = slot;
-    pull_body<EE>(p, int32_t(blockIdx.x), sh.p);
+    pull_body<EE>(p, bid, sh.p);
+  }
+}
+
+template <bool EE>
+__global__ __launch_bounds__(kThreads) void k_step(BfsArgs a, int32_t s, StepReportArgs rp) {
+  __shared__ LevelShared sh;
+  LevelTotals tot;
+  LevelState prev;
+  bool new_level;
+  const LevelState st = step_state(a, s, &tot, &prev, &new_level);
+  if (blockIdx.x == 0) {
+    publish_step(a.ctrl, s, st, prev, tot, new_level);
+    if (rp.host) step_report(a.ctrl, rp, s, st, prev, tot, new_level, 0);
+  }
+  if (st.done) return;
+  step_body<EE>(a, st, s, sh, int32_t(blockIdx.x), int32_t(gridDim.x));
+}
+
+// Waits until every block of the launch has arrived (see GridBar). Agent-scope
+// fences are whole-cache operations (write back / invalidate the XCD's L2), so
+// only thread 0 of a block issues them: every wave first waits for its own
+// memory operations to complete, then thread 0 releases before its block
+// arrives and acquires once after the wait (the polls themselves are relaxed);
+// the block barrier after it orders the other waves' reads behind that.
+// Returns false when the wait gave up (spin limit, or another block gave up).
+__device__ __forceinline__ bool grid_barrier(GridBar* bar, uint32_t target, uint32_t spin_limit) {
+  __shared__ int s_ok;
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's loads and stores are complete
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the block's writes reach memory
+    const uint32_t G = gridDim.x;
+    const uint32_t groups = G < uint32_t(kBarGroups) ? G : uint32_t(kBarGroups);
+    const uint32_t g = blockIdx.x % groups;
+    const uint32_t members = (G - g + groups - 1) / groups;  // blocks b < G with b % groups == g
+    const unsigned long long o = __hip_atomic_fetch_add(&bar->group[g].n, 1ull, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+    if ((o + 1) % members == 0) {
+      const unsigned long long o2 = __hip_atomic_fetch_add(&bar->top.n, 1ull, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+      if ((o2 + 1) % groups == 0) __hip_atomic_store(&bar->gen, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    int ok = 1;
+    uint32_t polls = 0;
+    while (int32_t(__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+      if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        ok = 0;
+        break;
+      }
+      if (++polls > spin_limit) {
+        __hip_atomic_fetch_or(&bar->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    // released, but another block gave up: it will not arrive again
+    if (ok && __hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // drop stale cache lines
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// The persistent step loop: steps s_first .. s_first + n - 1 in one launch of
+// co-resident blocks, a grid barrier between consecutive steps in place of a
+// kernel boundary. Every block derives each step's state as k_step does;
+// block 0 publishes it (with its start time when timing) and, at the launch's
+// last step or when the traversal is over, writes the batch's report. The
+// report says whether a barrier wait gave up; then every block leaves.
+template <bool EE>
+__global__ __launch_bounds__(kThreads) void k_steps(BfsArgs a, int32_t s_first, int32_t n, uint32_t spin_limit,
+                                                    int32_t timing, StepReportArgs rp) {
+  __shared__ LevelShared sh;
+  __shared__ uint32_t s_gen;
+  GridBar* bar = &a.ctrl->bar;
+  if (threadIdx.x == 0)  // no barrier of this traversal is in progress between launches
+    s_gen = __hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const uint32_t gen0 = s_gen;
+  const int32_t nvb = int32_t(main_blocks(a.nwords));
+  for (int32_t k = 0; k < n; ++k) {
+    const int32_t s = s_first + k;
+    LevelTotals tot;
+    LevelState prev;
+    bool new_level;
+    LevelState st = step_state(a, s, &tot, &prev, &new_level);
+    if (blockIdx.x == 0) {
+      if (timing) st.t0 = wall_clock64();
+      publish_step(a.ctrl, s, st, prev, tot, new_level);
+      // over early: the launch's remaining steps read as the final state, as steps enqueued
+      // past the end publish it in the one-launch-per-step loop
+      if (st.done)
+        for (int32_t j = 1 + int32_t(threadIdx.x); j < n - k; j += kThreads) a.ctrl->ring[(s + j) % kRing] = st;
+      if (rp.host && (k == n - 1 || st.done)) {
+        __syncthreads();
+        step_report(a.ctrl, rp, s, st, prev, tot, new_level, 0, n);
+      }
+    }
+    if (st.done) break;
+    for (int32_t vb = int32_t(blockIdx.x); vb < nvb; vb += int32_t(gridDim.x)) {
+      __syncthreads();  // the previous virtual block's LDS readers are done
+      step_body<EE>(a, st, s, sh, st.phase == kPhaseScan ? int32_t(blockIdx.x) : vb, nvb);
+      if (st.phase == kPhaseScan) break;  // tiles by ticket: one call per block
+    }
+    if (k == n - 1) break;  // the kernel boundary ends the last step
+    if (!grid_barrier(bar, gen0 + uint32_t(k) + 1u, spin_limit)) {
+      if (blockIdx.x == 0 && rp.host) step_report(a.ctrl, rp, s, st, prev, tot, new_level, 1);
+      break;
+    }
+  }
+  if (timing) {
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_max(&bar->t_end, (unsigned long long)wall_clock64(), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -1001,6 +1122,8 @@ __global__ void k_step_report(const Ctrl* c, int32_t s_first, int32_t n, int32_t
   if (threadIdx.x == 0) {
     host->end = end;
     host->nrec = nrec;
+    host->error = int32_t(c->bar.abort != 0);
+    host->t_end = c->bar.t_end;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1017,7 +1140,7 @@ __global__ __launch_bounds__(kThreads) void k_expand(ExpandArgs a, const uint32_
   __shared__ ExpandShared sh;
   if (m_dev) a.m = *m_dev;
   if (nf_dev) a.nf = int32_t(*nf_dev);
-  expand_body(a, sh);
+  expand_body(a, sh, blockIdx.x, gridDim.x);
 }
 
 template <bool EE>
@@ -1196,6 +1319,26 @@ hipError_t launch_step(hipStream_t s, const BfsArgs& a, int32_t step, hipEvent_t
   const StepReportArgs r = rp ? *rp : StepReportArgs{nullptr, 0u, 0, 0};
   if (a.early_exit) return launch_k(k_step<true>, g, s, t0, t1, a, step, r);
   return launch_k(k_step<false>, g, s, t0, t1, a, step, r);
+}
+
+hipError_t launch_steps(hipStream_t s, const BfsArgs& a, int32_t s_first, int32_t n, int32_t blocks,
+                        uint32_t spin_limit, bool timing, const StepReportArgs& rp, hipEvent_t t0, hipEvent_t t1) {
+  const dim3 g = dim3(static_cast<unsigned>(blocks));
+  const StepReportArgs r = rp;
+  const int32_t tm = timing ? 1 : 0;
+  if (a.early_exit) return launch_k(k_steps<true>, g, s, t0, t1, a, s_first, n, spin_limit, tm, r);
+  return launch_k(k_steps<false>, g, s, t0, t1, a, s_first, n, spin_limit, tm, r);
+}
+
+hipError_t persistent_capacity(int32_t* blocks) {
+  int dev = 0, cus = 0, per_t = 0, per_f = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_t, k_steps<true>, kThreads, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_f, k_steps<false>, kThreads, 0);
+  if (e != hipSuccess) return e;
+  *blocks = cus * std::min(per_t, per_f);
+  return hipSuccess;
 }
 
 hipError_t launch_step_report(hipStream_t s, const Ctrl* ctrl, int32_t s_first, int32_t n, int32_t rec_first,

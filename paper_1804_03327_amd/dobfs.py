@@ -27,6 +27,7 @@ MODES = {"full": MODE_FULL, "push_only": MODE_PUSH_ONLY, "pull_unmasked": MODE_P
          "pull_only": MODE_PULL_ONLY, "push_sort": MODE_PUSH_SORT}
 HEUR_RATIO, HEUR_EDGES = 0, 1
 OPT_TIME_KERNELS = 1
+OPT_PERSISTENT = 2
 MXV_EARLY_EXIT, MXV_ACCUM_OR = 1, 2
 
 
@@ -226,7 +227,7 @@ def options_default() -> Options:
 
 
 def make_options(mode="full", heuristic=HEUR_RATIO, alpha=0.01, beta=0.01, forced_dirs=None,
-                 time_kernels=False) -> Options:
+                 time_kernels=False, persistent=False) -> Options:
     """An Options struct; forced_dirs (list of DIR_*) is kept alive on the struct."""
     o = options_default()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
@@ -237,7 +238,7 @@ def make_options(mode="full", heuristic=HEUR_RATIO, alpha=0.01, beta=0.01, force
         o._forced = buf
         o.forced_dirs = buf.ctypes.data
         o.n_forced = buf.size
-    o.flags = OPT_TIME_KERNELS if time_kernels else 0
+    o.flags = (OPT_TIME_KERNELS if time_kernels else 0) | (OPT_PERSISTENT if persistent else 0)
     return o
 
 

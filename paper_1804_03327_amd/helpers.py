@@ -45,9 +45,9 @@ class BfsRunner:
         self.stats = dobfs.make_stats(stats_cap)
 
     def run(self, source: int, mode="full", heuristic=dobfs.HEUR_RATIO, alpha=0.01, beta=0.01,
-            forced_dirs=None, time_kernels=False, stream=None, opt=None):
+            forced_dirs=None, time_kernels=False, stream=None, opt=None, persistent=False):
         if opt is None:
-            opt = dobfs.make_options(mode, heuristic, alpha, beta, forced_dirs, time_kernels)
+            opt = dobfs.make_options(mode, heuristic, alpha, beta, forced_dirs, time_kernels, persistent)
         dobfs.bfs(self.g, source, self.depth, self.parent, opt, self.ws, stream=stream,
                   stats=self.stats)
         return self.stats
