@@ -209,6 +209,32 @@ def validate_sources(hg, sources, run):
     return out
 
 
+def loop_costs(g, srcs, heur, alpha, beta, reps, stream):
+    """Mean ms per BFS and us per level of the two forms of the single-source level loop (one
+    launch per step; the persistent kernel with a grid barrier between steps) over `srcs`."""
+    import torch
+    from paper_1804_03327_amd import dobfs
+    from paper_1804_03327_amd.helpers import BfsRunner
+    r = BfsRunner(g, with_parent=True)
+    out = {}
+    for name, pers in (("step_launches", False), ("persistent", True)):
+        opt = dobfs.make_options("full", heur, alpha, beta, persistent=pers)
+        st = dobfs.make_stats(0)
+        levels = 0
+        for s in srcs:
+            dobfs.bfs(g, s, r.depth, r.parent, opt, r.ws, stream=stream, stats=st)
+            levels += st.levels
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            for s in srcs:
+                dobfs.bfs(g, s, r.depth, r.parent, opt, r.ws, stream=stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / reps
+        out[name] = {"ms_per_bfs": round(1e3 * dt / len(srcs), 4), "us_per_level": round(1e6 * dt / levels, 2)}
+    return out
+
+
 def measure_lattice(args, heur, alpha, beta):
     """The high-diameter configuration: a 256^3 7-point lattice with 5% of its undirected edges
     deleted (seed 3), 16 sources (seed 4, degree > 0), in the benchmarked mode and rule. Every
@@ -250,6 +276,7 @@ def measure_lattice(args, heur, alpha, beta):
     torch.cuda.synchronize()
     roof, table, _ = step_roofline(hl.V, heur, list(zip(srcs, stats)), cand, None)
     levels = [st.levels for st in stats]
+    loops = loop_costs(gl, srcs[:4], heur, alpha, beta, 1, stream)
     cpu_src = srcs[:2]
     tc = 0.0
     for s in cpu_src:
@@ -262,8 +289,9 @@ def measure_lattice(args, heur, alpha, beta):
            "gteps_paper_convention": round(hl.nnz * n / dt / 1e9, 3),
            "ms_per_bfs": round(1e3 * dt / n, 4),
            "levels_mean": round(float(np.mean(levels)), 1),
-           "us_per_level": round(1e3 * dt / reps / max(1, sum(levels)), 3),
+           "us_per_level": round(1e6 * dt / reps / max(1, sum(levels)), 3),
            "validated_sources": len(want),
+           "level_loop": dict(loops, sources=4),
            "roofline": roof, "kernels": table,
            "cpu_baseline": {"value": round(sum(edges[s] for s in cpu_src) / tc / 1e9, 5), "unit": "GTEPS",
                             "cores": 1, "kind": "oracle",
@@ -352,11 +380,15 @@ def measure_batched(args, heur, alpha, beta):
 
 def measure_serving(args, hg22, g22, heur, alpha, beta):
     """The query server on four device-resident graphs (RMAT-16, RMAT-20, RMAT-22, a 2048x2048
-    grid): single-source queries with a uniformly drawn graph and source (degree > 0, seed 6)
-    arrive as a Poisson stream at 0.5x, 1x and 2x the sequential capacity. Compared with the same
-    arrival sequence served first-in first-out by plain single-source DOBFS, one query at a
-    time, using each query's own measured service time (host gaps between queries ignored,
-    which favours the baseline). Latency = arrival to depth final in device memory."""
+    grid): single-source queries with a uniformly drawn graph and a source drawn from 64
+    seeded degree > 0 vertices of it (seed 6) arrive as a Poisson stream at 0.5x .. 16x the
+    sequential capacity. A point offers up to --serve-queries queries, fewer when they would
+    take more than --serve-seconds of arrivals. Compared with the same arrival sequence served
+    first-in first-out by plain single-source DOBFS, one query at a time, using each query's
+    own measured service time (host gaps between queries ignored, which favours the baseline).
+    Latency = arrival to depth final in device memory. Depth buffers are recycled once a query
+    is answered; a submission that finds none free waits (counted as buffer stalls)."""
+    import queue
     import threading
     import torch
     import gen
@@ -368,27 +400,41 @@ def measure_serving(args, hg22, g22, heur, alpha, beta):
     gs = [g22 if h is hg22 else upload(h, device=0, hubs_first=not args.stored_order) for _, h in specs]
     opt = dobfs.make_options("full", heur, alpha, beta)
     rng = np.random.default_rng(6)
-    N = args.serve_queries
-    pools = [np.asarray(gen.sample_sources(h, 256, seed=7 + i)) for i, (_, h) in enumerate(specs)]
-    qg = rng.integers(0, len(specs), N)
-    qs = [int(pools[gi][rng.integers(0, 256)]) for gi in qg]
-    # standalone service time of every query (plain single-source DOBFS, depths only: the
-    # output the server gives)
-    runners = [BfsRunner(g, with_parent=False) for g in gs]
-    for gi, r in enumerate(runners):
+    npool = 64
+    pools = [np.asarray(gen.sample_sources(h, npool, seed=7 + i)) for i, (_, h) in enumerate(specs)]
+    # standalone service time of every (graph, source) a query can ask for (plain single-source
+    # DOBFS, depths only: the output the server gives), the median of two runs
+    svc_tab = np.zeros((len(specs), npool))
+    for gi, g in enumerate(gs):
+        r = BfsRunner(g, with_parent=False)
         r.run(int(pools[gi][0]), opt=opt)
-    torch.cuda.synchronize()
-    svc = np.zeros(N)
-    for i in range(N):
-        r = runners[qg[i]]
-        t1 = time.perf_counter()
-        dobfs.bfs(gs[qg[i]], qs[i], r.depth, r.parent, opt, r.ws)  # blocks until final
-        svc[i] = time.perf_counter() - t1
-    cap = 1.0 / float(svc.mean())
-    del runners
+        torch.cuda.synchronize()
+        for j in range(npool):
+            ts = []
+            for _ in range(2):
+                t1 = time.perf_counter()
+                dobfs.bfs(g, int(pools[gi][j]), r.depth, r.parent, opt, r.ws)  # blocks until final
+                ts.append(time.perf_counter() - t1)
+            svc_tab[gi, j] = min(ts)
+        del r
+    cap = 1.0 / float(svc_tab.mean())  # uniform graph and source
+    grid_loops = loop_costs(gs[3], [int(x) for x in pools[3][:2]], heur, alpha, beta, 1, torch.cuda.current_stream())
+    log("grid level loops:", json.dumps(grid_loops))
+    log("serving: sequential capacity %.1f q/s (mean service %s ms)" % (
+        cap, ", ".join("%s %.3f" % (n, 1e3 * svc_tab[i].mean()) for i, (n, _) in enumerate(specs))))
+    nbuf = [512, 512, 384, 384]
+    bufs = [[torch.empty(g.V, dtype=torch.int32, device="cuda") for _ in range(nbuf[gi])] for gi, g in enumerate(gs)]
+    free = [queue.SimpleQueue() for _ in gs]
+    for gi in range(len(gs)):
+        for b in range(nbuf[gi]):
+            free[gi].put(b)
     points = []
-    for mult in (0.5, 1.0, 2.0):
+    for mult in (0.5, 1.0, 2.0, 4.0, 8.0, 16.0):
         lam = mult * cap
+        N = int(min(args.serve_queries, max(64, round(lam * args.serve_seconds))))
+        qg = rng.integers(0, len(specs), N)
+        qj = rng.integers(0, npool, N)
+        svc = svc_tab[qg, qj]
         arrivals = np.cumsum(rng.exponential(1.0 / lam, N))
         # FIFO, one query at a time (Lindley recursion on the measured service times)
         done, fifo_lat = 0.0, np.zeros(N)
@@ -397,49 +443,72 @@ def measure_serving(args, hg22, g22, heur, alpha, beta):
             done = start + svc[i]
             fifo_lat[i] = done - arrivals[i]
         fifo_qps = N / (done - arrivals[0])
-        outs = [torch.empty(gs[gi].V, dtype=torch.int32, device="cuda") for gi in qg]
         srv = dobfs.Server(gs, slots=args.serve_slots, max_batch=64, opt=opt)
         ids = [None] * N
+        bid = [None] * N
         infos = [None] * N
-        submitted = threading.Semaphore(0)
+        todo = queue.SimpleQueue()
+        stalls = [0]
 
         def waiter():
-            for i in range(N):
-                submitted.acquire()
+            while True:
+                i = todo.get()
+                if i is None:
+                    return
                 infos[i] = srv.wait(ids[i])
+                free[int(qg[i])].put(bid[i])
 
-        th = threading.Thread(target=waiter)
-        th.start()
+        nw = 8
+        ths = [threading.Thread(target=waiter) for _ in range(nw)]
+        for th in ths:
+            th.start()
         t_base = time.perf_counter()
         for i in range(N):
             delay = t_base + arrivals[i] - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
-            ids[i] = srv.submit(int(qg[i]), qs[i], outs[i])
-            submitted.release()
-        th.join()
+            gi = int(qg[i])
+            try:
+                b = free[gi].get_nowait()
+            except queue.Empty:
+                stalls[0] += 1
+                b = free[gi].get()
+            bid[i] = b
+            ids[i] = srv.submit(gi, int(pools[gi][qj[i]]), bufs[gi][b])
+            todo.put(i)
+        for _ in ths:
+            todo.put(None)
+        for th in ths:
+            th.join()
         srv.close()
         lat = np.array([x["t_done_ms"] - x["t_submit_ms"] for x in infos])
-        span = (max(x["t_done_ms"] for x in infos) - min(x["t_submit_ms"] for x in infos)) / 1e3
+        t_first = min(x["t_submit_ms"] for x in infos)
+        span = (max(x["t_done_ms"] for x in infos) - t_first) / 1e3
         sizes = np.array([x["batch_size"] for x in infos])
-        points.append({"rate_x_sequential": mult, "offered_qps": round(lam, 1), "served_qps": round(N / span, 1),
+        points.append({"rate_x_sequential": mult, "queries": N, "offered_qps": round(lam, 1),
+                       "served_qps": round(N / span, 1),
                        "p50_ms": round(float(np.percentile(lat, 50)), 2),
                        "p99_ms": round(float(np.percentile(lat, 99)), 2),
-                       "mean_batch": round(float(sizes.mean()), 2),
+                       "p99_ms_by_graph": {name: round(float(np.percentile(lat[qg == gi], 99)), 2)
+                                           for gi, (name, _) in enumerate(specs) if (qg == gi).any()},
+                       "mean_batch": round(float(sizes.mean()), 2), "buffer_stalls": stalls[0],
                        "fifo_plain_dobfs": {"served_qps": round(fifo_qps, 1),
                                             "p50_ms": round(float(np.percentile(fifo_lat, 50)) * 1e3, 2),
                                             "p99_ms": round(float(np.percentile(fifo_lat, 99)) * 1e3, 2)}})
         log("serving %.1fx:" % mult, json.dumps(points[-1]))
-        del outs
+    del bufs
     for g in gs:
         if g is not g22:
             dobfs.graph_destroy(g)
+    peak = max(p["served_qps"] for p in points)
     return {"workload": "4 graphs (rmat16, rmat20, rmat22 ef%d; grid 2048x2048), uniform graph and "
-                        "source, Poisson arrivals (seed 6)" % args.edgefactor,
-            "queries_per_point": N, "slots": args.serve_slots, "max_batch": 64,
+                        "source (64 seeded sources per graph), Poisson arrivals (seed 6)" % args.edgefactor,
+            "queries_per_point": "min(%d, %.0f s of arrivals)" % (args.serve_queries, args.serve_seconds),
+            "slots": args.serve_slots, "max_batch": 64,
             "sequential_capacity_qps": round(cap, 1),
-            "mean_service_ms": {name: round(float(svc[qg == gi].mean()) * 1e3, 3)
-                                for gi, (name, _) in enumerate(specs) if (qg == gi).any()},
+            "peak_served_qps": peak, "peak_served_x_sequential": round(peak / cap, 2),
+            "mean_service_ms": {name: round(1e3 * float(svc_tab[gi].mean()), 3) for gi, (name, _) in enumerate(specs)},
+            "grid2048_level_loop": dict(grid_loops, sources=2),
             "points": points}
 
 
@@ -465,8 +534,10 @@ def main():
                     help="skip the direction-rule autotuner (tuned on 16 other sources, then timed on these)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the query-server measurement (4 graphs, Poisson arrivals)")
-    ap.add_argument("--serve-queries", type=int, default=600)
-    ap.add_argument("--serve-slots", type=int, default=2)
+    ap.add_argument("--serve-queries", type=int, default=10000)
+    ap.add_argument("--serve-seconds", type=float, default=6.0,
+                    help="a serving point offers at most this many seconds of arrivals")
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--no-lattice", action="store_true",
                     help="skip the 256^3 lattice (5%% of edges deleted, 16 sources) measurement")
     ap.add_argument("--lattice-n", type=int, default=256)
@@ -619,6 +690,10 @@ def main():
                           "over a repeat of the timed steps (%.1f ms/step with events)" % (1e3 * t_ev / args.steps))
     log("kernels:", json.dumps(kernel_table))
 
+    # the two forms of the level loop on the same graph (NEXT-2 A/B)
+    level_loop = dict(loop_costs(g, sources[:16], heur, alpha, beta, 2, stream), sources=16)
+    log("level loops:", json.dumps(level_loop))
+
     # the library's own Graph500 edge counts (stats) against the oracle's
     if validated is not None:
         bad = [s for i, s in enumerate(sources) if pool[0][i].edges_g500 != edges_g500[s]]
@@ -751,6 +826,7 @@ def main():
         "roofline": roofline,
         "kernels": kernel_table,
         "cpu_baseline": cpu,
+        "level_loop": level_loop,
         "ablation_gteps": ablation,
         "stored_order_gteps": stored,
         "other_direction_rule": other,

@@ -326,21 +326,25 @@ dobfs_status dobfs_bfs_batch(dobfs_graph g, const int32_t *sources, int32_t k,
  * only, its own smaller workspace). `slots` batches run at the same time,
  * each on a host thread and HIP stream of its own, so queries that arrive
  * while a batch is on the GPU are admitted into the next free slot and run
- * beside it (continuous batching, not a single queue). A batch starts only
- * when the device bytes of its workspace fit, together with the batches
- * already running, in mem_budget (admission by memory); a batch is cut
- * down to the number of sources that fits. Each query's depths are those
- * dobfs_bfs returns for its source (the server runs no other arithmetic).
- * The server owns its workspaces and streams; graphs stay owned by the
- * caller and must outlive the server. Thread-safe: any thread may submit
- * and wait.
+ * beside it (continuous batching, not a single queue). Graphs whose batches
+ * have taken more than 2 ms on average may occupy at most slots - 1 slots at
+ * once, so a deep traversal never holds every slot. Admission by memory: the
+ * server makes one device allocation of mem_budget bytes when it is created
+ * and carves every batch's workspace out of it; a batch starts only when its
+ * workspace fits in what the running batches leave free, and a batch is cut
+ * down to the number of sources whose workspace fits in the whole budget
+ * (queries of a graph for which not even one fits fail with
+ * DOBFS_ERR_OUT_OF_MEMORY). Each query's depths are those dobfs_bfs returns
+ * for its source (the server runs no other arithmetic). The server owns its
+ * memory and streams; graphs stay owned by the caller and must outlive the
+ * server. Thread-safe: any thread may submit and wait.
  */
 typedef struct dobfs_server_s *dobfs_server;
 
 typedef struct {
-  int32_t slots;      /* batches in flight at once, 1..16 (default 2) */
+  int32_t slots;      /* batches in flight at once, 1..16 (default 4) */
   int32_t max_batch;  /* sources per batch, 1..64 (default 64) */
-  size_t mem_budget;  /* device bytes all running batches' workspaces may take together;
+  size_t mem_budget;  /* device bytes the server allocates for all running batches' workspaces;
                          0 = slots x the largest batch workspace (default 0) */
   dobfs_options opt;  /* traversal options of every batch: modes FULL, PUSH_ONLY, PULL_ONLY */
 } dobfs_server_options;
@@ -354,12 +358,12 @@ typedef struct {
   double t_done_ms;     /* depth is final in device memory */
 } dobfs_query_info;
 
-/* Defaults: 2 slots, batches of up to 64, no budget beyond the slots, default BFS options. */
+/* Defaults: 4 slots, batches of up to 64, no budget beyond the slots, default BFS options. */
 dobfs_status dobfs_server_options_default(dobfs_server_options *opt);
 
 /* graphs: host array of n_graphs handles on one device (copied). Allocates
- * one workspace and stream per slot. Errors: INVALID_ARG, OUT_OF_MEMORY,
- * DEVICE, UNSUPPORTED (options). */
+ * the memory pool (mem_budget bytes) and one stream per slot. Errors:
+ * INVALID_ARG, OUT_OF_MEMORY, DEVICE, UNSUPPORTED (options). */
 dobfs_status dobfs_server_create(const dobfs_graph *graphs, int32_t n_graphs,
                                  const dobfs_server_options *opt, dobfs_server *out);
 

@@ -1,17 +1,20 @@
 // Query server of libdobfs (declared in include/dobfs.h): single-source BFS
 // queries are answered by multi-source traversals that run several at a time.
 //
-// Each slot is a host thread with its own HIP stream and workspace. A free
-// slot takes the graph whose oldest queued query has waited longest, takes
-// up to max_batch queued queries of that graph in arrival order, waits until
-// its workspace bytes fit in the memory budget beside the batches already
-// running, and runs them as one multi-source traversal whose depth rows are
-// written straight into the callers' buffers. A batch of one runs the
-// single-source traversal instead (depths only): one kernel per level and a
-// smaller workspace, where the multi-source loop takes two kernels per level,
-// which tells on deep graphs. Queries that arrive while a batch is on the GPU
-// go to the next free slot, so their traversal overlaps the running one on
-// the device.
+// Each slot is a host thread with its own HIP stream. A free slot takes the
+// graph whose oldest queued query has waited longest, takes up to max_batch
+// queued queries of that graph in arrival order, waits until the batch's
+// workspace can be carved out of the server's memory pool (one device
+// allocation of mem_budget bytes: admission by memory), and runs them as one
+// multi-source traversal whose depth rows are written straight into the
+// callers' buffers. A batch of one runs the single-source traversal instead
+// (depths only): one kernel per level and a smaller workspace, where the
+// multi-source loop takes two kernels per level, which tells on deep graphs.
+// Queries that arrive while a batch is on the GPU go to the next free slot,
+// so their traversal overlaps the running one on the device. Graphs whose
+// batches have been taking long (a running mean of their service times above
+// kLongMs) may hold at most slots - 1 slots at once, so one slot stays free for
+// the others' queries instead of queueing them behind deep traversals.
 
 #include "dobfs.h"
 #include "dobfs_internal.h"
@@ -20,6 +23,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -31,6 +35,55 @@ using namespace dobfs;
 namespace {
 
 constexpr int kMaxSlots = 16;
+constexpr double kLongMs = 2.0;  // a graph whose batches take longer than this on average is "long"
+
+// First-fit allocator over one device allocation, in 256-byte units.
+struct Pool {
+  uint8_t* base = nullptr;
+  size_t size = 0;
+  std::map<size_t, size_t> free_at;  // offset -> length of every free range, coalesced
+
+  static size_t round(size_t b) { return (b + 255) & ~size_t(255); }
+  void reset(uint8_t* p, size_t n) {
+    base = p;
+    size = n;
+    free_at.clear();
+    if (n) free_at[0] = n;
+  }
+  bool can_take(size_t need) const {
+    need = round(need);
+    for (const auto& f : free_at)
+      if (f.second >= need) return true;
+    return false;
+  }
+  size_t take(size_t need) {  // SIZE_MAX when no free range is large enough
+    need = round(need);
+    for (auto it = free_at.begin(); it != free_at.end(); ++it) {
+      if (it->second < need) continue;
+      const size_t off = it->first, len = it->second;
+      free_at.erase(it);
+      if (len > need) free_at[off + need] = len - need;
+      return off;
+    }
+    return SIZE_MAX;
+  }
+  void give(size_t off, size_t need) {
+    need = round(need);
+    auto next = free_at.lower_bound(off);
+    if (next != free_at.end() && off + need == next->first) {  // merge with the range after
+      need += next->second;
+      next = free_at.erase(next);
+    }
+    if (next != free_at.begin()) {  // merge with the range before
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += need;
+        return;
+      }
+    }
+    free_at[off] = need;
+  }
+};
 
 struct Query {
   int32_t graph = 0, source = 0;
@@ -44,6 +97,8 @@ struct Query {
 struct GraphInfo {
   int32_t V = 0;
   int64_t nnz = 0;
+  double mean_ms = 0.0;  // running mean of this graph's batch service times (0: none yet)
+  int32_t running = 0;   // slots running a batch of this graph
 };
 
 }  // namespace
@@ -53,7 +108,9 @@ struct dobfs_server_s {
   std::vector<dobfs_graph> graphs;
   std::vector<GraphInfo> info;
   int device = 0;
-  size_t budget = 0, in_use = 0;
+  size_t budget = 0;
+  Pool pool;                       // batches' workspaces are carved out of one allocation
+  int32_t long_running = 0;        // slots running a batch of a long graph
   std::chrono::steady_clock::time_point t0;
 
   std::mutex mu;
@@ -64,8 +121,7 @@ struct dobfs_server_s {
 
   std::vector<std::thread> workers;
   std::vector<hipStream_t> streams;
-  std::vector<void*> ws;
-  size_t ws_bytes = 0;
+  void* pool_mem = nullptr;
 
   double now_ms() const {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -87,14 +143,31 @@ size_t run_bytes(dobfs_graph g, const dobfs_options& opt, int32_t k) {
   return batch_bytes(g, k);
 }
 
+bool is_long(const GraphInfo& g) { return g.mean_ms > kLongMs; }
+
+// The graph a free slot serves next: that of the oldest queued query, skipping
+// long graphs while slots - 1 slots already run long batches; -1 if none may go.
+int32_t pick_graph(dobfs_server s) {
+  const bool long_full = s->opt.slots > 1 && s->long_running >= s->opt.slots - 1;
+  for (uint64_t id : s->pending) {
+    const int32_t gi = s->queries[id].graph;
+    if (!long_full || !is_long(s->info[size_t(gi)])) return gi;
+  }
+  return -1;
+}
+
 void worker(dobfs_server s, int slot) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
-    s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty(); });
-    if (s->pending.empty()) break;  // stopping and nothing left
-    // the graph whose oldest query has waited longest, and up to max_batch of its queries
-    const int32_t gi = s->queries[s->pending.front()].graph;
+    int32_t gi = -1;
+    s->cv_work.wait(lk, [&] {
+      if (s->stop && s->pending.empty()) return true;
+      gi = pick_graph(s);
+      return gi >= 0;
+    });
+    if (gi < 0) break;  // stopping and nothing left
+    // up to max_batch of the graph's queries, in arrival order
     std::vector<uint64_t> take;
     for (auto it = s->pending.begin(); it != s->pending.end() && int32_t(take.size()) < s->opt.max_batch;) {
       if (s->queries[*it].graph == gi) {
@@ -104,7 +177,7 @@ void worker(dobfs_server s, int slot) {
         ++it;
       }
     }
-    // admission by memory: the batch's workspace must fit beside the running ones
+    // admission by memory: the batch's workspace must fit in the pool
     int32_t k = int32_t(take.size());
     while (k > 1 && run_bytes(s->graphs[gi], s->opt.opt, k) > s->budget) --k;
     for (size_t q = take.size(); q > size_t(k); --q) s->pending.push_front(take[q - 1]);  // back to the head, in order
@@ -122,8 +195,12 @@ void worker(dobfs_server s, int slot) {
       s->cv_done.notify_all();
       continue;
     }
-    s->cv_mem.wait(lk, [&] { return s->in_use + need <= s->budget; });
-    s->in_use += need;
+    GraphInfo& info = s->info[size_t(gi)];
+    const bool lng = is_long(info);
+    ++info.running;
+    if (lng) ++s->long_running;
+    s->cv_mem.wait(lk, [&] { return s->pool.can_take(need); });
+    const size_t off = s->pool.take(need);
     std::vector<int32_t> src(static_cast<size_t>(k));
     DepthRows rows{};
     const double t_start = s->now_ms();
@@ -134,15 +211,22 @@ void worker(dobfs_server s, int slot) {
       q.t_start = t_start;
     }
     lk.unlock();
+    void* ws = s->pool.base + off;
     // both calls return once the depth rows are final
     const dobfs_status st =
-        k == 1 ? dobfs_bfs(s->graphs[gi], src[0], &s->opt.opt, rows.row[0], nullptr, s->ws[size_t(slot)],
-                           s->ws_bytes, s->streams[size_t(slot)], nullptr)
-               : bfs_batch_rows(s->graphs[gi], src.data(), k, &s->opt.opt, rows, s->ws[size_t(slot)],
-                                s->ws_bytes, s->streams[size_t(slot)], nullptr);
+        k == 1 ? dobfs_bfs(s->graphs[gi], src[0], &s->opt.opt, rows.row[0], nullptr, ws, need,
+                           s->streams[size_t(slot)], nullptr)
+               : bfs_batch_rows(s->graphs[gi], src.data(), k, &s->opt.opt, rows, ws, need,
+                                s->streams[size_t(slot)], nullptr);
+    // a later batch may reuse this memory from another stream: the traversal's last kernels
+    // may still read their control block after the results are final
+    (void)hipStreamSynchronize(s->streams[size_t(slot)]);
     lk.lock();
-    s->in_use -= need;
+    s->pool.give(off, need);
     const double t_done = s->now_ms();
+    info.mean_ms = info.mean_ms == 0.0 ? (t_done - t_start) : 0.75 * info.mean_ms + 0.25 * (t_done - t_start);
+    --info.running;
+    if (lng) --s->long_running;
     for (uint64_t id : take) {
       Query& q = s->queries[id];
       q.status = st;
@@ -152,7 +236,7 @@ void worker(dobfs_server s, int slot) {
     }
     s->cv_mem.notify_all();
     s->cv_done.notify_all();
-    if (!s->pending.empty()) s->cv_work.notify_one();
+    s->cv_work.notify_all();  // a long slot freed, or queries left
   }
 }
 
@@ -167,8 +251,7 @@ void release(dobfs_server s) {
   (void)hipSetDevice(s->device);
   for (hipStream_t st : s->streams)
     if (st) (void)hipStreamDestroy(st);
-  for (void* p : s->ws)
-    if (p) (void)hipFree(p);
+  if (s->pool_mem) (void)hipFree(s->pool_mem);
   delete s;
 }
 
@@ -179,7 +262,7 @@ extern "C" {
 dobfs_status dobfs_server_options_default(dobfs_server_options* o) {
   if (!o) return set_error(DOBFS_ERR_INVALID_ARG, "options pointer is NULL");
   *o = dobfs_server_options{};
-  o->slots = 2;
+  o->slots = 4;
   o->max_batch = 64;
   o->mem_budget = 0;
   return dobfs_options_default(&o->opt);
@@ -223,8 +306,7 @@ dobfs_status dobfs_server_create(const dobfs_graph* graphs, int32_t n_graphs, co
     s->info.push_back(gi);
     largest = std::max(largest, std::max(run_bytes(graphs[i], o.opt, 1), run_bytes(graphs[i], o.opt, o.max_batch)));
   }
-  s->ws_bytes = largest;
-  s->budget = o.mem_budget ? o.mem_budget : largest * size_t(o.slots);
+  s->budget = o.mem_budget ? o.mem_budget : Pool::round(largest) * size_t(o.slots);
   int prev = -1;
   (void)hipGetDevice(&prev);
   if (hipSetDevice(s->device) != hipSuccess) {
@@ -233,20 +315,20 @@ dobfs_status dobfs_server_create(const dobfs_graph* graphs, int32_t n_graphs, co
   }
   for (int k = 0; k < o.slots; ++k) {
     hipStream_t stream = nullptr;
-    void* p = nullptr;
     if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) {
       release(s);
       if (prev >= 0) (void)hipSetDevice(prev);
       return set_error(DOBFS_ERR_DEVICE, "hipStreamCreateWithFlags failed");
     }
     s->streams.push_back(stream);
-    if (hipMalloc(&p, largest) != hipSuccess) {
-      release(s);
-      if (prev >= 0) (void)hipSetDevice(prev);
-      return set_error(DOBFS_ERR_OUT_OF_MEMORY, "server workspace allocation failed");
-    }
-    s->ws.push_back(p);
   }
+  if (hipMalloc(&s->pool_mem, s->budget) != hipSuccess) {
+    s->pool_mem = nullptr;
+    release(s);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return set_error(DOBFS_ERR_OUT_OF_MEMORY, "server memory pool allocation failed");
+  }
+  s->pool.reset(static_cast<uint8_t*>(s->pool_mem), s->budget);
   if (prev >= 0) (void)hipSetDevice(prev);
   for (int k = 0; k < o.slots; ++k) s->workers.emplace_back(worker, s, k);
   *out = s;

@@ -338,7 +338,7 @@ class Server:
     or on garbage collection. Keeps the graphs and every submitted depth buffer alive until the
     server is gone."""
 
-    def __init__(self, graphs, slots=2, max_batch=64, mem_budget=0, opt=None):
+    def __init__(self, graphs, slots=4, max_batch=64, mem_budget=0, opt=None):
         lib = load()
         so = ServerOptions()
         _check(lib.dobfs_server_options_default(ctypes.byref(so)))

@@ -103,6 +103,16 @@ def test_server_memory_budget(graphs):
     # room for one 8-source batch: batches are cut to 8, and the batches in flight at any time
     # never hold more workspace than the budget (a lone query's smaller one may run beside
     # another)
+    # the device memory a server holds is its pool of the budget's size, whatever the slots and
+    # batch widths would want (up to HIP's allocation granularity and its streams' own memory)
+    slack = 16 << 20
+    for budget in (need8, 256 << 20):
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        probe = dobfs.Server([g], slots=3, max_batch=64, mem_budget=budget)
+        used = free0 - torch.cuda.mem_get_info()[0]
+        probe.close()
+        assert budget - slack <= used <= budget + slack, "server holds %d bytes for a budget of %d" % (used, budget)
     srv = dobfs.Server([g], slots=3, max_batch=64, mem_budget=need8)
     qs = []
     for n in range(120):
@@ -163,3 +173,35 @@ def test_server_errors(graphs):
     with pytest.raises(dobfs.DobfsError) as e:
         dobfs.Server([g], opt=dobfs.make_options("pull_masked"))
     assert e.value.status == dobfs.ERR_UNSUPPORTED
+
+
+def test_long_graph_keeps_a_slot_free(graphs):
+    """With two slots, batches of a graph whose traversals take more than 2 ms (a 400 x 400
+    grid, about 800 levels) never hold both slots once that is known: the other graph's
+    queries find a free slot."""
+    hg_long = gen.grid2d(400, 400)
+    g_long = upload(hg_long)
+    hg, g = graphs[1]
+    srv = dobfs.Server([g_long, g], slots=2, max_batch=1)
+    d0 = torch.full((g_long.V,), -7, dtype=torch.int32, device="cuda")
+    first = srv.wait(srv.submit(0, 0, d0))  # its service time is now known
+    assert first["t_done_ms"] - first["t_start_ms"] > 2.0
+    qs = []
+    for n in range(8):
+        s = int(gen.sample_sources(hg_long, 1, seed=3000 + n)[0])
+        depth = torch.full((g_long.V,), -7, dtype=torch.int32, device="cuda")
+        qs.append((0, s, depth, srv.submit(0, s, depth)))
+        for m in range(5):
+            s = int(gen.sample_sources(hg, 1, seed=4000 + 5 * n + m)[0])
+            depth = torch.full((g.V,), -7, dtype=torch.int32, device="cuda")
+            qs.append((1, s, depth, srv.submit(1, s, depth)))
+    infos = [srv.wait(q[3]) for q in qs]
+    srv.close()
+    spans = sorted((i["t_start_ms"], i["t_done_ms"]) for i in infos if i["graph"] == 0)
+    for a, b in zip(spans, spans[1:]):
+        assert b[0] >= a[1], "two long batches ran at once: %s and %s" % (a, b)
+    for (gi, s, depth, _), info in zip(qs, infos):
+        assert info["status"] == dobfs.OK
+        gg = g_long if gi == 0 else g
+        assert np.array_equal(depth.cpu().numpy(), _alone(gg, s))
+    dobfs.graph_destroy(g_long)
