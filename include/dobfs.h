@@ -152,6 +152,17 @@ typedef struct {
   const int8_t *forced_dirs; /* host, optional: direction of levels 0 .. n_forced-1 */
   int32_t n_forced;          /* levels past n_forced follow the mode and heuristic */
   uint32_t flags;            /* DOBFS_OPT_* */
+  /* Schedule settings of the single-source kernels (results do not depend on them; 0 keeps
+     the default; out-of-range values -> INVALID_ARG). The autotuner chooses them per graph. */
+  int32_t pull_mid;          /* pull: in-neighbours a thread scans before a wave of 64 lanes takes
+                                the row over, 4 .. 2^20 (default 32) */
+  int32_t bitmap_rows;       /* push after a pull runs block-local over the pull's bits when no
+                                4096-row tile found more rows than this, 0 .. 4096 (default 512) */
+  int32_t local_unit;        /* block-local push: frontier vertices a block takes at once,
+                                1 .. 256 (default 128) */
+  int32_t local_chunks;      /* block-local push: most 1024-edge chunks of a unit one block may
+                                get before the push needs the global degree scan, 1 .. 2^20
+                                (default 4) */
 } dobfs_options;
 
 /* Fill *opt with the defaults (FULL, RATIO, alpha = beta = 0.01). */

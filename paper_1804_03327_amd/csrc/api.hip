@@ -300,6 +300,14 @@ dobfs_status check_options(const dobfs_options& o) {
                   int(o.forced_dirs[k]));
   if (o.flags & ~uint32_t(DOBFS_OPT_TIME_KERNELS | DOBFS_OPT_PERSISTENT))
     return fail(DOBFS_ERR_INVALID_ARG, "unknown option flags 0x%x", o.flags);
+  if (o.pull_mid != 0 && (o.pull_mid < kPullFirst || o.pull_mid > (1 << 20)))
+    return fail(DOBFS_ERR_INVALID_ARG, "pull_mid = %d not in [%d, 2^20]", o.pull_mid, kPullFirst);
+  if (o.bitmap_rows < 0 || o.bitmap_rows > kPullTileV)
+    return fail(DOBFS_ERR_INVALID_ARG, "bitmap_rows = %d not in [0, %d]", o.bitmap_rows, kPullTileV);
+  if (o.local_unit < 0 || o.local_unit > kThreads)
+    return fail(DOBFS_ERR_INVALID_ARG, "local_unit = %d not in [0, %d]", o.local_unit, kThreads);
+  if (o.local_chunks < 0 || o.local_chunks > (1 << 20))
+    return fail(DOBFS_ERR_INVALID_ARG, "local_chunks = %d not in [0, 2^20]", o.local_chunks);
   return DOBFS_OK;
 }
 
@@ -482,6 +490,11 @@ BfsArgs bfs_args(dobfs_graph g, uint8_t* ws, const Layout& L, const dobfs_option
   a.edge_rule = opt.heuristic == DOBFS_HEUR_EDGES ? 1 : 0;
   a.local_push = a.need_F ? 0 : 1;  // (the frontier bitmap a push writes is cleared by its scan step)
   a.low_degree = g->max_outdeg <= uint32_t(kLocalDeg) ? 1 : 0;
+  a.sched = default_sched();
+  if (opt.pull_mid) a.sched.pull_mid = opt.pull_mid;
+  if (opt.bitmap_rows) a.sched.bitmap_rows = opt.bitmap_rows;
+  if (opt.local_unit) a.sched.local_unit = opt.local_unit;
+  if (opt.local_chunks) a.sched.local_chunks = opt.local_chunks;
   return a;
 }
 
@@ -1340,6 +1353,7 @@ dobfs_status dobfs_mxv(dobfs_graph g, const uint32_t* x_bits, const int32_t* x_i
     pa.out = y_bits;
     pa.parent = y_witness;
     pa.early_exit = (flags_in & DOBFS_MXV_EARLY_EXIT) ? 1 : 0;
+    pa.mid = kPullMid;
     pa.count_out = 1;
     pa.slot = &ctrl->slot[0];
     HIPCK(launch_pull(s, pa));

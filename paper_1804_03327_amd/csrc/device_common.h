@@ -496,7 +496,7 @@ __device__ LevelState next_state(const Args& a, int32_t L, int32_t forced, const
       st.active = batch ? uniform64(wave_or64(x.v4)) : 0ull;
       // a push needs no global scan when its frontier's edges can be shared out inside
       // blocks: a list from a push whose sizes local_fits() accepts (local 1), or the bits a
-      // pull left when no tile found more than kBitmapLocalRows rows and none of high
+      // pull left when no tile found more than sched.bitmap_rows rows and none of high
       // out-degree (local 2: every block expands its own slice of the bitmap)
       st.local = 0;
       st.share = 1;
@@ -508,13 +508,13 @@ __device__ LevelState next_state(const Args& a, int32_t L, int32_t forced, const
           const int64_t mf_b = tracked ? int64_t(t.mnew) : INT64_MAX;
           const int64_t md_b = tracked ? int64_t(__builtin_amdgcn_readfirstlane(wave_max32(x.v5))) : int64_t(kLocalDeg);
           const int64_t G = main_blocks(a.nwords);
-          if (a.low_degree || local_fits(n_new, mf_b, md_b, G)) {
+          if (a.low_degree || local_fits(n_new, mf_b, md_b, G, a.sched.local_unit, a.sched.local_chunks)) {
             st.local = 1;
-            st.share = local_share(n_new, mf_b, md_b, G);
+            st.share = local_share(n_new, mf_b, md_b, G, a.sched.local_unit);
           }
         } else {
           const uint32_t tm = __builtin_amdgcn_readfirstlane(wave_max32(x.v7));
-          st.local = tm <= uint32_t(kBitmapLocalRows) ? 2 : 0;
+          st.local = tm <= uint32_t(a.sched.bitmap_rows) ? 2 : 0;
         }
       }
       st.phase = (next == 0 && !st.local) ? kPhaseScan : kPhaseWhole;

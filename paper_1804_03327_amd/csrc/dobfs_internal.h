@@ -159,32 +159,45 @@ __host__ __device__ inline int64_t main_blocks(int64_t nwords) {
   const int64_t t = pull_tiles(nwords);
   return t > kExpandBlocks ? t : kExpandBlocks;
 }
+// Schedule settings of the single-source kernels a caller may tune (the tuning fields of
+// dobfs_options; 0 there selects the defaults above).
+struct Sched {
+  int32_t pull_mid;      // pull: in-neighbours a thread scans before a wave takes the row (kPullMid)
+  int32_t bitmap_rows;   // bitmap push: most rows one pull tile may have found (kBitmapLocalRows)
+  int32_t local_unit;    // local push: frontier vertices a block takes at once, 1..kThreads (kLocalUnit)
+  int32_t local_chunks;  // local push: most edge chunks of a unit one block may get (kLocalChunks)
+};
+inline Sched default_sched() { return Sched{kPullMid, kBitmapLocalRows, kLocalUnit, kLocalChunks}; }
+
 // Whether a push over a frontier list of nf vertices with m_f out-edges in all, none above
 // maxdeg, can balance its load inside blocks (no global degree scan): the list is cut into
-// units of kLocalUnit vertices, a unit holds at most min(m_f, kLocalUnit * maxdeg) edges, and
+// units of `unit` vertices, a unit holds at most min(m_f, unit * maxdeg) edges, and
 // when there are fewer units than blocks each unit's edge chunks are shared by
-// blocks / units blocks. Local when no block gets more than kLocalChunks chunks of a unit.
-// (Every thread of a level's first kernel evaluates this: 32-bit arithmetic, one division.)
-__host__ __device__ inline uint32_t local_unit_chunks_bound(int64_t m_f, int64_t maxdeg) {
-  const int64_t cap = int64_t(kLocalUnit) * maxdeg;
+// blocks / units blocks. Local when no block gets more than `chunks` chunks of a unit.
+// (Every thread of a level's first kernel evaluates this: 32-bit arithmetic, two divisions.)
+__host__ __device__ inline uint32_t local_unit_chunks_bound(int64_t m_f, int64_t maxdeg, int32_t unit) {
+  const int64_t cap = int64_t(unit) * maxdeg;
   const int64_t edges = m_f < cap ? m_f : cap;
   const int64_t chunks = (edges + kExpandChunk - 1) >> 10;  // kExpandChunk = 1024
   return chunks > 0xffffffffll ? 0xffffffffu : uint32_t(chunks);
 }
-__host__ __device__ inline uint32_t local_units(int64_t nf) { return uint32_t((nf + kLocalUnit - 1) >> 7); }
-__host__ __device__ inline bool local_fits(int64_t nf, int64_t m_f, int64_t maxdeg, int64_t blocks) {
-  static_assert(kExpandChunk == 1024 && kLocalUnit == 128, "shifts below");
-  const uint32_t units = local_units(nf);
+__host__ __device__ inline uint32_t local_units(int64_t nf, int32_t unit) {
+  return uint32_t((uint64_t(nf) + uint32_t(unit) - 1) / uint32_t(unit));
+}
+__host__ __device__ inline bool local_fits(int64_t nf, int64_t m_f, int64_t maxdeg, int64_t blocks, int32_t unit,
+                                           int32_t max_chunks) {
+  static_assert(kExpandChunk == 1024, "shift below");
+  const uint32_t units = local_units(nf, unit);
   if (units == 0) return true;
   const uint32_t per_unit = units < uint32_t(blocks) ? uint32_t(blocks) / units : 1u;
-  return uint64_t(local_unit_chunks_bound(m_f, maxdeg)) <= uint64_t(kLocalChunks) * per_unit;
+  return uint64_t(local_unit_chunks_bound(m_f, maxdeg, unit)) <= uint64_t(max_chunks) * per_unit;
 }
 // Blocks that share each unit's chunks in a local push: as many as the unit's
 // chunks could need, at most blocks / units (so idle blocks exit at once).
-__host__ __device__ inline int32_t local_share(int64_t nf, int64_t m_f, int64_t maxdeg, int64_t blocks) {
-  const uint32_t units = local_units(nf);
+__host__ __device__ inline int32_t local_share(int64_t nf, int64_t m_f, int64_t maxdeg, int64_t blocks, int32_t unit) {
+  const uint32_t units = local_units(nf, unit);
   if (units == 0 || units >= uint32_t(blocks)) return 1;
-  const uint32_t chunks = local_unit_chunks_bound(m_f, maxdeg);
+  const uint32_t chunks = local_unit_chunks_bound(m_f, maxdeg, unit);
   const uint32_t most = uint32_t(blocks) / units;
   return int32_t(chunks < 1u ? 1u : (chunks < most ? chunks : most));
 }
@@ -217,6 +230,7 @@ struct PullArgs {
   int32_t* parent;           // nullable: parent (BFS) or witness (mxv)
   int32_t level;
   int32_t early_exit;
+  int32_t mid;               // in-neighbours a thread scans before a wave takes the row
   int32_t count_out;         // 1: add popcount(out) to the stripes' aux (mxv)
   const uint32_t* heavy;     // nullable: rows of out-degree above kLocalDeg (tilemax bookkeeping)
   LevelSlot* slot;
@@ -245,6 +259,7 @@ struct ExpandArgs {
   // bitmap push (a frontier the previous pull left as bits): the frontier bits, the visited
   // set before that pull, rows with in-edges, and where the recount of m_u goes (nullable)
   int32_t share;             // local list push: blocks per unit (LevelState::share)
+  int32_t unit;              // local push: frontier vertices a block takes at once
   const uint32_t* front;
   const uint32_t* vis_before;
   const uint32_t* nz;
@@ -287,6 +302,7 @@ struct BfsArgs {
   int32_t local_push;        // push levels of small out-degree may skip the global scan
   int32_t low_degree;        // every out-degree of the graph is <= kLocalDeg
   int32_t n_forced;          // levels whose direction Ctrl::forced fixes
+  Sched sched;
 };
 
 // ---- multi-source BFS: up to 64 sources, one bit of a uint64 per source ----
@@ -322,6 +338,7 @@ struct BatchArgs {
   int32_t edge_rule;
   int32_t local_push;        // always 0: the multi-source push always scans
   int32_t low_degree;        // unused here
+  Sched sched;               // unused here (no local push)
   int32_t src[kMaxSources];  // source of bit b
   int32_t uniq[kMaxSources]; // the distinct sources: the first frontier list
 };

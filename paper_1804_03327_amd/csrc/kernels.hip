@@ -169,7 +169,7 @@ __device__ __forceinline__ void expand_body(const ExpandArgs& a, ExpandShared& s
 }
 
 // Pushes that need no global degree scan: the load balancing of the
-// column-based matvec is done inside each block. A block takes kLocalUnit
+// column-based matvec is done inside each block. A block takes a.unit
 // frontier vertices at a time (a unit), scans their degrees in LDS and walks
 // the unit's edges kExpandChunk at a time, each edge finding its vertex by a
 // search over the unit's prefix; the claim and the winners' bookkeeping are
@@ -300,7 +300,8 @@ __device__ __forceinline__ void local_finish(const ExpandArgs& a, LocalShared& s
 // degrees and take its chunks in turn; otherwise a block takes whole units.
 __device__ __forceinline__ void local_expand_body(const ExpandArgs& a, LocalShared& sh, int32_t bid, int32_t nblk) {
   const int32_t nf = a.nf;
-  const int32_t nunits = (nf + kLocalUnit - 1) / kLocalUnit;
+  const int32_t unit = a.unit;
+  const int32_t nunits = (nf + unit - 1) / unit;
   const int32_t G = nblk;
   const int32_t per_unit = max(1, a.share);  // blocks sharing one unit's chunks (at most G / nunits)
   const int32_t nwork = nunits * per_unit;     // (unit, share) pairs
@@ -310,17 +311,17 @@ __device__ __forceinline__ void local_expand_body(const ExpandArgs& a, LocalShar
   LocalAcc acc;
   for (int32_t wi = bid; wi < nwork; wi += G) {
     const int32_t u = per_unit == 1 ? wi : wi / per_unit, share = per_unit == 1 ? 0 : wi - u * per_unit;
-    const int32_t i = u * kLocalUnit + tid;
-    const uint32_t total = local_unit_prefix(a, sh, (tid < kLocalUnit && i < nf) ? a.Q[i] : -1);
+    const int32_t i = u * unit + tid;
+    const uint32_t total = local_unit_prefix(a, sh, (tid < unit && i < nf) ? a.Q[i] : -1);
     acc.edges += (tid == 0 && share == 0) ? total : 0;  // each unit's edges counted once
-    local_unit_chunks(a, sh, min(kLocalUnit, nf - u * kLocalUnit), total, uint32_t(share) * kExpandChunk,
+    local_unit_chunks(a, sh, min(unit, nf - u * unit), total, uint32_t(share) * kExpandChunk,
                       uint32_t(per_unit) * kExpandChunk, acc);
   }
   local_finish(a, sh, acc, 0);
 }
 
 // Push over the frontier a pull left as bits (a.front), when no pull tile
-// found more than kBitmapLocalRows rows and none of high out-degree: block b
+// found more than sched.bitmap_rows rows and none of high out-degree: block b
 // lists the frontier rows of its own slice of the bitmap (at most one pull
 // tile) in LDS and expands them unit by unit, so the level needs neither the
 // bitmap-to-list conversion nor the degree scan. Under the edge-count rule
@@ -357,13 +358,14 @@ __device__ __forceinline__ void bitmap_expand_body(const ExpandArgs& a, int32_t 
     }
   }
   LocalAcc acc;
-  for (uint32_t u0 = 0; u0 < nfront; u0 += kLocalUnit) {
+  const uint32_t unit = uint32_t(a.unit);
+  for (uint32_t u0 = 0; u0 < nfront; u0 += unit) {
     __syncthreads();  // the list is written (first unit) / the previous unit's chunks are done
     const uint32_t i = u0 + uint32_t(tid);
-    const int32_t v = (tid < kLocalUnit && i < nfront) ? w0 * 32 + int32_t(sh.list[i]) : -1;
+    const int32_t v = (uint32_t(tid) < unit && i < nfront) ? w0 * 32 + int32_t(sh.list[i]) : -1;
     const uint32_t total = local_unit_prefix(a, sh, v);
     acc.edges += tid == 0 ? total : 0;
-    local_unit_chunks(a, sh, int32_t(min(uint32_t(kLocalUnit), nfront - u0)), total, 0, kExpandChunk, acc);
+    local_unit_chunks(a, sh, int32_t(min(unit, nfront - u0)), total, 0, kExpandChunk, acc);
   }
   local_finish(a, sh, acc, mu);
 }
@@ -385,7 +387,7 @@ struct PullShared {
 // head array (kPullHeadBatch rows per thread at once); the slab (in-neighbours
 // 1..3, one 16-byte read) of the rows still open, kPullBatch per thread; then
 // rows still open, one per thread, kPullStep positions per load round, up to
-// kPullMid; then what is left, one row per wave, 64 in-neighbours per step
+// a.mid; then what is left, one row per wave, 64 in-neighbours per step
 // with the lowest hitting lane kept. Every phase scans positions in
 // order and keeps the first hit, so the reported parent is always the first
 // in stored order. Results gather in LDS and the tile's words of the output
@@ -524,7 +526,7 @@ __device__ __forceinline__ void pull_body(const PullArgs& a, int32_t tile, PullS
     const int32_t off = sh.cand[ent & 0x7fff];
     const int32_t i = v0 + off;
     const int32_t beg0 = a.colptr[i], end = a.colptr[i + 1];
-    const int32_t lim = min(end, beg0 + kPullMid);
+    const int32_t lim = end - beg0 > a.mid ? beg0 + a.mid : end;  // (no overflow near 2^31 entries)
     int32_t hit = -1;
     unsigned long long n = 0;
     for (int32_t p = beg0 + kPullFirst; p < lim && (!EE || hit < 0); p += kPullStep) {
@@ -555,7 +557,7 @@ __device__ __forceinline__ void pull_body(const PullArgs& a, int32_t tile, PullS
     const int32_t off = sh.cand[ent & 0x7fff];
     const int32_t i = v0 + off;
     const int32_t beg0 = a.colptr[i], end = a.colptr[i + 1];
-    const int32_t beg = beg0 + kPullMid;
+    const int32_t beg = beg0 + a.mid;
     int32_t hit = -1;
     unsigned long long n = 0;
     for (int32_t p = beg; p < end; p += 64) {
@@ -688,8 +690,9 @@ __global__ __launch_bounds__(kThreads) void k_bfs_init(BfsArgs a, int32_t source
       st.m_u = a.nnz - c->src_indeg;
       st.active = 0;
       st.local = (a.local_push && dir0 == 0 &&
-                  local_fits(1, c->src_outdeg, c->src_outdeg, main_blocks(a.nwords))) ? 1 : 0;
-      st.share = local_share(1, c->src_outdeg, c->src_outdeg, main_blocks(a.nwords));
+                  local_fits(1, c->src_outdeg, c->src_outdeg, main_blocks(a.nwords), a.sched.local_unit,
+                             a.sched.local_chunks)) ? 1 : 0;
+      st.share = local_share(1, c->src_outdeg, c->src_outdeg, main_blocks(a.nwords), a.sched.local_unit);
       st.phase = (dir0 == 0 && !st.local) ? kPhaseScan : kPhaseWhole;
       c->ring[0] = st;
     }
@@ -929,6 +932,7 @@ __device__ __forceinline__ ExpandArgs step_expand_args(const BfsArgs& a, const L
   e.in_colptr = a.edge_rule ? a.colptr : nullptr;
   e.slot = &c->slot[s % kSlots];
   e.share = st.share;
+  e.unit = a.sched.local_unit;
   e.front = front;
   e.vis_before = vis_before;
   e.nz = a.nz_in;
@@ -986,6 +990,7 @@ __device__ __forceinline__ void step_body(const BfsArgs& a, const LevelState& st
     p.parent = a.parent;
     p.level = L;
     p.early_exit = EE;
+    p.mid = a.sched.pull_mid;
     p.count_out = 0;
     p.slot = slot;
     pull_body<EE>(p, bid, sh.p);

@@ -35,7 +35,8 @@ class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("heuristic", ctypes.c_int32),
                 ("alpha", ctypes.c_float), ("beta", ctypes.c_float),
                 ("forced_dirs", ctypes.c_void_p), ("n_forced", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("pull_mid", ctypes.c_int32), ("bitmap_rows", ctypes.c_int32),
+                ("local_unit", ctypes.c_int32), ("local_chunks", ctypes.c_int32)]
 
 
 class LevelStats(ctypes.Structure):
@@ -226,9 +227,13 @@ def options_default() -> Options:
     return o
 
 
+SCHED_FIELDS = ("pull_mid", "bitmap_rows", "local_unit", "local_chunks")
+
+
 def make_options(mode="full", heuristic=HEUR_RATIO, alpha=0.01, beta=0.01, forced_dirs=None,
-                 time_kernels=False, persistent=False) -> Options:
-    """An Options struct; forced_dirs (list of DIR_*) is kept alive on the struct."""
+                 time_kernels=False, persistent=False, sched=None) -> Options:
+    """An Options struct; forced_dirs (list of DIR_*) is kept alive on the struct; sched: a dict
+    of schedule settings (SCHED_FIELDS; missing or 0 = the library's default)."""
     o = options_default()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.heuristic = int(heuristic)
@@ -239,6 +244,10 @@ def make_options(mode="full", heuristic=HEUR_RATIO, alpha=0.01, beta=0.01, force
         o.forced_dirs = buf.ctypes.data
         o.n_forced = buf.size
     o.flags = (OPT_TIME_KERNELS if time_kernels else 0) | (OPT_PERSISTENT if persistent else 0)
+    for k, v in (sched or {}).items():
+        if k not in SCHED_FIELDS:
+            raise ValueError("unknown schedule setting %r" % k)
+        setattr(o, k, int(v))
     return o
 
 
