@@ -659,13 +659,20 @@ def main():
 
     if args.profile_steps:
         if args.copy_mb:
+            # counter calibration, each stream larger than the 256 MB Infinity Cache: a write-only
+            # fill, a read-only reduction (its output is a few bytes), and a copy
             n = args.copy_mb << 20
-            src_t = torch.ones(n, dtype=torch.uint8, device="cuda")
-            dst_t = torch.empty_like(src_t)
+            src_t = torch.empty(n // 4, dtype=torch.int32, device="cuda")
+            src_t.fill_(1)
             torch.cuda.synchronize()
+            log("calibration fill (write only) of %d bytes done" % n)
+            tot = int(src_t.sum())
+            torch.cuda.synchronize()
+            log("calibration sum (read only) of %d bytes done (%d)" % (n, tot))
+            dst_t = torch.empty_like(src_t)
             dst_t.copy_(src_t)
             torch.cuda.synchronize()
-            log("reference copy of %d bytes done" % n)
+            log("calibration copy of %d bytes done" % n)
             del src_t, dst_t
         for k in range(args.profile_steps):  # the configuration of the roofline pass
             for s in sources:
@@ -773,14 +780,18 @@ def main():
     ablation = None
     if not args.no_ablation:
         ablation = {}
-        # Table 2's rows in order: the sort-based push (Baseline), the structure-only push, then
-        # direction change, masking, early exit and operand reuse added one at a time
-        for mode in ("push_sort", "push_only", "pull_unmasked", "pull_masked", "pull_masked_ee", "full"):
+        # Table 2's rows in order: the sort-based push (Baseline: key-value sort), the
+        # structure-only push (key-only sort, no parents), then the atomic push, direction
+        # change, masking, early exit and operand reuse added one at a time
+        for mode in ("push_sort", "push_sort_keys", "push_only", "pull_unmasked", "pull_masked",
+                     "pull_masked_ee", "full"):
             o = options(mode)
-            ws_m = None if mode == "push_sort" else runner.ws  # the sort needs its larger workspace
+            sort = mode.startswith("push_sort")
+            ws_m = None if sort else runner.ws  # the sort needs its larger workspace
+            par = None if mode == "push_sort_keys" else runner.parent
 
             def one(s):
-                dobfs.bfs(g, s, runner.depth, runner.parent, o, ws_m, stream=stream)
+                dobfs.bfs(g, s, runner.depth, par, o, ws_m, stream=stream)
 
             for s in sources[:4]:
                 one(s)

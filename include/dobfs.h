@@ -116,11 +116,17 @@ enum {
   DOBFS_MODE_PULL_MASKED = 3,    /* pull computes unvisited rows only, scans whole rows */
   DOBFS_MODE_PULL_MASKED_EE = 4, /* as above, stopping at the first parent found */
   DOBFS_MODE_PULL_ONLY = 5,      /* FULL's pull at every level (no direction change) */
-  DOBFS_MODE_PUSH_SORT = 6       /* Table 2 "Baseline": push at every level as Algorithm 3 prints it:
+  DOBFS_MODE_PUSH_SORT = 6,      /* Table 2 "Baseline": push at every level as Algorithm 3 prints it:
                                     gather (neighbour, vertex) pairs, key-value radix sort, keep the
                                     first pair of each key, drop visited keys; the host reads each
                                     level's counts back. Needs the larger workspace that
                                     dobfs_bfs_workspace_bytes reports for this mode. */
+  DOBFS_MODE_PUSH_SORT_KEYS = 7  /* Table 2 "Structure only" as the paper measures it (Section 5.5:
+                                    a Boolean BFS needs the matrix's structure, not its values): the
+                                    push of PUSH_SORT with the values dropped, a key-only radix sort
+                                    of the gathered neighbours, unique keys, drop visited keys. It
+                                    computes depths only: parent must be NULL (else INVALID_ARG).
+                                    Same workspace as PUSH_SORT. */
 };
 
 enum {

@@ -286,7 +286,7 @@ dobfs_options defaults() {
 }
 
 dobfs_status check_options(const dobfs_options& o) {
-  if (o.mode < DOBFS_MODE_FULL || o.mode > DOBFS_MODE_PUSH_SORT)
+  if (o.mode < DOBFS_MODE_FULL || o.mode > DOBFS_MODE_PUSH_SORT_KEYS)
     return fail(DOBFS_ERR_INVALID_ARG, "unknown mode %d", o.mode);
   if (o.heuristic != DOBFS_HEUR_RATIO && o.heuristic != DOBFS_HEUR_EDGES)
     return fail(DOBFS_ERR_INVALID_ARG, "unknown heuristic %d", o.heuristic);
@@ -762,6 +762,7 @@ dobfs_status bfs_sort_push(dobfs_graph g, int32_t source, const dobfs_options& o
   if (st != DOBFS_OK) return st;
   hipEvent_t* ev = events_for(g->device);
   if (!ev) return fail(DOBFS_ERR_DEVICE, "event creation failed");
+  const bool keys_only = opt_in.mode == DOBFS_MODE_PUSH_SORT_KEYS;
   dobfs_options opt = opt_in;
   opt.mode = DOBFS_MODE_PUSH_ONLY;  // the level state machine: push at every level
   BfsArgs a = bfs_args(g, ws, SL.base, opt, depth, parent);
@@ -819,10 +820,17 @@ dobfs_status bfs_sort_push(dobfs_graph g, int32_t source, const dobfs_options& o
     e.chunk_first = a.chunk_first;
     e.colind = a.colind;
     e.m = m;
-    HIPCK(launch_sort_gather(s, e, kA, vA));
-    HIPCK(sort_pairs(s, tmp, SL.tmp_bytes, kA, kB, vA, vB, m, bits));
-    HIPCK(launch_sort_filter(s, kB, vB, m, a.vis[stL.vis_idx], depth, parent, L, a.Q[(L + 1) % 2],
-                             &c->qcount[L % kSlots], &c->slot[L % kSlots]));
+    if (keys_only) {  // structure only: the neighbours alone, no frontier vertex alongside
+      HIPCK(launch_sort_gather(s, e, kA, nullptr));
+      HIPCK(sort_keys(s, tmp, SL.tmp_bytes, kA, kB, m, bits));
+      HIPCK(launch_sort_filter(s, kB, nullptr, m, a.vis[stL.vis_idx], depth, nullptr, L, a.Q[(L + 1) % 2],
+                               &c->qcount[L % kSlots], &c->slot[L % kSlots]));
+    } else {
+      HIPCK(launch_sort_gather(s, e, kA, vA));
+      HIPCK(sort_pairs(s, tmp, SL.tmp_bytes, kA, kB, vA, vB, m, bits));
+      HIPCK(launch_sort_filter(s, kB, vB, m, a.vis[stL.vis_idx], depth, parent, L, a.Q[(L + 1) % 2],
+                               &c->qcount[L % kSlots], &c->slot[L % kSlots]));
+    }
   }
   HIPCK(hipEventRecord(ev[kEvEnd], s));
   HIPCK(hipEventSynchronize(ev[kEvEnd]));
@@ -1085,7 +1093,8 @@ dobfs_status dobfs_graph_info(dobfs_graph g, int32_t* V, int64_t* nnz, int32_t* 
 
 dobfs_status dobfs_bfs_workspace_bytes(dobfs_graph g, const dobfs_options* opt, size_t* bytes) {
   if (!g || !bytes) return fail(DOBFS_ERR_INVALID_ARG, "graph or bytes is NULL");
-  *bytes = (opt && opt->mode == DOBFS_MODE_PUSH_SORT) ? plan_sort(g->V, g->nnz).total
+  *bytes = (opt && (opt->mode == DOBFS_MODE_PUSH_SORT || opt->mode == DOBFS_MODE_PUSH_SORT_KEYS))
+               ? plan_sort(g->V, g->nnz).total
                                                        : plan(g->V, g->nnz).total;
   return DOBFS_OK;
 }
@@ -1104,7 +1113,9 @@ dobfs_status dobfs_bfs(dobfs_graph g, int32_t source, const dobfs_options* opt_i
   if (st != DOBFS_OK) return st;
   DeviceScope ds(g->device);
   if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice", __LINE__);
-  if (opt.mode == DOBFS_MODE_PUSH_SORT)
+  if (opt.mode == DOBFS_MODE_PUSH_SORT_KEYS && parent)
+    return fail(DOBFS_ERR_INVALID_ARG, "the key-only sort push computes no parents: parent must be NULL");
+  if (opt.mode == DOBFS_MODE_PUSH_SORT || opt.mode == DOBFS_MODE_PUSH_SORT_KEYS)
     return bfs_sort_push(g, source, opt, depth, parent, workspace, ws_bytes, stream, stats);
   const Layout L = plan(g->V, g->nnz);
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1125,7 +1136,7 @@ dobfs_status dobfs_bfs_static(dobfs_graph g, int32_t source, const dobfs_options
   dobfs_options opt;
   dobfs_status st = check_bfs_call(g, source, opt_in, depth, stats, &opt);
   if (st != DOBFS_OK) return st;
-  if (opt.mode == DOBFS_MODE_PUSH_SORT)
+  if (opt.mode == DOBFS_MODE_PUSH_SORT || opt.mode == DOBFS_MODE_PUSH_SORT_KEYS)
     return fail(DOBFS_ERR_UNSUPPORTED, "the sort-based push needs a workspace beyond the static scratch");
   if (opt.flags & DOBFS_OPT_TIME_KERNELS)
     return fail(DOBFS_ERR_UNSUPPORTED, "kernel timing needs events, which this call does not create");

@@ -468,7 +468,7 @@ hipError_t launch_check_indices(hipStream_t s, const int32_t* idx, int64_t nnz, 
                                 int32_t* err);
 
 // ---- sort-based push (sortpush.hip) ----
-size_t sort_push_bytes(int64_t nnz);  // radix-sort scratch for nnz pairs
+size_t sort_push_bytes(int64_t nnz);  // radix-sort scratch for nnz pairs (enough for nnz keys alone)
 // rowind_out = every CSC column of rowind_in reordered by decreasing out-degree of its rows
 // (stable: equal degrees keep their order); allocates and frees its own scratch.
 hipError_t hubs_first(hipStream_t s, const int32_t* rowptr, const int32_t* colptr, const int32_t* rowind_in,
@@ -476,6 +476,8 @@ hipError_t hubs_first(hipStream_t s, const int32_t* rowptr, const int32_t* colpt
 hipError_t launch_sort_gather(hipStream_t s, const ExpandArgs& a, uint32_t* keys, int32_t* vals);
 hipError_t sort_pairs(hipStream_t s, void* tmp, size_t tmp_bytes, const uint32_t* kin, uint32_t* kout,
                       const int32_t* vin, int32_t* vout, uint32_t m, int bits);
+hipError_t sort_keys(hipStream_t s, void* tmp, size_t tmp_bytes, const uint32_t* kin, uint32_t* kout, uint32_t m,
+                     int bits);
 hipError_t launch_sort_filter(hipStream_t s, const uint32_t* keys, const int32_t* vals, uint32_t m, uint32_t* vis,
                               int32_t* depth, int32_t* parent, int32_t level, int32_t* Qout, uint32_t* qcount,
                               LevelSlot* slot);

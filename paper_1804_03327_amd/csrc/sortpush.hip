@@ -1,4 +1,4 @@
-// Sort-based push BFS of libdobfs (mode DOBFS_MODE_PUSH_SORT): the
+// Sort-based push BFS of libdobfs (modes DOBFS_MODE_PUSH_SORT and _KEYS): the
 // column-based masked matvec the way Algorithm 3 prints it and Table 2's
 // "Baseline" row measures it. Every level gathers the frontier's adjacency
 // lists as (neighbour, frontier vertex) pairs, sorts them by neighbour with a
@@ -7,8 +7,11 @@
 // merges duplicates) and filters it by the mask not(visited). The winner of a
 // run is the parent. The host reads each level's frontier and edge counts
 // back, as the paper's loop does, since the sort takes its size on the host.
+// The key-only form (Table 2's "Structure only") gathers the neighbours alone,
+// sorts keys only and keeps each distinct key: depths without parents.
 // Kept for the ablation; the default push merges by atomic claim instead.
 
+#include <algorithm>
 #include <cstring>
 
 #include "device_common.h"
@@ -58,7 +61,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_gather(ExpandArgs a, uint32_t
         s = a.S[kk]; rs = a.R[kk]; u = a.Q[kk];
       }
       keys[e] = uint32_t(a.colind[rs + int32_t(e - uint32_t(s))]);
-      vals[e] = u;
+      if (vals) vals[e] = u;
     }
   }
 }
@@ -170,12 +173,14 @@ hipError_t hubs_first(hipStream_t s, const int32_t* rowptr, const int32_t* colpt
 }
 
 size_t sort_push_bytes(int64_t nnz) {
-  size_t tmp = 0;
+  size_t tmp = 0, tk = 0;
   const unsigned n = unsigned(nnz > 0 ? nnz : 1);
   (void)rocprim::radix_sort_pairs(nullptr, tmp, static_cast<const uint32_t*>(nullptr),
                                   static_cast<uint32_t*>(nullptr), static_cast<const int32_t*>(nullptr),
                                   static_cast<int32_t*>(nullptr), n, 0, 32);
-  return tmp;
+  (void)rocprim::radix_sort_keys(nullptr, tk, static_cast<const uint32_t*>(nullptr),
+                                 static_cast<uint32_t*>(nullptr), n, 0, 32);
+  return std::max(tmp, tk);
 }
 
 hipError_t launch_sort_gather(hipStream_t s, const ExpandArgs& a, uint32_t* keys, int32_t* vals) {
@@ -189,6 +194,12 @@ hipError_t sort_pairs(hipStream_t s, void* tmp, size_t tmp_bytes, const uint32_t
                       const int32_t* vin, int32_t* vout, uint32_t m, int bits) {
   size_t tb = tmp_bytes;
   return rocprim::radix_sort_pairs(tmp, tb, kin, kout, vin, vout, m, 0, bits, s);
+}
+
+hipError_t sort_keys(hipStream_t s, void* tmp, size_t tmp_bytes, const uint32_t* kin, uint32_t* kout, uint32_t m,
+                     int bits) {
+  size_t tb = tmp_bytes;
+  return rocprim::radix_sort_keys(tmp, tb, kin, kout, m, 0, bits, s);
 }
 
 hipError_t launch_sort_filter(hipStream_t s, const uint32_t* keys, const int32_t* vals, uint32_t m, uint32_t* vis,

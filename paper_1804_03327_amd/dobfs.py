@@ -21,10 +21,10 @@ UPLOAD_VALIDATE = 1
 UPLOAD_HUBS_FIRST = 2
 DIR_PUSH, DIR_PULL = 0, 1
 MODE_FULL, MODE_PUSH_ONLY, MODE_PULL_UNMASKED, MODE_PULL_MASKED, MODE_PULL_MASKED_EE, \
-    MODE_PULL_ONLY, MODE_PUSH_SORT = range(7)
+    MODE_PULL_ONLY, MODE_PUSH_SORT, MODE_PUSH_SORT_KEYS = range(8)
 MODES = {"full": MODE_FULL, "push_only": MODE_PUSH_ONLY, "pull_unmasked": MODE_PULL_UNMASKED,
          "pull_masked": MODE_PULL_MASKED, "pull_masked_ee": MODE_PULL_MASKED_EE,
-         "pull_only": MODE_PULL_ONLY, "push_sort": MODE_PUSH_SORT}
+         "pull_only": MODE_PULL_ONLY, "push_sort": MODE_PUSH_SORT, "push_sort_keys": MODE_PUSH_SORT_KEYS}
 HEUR_RATIO, HEUR_EDGES = 0, 1
 OPT_TIME_KERNELS = 1
 OPT_PERSISTENT = 2

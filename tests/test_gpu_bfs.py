@@ -137,6 +137,39 @@ def test_push_sort_matches_oracle(graphs, name):
     assert e.value.status == dobfs.ERR_WORKSPACE_TOO_SMALL
 
 
+@pytest.mark.parametrize("name", ["rmat10", "rmat14", "directed100003", "lattice37", "grid61x53"])
+def test_push_sort_keys_matches_oracle(graphs, name):
+    """Table 2's structure-only row as the paper measures it: the sort push with the values
+    dropped (key-only radix sort, unique keys, mask filter). Depths exact, push at every level,
+    the oracle's level sizes and nnz(m_f^+) gathered per level; parents are not computed, so a
+    parent buffer is refused, and the larger sort workspace is needed."""
+    hg, g = graphs[name]
+    outdeg = hg.out_degree()
+    opt = dobfs.make_options("push_sort_keys")
+    need = dobfs.bfs_workspace_bytes(g, opt)
+    assert need == dobfs.bfs_workspace_bytes(g, dobfs.make_options("push_sort"))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    depth = torch.full((g.V,), -7, dtype=torch.int32, device="cuda")
+    st = dobfs.make_stats(4096)
+    for s in _sources(hg, 3, seed=2):
+        tag = "%s src=%d push_sort_keys" % (name, s)
+        _say(tag)
+        want, _ = oracle.bfs(hg, s)
+        dobfs.bfs(g, s, depth, None, opt, ws, stats=st)
+        assert np.array_equal(depth.cpu().numpy(), want), tag + ": depth mismatch"
+        lv = dobfs.stats_levels(st)
+        assert [r["nf"] for r in lv] == oracle.level_sizes(want), tag
+        assert set(r["dir"] for r in lv) == {PUSH}, tag
+        for L, r in enumerate(lv):
+            m_f = int(outdeg[want == L].sum())
+            assert r["m_f"] == m_f and r["edges"] == m_f, "%s level %d" % (tag, L)
+        assert st.edges_g500 == oracle.teps_edges(hg, want)["graph500"], tag
+    parent = torch.empty(g.V, dtype=torch.int32, device="cuda")
+    with pytest.raises(dobfs.DobfsError) as e:
+        dobfs.bfs(g, 0, depth, parent, opt, ws)
+    assert e.value.status == dobfs.ERR_INVALID_ARG
+
+
 @pytest.mark.parametrize("name", ["rmat14", "lattice37"])
 def test_launch_totals(graphs, name):
     """The whole-call launch totals count what a kernel profiler counts: every launch of the

@@ -33,7 +33,8 @@ def _say(*a):
 
 BENCH_OPT = dict(mode="full", heuristic=dobfs.HEUR_EDGES, alpha=1 / 14, beta=1 / 24)
 # the Table 2 rows the benchmark times, each with the benchmark's direction rule
-ABLATION_MODES = ("push_sort", "push_only", "pull_unmasked", "pull_masked", "pull_masked_ee", "full")
+ABLATION_MODES = ("push_sort", "push_sort_keys", "push_only", "pull_unmasked", "pull_masked", "pull_masked_ee",
+                  "full")
 
 
 def _oracle_many(hg, sources):
@@ -91,7 +92,12 @@ def test_rmat22_ablation_modes(rmat22):
             _say(tag)
             opt = dobfs.make_options(mode, BENCH_OPT["heuristic"], BENCH_OPT["alpha"], BENCH_OPT["beta"])
             # the sort-based push needs its larger workspace: the library's own, as the bench runs it
-            ws = None if mode == "push_sort" else r.ws
+            ws = None if mode.startswith("push_sort") else r.ws
+            if mode == "push_sort_keys":  # depths only
+                dobfs.bfs(g, s, r.depth, None, opt, ws, stats=r.stats)
+                d = r.depth.cpu().numpy()
+                assert np.array_equal(d, want[s]), tag
+                continue
             dobfs.bfs(g, s, r.depth, r.parent, opt, ws, stats=r.stats)
             d, p = r.result()
             _check(hg, s, want[s], d, p, tag)
