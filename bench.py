@@ -471,6 +471,35 @@ def measure_serving(args, hg22, g22, heur, alpha, beta):
     cap = 1.0 / float(svc_tab.mean())  # uniform graph and source
     grid_loops = loop_costs(gs[3], [int(x) for x in pools[3][:2]], heur, alpha, beta, 1, torch.cuda.current_stream())
     log("grid level loops:", json.dumps(grid_loops))
+    # device-side overlap: two grid traversals from two host threads on two streams, against the
+    # same two one after the other (best of three each)
+    ov_runners = [BfsRunner(gs[3], with_parent=False) for _ in range(2)]
+    ov_streams = [torch.cuda.Stream() for _ in range(2)]
+    ov_src = [int(pools[3][0]), int(pools[3][1])]
+
+    def ov_one(i):
+        ov_runners[i].run(ov_src[i], opt=opt, stream=ov_streams[i])
+
+    ov_seq, ov_par = [], []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ov_one(0)
+        ov_one(1)
+        torch.cuda.synchronize()
+        ov_seq.append(time.perf_counter() - t1)
+        ths = [threading.Thread(target=ov_one, args=(i,)) for i in range(2)]
+        t1 = time.perf_counter()
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join()
+        torch.cuda.synchronize()
+        ov_par.append(time.perf_counter() - t1)
+    overlap = {"two_grid_traversals_sequential_ms": round(1e3 * min(ov_seq), 2),
+               "two_grid_traversals_two_streams_ms": round(1e3 * min(ov_par), 2)}
+    log("two-stream overlap:", json.dumps(overlap))
+    del ov_runners
     log("serving: sequential capacity %.1f q/s (mean service %s ms)" % (
         cap, ", ".join("%s %.3f" % (n, 1e3 * svc_tab[i].mean()) for i, (n, _) in enumerate(specs))))
     nbuf = [512, 512, 384, 384]
@@ -480,7 +509,7 @@ def measure_serving(args, hg22, g22, heur, alpha, beta):
         for b in range(nbuf[gi]):
             free[gi].put(b)
     points = []
-    for mult in (0.5, 1.0, 2.0, 4.0, 8.0, 16.0):
+    for mult in [float(x) for x in args.serve_points.split(",")]:
         lam = mult * cap
         N = int(min(args.serve_queries, max(64, round(lam * args.serve_seconds))))
         qg = rng.integers(0, len(specs), N)
@@ -560,6 +589,7 @@ def measure_serving(args, hg22, g22, heur, alpha, beta):
             "peak_served_qps": peak, "peak_served_x_sequential": round(peak / cap, 2),
             "mean_service_ms": {name: round(1e3 * float(svc_tab[gi].mean()), 3) for gi, (name, _) in enumerate(specs)},
             "grid2048_level_loop": dict(grid_loops, sources=2),
+            "device_overlap": overlap,
             "points": points}
 
 
@@ -600,6 +630,10 @@ def main():
     ap.add_argument("--profile-batched", type=int, default=0,
                     help="only run this many multi-source launches on the batched workload "
                          "(for rocprofv3), print nothing else")
+    ap.add_argument("--profile-serving", action="store_true",
+                    help="only run the serving workload at --serve-points (for a rocprofv3 kernel trace)")
+    ap.add_argument("--serve-points", default="0.5,1,2,4,8,16",
+                    help="offered loads of the serving sweep, in multiples of the sequential capacity")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="with --profile-steps: also copy this many MiB device-to-device once, "
                          "the known-size reference for scaling PMC byte counters")
@@ -653,6 +687,11 @@ def main():
 
     def options(mode, time_kernels=False):
         return dobfs.make_options(mode, heur, alpha, beta, time_kernels=time_kernels)
+
+    if args.profile_serving:
+        res = measure_serving(args, hg, g, heur, alpha, beta)
+        log("profile serving:", json.dumps(res["points"]))
+        return
 
     opt_plain = options("full")
     opt_timed = options("full", time_kernels=True)

@@ -268,6 +268,13 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
   uint64_t* vout = a.vis[st.vis_idx ^ 1];
   uint64_t* Fn = mb_frontier(a, L + 1);
   const uint64_t active = st.active;  // a source with an empty frontier finds nothing more
+  // after a push, vin lacks this level's frontier words (the prep leaves the merge to this
+  // pull): a row's own word is vin | Fc, and the in-neighbours' words are read from Fc, which for
+  // every source bit a row still needs holds the same bits as the merged words (a source's
+  // visited in-neighbour of a row it has not reached was reached at this level, Section 5.4)
+  const bool merge = st.local == 1;
+  const uint64_t* Fc = mb_frontier(a, L);
+  const uint64_t* xin = merge ? Fc : vin;
   if (tid < kMbTileWords) sh.nzf[tid] = 0;
   if (tid == 0) {
     sh.ncand = 0;
@@ -279,7 +286,7 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
     const int32_t v = v0 + r;
     bool cand = false;
     if (v < a.V) {
-      const uint64_t m = vin[v];
+      const uint64_t m = merge ? (vin[v] | Fc[v]) : vin[v];
       cand = ((~m & active) != 0) && get_bit(a.nz_in, v);
       if (!cand) {
         vout[v] = m;
@@ -319,7 +326,7 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
   for (int32_t idx = tid; idx < ncand; idx += kThreads) {
     const int r = sh.cand[idx];
     const int32_t v = v0 + r;
-    const uint64_t m = vin[v];
+    const uint64_t m = merge ? (vin[v] | Fc[v]) : vin[v];
     const uint64_t need = ~m & active;
     // the slab: the row's first kSlab in-neighbours from one coalesced read
     const int4 hd = a.slab[v];
@@ -328,7 +335,7 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
 #pragma unroll
     for (int q = 0; q < kSlab; ++q) {
       if (e[q] >= 0) {
-        acc |= vin[e[q]];
+        acc |= xin[e[q]];
         ++checks;
       }
     }
@@ -346,7 +353,7 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if (j[q] < 0 || (acc & need) == need) continue;
-        acc |= vin[j[q]];
+        acc |= xin[j[q]];
         ++checks;
       }
       p += 4;
@@ -359,7 +366,7 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
         continue;
       }
       for (int32_t q = lim; q < end && (acc & need) != need; ++q) {  // wave list full: finish here
-        acc |= vin[a.rowind[q]];
+        acc |= xin[a.rowind[q]];
         ++checks;
       }
     }
@@ -370,14 +377,14 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
   for (int32_t i = tid >> 6; i < nlong; i += kThreads / 64) {
     const int r = sh.lng[i];
     const int32_t v = v0 + r;
-    const uint64_t m = vin[v];
+    const uint64_t m = merge ? (vin[v] | Fc[v]) : vin[v];
     const uint64_t need = ~m & active;
     const int32_t beg = a.colptr[v] + kMbMid, end = a.colptr[v + 1];
     uint64_t acc = sh.lacc[i];
     unsigned long long n = 0;
     for (int32_t p = beg; p < end; p += 64) {
       const int32_t q = p + lane();
-      const uint64_t x = q < end ? vin[a.rowind[q]] : 0ull;
+      const uint64_t x = q < end ? xin[a.rowind[q]] : 0ull;
       acc |= wave_or64(x);
       n += uint64_t(min(64, end - p));
       if ((acc & need) == need) break;
@@ -411,7 +418,9 @@ __global__ __launch_bounds__(kThreads) void k_mb_prep(BatchArgs a, int32_t L, in
   Ctrl* c = a.ctrl;
   LevelTotals tot;
   LevelState prev;
-  const LevelState st = level_state(a, L, forced, &tot, &prev);
+  LevelState st = level_state(a, L, forced, &tot, &prev);
+  // a pull after a push merges the push's winners into the visited words itself (local = 1)
+  st.local = (L >= 1 && !st.done && st.dir == 1 && prev.dir == 0) ? 1 : 0;
   publish_level(c, L, st, prev, tot);
   if (L == 0 && blockIdx.x == 0 && int32_t(threadIdx.x) < a.k) {
     // the sources: bit b of Vis and of level 0's frontier at sources[b] (depth 0)
@@ -420,9 +429,10 @@ __global__ __launch_bounds__(kThreads) void k_mb_prep(BatchArgs a, int32_t L, in
     atomicOr(reinterpret_cast<unsigned long long*>(a.vis[0] + v), bit);
     atomicOr(reinterpret_cast<unsigned long long*>(a.Fs + v), bit);
   }
-  if (L >= 1 && !st.done && prev.dir == 0) {
-    // a push leaves Vis as the level began: merge in what it found, through its list when it
-    // made a short one, else in one dense pass (random lines of two arrays cost more than a sweep)
+  if (L >= 1 && !st.done && prev.dir == 0 && st.dir == 0) {
+    // a push leaves Vis as the level began: before another push, merge in what it found, through
+    // its list when it made a short one, else in one dense pass (random lines of two arrays cost
+    // more than a sweep)
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int32_t* Qc = a.Q[L % 2];
@@ -538,7 +548,10 @@ static_assert(kMbSnap <= 16, "depths of the kept levels are folded into four bit
 __global__ __launch_bounds__(kThreads) void k_mb_depth(BatchArgs a, int32_t level, DepthRows rows) {
   const LevelState end = a.ctrl->ring[level % kRing];
   if (!end.done) return;  // not over yet: a later batch's transpose writes the rows
-  const uint64_t* vis = a.vis[end.vis_idx];
+  // the final visited words: the state that found the end keeps the last level's direction and
+  // buffer index, and a last pull wrote its result to the other buffer (merged with what the push
+  // before it found, which its input may lack)
+  const uint64_t* vis = a.vis[end.dir == 1 ? (end.vis_idx ^ 1) : end.vis_idx];
   const int32_t k = a.k;
   const int32_t nsnap = min(end.levels, kMbSnap);  // kept frontiers: levels 0 .. nsnap-1
   const int64_t ngroups = (int64_t(a.V) + kMbDepthVPT - 1) / kMbDepthVPT;

@@ -282,3 +282,19 @@ def test_interleaved_with_single_source_reports():
                     assert np.array_equal(row, refs[s]), "batch row of source %d, round %d" % (s, rnd)
         _say("interleaved round", rnd, "ok")
 
+
+
+@pytest.mark.parametrize("name", ["rmat14", "lattice37"])
+def test_batch_last_level_pull_after_push(graphs, name):
+    """Schedules whose last level is a pull right after a push: that pull merges the push's
+    winners into the visited words itself, and the depth rows must read its output."""
+    hg, g = graphs[name]
+    srcs = _sources(hg, 64, 11)
+    n = int(np.stack([_ref(hg, s) for s in srcs]).max()) + 1  # levels of the batch
+    alternating = [PUSH if (n - 1 - i) % 2 == 1 else PULL for i in range(n)]
+    for sc in ([PUSH] * (n - 1) + [PULL], [PULL] * (n - 2) + [PUSH, PULL], alternating):
+        tag = "%s last-pull schedule %s" % (name, "".join(str(int(x)) for x in sc))
+        _say(tag)
+        d, st = _run(g, srcs, dobfs.make_options("full", forced_dirs=sc))
+        _check(hg, srcs, d, st, tag)
+        assert [x["dir"] for x in dobfs.stats_levels(st)] == sc, tag
