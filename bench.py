@@ -31,6 +31,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+ATOMIC_CEILING_PER_S = 27e9  # device atomics on distinct words, measured on MI355X
 METRIC = "GTEPS DOBFS RMAT-22 (1 GPU)"
 KERNEL_DIR = os.path.join(ROOT, "paper_1804_03327_amd", "csrc")
 
@@ -122,6 +123,7 @@ def step_roofline(V, heur, runs, cand_tables, traffic):
     from paper_1804_03327_amd import dobfs
     kinds = {k: {"ms": 0.0, "launches": 0, "bytes": 0.0} for k in
              ("step", "init", "push", "push_scan", "pull")}
+    push_edges, push_big = 0, {"edges": 0, "ms": 0.0, "levels": 0}
 
     def add(kind, ms, nbytes, launches=1):
         kinds[kind]["ms"] += ms
@@ -150,6 +152,13 @@ def step_roofline(V, heur, runs, cand_tables, traffic):
                 else:  # block-local over the bits the pull found
                     main = V / 8 + mu + bytes_local_expand(lv["nf"], lv["m_f"], lv["n_new"]) - 4 * lv["nf"]
                 add("push", lv["ms_main"], main)
+                # the push's adjacency entries, each one plain load of a visited word and, when the
+                # target still looks unvisited, one atomic claim: against the atomic rate
+                push_edges += lv["edges"]
+                if lv["edges"] >= 1 << 15:  # the pushes large enough to keep the atomics busy
+                    push_big["edges"] += lv["edges"]
+                    push_big["ms"] += lv["ms_main"] + lv["ms_aux"]
+                    push_big["levels"] += 1
             else:
                 nc = cand_tables[s][L] if L < len(cand_tables[s]) else cand_tables[s][-1]
                 main = bytes_pull(V, int(nc), lv["edges"], lv["n_new"])
@@ -173,6 +182,13 @@ def step_roofline(V, heur, runs, cand_tables, traffic):
                         "avg_us": round(1e3 * v["ms"] / max(1, v["launches"]), 3),
                         "GBps": round(v["bytes"] / max(1e-12, v["ms"] * 1e-3) / 1e9, 1)}
                     for k, v in kinds.items()}
+    # push levels against the atomic ceiling (27 G/s for atomics on distinct words, measured on
+    # the box): edges per second, each at most one claim
+    kernel_table["push"]["edges_per_s"] = round(push_edges / max(1e-12, kinds["push"]["ms"] * 1e-3), 0)
+    kernel_table["push"]["large_levels_edges_per_s"] = round(
+        push_big["edges"] / max(1e-12, push_big["ms"] * 1e-3), 0)
+    kernel_table["push"]["large_levels"] = push_big["levels"]
+    kernel_table["push"]["atomic_ceiling_per_s"] = ATOMIC_CEILING_PER_S
     return roofline, kernel_table, bfs_ms
 
 
