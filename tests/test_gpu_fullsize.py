@@ -155,3 +155,37 @@ def test_rmat20_multi_source_all_rows():
         assert np.array_equal(rows[b], want[srcs[b]]), "row %d (source %d) differs" % (b, srcs[b])
     _say("rmat20: 64 rows match")
     dobfs.graph_destroy(g)
+
+
+def test_full_size_persistent_loop(rmat22):
+    """The persistent level loop at full size: four RMAT-22 bench sources and two lattice
+    sources in the benchmarked configuration, against the oracle and the step-launch loop's
+    per-level sizes and directions."""
+    hg, srcs = rmat22
+    g = upload(hg, hubs_first=True)
+    r = BfsRunner(g)
+    pick = [srcs[0], srcs[13], srcs[29], srcs[51]]
+    want = _oracle_many(hg, pick)
+    for s in pick:
+        tag = "rmat22 persistent source %d" % s
+        _say(tag)
+        r.run(s, **BENCH_OPT)
+        ref = [(x["dir"], x["nf"], x["n_new"]) for x in r.levels()]
+        r.run(s, persistent=True, **BENCH_OPT)
+        d, p = r.result()
+        _check(hg, s, want[s], d, p, tag, BENCH_OPT, r.levels())
+        assert [(x["dir"], x["nf"], x["n_new"]) for x in r.levels()] == ref, tag
+    dobfs.graph_destroy(g)
+    hl = gen.lattice3d(256, 0.05, seed=3)
+    lsrc = [int(x) for x in gen.sample_sources(hl, 16, seed=4)]
+    pick = [lsrc[3], lsrc[12]]
+    want = _oracle_many(hl, pick)
+    g = upload(hl, hubs_first=True)
+    r = BfsRunner(g)
+    for s in pick:
+        tag = "lattice256 persistent source %d" % s
+        _say(tag)
+        r.run(s, persistent=True, **BENCH_OPT)
+        d, p = r.result()
+        _check(hl, s, want[s], d, p, tag, BENCH_OPT, r.levels())
+    dobfs.graph_destroy(g)
