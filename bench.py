@@ -293,6 +293,25 @@ def measure_lattice(args, heur, alpha, beta):
     roof, table, _ = step_roofline(hl.V, heur, list(zip(srcs, stats)), cand, None)
     levels = [st.levels for st in stats]
     loops = loop_costs(gl, srcs[:4], heur, alpha, beta, 1, stream)
+    tuned = None
+    if not args.no_autotune:  # the rule and schedule settings tuned on 4 other sources
+        from paper_1804_03327_amd import autotune
+        pool = [int(x) for x in gen.sample_sources(hl, 40, seed=5)]
+        tsrc = [x for x in pool if x not in set(srcs)][:4]
+        rt = autotune.tune_schedule(gl, tsrc, reps=2)
+        ot = dobfs.make_options("full", rt["heuristic"], rt["alpha"], rt["beta"], sched=rt["sched"])
+        passes = {"tuned": [], "fixed": []}
+        for _ in range(2):
+            for name, o in (("fixed", opt), ("tuned", ot)):
+                t1 = time.perf_counter()
+                for s in srcs[:8]:
+                    dobfs.bfs(gl, s, r.depth, r.parent, o, r.ws, stream=stream)
+                torch.cuda.synchronize()
+                passes[name].append(1e3 * (time.perf_counter() - t1) / 8)
+        tuned = {"settings": autotune.describe(rt), "ms_per_bfs": round(float(np.mean(passes["tuned"])), 4),
+                 "ms_per_bfs_fixed_same_passes": round(float(np.mean(passes["fixed"])), 4),
+                 "passes": 2, "timed_sources": 8, "tuning_sources": len(tsrc)}
+        log("lattice autotuned:", json.dumps(tuned))
     cpu_src = srcs[:2]
     tc = 0.0
     for s in cpu_src:
@@ -308,6 +327,7 @@ def measure_lattice(args, heur, alpha, beta):
            "us_per_level": round(1e6 * dt / reps / max(1, sum(levels)), 3),
            "validated_sources": len(want),
            "level_loop": dict(loops, sources=4),
+           "autotuned": tuned,
            "roofline": roof, "kernels": table,
            "cpu_baseline": {"value": round(sum(edges[s] for s in cpu_src) / tc / 1e9, 5), "unit": "GTEPS",
                             "cores": 1, "kind": "oracle",
