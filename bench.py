@@ -338,15 +338,15 @@ def measure_lattice(args, heur, alpha, beta):
 
 
 def batched_roofline(gb, hb, srcs, rows, opt, ws, depth, stream, heur, alpha, beta, reps=5):
-    """Roofline of the multi-source level kernel (k_mb_main, the one with the largest share of
-    a launch): algorithmic bytes of every level over its own execution time, from `reps` launches
-    whose kernels are timed with start/end events. Bytes per level (int32 indices, uint64 source
-    words, each random word access counted at its size):
+    """Roofline of the multi-source step kernel (k_mb_step) over the steps that push or pull
+    (the bulk of a launch): algorithmic bytes of every level over its step's own execution time,
+    from `reps` launches whose kernels are timed with start/end events. Bytes per level (int32
+    indices, uint64 source words, each random word access counted at its size):
       push: 20 nf (list entry, offset pair, F[u]) + 12 m_f (column index, Vis[w]) + 12 n_new (claim, list)
       pull: 24 V (Vis read, Vis' and F' written) + 24 n_cand (slab, offset pair) + 12 checks
     where n_cand (rows with a source still expanding that has not reached them, in-degree > 0)
-    comes from the 64 oracle-checked depth rows. The prep kernel (direction, merge, scan) is
-    reported beside it."""
+    comes from the 64 oracle-checked depth rows. The scan steps of push levels (merge, clears,
+    degree scan) are reported beside it."""
     from paper_1804_03327_amd import dobfs
     import torch
     ot = dobfs.make_options("full", heur, alpha, beta, time_kernels=True)
@@ -361,7 +361,7 @@ def batched_roofline(gb, hb, srcs, rows, opt, ws, depth, stream, heur, alpha, be
             cand_cache[L] = int((unreached.any(axis=0) & indeg_nz).sum())
         return cand_cache[L]
 
-    tot_bytes, tot_ms, tot_prep, n_main, levels = 0, 0.0, 0.0, 0, []
+    tot_bytes, tot_ms, tot_scan, n_main, n_scan, levels = 0, 0.0, 0.0, 0, 0, []
     for _ in range(reps):
         st = dobfs.make_stats(256)
         dobfs.bfs_batch(gb, srcs, depth, opt=ot, workspace=ws, stream=stream, stats=st)
@@ -374,15 +374,19 @@ def batched_roofline(gb, hb, srcs, rows, opt, ws, depth, stream, heur, alpha, be
                 b = 24 * hb.V + 24 * n_cand(L) + 12 * x["edges"]
             tot_bytes += b
             tot_ms += x["ms_main"]
-            tot_prep += x["ms_aux"]
+            if x["dir"] == dobfs.DIR_PUSH:
+                tot_scan += x["ms_aux"]
+                n_scan += 1
             n_main += 1
         levels = [("push", "pull")[x["dir"]] for x in lv]
     gbps = tot_bytes / (tot_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "kernel": "k_mb_main", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS,
+    return {"bound": "hbm", "kernel": "k_mb_step (push and pull steps)", "achieved": round(gbps, 1),
+            "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBS, 4), "traffic": None,
             "algorithmic_bytes_per_launch": int(tot_bytes / n_main), "avg_launch_us": round(1e3 * tot_ms / n_main, 3),
             "launches": n_main, "levels": levels,
-            "prep_avg_launch_us": round(1e3 * tot_prep / n_main, 3),
+            "scan_step_avg_us": round(1e3 * tot_scan / max(1, n_scan), 3),
+            "steps_per_launch": st.launches_main,
             "timing": "each kernel's own start/end events (hipExtLaunchKernel), %d launches of 64 sources" % reps}
 
 

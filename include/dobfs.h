@@ -156,7 +156,8 @@ typedef struct {
   int32_t heuristic;         /* DOBFS_HEUR_* */
   float alpha, beta;         /* switch points; 0.01 and 0.01 by default (Section 6.3) */
   const int8_t *forced_dirs; /* host, optional: direction of levels 0 .. n_forced-1 */
-  int32_t n_forced;          /* levels past n_forced follow the mode and heuristic */
+  int32_t n_forced;          /* levels past n_forced, or past the first 1024, follow the mode
+                                and heuristic */
   uint32_t flags;            /* DOBFS_OPT_* */
   /* Schedule settings of the single-source kernels (results do not depend on them; 0 keeps
      the default; out-of-range values -> INVALID_ARG). The autotuner chooses them per graph. */
@@ -202,12 +203,12 @@ typedef struct {
   int64_t edges;   /* push: nnz(m_f^+) adjacency entries read; pull: in-neighbours checked */
   int64_t m_f;     /* push: out-edges of the input frontier (0 on pull levels) */
   float ms_main;   /* execution time (DOBFS_OPT_TIME_KERNELS, else 0) of the level's pull or
-                      push: single source, the step that decides and runs the level (the
-                      expansion step after a scan); multi-source, the level's second kernel */
-  float ms_aux;    /* single source: the scan step of a push level that needs the global
-                      degree scan (with the bitmap-to-list conversion after a pull level), 0
-                      otherwise; multi-source: the level's first kernel (direction decision,
-                      frontier scan) */
+                      push: the step that decides and runs the level (the expansion step
+                      after a scan) */
+  float ms_aux;    /* the scan step of a push level that needs the global degree scan (with
+                      the bitmap-to-list conversion after a pull level), 0 otherwise; every
+                      multi-source push level has one (it also merges the push before's
+                      winners into the visited words and clears the next frontier) */
 } dobfs_level_stats;
 
 typedef struct {
@@ -219,12 +220,10 @@ typedef struct {
   int64_t reached;          /* vertices with depth >= 0 (multi-source: (vertex, source) pairs) */
   /* Every launch of the per-level kernels in the call, counted the way a kernel profiler
      counts them, with their summed execution times (DOBFS_OPT_TIME_KERNELS, else 0).
-     Single source: one step kernel, launched once per level, twice for a push level that
-     needs the global degree scan, once more for the step that finds the end, and for any
-     steps enqueued past the end (they exit at once); launches_aux and ms_aux_all are 0.
-     Multi-source: the levels' second kernels (main) and first kernels (aux, one more: the
-     one that finds the end), levels enqueued past the end included. The sort-based push
-     mode leaves all four at 0. */
+     One step kernel, launched once per level, twice for a push level that needs the
+     global degree scan (every multi-source push level does), once more for the step that
+     finds the end, and for any steps enqueued past the end (they exit at once);
+     launches_aux and ms_aux_all are 0. The sort-based push mode leaves all four at 0. */
   int32_t launches_main;
   int32_t launches_aux;
   float ms_main_all;

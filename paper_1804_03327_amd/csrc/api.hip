@@ -37,9 +37,8 @@ struct dobfs_graph_s {
   int32_t* head = nullptr;          // first entry of every CSC(A) column, complemented when more follow
   uint32_t max_outdeg = 0;          // largest CSR(A) row length
   bool symmetric = false;           // given as undirected: the same arrays for CSR(A) and CSC(A)
-  std::atomic<int32_t> last_levels{8};  // level count of the previous BFS (first batch size)
   std::atomic<int32_t> last_steps{8};   // step count of the previous single-source BFS
-  std::atomic<int32_t> last_levels_mb{8};  // the same for multi-source traversals
+  std::atomic<int32_t> last_steps_mb{8};   // the same for multi-source traversals
   void* owned[4] = {nullptr, nullptr, nullptr, nullptr};
   std::mutex mu;                    // guards the internal workspace
   void* ws = nullptr;
@@ -248,13 +247,11 @@ hipError_t fetch_report(const ReportSink& r, uint32_t seq, hipStream_t s) {
 }
 
 // Per-thread, per-device events for the level loop's timers: the start and
-// end of every prep (kMaxBatch + 1 slots) and main (kMaxBatch slots) kernel
-// of a batch, of the init kernel, and of the whole call.
-constexpr int ev_p0(int j) { return j; }
-constexpr int ev_p1(int j) { return kMaxBatch + 1 + j; }
-constexpr int ev_m0(int k) { return 2 * kMaxBatch + 2 + k; }
-constexpr int ev_m1(int k) { return 3 * kMaxBatch + 2 + k; }
-constexpr int kEvStart = 4 * kMaxBatch + 2, kEvInit0 = kEvStart + 1, kEvInit1 = kEvStart + 2,
+// end of every step of a batch (kMaxBatch slots each), of the init kernel,
+// and of the whole call.
+constexpr int ev_m0(int k) { return k; }
+constexpr int ev_m1(int k) { return kMaxBatch + k; }
+constexpr int kEvStart = 2 * kMaxBatch, kEvInit0 = kEvStart + 1, kEvInit1 = kEvStart + 2,
               kEvEnd = kEvStart + 3;
 constexpr int kEvents = kEvEnd + 1;
 hipEvent_t* events_for(int device) {
@@ -504,94 +501,9 @@ struct LoopResult {
   int64_t sum_new = 0;  // vertices discovered over all levels
   int64_t sum_aux = 0;  // multi-source: (vertex, source) pairs discovered
   LevelState end{};     // state after the last level
-  int32_t n_main = 0, n_aux = 0;            // every launch of the two level kernels
-  float ms_main_all = 0.f, ms_aux_all = 0.f;  // their execution times (when timing)
+  int32_t n_main = 0, n_aux = 0;            // every launch of the step kernel (n_aux: 0)
+  float ms_main_all = 0.f, ms_aux_all = 0.f;  // their execution times (when timing; ms_aux_all: 0)
 };
-
-// The level loop shared by the single- and multi-source traversals. Level l
-// is prep(l) then main(l); the state that decides level l+1 is computed on
-// the device by prep(l+1), which also records level l's counters. The host
-// enqueues levels in batches and reads the state back once per batch (a
-// report kernel writes it to pinned memory); levels enqueued past the end
-// exit at once. The first batch is one level longer than the previous
-// traversal of the same kind needed (a level past the end costs a few
-// microseconds, a second batch a host round trip); later batches start at 4
-// and double. The init kernel and ev[kEvStart] precede the call. When
-// timing, every kernel gets start / end events of its own execution: the
-// k-th level of a batch uses prep slot k and main slot k, and the prep that
-// opens the next batch uses prep slot `batch`.
-template <class Prep, class Main, class Forced, class Before>
-dobfs_status run_levels(std::atomic<int32_t>& last_levels, hipStream_t s, bool timing, hipEvent_t* ev,
-                        Forced forced, Prep prep, Main main, Before before_report, const Ctrl* ctrl,
-                        int64_t max_levels, dobfs_status too_deep, dobfs_stats* stats, LoopResult* res) {
-  HostReport* rep = host_report();
-  if (!rep) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
-  int64_t lvl = 0;
-  int32_t batch = std::min(std::max(last_levels.load(std::memory_order_relaxed) + 1, 2), kMaxBatch);
-  int32_t next_batch = 4;
-  float first_aux = 0.f;  // prep time of a batch's first level
-  auto E = [&](int i) -> hipEvent_t { return timing ? ev[i] : nullptr; };
-  HIPCK(prep(0, forced(0), E(ev_p0(0)), E(ev_p1(0))));
-  res->n_aux = 1;
-  while (true) {
-    if (lvl + batch > max_levels) batch = int32_t(max_levels - lvl);
-    const int64_t l1 = lvl + batch - 1;
-    for (int64_t l = lvl; l <= l1; ++l) {
-      const int32_t k = int32_t(l - lvl);
-      HIPCK(main(int32_t(l), E(ev_m0(k)), E(ev_m1(k))));
-      HIPCK(prep(int32_t(l + 1), forced(l + 1), E(ev_p0(k + 1)), E(ev_p1(k + 1))));
-    }
-    const uint32_t seq = next_report_seq();
-    HIPCK(before_report(int32_t(l1 + 1)));  // sees the state level l1 + 1 would start from
-    HIPCK(launch_report(s, ctrl, int32_t(lvl), batch, rep, seq));
-    HIPCK(wait_report(rep, seq, s));
-    if (timing && lvl == 0) {
-      first_aux = elapsed(ev[ev_p0(0)], ev[ev_p1(0)]);
-      res->ms_aux_all += first_aux;
-    }
-    res->n_main += batch;
-    res->n_aux += batch;
-    if (timing)
-      for (int32_t k = 0; k < batch; ++k) {
-        res->ms_main_all += elapsed(ev[ev_m0(k)], ev[ev_m1(k)]);
-        res->ms_aux_all += elapsed(ev[ev_p0(k + 1)], ev[ev_p1(k + 1)]);
-      }
-    const LevelState& end = rep->end;
-    const int64_t last = end.done ? int64_t(end.levels) - 1 : l1;  // last level that ran
-    for (int64_t l = lvl; l <= last; ++l) {
-      const LevelRecord& r = rep->rec[l - lvl];
-      res->sum_new += r.n_new;
-      res->sum_aux += int64_t(r.aux);
-      if (stats && l < stats->cap) {
-        dobfs_level_stats& ls = stats->level[l];
-        const int32_t k = int32_t(l - lvl);
-        ls.dir = r.dir;
-        ls.nf = r.nf;
-        ls.n_new = r.n_new;
-        ls.variant = r.variant;
-        ls.edges = r.edges;
-        ls.m_f = r.m_f;
-        ls.ms_aux = timing ? (k == 0 ? first_aux : elapsed(ev[ev_p0(k)], ev[ev_p1(k)])) : 0.f;
-        ls.ms_main = timing ? elapsed(ev[ev_m0(k)], ev[ev_m1(k)]) : 0.f;
-      }
-    }
-    if (end.done) {
-      res->levels = end.levels;
-      res->end = end;
-      break;
-    }
-    if (l1 + 1 >= max_levels) {
-      (void)hipStreamSynchronize(s);
-      return fail(too_deep, "traversal needs more than %lld levels", (long long)max_levels);
-    }
-    if (timing) first_aux = elapsed(ev[ev_p0(batch)], ev[ev_p1(batch)]);  // prep(l1 + 1)
-    lvl = l1 + 1;
-    batch = next_batch;
-    next_batch = std::min(2 * next_batch, kMaxBatch);
-  }
-  last_levels.store(int32_t(res->levels), std::memory_order_relaxed);
-  return DOBFS_OK;
-}
 
 // The persistent step loop on one device: how many of its blocks fit at once
 // (its grid), the wall-clock rate, and a lock held from one of its launches
@@ -628,18 +540,53 @@ uint32_t env_u32(const char* name, uint32_t dflt) {
   return x > 0xffffffffull ? 0xffffffffu : uint32_t(x);
 }
 
-// The single-source level loop: the host enqueues steps (k_step, one launch
+// How run_steps launches the steps of one traversal kind. step(): step k (rp: this step
+// also writes the batch's report, only where self_report); before_report(): what must run
+// after a batch's last step (k_last) and before its report; persistent(): the persistent
+// form of a batch (single source only).
+struct SingleSteps {
+  const BfsArgs& a;
+  static constexpr bool self_report = true;
+  hipError_t step(hipStream_t s, int32_t k, hipEvent_t t0, hipEvent_t t1, const StepReportArgs* rp) const {
+    return launch_step(s, a, k, t0, t1, rp);
+  }
+  hipError_t before_report(hipStream_t, int32_t) const { return hipSuccess; }
+  hipError_t persistent(hipStream_t s, int32_t s_first, int32_t n, int32_t blocks, uint32_t spin_limit,
+                        bool timing, const StepReportArgs& rp, hipEvent_t t0, hipEvent_t t1) const {
+    return launch_steps(s, a, s_first, n, blocks, spin_limit, timing, rp, t0, t1);
+  }
+};
+struct BatchSteps {
+  const BatchArgs& a;
+  const DepthRows& rows;
+  static constexpr bool self_report = false;
+  hipError_t step(hipStream_t s, int32_t k, hipEvent_t t0, hipEvent_t t1, const StepReportArgs*) const {
+    return launch_mb_step(s, a, k, t0, t1);
+  }
+  // the depth rows: a transpose that exits at once unless the state the batch's last step
+  // published says the traversal is over, so the last report already finds the rows final
+  hipError_t before_report(hipStream_t s, int32_t k_last) const { return launch_mb_depth(s, a, k_last, rows); }
+  hipError_t persistent(hipStream_t, int32_t, int32_t, int32_t, uint32_t, bool, const StepReportArgs&,
+                        hipEvent_t, hipEvent_t) const {
+    return hipErrorNotSupported;
+  }
+};
+
+// The level loop of both traversal kinds: the host enqueues steps (one launch
 // each) in batches and reads back, once per batch, the state every step
 // published and the records of the levels that are complete; steps enqueued
 // past the end exit at once. The first batch is one step longer than the
-// previous traversal of the graph needed; later batches start at 4 and
-// double. When timing, step k of a batch has events ev_m0(k) / ev_m1(k); a
-// level's scan step counts as its ms_aux, its other step as its ms_main.
-// With `pd` (persistent loop on that device) a batch is one launch of
-// k_steps running the batch's steps, with the same report; per-step times
-// then come from the device clock at each step's start (and the launch's end).
+// previous traversal of the same kind on the graph needed; later batches start
+// at 4 and double. When timing, step k of a batch has events ev_m0(k) /
+// ev_m1(k); a level's scan step counts as its ms_aux, its other step as its
+// ms_main. With `pd` (persistent loop on that device) a batch is one launch of
+// k_steps running the batch's steps, with the same report; per-step times then
+// come from the device clock at each step's start (and the launch's end).
+// max_levels: a traversal that reaches that many levels fails with too_deep.
+template <class Steps>
 dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool timing, hipEvent_t* ev,
-                       const BfsArgs& a, int64_t max_steps, const ReportSink& sink, PersistentDevice* pd,
+                       const Steps& S, const Ctrl* ctrl, int32_t nwords, int64_t max_steps, int64_t max_levels,
+                       dobfs_status too_deep, const ReportSink& sink, PersistentDevice* pd,
                        dobfs_stats* stats, LoopResult* res) {
   HostReport* rep = sink.host;
   int64_t s0 = 0;
@@ -647,7 +594,7 @@ dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool tim
   int32_t batch = std::min(std::max(last_steps.load(std::memory_order_relaxed) + 1, 2), kMaxBatch);
   int32_t next_batch = 4;
   auto E = [&](int i) -> hipEvent_t { return timing ? ev[i] : nullptr; };
-  const int32_t blocks = pd ? int32_t(std::min<int64_t>(main_blocks(a.nwords),
+  const int32_t blocks = pd ? int32_t(std::min<int64_t>(main_blocks(nwords),
                                                         int64_t(env_u32("DOBFS_PERSIST_BLOCKS", uint32_t(pd->capacity)))))
                             : 0;
   const uint32_t spin_limit = env_u32("DOBFS_SPIN_LIMIT", 1u << 22);
@@ -662,15 +609,16 @@ dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool tim
     const StepReportArgs rp{sink.dev, seq, int32_t(s0), rec_first};
     if (pd) {
       std::lock_guard<std::mutex> lk(pd->mu);
-      HIPCK(launch_steps(s, a, int32_t(s0), batch, blocks, spin_limit, timing,
+      HIPCK(S.persistent(s, int32_t(s0), batch, blocks, spin_limit, timing,
                          timing ? StepReportArgs{nullptr, 0u, 0, 0} : rp, E(ev_m0(0)), E(ev_m1(0))));
-      if (timing) HIPCK(launch_step_report(s, a.ctrl, int32_t(s0), batch, rec_first, sink.dev, seq));
+      if (timing) HIPCK(launch_step_report(s, ctrl, int32_t(s0), batch, rec_first, sink.dev, seq));
       HIPCK(fetch_report(sink, seq, s));
     } else {
+      const bool self = Steps::self_report && !timing;
       for (int32_t k = 0; k < batch; ++k)
-        HIPCK(launch_step(s, a, int32_t(s0 + k), E(ev_m0(k)), E(ev_m1(k)),
-                          (!timing && k == batch - 1) ? &rp : nullptr));
-      if (timing) HIPCK(launch_step_report(s, a.ctrl, int32_t(s0), batch, rec_first, sink.dev, seq));
+        HIPCK(S.step(s, int32_t(s0 + k), E(ev_m0(k)), E(ev_m1(k)), (self && k == batch - 1) ? &rp : nullptr));
+      HIPCK(S.before_report(s, int32_t(s0 + batch - 1)));
+      if (!self) HIPCK(launch_step_report(s, ctrl, int32_t(s0), batch, rec_first, sink.dev, seq));
       HIPCK(fetch_report(sink, seq, s));
     }
     if (rep->error) {
@@ -717,6 +665,10 @@ dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool tim
       res->levels = end.levels;
       res->end = end;
       break;
+    }
+    if (int64_t(end.level) + 1 >= max_levels) {
+      (void)hipStreamSynchronize(s);
+      return fail(too_deep, "traversal needs more than %lld levels", (long long)max_levels);
     }
     if (s0 + batch >= max_steps) {
       (void)hipStreamSynchronize(s);
@@ -888,7 +840,8 @@ dobfs_status bfs_steps(dobfs_graph g, int32_t source, const dobfs_options& opt, 
     pd = persistent_device(g->device);
     if (!pd) return fail(DOBFS_ERR_UNSUPPORTED, "the persistent level loop is not available on device %d", g->device);
   }
-  dobfs_status st = run_steps(g->last_steps, s, timing, ev, a, max_steps, sink, pd, stats, &res);
+  dobfs_status st = run_steps(g->last_steps, s, timing, ev, SingleSteps{a}, a.ctrl, a.nwords, max_steps,
+                              INT64_MAX, DOBFS_ERR_INTERNAL, sink, pd, stats, &res);
   if (st != DOBFS_OK) return st;
   if (stats) {
     if (ev) {
@@ -1247,27 +1200,25 @@ dobfs_status dobfs::bfs_batch_rows(dobfs_graph g, const int32_t* sources, int32_
     for (int32_t c = 0; c < a.nuniq; ++c) seen = seen || a.uniq[c] == sources[b];
     if (!seen) a.uniq[a.nuniq++] = sources[b];
   }
-  auto forced = [&](int64_t l) -> int32_t {
-    return l < opt.n_forced ? int32_t(opt.forced_dirs[l]) : -1;
-  };
-  const int32_t dir0 = forced(0) >= 0 ? forced(0)
-                                      : (opt.mode == DOBFS_MODE_PULL_ONLY ? DOBFS_DIR_PULL : DOBFS_DIR_PUSH);
+  const int32_t dir0 = opt.n_forced > 0 ? int32_t(opt.forced_dirs[0])
+                                        : (opt.mode == DOBFS_MODE_PULL_ONLY ? DOBFS_DIR_PULL : DOBFS_DIR_PUSH);
+  a.n_forced = std::min<int32_t>(opt.n_forced, kRing);  // later levels follow the rule
+  if (a.n_forced > 0)
+    HIPCK(hipMemcpyAsync(a.ctrl->forced, opt.forced_dirs, size_t(a.n_forced), hipMemcpyHostToDevice, s));
   // levels are kept as uint16 (level L stamps L + 1)
   const int64_t cap = std::min<int64_t>(int64_t(g->V) + 2, 0xfffe);
+  // a level takes at most two steps; scan tile flags carry 2 * step + 2 in 30 bits
+  const int64_t max_steps = std::min<int64_t>(2 * cap + 2, (int64_t(1) << 29) - 2);
+  HostReport* rep = host_report();  // pinned: the device writes the reports into it
+  if (!rep) return fail(DOBFS_ERR_OUT_OF_MEMORY, "pinned host buffer");
+  const ReportSink sink{rep, rep};
 
   if (stats) HIPCK(hipEventRecord(ev[kEvStart], s));
   HIPCK(launch_mb_init(s, a, dir0, L.nflags, timing ? ev[kEvInit0] : nullptr,
                        timing ? ev[kEvInit1] : nullptr));
   LoopResult res;
-  st = run_levels(
-      g->last_levels_mb, s, timing, ev, forced,
-      [&](int32_t l, int32_t f, hipEvent_t t0, hipEvent_t t1) { return launch_mb_prep(s, a, l, f, t0, t1); },
-      [&](int32_t l, hipEvent_t t0, hipEvent_t t1) { return launch_mb_main(s, a, l, t0, t1); },
-      // the depth rows ahead of each report: a transpose that exits at once unless the state
-      // level l would start from says the traversal is over, so the last report already
-      // finds the rows final
-      [&](int32_t l) { return launch_mb_depth(s, a, l, rows); }, a.ctrl, cap,
-      cap < int64_t(g->V) + 2 ? DOBFS_ERR_UNSUPPORTED : DOBFS_ERR_INTERNAL, stats, &res);
+  st = run_steps(g->last_steps_mb, s, timing, ev, BatchSteps{a, rows}, a.ctrl, a.nwords, max_steps, cap,
+                 cap < int64_t(g->V) + 2 ? DOBFS_ERR_UNSUPPORTED : DOBFS_ERR_INTERNAL, sink, nullptr, stats, &res);
   if (st != DOBFS_OK) return st;
   if (!stats) return DOBFS_OK;
   HIPCK(hipEventRecord(ev[kEvEnd], s));

@@ -10,9 +10,12 @@
 // covered. Operand reuse (Section 5.4) holds bit by bit: for every source the
 // visited set read by the pull stands in for that source's frontier.
 //
-// Levels are laid out as in the single-source path: mb_prep decides the
-// direction on the device and, for push, lists the frontier vertices with
-// their degree prefix; mb_main runs the expansion or the pull. The frontier
+// Levels run as steps, one launch each, as in the single-source path: a pull
+// level is one step, a push level two (the scan step lists the frontier
+// vertices with their degree prefix, the expansion step pushes). Every block
+// of a step derives the step's state from the state the step before published
+// and the counters it left, so the direction is decided on the device inside
+// the level's own kernel. The frontier
 // words of a level are exactly the (vertex, source) pairs first reached at
 // that level, so those of the first kMbSnap levels are kept and are the depth
 // record; deeper levels stamp a vertex-major [V][k] uint16 level table.
@@ -41,10 +44,12 @@ __device__ __forceinline__ void stamp_levels(uint16_t* lvl, int32_t k, int32_t v
 }
 
 // ----------------------------------------------------------------- init
-// Visited and level-0/1 frontier words start cleared (16-byte stores; the
-// level-0 prep then sets the source bits, after this kernel, so no store here
-// needs to know where the sources are), and the control block starts a push
-// level whose list is the distinct sources.
+// Visited and level-0/1 frontier words start cleared (16-byte stores), then
+// take the source bits (depth 0): bit b of Vis and of level 0's frontier at
+// sources[b]. The thread that cleared a source's pair of words sets its bit,
+// after its own clear, so no other thread's store can come between. The
+// control block starts level 0 (a push whose list is the distinct sources,
+// unless the level is forced to pull).
 __global__ __launch_bounds__(kThreads) void k_mb_init(BatchArgs a, int32_t dir0, int64_t nflags) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -62,6 +67,27 @@ __global__ __launch_bounds__(kThreads) void k_mb_init(BatchArgs a, int32_t dir0,
     a.vis[0][a.V - 1] = 0ull;
     a.Fs[a.V - 1] = 0ull;
     a.Fs[a.fstride + a.V - 1] = 0ull;
+  }
+  // The grid is a power of two, so the thread that cleared pair i is i mod stride (pair
+  // npair is the last vertex of an odd V, which thread 0 cleared). Lane b of every wave takes
+  // source b and the wave picks out the sources whose clearing thread is one of its own lanes;
+  // those few are set one by one, each by its clearing lane.
+  const int64_t mask = stride - 1;
+  auto owner_of = [&](int32_t v) -> int64_t {
+    const int64_t pair = int64_t(v) / 2;
+    return pair < npair ? (pair & mask) : 0;
+  };
+  const int ln = lane();
+  const int32_t sv = ln < a.k ? a.src[ln] : 0;
+  uint64_t here = __ballot(ln < a.k && (owner_of(sv) >> 6) == (t0 >> 6));
+  while (here) {
+    const int b = __ffsll((unsigned long long)here) - 1;
+    here &= here - 1;
+    const int32_t v = __shfl(sv, b, 64);
+    if (owner_of(v) == t0) {
+      a.vis[0][v] |= 1ull << b;
+      a.Fs[v] |= 1ull << b;
+    }
   }
   for (int64_t k = t0; k < nflags; k += stride) {
     a.flagsA[k] = 0;
@@ -83,6 +109,8 @@ __global__ __launch_bounds__(kThreads) void k_mb_init(BatchArgs a, int32_t dir0,
         c->qcount[s] = 0;
         c->mf[s] = 0;
       }
+      c->bar.abort = 0;  // read by the report (no grid barrier waits here)
+      c->bar.t_end = 0;
       LevelState st;
       st.dir = dir0;
       st.done = 0;
@@ -93,8 +121,10 @@ __global__ __launch_bounds__(kThreads) void k_mb_init(BatchArgs a, int32_t dir0,
       st.level = 0;
       st.local = 0;
       st.share = 1;
+      st.phase = dir0 == 0 ? kPhaseScan : kPhaseWhole;
       st.m_u = a.nnz;  // in-edges of vertices some source has not reached yet
       st.active = a.active;
+      st.t0 = 0;
       c->ring[0] = st;
     }
   }
@@ -111,13 +141,16 @@ struct MbExpandShared {
 // adjacency carries F[u]'s source bits to w. The bits w had not seen when the
 // level began are claimed with one 64-bit atomicOr on w's next-frontier word
 // (Vis is not written during the level: the next frontier is exactly what it
-// gains, merged in by the next level's prep); the bits a thread newly set are
+// gains, merged in by the next level's first step); the bits a thread newly set are
 // its own to count, and the thread whose add made the word nonzero lists w
 // for the next level. The chunked, load-balanced walk over the edges is the
 // one of the single-source expansion.
-__device__ void mb_expand_body(const BatchArgs& a, int32_t L, const LevelState& st, MbExpandShared& sh) {
+// The expansion step s of level st.level: m_f from the scan step before it, counters into
+// slot s.
+__device__ void mb_expand_body(const BatchArgs& a, const LevelState& st, int32_t s, MbExpandShared& sh) {
+  const int32_t L = st.level;
   const int32_t nf = st.nf;
-  const uint32_t m = a.ctrl->mf[L % kSlots];
+  const uint32_t m = a.ctrl->mf[s % kSlots];
   if (nf <= 0 || m == 0) return;
   const uint32_t nchunks = (m + kExpandChunk - 1) / kExpandChunk;
   if (blockIdx.x >= nchunks) return;
@@ -126,7 +159,7 @@ __device__ void mb_expand_body(const BatchArgs& a, int32_t L, const LevelState& 
   const uint64_t* Fc = mb_frontier(a, L);
   uint64_t* Fn = mb_frontier(a, L + 1);
   uint64_t* vis = a.vis[st.vis_idx];
-  uint32_t* qcount = &a.ctrl->qcount[(L + 1) % kSlots];
+  uint32_t* qcount = &a.ctrl->qcount[s % kSlots];
   uint32_t* nzn = a.nzF[(L + 1) % 2];
   const bool marks = mb_push_marks(m);  // winners go to the non-zero bitmap, not the list
   const uint64_t active = a.active;
@@ -197,7 +230,7 @@ __device__ void mb_expand_body(const BatchArgs& a, int32_t L, const LevelState& 
       listed[t] = false;
       if (x[t]) {
         // the next frontier word collects exactly the bits w gains at this level, so it is the
-        // only word claimed here; the visited words take them in the next level's prep
+        // only word claimed here; the visited words take them in the next level's first step
         const uint64_t oldf = atomicOr((unsigned long long*)(Fn + w[t]), (unsigned long long)x[t]);
         const uint64_t nb = x[t] & ~oldf;
         if (nb) {
@@ -234,11 +267,11 @@ __device__ void mb_expand_body(const BatchArgs& a, int32_t L, const LevelState& 
   block_sum4(v4);
   fbits = block_or64(fbits);
   if (threadIdx.x == 0) {
-    stripe_or(&a.ctrl->slot[L % kSlots], fbits);
+    stripe_or(&a.ctrl->slot[s % kSlots], fbits);
     unsigned long long edges = 0;
     for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x)
       edges += min(uint32_t(kExpandChunk), m - c * kExpandChunk);
-    stripe_add(&a.ctrl->slot[L % kSlots], v4[0], v4[1], edges, v4[2], v4[3]);
+    stripe_add(&a.ctrl->slot[s % kSlots], v4[0], v4[1], edges, v4[2], v4[3]);
   }
 }
 
@@ -258,18 +291,19 @@ struct MbPullShared {
 // A thread takes a row's slab (first kSlab in-neighbours, one read), then the
 // row up to kMbMid in-neighbours, then a wave finishes it, 64 per step. The
 // tile's new visited words (old | found), next-frontier words and nonzero
-// bits are written whole; no atomics touch them.
-__device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st, int32_t tile,
+// bits are written whole; no atomics touch them. Step s's counters go to slot s.
+__device__ void mb_pull_body(const BatchArgs& a, const LevelState& st, int32_t s, int32_t tile,
                              MbPullShared& sh) {
   const int tid = threadIdx.x;
+  const int32_t L = st.level;
   const int32_t w0 = tile * kMbTileWords;
   const int32_t v0 = w0 * 32;
   const uint64_t* vin = a.vis[st.vis_idx];
   uint64_t* vout = a.vis[st.vis_idx ^ 1];
   uint64_t* Fn = mb_frontier(a, L + 1);
   const uint64_t active = st.active;  // a source with an empty frontier finds nothing more
-  // after a push, vin lacks this level's frontier words (the prep leaves the merge to this
-  // pull): a row's own word is vin | Fc, and the in-neighbours' words are read from Fc, which for
+  // after a push, vin lacks this level's frontier words (the merge is left to this pull):
+  // a row's own word is vin | Fc, and the in-neighbours' words are read from Fc, which for
   // every source bit a row still needs holds the same bits as the merged words (a source's
   // visited in-neighbour of a row it has not reached was reached at this level, Section 5.4)
   const bool merge = st.local == 1;
@@ -402,39 +436,61 @@ __device__ void mb_pull_body(const BatchArgs& a, int32_t L, const LevelState& st
   block_sum4(i4);
   fbits = block_or64(fbits);
   if (tid == 0) {
-    stripe_add(&a.ctrl->slot[L % kSlots], v4[0], v4[1], v4[2], v4[3], i4[0]);
-    stripe_or(&a.ctrl->slot[L % kSlots], fbits);
+    stripe_add(&a.ctrl->slot[s % kSlots], v4[0], v4[1], v4[2], v4[3], i4[0]);
+    stripe_or(&a.ctrl->slot[s % kSlots], fbits);
   }
 }
 
-// --------------------------------------------------------- level kernels
-// First kernel of level L: the state (direction rule on vertex counts and
-// edge counts of the whole batch), the previous level's record, and for a
-// push level the frontier list with its degree prefix. Before a push level
-// adds into the next frontier buffer, the buffer is cleared: densely when it
-// is one of this traversal's fresh buffers, else (it holds the frontier of
-// two levels back) sparsely through that level's list when it has one.
-__global__ __launch_bounds__(kThreads) void k_mb_prep(BatchArgs a, int32_t L, int32_t forced) {
-  Ctrl* c = a.ctrl;
-  LevelTotals tot;
-  LevelState prev;
-  LevelState st = level_state(a, L, forced, &tot, &prev);
-  // a pull after a push merges the push's winners into the visited words itself (local = 1)
-  st.local = (L >= 1 && !st.done && st.dir == 1 && prev.dir == 0) ? 1 : 0;
-  publish_level(c, L, st, prev, tot);
-  if (L == 0 && blockIdx.x == 0 && int32_t(threadIdx.x) < a.k) {
-    // the sources: bit b of Vis and of level 0's frontier at sources[b] (depth 0)
-    const int32_t v = a.src[threadIdx.x];
-    const unsigned long long bit = 1ull << threadIdx.x;
-    atomicOr(reinterpret_cast<unsigned long long*>(a.vis[0] + v), bit);
-    atomicOr(reinterpret_cast<unsigned long long*>(a.Fs + v), bit);
+// ---------------------------------------------------------- step loop
+// One launch per step. Every block derives step s's state from the state step
+// s-1 published and the counters it left (one round trip): the expansion that
+// a scan step prepared, or a new level, whose direction the rule of Section
+// 6.3 (or the edge form) decides on the counts of the whole batch. The
+// counters of step s gather in slot s % kSlots; step s clears slot
+// (s + 2) % kSlots, which nothing touches until step s + 2.
+__device__ __forceinline__ LevelState mb_step_state(const BatchArgs& a, int32_t s, LevelTotals* tot,
+                                                    LevelState* prev_out, bool* new_level) {
+  const Ctrl* c = a.ctrl;
+  *new_level = false;
+  *tot = LevelTotals{0, 0, 0, 0, 0, 0};
+  if (s == 0) {  // level 0 as the init kernel left it
+    const LevelState st = c->ring[0];
+    *prev_out = st;
+    return st;
   }
-  if (L >= 1 && !st.done && prev.dir == 0 && st.dir == 0) {
-    // a push leaves Vis as the level began: before another push, merge in what it found, through
-    // its list when it made a short one, else in one dense pass (random lines of two arrays cost
-    // more than a sweep)
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const StripeLanes x = load_stripes(c->slot[(s - 1) % kSlots]);
+  const LevelState prev = c->ring[(s - 1) % kRing];
+  stripes_needed(x);
+  *prev_out = prev;
+  if (prev.done) return prev;  // past the end
+  if (prev.phase == kPhaseScan) {  // the expansion the scan step prepared
+    LevelState st = prev;
+    st.phase = kPhaseExpand;
+    return st;
+  }
+  const int32_t L = prev.level + 1;
+  const int32_t forced = L < a.n_forced ? int32_t(c->forced[L]) : -1;
+  *new_level = true;
+  LevelState st = next_state(a, L, forced, prev, x, (s - 1) % kSlots, tot);
+  // a pull after a push merges the push's winners into the visited words itself
+  st.local = (!st.done && st.dir == 1 && prev.dir == 0) ? 1 : 0;
+  return st;
+}
+
+// The scan step of push level L = st.level (prev: the state of level L-1). A push leaves Vis
+// as its level began, so before another push what it found is merged in, through its list
+// when it made a short one, else in one dense pass (random lines of two arrays cost more than
+// a sweep). The next frontier's buffer and non-zero bitmap are cleared: the buffer densely
+// when it is one of this traversal's fresh buffers, else (it holds the frontier of two levels
+// back) sparsely through that level's list. Then the frontier list with its degree prefix
+// (Section 6.2), from the list the push before left or from the non-zero bitmap; m_f goes
+// where the expansion step reads it.
+__device__ void mb_scan_step(const BatchArgs& a, const LevelState& st, const LevelState& prev, int32_t s) {
+  Ctrl* c = a.ctrl;
+  const int32_t L = st.level;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (L >= 1 && prev.dir == 0) {
     const int32_t* Qc = a.Q[L % 2];
     const uint64_t* Fc = mb_frontier(a, L);
     uint64_t* vis = a.vis[st.vis_idx];
@@ -470,15 +526,12 @@ __global__ __launch_bounds__(kThreads) void k_mb_prep(BatchArgs a, int32_t L, in
       }
     }
   }
-  if (st.done || st.dir != 0) return;
   {  // the non-zero bitmap of the next frontier, in case this push marks its winners there
     uint32_t* nzn = a.nzF[(L + 1) % 2];
     for (int32_t w = blockIdx.x * kThreads + threadIdx.x; w < a.nwords; w += gridDim.x * kThreads) nzn[w] = 0;
   }
   uint64_t* Fn = mb_frontier(a, L + 1);
   if (L >= 1) {  // level 1's buffer is cleared by the init kernel
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (mb_frontier_recycled(L + 1) && (prev.list_valid || prev.dir == 0)) {
       // a push level always had its frontier as a list
       const int32_t* Qp = a.Q[(L + 1) % 2];
@@ -489,10 +542,10 @@ __global__ __launch_bounds__(kThreads) void k_mb_prep(BatchArgs a, int32_t L, in
       for (int64_t i = t0; i < (int64_t(a.V) + 1) / 2; i += stride) F2[i] = z;
     }
   }
-  uint32_t* mf_out = &c->mf[L % kSlots];
+  uint32_t* mf_out = &c->mf[(s + 1) % kSlots];
   if (st.list_valid) {
-    scan_list(a.Q[L % 2], st.nf, a.rowptr, a.S, a.R, a.chunk_first, a.flagsA, uint32_t(2 * L + 1),
-              &c->ticket[L % 2], mf_out);
+    scan_list(a.Q[L % 2], st.nf, a.rowptr, a.S, a.R, a.chunk_first, a.flagsA, uint32_t(2 * s + 1),
+              &c->ticket[s % 2], mf_out);
   } else {
     ScanBitsArgs sb{};
     sb.a = a.nzF[L % 2];
@@ -506,9 +559,9 @@ __global__ __launch_bounds__(kThreads) void k_mb_prep(BatchArgs a, int32_t L, in
     sb.chunk_first = a.chunk_first;
     sb.flagsA = a.flagsA;
     sb.flagsB = a.flagsB;
-    sb.epochA = uint32_t(2 * L + 1);
-    sb.epochB = uint32_t(2 * L + 2);
-    sb.ticket = &c->ticket[L % 2];
+    sb.epochA = uint32_t(2 * s + 1);
+    sb.epochB = uint32_t(2 * s + 2);
+    sb.ticket = &c->ticket[s % 2];
     sb.nf_out = &c->nf32;
     sb.mf_out = mf_out;
     scan_bits(sb);
@@ -520,17 +573,23 @@ union MbShared {
   MbPullShared p;
 };
 
-__global__ __launch_bounds__(kThreads) void k_mb_main(BatchArgs a, int32_t L) {
+__global__ __launch_bounds__(kThreads) void k_mb_step(BatchArgs a, int32_t s) {
   __shared__ MbShared sh;
-  const LevelState st = a.ctrl->ring[L % kRing];
+  LevelTotals tot;
+  LevelState prev;
+  bool new_level;
+  const LevelState st = mb_step_state(a, s, &tot, &prev, &new_level);
+  if (blockIdx.x == 0) publish_step(a.ctrl, s, st, prev, tot, new_level);
   if (st.done) return;
-  if (st.dir == 0) {
-    mb_expand_body(a, L, st, sh.e);
+  if (st.phase == kPhaseScan) {
+    mb_scan_step(a, st, prev, s);
+  } else if (st.dir == 0) {
+    mb_expand_body(a, st, s, sh.e);
   } else {
     const int32_t ntiles = (a.nwords + kMbTileWords - 1) / kMbTileWords;
     for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
       __syncthreads();  // LDS of the previous tile is no longer read
-      mb_pull_body(a, L, st, t, sh.p);
+      mb_pull_body(a, st, s, t, sh.p);
     }
   }
 }
@@ -545,8 +604,8 @@ __global__ __launch_bounds__(kThreads) void k_mb_main(BatchArgs a, int32_t L) {
 // only where a pair was first reached at level kMbSnap or later.
 constexpr int kMbDepthVPT = 4;
 static_assert(kMbSnap <= 16, "depths of the kept levels are folded into four bit planes");
-__global__ __launch_bounds__(kThreads) void k_mb_depth(BatchArgs a, int32_t level, DepthRows rows) {
-  const LevelState end = a.ctrl->ring[level % kRing];
+__global__ __launch_bounds__(kThreads) void k_mb_depth(BatchArgs a, int32_t step, DepthRows rows) {
+  const LevelState end = a.ctrl->ring[step % kRing];
   if (!end.done) return;  // not over yet: a later batch's transpose writes the rows
   // the final visited words: the state that found the end keeps the last level's direction and
   // buffer index, and a last pull wrote its result to the other buffer (merged with what the push
@@ -646,25 +705,22 @@ __global__ __launch_bounds__(kThreads) void k_mb_depth(BatchArgs a, int32_t leve
 hipError_t launch_mb_init(hipStream_t s, const BatchArgs& a, int32_t dir0, int64_t nflags, hipEvent_t t0,
                          hipEvent_t t1) {
   const int64_t n = std::max<int64_t>(int64_t(a.V) / 2 + 1, nflags);
-  const unsigned g = unsigned(std::min<int64_t>((n + kThreads - 1) / kThreads, 8192));
-  return launch_k(k_mb_init, dim3(g > 0 ? g : 1), s, t0, t1, a, dir0, nflags);
+  const int64_t want = std::min<int64_t>((n + kThreads - 1) / kThreads, 8192);
+  unsigned g = 1;  // a power of two (the kernel finds a source's clearing thread with a mask)
+  while (int64_t(g) < want) g *= 2;
+  return launch_k(k_mb_init, dim3(g), s, t0, t1, a, dir0, nflags);
 }
 
-hipError_t launch_mb_prep(hipStream_t s, const BatchArgs& a, int32_t level, int32_t forced_dir,
-                         hipEvent_t t0, hipEvent_t t1) {
-  return launch_k(k_mb_prep, dim3(unsigned(scan_grid(a.V))), s, t0, t1, a, level, forced_dir);
-}
-
-hipError_t launch_mb_main(hipStream_t s, const BatchArgs& a, int32_t level, hipEvent_t t0, hipEvent_t t1) {
+hipError_t launch_mb_step(hipStream_t s, const BatchArgs& a, int32_t step, hipEvent_t t0, hipEvent_t t1) {
   const int64_t tiles = (int64_t(a.nwords) + kMbTileWords - 1) / kMbTileWords;
   const dim3 g(unsigned(std::max<int64_t>(kExpandBlocks, tiles)));
-  return launch_k(k_mb_main, g, s, t0, t1, a, level);
+  return launch_k(k_mb_step, g, s, t0, t1, a, step);
 }
 
-hipError_t launch_mb_depth(hipStream_t s, const BatchArgs& a, int32_t level, const DepthRows& rows) {
+hipError_t launch_mb_depth(hipStream_t s, const BatchArgs& a, int32_t step, const DepthRows& rows) {
   const int64_t groups = (int64_t(a.V) + kMbDepthVPT - 1) / kMbDepthVPT;
   const unsigned g = unsigned(std::min<int64_t>((groups + kThreads - 1) / kThreads, 4096));
-  hipLaunchKernelGGL(k_mb_depth, dim3(g > 0 ? g : 1), dim3(kThreads), 0, s, a, level, rows);
+  hipLaunchKernelGGL(k_mb_depth, dim3(g > 0 ? g : 1), dim3(kThreads), 0, s, a, step, rows);
   return hipGetLastError();
 }
 

@@ -432,46 +432,74 @@ __host__ __device__ constexpr bool is_batch(const BatchArgs&) { return true; }
 // loads; this measured several microseconds faster per launch than one wave
 // computing it and broadcasting it through LDS. All blocks of a level_prep
 // compute the same state.
-// The counters one level left, one stripe per lane (lanes past kStripes read nothing).
+// The counters one level left, spread over the lanes for the wave reductions: every block's
+// waves read them at the start of a step, so the read is laid out for the fewest cache lines
+// per load. Lane j reads bytes 16 (j % 4) .. 16 (j % 4) + 15 of stripes j / 4 and 16 + j / 4
+// (the 56 bytes of counters start every 128-byte stripe): two 16-byte loads touching 16 lines
+// each, where one stripe per lane and field took seven loads of 32 lines. A lane holds the
+// combined value of its two stripes for the fields in its quarter, zero for the others.
+static_assert(kStripes == 32 && sizeof(Stripe) == 128, "two loads of 16 stripes");
+static_assert(offsetof(Stripe, edges) == 8 && offsetof(Stripe, mnew) == 16 && offsetof(Stripe, insub) == 24 &&
+                  offsetof(Stripe, fbits) == 32 && offsetof(Stripe, mu) == 40 &&
+                  offsetof(Stripe, maxdeg) == 48 && offsetof(Stripe, tilemax) == 52,
+              "stripe counters in four 16-byte quarters");
 struct StripeLanes {
-  uint64_t v0, v1, v2, v3, v4, v6;  // count | aux << 32, edges, mnew, insub, fbits, mu
-  uint32_t v5, v7;                  // maxdeg, tilemax
+  uint64_t count, aux, edges, mnew, insub, fbits, mu;
+  uint32_t maxdeg, tilemax;
 };
 __device__ __forceinline__ StripeLanes load_stripes(const LevelSlot& sl) {
   const int k = lane();
-  const Stripe* sk = &sl.s[k & (kStripes - 1)];
-  const bool mine = k < kStripes;
+  const int q = k & 3;
+  const ulonglong2 x0 = reinterpret_cast<const ulonglong2*>(&sl.s[k >> 2])[q];
+  const ulonglong2 x1 = reinterpret_cast<const ulonglong2*>(&sl.s[16 + (k >> 2)])[q];
   StripeLanes x;
-  x.v0 = mine ? uint64_t(sk->count) | (uint64_t(sk->aux) << 32) : 0ull;
-  x.v1 = mine ? sk->edges : 0ull;
-  x.v2 = mine ? sk->mnew : 0ull;
-  x.v3 = mine ? sk->insub : 0ull;
-  x.v4 = mine ? sk->fbits : 0ull;
-  x.v5 = mine ? sk->maxdeg : 0u;
-  x.v6 = mine ? sk->mu : 0ull;
-  x.v7 = mine ? sk->tilemax : 0u;
+  x.count = q == 0 ? (x0.x & 0xffffffffull) + (x1.x & 0xffffffffull) : 0ull;
+  x.aux = q == 0 ? (x0.x >> 32) + (x1.x >> 32) : 0ull;
+  x.edges = q == 0 ? x0.y + x1.y : 0ull;
+  x.mnew = q == 1 ? x0.x + x1.x : 0ull;
+  x.insub = q == 1 ? x0.y + x1.y : 0ull;
+  x.fbits = q == 2 ? (x0.x | x1.x) : 0ull;
+  x.mu = q == 2 ? x0.y + x1.y : 0ull;
+  x.maxdeg = q == 3 ? max(uint32_t(x0.x), uint32_t(x1.x)) : 0u;
+  x.tilemax = q == 3 ? max(uint32_t(x0.x >> 32), uint32_t(x1.x >> 32)) : 0u;
   return x;
+}
+// The wave's total of a count whose total is below 2^32, as a scalar.
+__device__ __forceinline__ uint64_t wave_total(uint64_t v) {
+  return uint64_t(__builtin_amdgcn_readfirstlane(wave_sum(uint32_t(v))));
+}
+// Marks the counters as needed here, so that their loads go out together with the load of
+// the previous state (the compiler would otherwise sink them into the branch that starts a
+// level, a round trip later).
+__device__ __forceinline__ void stripes_needed(const StripeLanes& x) {
+  asm volatile("" ::"v"(x.count), "v"(x.mnew), "v"(x.fbits), "v"(x.maxdeg));
 }
 
 // The state entering level L from the state entering L-1 (prev) and the
 // counters L-1 left (x): the direction rule of Section 6.3 (or Beamer's edge
 // form), forced directions and mode overrides, buffer parities, and whether
 // a push can share out its own work.
+// prev_slot: the counter slot of the step that ended level L-1 (multi-source: its m_f tells
+// whether that push listed its winners or marked them).
 template <class Args>
 __device__ LevelState next_state(const Args& a, int32_t L, int32_t forced, const LevelState& prev,
-                                 const StripeLanes& x, LevelTotals* tot_out) {
+                                 const StripeLanes& x, int32_t prev_slot, LevelTotals* tot_out) {
   LevelTotals t{0, 0, 0, 0, 0, 0};
   LevelState st = prev;
   st.level = L;
   if (!prev.done) {
-    // each cross-lane reduction costs a few hundred cycles of a launch every level runs, so
-    // only the totals this traversal and level use are formed (the branches are uniform)
+    // each cross-lane reduction costs a few hundred cycles in every wave of a launch every
+    // level runs, so only the totals this traversal and level use are formed (the branches
+    // are uniform): the ones that decide the level in every block, the record's (edges,
+    // pairs) only in block 0, which publishes it. Vertex and edge totals are below 2^31
+    // (int32 vertex ids and CSR offsets), so they add up in 32 bits.
     constexpr bool batch = is_batch(Args{});
-    t.count = uniform64(wave_sum64(x.v0 & 0xffffffffull));
-    t.edges = uniform64(wave_sum64(x.v1));
-    t.mnew = uniform64(wave_sum64(x.v2));
-    if (batch) t.aux = uniform64(wave_sum64(x.v0 >> 32));
-    if (a.edge_rule) t.insub = uniform64(wave_sum64(x.v3));
+    const bool record = blockIdx.x == 0;
+    t.count = wave_total(x.count);
+    t.mnew = wave_total(x.mnew);
+    if (record) t.edges = wave_total(x.edges);
+    if (batch && record) t.aux = uniform64(wave_sum64(x.aux));
+    if (a.edge_rule) t.insub = wave_total(x.insub);
     if (t.count == 0) {
       st.done = 1;
       st.levels = L;
@@ -480,7 +508,7 @@ __device__ LevelState next_state(const Args& a, int32_t L, int32_t forced, const
       // m_u loses the in-edges of each push level's winners; pulls leave it alone, and the
       // push that follows a pull recounts it (single source)
       const bool recounted = recounts_mu(a) && prev.dir == 0 && !prev.list_valid;
-      if (recounted) t.mu = uniform64(wave_sum64(x.v6));
+      if (recounted) t.mu = wave_total(x.mu);
       const int64_t m_u = (recounted ? int64_t(t.mu) : prev.m_u) - (a.edge_rule ? int64_t(t.insub) : 0);
       int32_t next = next_direction_rule(a.heuristic, a.alpha, a.beta, prev.dir, a.V, prev.nf, n_new,
                                          int64_t(t.mnew), m_u);
@@ -490,10 +518,10 @@ __device__ LevelState next_state(const Args& a, int32_t L, int32_t forced, const
       st.dir = next;
       st.nf = int32_t(n_new);
       // a push level appended its winners to Q[L % 2], unless (multi-source) it marked them
-      st.list_valid = (prev.dir == 0 && !(batch && mb_push_marks(a.ctrl->mf[(L - 1) % kSlots]))) ? 1 : 0;
+      st.list_valid = (prev.dir == 0 && !(batch && mb_push_marks(a.ctrl->mf[prev_slot]))) ? 1 : 0;
       st.vis_idx = prev.dir == 1 ? (prev.vis_idx ^ 1) : prev.vis_idx;
       st.m_u = m_u;
-      st.active = batch ? uniform64(wave_or64(x.v4)) : 0ull;
+      st.active = batch ? uniform64(wave_or64(x.fbits)) : 0ull;
       // a push needs no global scan when its frontier's edges can be shared out inside
       // blocks: a list from a push whose sizes local_fits() accepts (local 1), or the bits a
       // pull left when no tile found more than sched.bitmap_rows rows and none of high
@@ -506,14 +534,14 @@ __device__ LevelState next_state(const Args& a, int32_t L, int32_t forced, const
           // rule needs no m_f; then kLocalDeg bounds them
           const bool tracked = a.edge_rule || !a.low_degree;
           const int64_t mf_b = tracked ? int64_t(t.mnew) : INT64_MAX;
-          const int64_t md_b = tracked ? int64_t(__builtin_amdgcn_readfirstlane(wave_max32(x.v5))) : int64_t(kLocalDeg);
+          const int64_t md_b = tracked ? int64_t(__builtin_amdgcn_readfirstlane(wave_max32(x.maxdeg))) : int64_t(kLocalDeg);
           const int64_t G = main_blocks(a.nwords);
           if (a.low_degree || local_fits(n_new, mf_b, md_b, G, a.sched.local_unit, a.sched.local_chunks)) {
             st.local = 1;
             st.share = local_share(n_new, mf_b, md_b, G, a.sched.local_unit);
           }
         } else {
-          const uint32_t tm = __builtin_amdgcn_readfirstlane(wave_max32(x.v7));
+          const uint32_t tm = __builtin_amdgcn_readfirstlane(wave_max32(x.tilemax));
           st.local = tm <= uint32_t(a.sched.bitmap_rows) ? 2 : 0;
         }
       }
@@ -542,7 +570,7 @@ __device__ LevelState level_state(const Args& a, int32_t L, int32_t forced, Leve
   const StripeLanes x = load_stripes(c->slot[(L - 1) % kSlots]);
   const LevelState prev = c->ring[(L - 1) % kRing];
   *prev_out = prev;
-  return next_state(a, L, forced, prev, x, tot_out);
+  return next_state(a, L, forced, prev, x, (L - 1) % kSlots, tot_out);
 }
 
 // Block 0 of level L's first kernel: publish the level's state and the
@@ -574,6 +602,36 @@ __device__ void publish_level(Ctrl* c, int32_t L, const LevelState& st, const Le
     c->ticket[(L + 1) % 2] = 0;
   }
   for (int k = threadIdx.x; k < kStripes; k += blockDim.x) zero_stripe(c->slot[(L + 1) % kSlots].s[k]);
+}
+
+// The record of the level before the one step s starts (prev is that level's state).
+__device__ __forceinline__ LevelRecord step_record(const Ctrl* c, int32_t s, const LevelState& prev,
+                                                   const LevelTotals& tot) {
+  LevelRecord r;
+  r.dir = prev.dir;
+  r.nf = prev.nf;
+  r.n_new = int32_t(tot.count);
+  r.variant = prev.dir == 0 ? prev.local : 0;
+  r.edges = int64_t(tot.edges);
+  // a scanned push level's m_f comes from its scan; a local one reads exactly its m_f edges
+  r.m_f = prev.dir == 0 ? (prev.local ? int64_t(tot.edges) : int64_t(c->mf[(s - 1) % kSlots])) : 0;
+  r.mnew = tot.mnew;
+  r.insub = tot.insub;
+  r.aux = tot.aux;
+  return r;
+}
+
+// Block 0: publish step s's state and, when it starts a level, the record of
+// the level before; clear what step s + 2 will count into.
+__device__ __forceinline__ void publish_step(Ctrl* c, int32_t s, const LevelState& st, const LevelState& prev,
+                             const LevelTotals& tot, bool new_level) {
+  if (threadIdx.x == 0) {
+    c->ring[s % kRing] = st;
+    if (new_level) c->rec[(st.level - 1) % kRing] = step_record(c, s, prev, tot);
+    c->qcount[(s + 2) % kSlots] = 0;
+    c->ticket[(s + 1) % 2] = 0;
+  }
+  for (int k = threadIdx.x; k < kStripes; k += blockDim.x) zero_stripe(c->slot[(s + 2) % kSlots].s[k]);
 }
 
 }  // namespace

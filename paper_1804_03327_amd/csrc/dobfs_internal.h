@@ -45,15 +45,16 @@ struct alignas(64) LevelState {
   int32_t levels;      // when done: number of levels run
   int32_t level;       // index of this level
   int32_t local;       // push level expanded with block-local load balancing, no global scan:
-                       // 1 over the frontier list, 2 over the bits the previous pull found
+                       // 1 over the frontier list, 2 over the bits the previous pull found;
+                       // multi-source pull: 1 when it merges the winners of the push before
   int32_t share;       // local 1: blocks that share one unit's edge chunks (local_share)
-  int32_t phase;       // single-source step loop: kPhaseWhole, kPhaseScan or kPhaseExpand
+  int32_t phase;       // step loops: kPhaseWhole, kPhaseScan or kPhaseExpand
   int64_t m_u;         // edge-count rule: in-edges of still-unvisited vertices
   uint64_t active;     // multi-source: sources whose frontier entering the level is non-empty
   uint64_t t0;         // single source, persistent loop: device clock when the step started
 };
 static_assert(sizeof(LevelState) == 64, "one state per 64-byte line");
-// What one step of the single-source loop does for its level: all of it
+// What one step of a step loop does for its level: all of it
 // (a pull, or a push that shares out its own work), or one of the two steps of
 // a push that needs the global degree scan.
 constexpr int32_t kPhaseWhole = 0, kPhaseScan = 1, kPhaseExpand = 2;
@@ -87,7 +88,7 @@ struct GridBar {
 };
 
 struct Ctrl {
-  unsigned long long ticket[2];  // scan tile tickets, one counter per level parity
+  unsigned long long ticket[2];  // scan tile tickets, one counter per level (or step) parity
   uint32_t mf32;                 // m_f of the latest frontier scan (expand reads it)
   uint32_t nf32;                 // frontier length of the latest bitmap scan
   int64_t src_outdeg;            // out-degree of the BFS source
@@ -98,7 +99,7 @@ struct Ctrl {
   LevelSlot slot[kSlots];
   LevelState ring[kRing];
   LevelRecord rec[kRing];
-  int8_t forced[kRing];          // single source: forced direction of levels 0 .. n_forced-1
+  int8_t forced[kRing];          // step loops: forced direction of levels 0 .. n_forced-1
   LevelSlot tail;                // after a traversal: out-degree sum of the reached vertices (edges)
   GridBar bar;                   // single source: the persistent loop's grid barrier
 };
@@ -337,6 +338,7 @@ struct BatchArgs {
   double alpha, beta;
   int32_t edge_rule;
   int32_t local_push;        // always 0: the multi-source push always scans
+  int32_t n_forced;          // levels whose direction Ctrl::forced fixes
   int32_t low_degree;        // unused here
   Sched sched;               // unused here (no local push)
   int32_t src[kMaxSources];  // source of bit b
@@ -447,21 +449,18 @@ hipError_t launch_steps(hipStream_t s, const BfsArgs& a, int32_t s_first, int32_
                         hipEvent_t t1 = nullptr);
 // Blocks of the persistent step loop that fit on the current device at once.
 hipError_t persistent_capacity(int32_t* blocks);
-hipError_t launch_report(hipStream_t s, const Ctrl* ctrl, int32_t l_first, int32_t n,
-                         HostReport* host, uint32_t seq);
 hipError_t launch_mb_init(hipStream_t s, const BatchArgs& a, int32_t dir0, int64_t nflags,
                          hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
-hipError_t launch_mb_prep(hipStream_t s, const BatchArgs& a, int32_t level, int32_t forced_dir,
-                         hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
-hipError_t launch_mb_main(hipStream_t s, const BatchArgs& a, int32_t level, hipEvent_t t0 = nullptr,
-                         hipEvent_t t1 = nullptr);
+// Step `step` of the multi-source step loop (k_mb_step).
+hipError_t launch_mb_step(hipStream_t s, const BatchArgs& a, int32_t step, hipEvent_t t0 = nullptr,
+                          hipEvent_t t1 = nullptr);
 // Destination of each source's depth row (int32[V], device).
 struct DepthRows {
   int32_t* row[kMaxSources];
 };
-// depth rows from the level table, when ring state `level` says the traversal
+// depth rows from the level table, when the state step `step` published says the traversal
 // is over (its vis_idx names the final visited words); otherwise nothing
-hipError_t launch_mb_depth(hipStream_t s, const BatchArgs& a, int32_t level, const DepthRows& rows);
+hipError_t launch_mb_depth(hipStream_t s, const BatchArgs& a, int32_t step, const DepthRows& rows);
 hipError_t launch_check_offsets(hipStream_t s, const int32_t* ptr, int32_t V, int64_t nnz,
                                 int32_t* err);
 hipError_t launch_check_indices(hipStream_t s, const int32_t* idx, int64_t nnz, int32_t V,

@@ -778,6 +778,7 @@ __device__ __forceinline__ LevelState step_state(const BfsArgs& a, int32_t s, Le
   }
   const StripeLanes x = load_stripes(c->slot[(s - 1) % kSlots]);
   const LevelState prev = c->ring[(s - 1) % kRing];
+  stripes_needed(x);
   *prev_out = prev;
   if (prev.done) return prev;  // past the end
   if (prev.phase == kPhaseScan) {  // the expansion the scan step prepared
@@ -788,24 +789,7 @@ __device__ __forceinline__ LevelState step_state(const BfsArgs& a, int32_t s, Le
   const int32_t L = prev.level + 1;
   const int32_t forced = L < a.n_forced ? int32_t(c->forced[L]) : -1;
   *new_level = true;
-  return next_state(a, L, forced, prev, x, tot);
-}
-
-// The record of the level before the one step s starts (prev is that level's state).
-__device__ __forceinline__ LevelRecord step_record(const Ctrl* c, int32_t s, const LevelState& prev,
-                                                   const LevelTotals& tot) {
-  LevelRecord r;
-  r.dir = prev.dir;
-  r.nf = prev.nf;
-  r.n_new = int32_t(tot.count);
-  r.variant = prev.dir == 0 ? prev.local : 0;
-  r.edges = int64_t(tot.edges);
-  // a scanned push level's m_f comes from its scan; a local one reads exactly its m_f edges
-  r.m_f = prev.dir == 0 ? (prev.local ? int64_t(tot.edges) : int64_t(c->mf[(s - 1) % kSlots])) : 0;
-  r.mnew = tot.mnew;
-  r.insub = tot.insub;
-  r.aux = tot.aux;
-  return r;
+  return next_state(a, L, forced, prev, x, (s - 1) % kSlots, tot);
 }
 
 // The last step of a batch writes the batch's report itself (block 0, right
@@ -840,19 +824,6 @@ __device__ __forceinline__ void step_report(const Ctrl* c, const StepReportArgs&
     __threadfence_system();
     __hip_atomic_store(&host->seq, rp.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
-}
-
-// Block 0: publish step s's state and, when it starts a level, the record of
-// the level before; clear what step s + 2 will count into.
-__device__ __forceinline__ void publish_step(Ctrl* c, int32_t s, const LevelState& st, const LevelState& prev,
-                             const LevelTotals& tot, bool new_level) {
-  if (threadIdx.x == 0) {
-    c->ring[s % kRing] = st;
-    if (new_level) c->rec[(st.level - 1) % kRing] = step_record(c, s, prev, tot);
-    c->qcount[(s + 2) % kSlots] = 0;
-    c->ticket[(s + 1) % 2] = 0;
-  }
-  for (int k = threadIdx.x; k < kStripes; k += blockDim.x) zero_stripe(c->slot[(s + 2) % kSlots].s[k]);
 }
 
 // The scan step of a push level: its frontier list with the degree prefix
@@ -1268,18 +1239,6 @@ __global__ void k_zero_slot(LevelSlot* slot) {
   for (int k = threadIdx.x; k < kStripes; k += blockDim.x) zero_stripe(slot->s[k]);
 }
 
-// Copies the state after a batch and the batch's level records into pinned
-// host memory, then publishes `seq` with a system-scope release.
-__global__ void k_report(const Ctrl* c, int32_t l_first, int32_t n, HostReport* host, uint32_t seq) {
-  for (int k = threadIdx.x; k < n; k += blockDim.x) host->rec[k] = c->rec[(l_first + k) % kRing];
-  if (threadIdx.x == 0) host->end = c->ring[(l_first + n) % kRing];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence_system();
-    __hip_atomic_store(&host->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-  }
-}
-
 __global__ __launch_bounds__(kThreads) void k_check_offsets(const int32_t* ptr, int32_t V, int64_t nnz,
                                                             int32_t* err) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
@@ -1423,11 +1382,6 @@ hipError_t launch_reached_degree(hipStream_t s, const int32_t* ptr, const int32_
   return hipGetLastError();
 }
 
-hipError_t launch_report(hipStream_t s, const Ctrl* ctrl, int32_t l_first, int32_t n,
-                         HostReport* host, uint32_t seq) {
-  hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, ctrl, l_first, n, host, seq);
-  return hipGetLastError();
-}
 
 hipError_t launch_check_offsets(hipStream_t s, const int32_t* ptr, int32_t V, int64_t nnz,
                                 int32_t* err) {

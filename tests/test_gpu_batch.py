@@ -85,8 +85,10 @@ def _check(hg, sources, d, st, tag):
     ecc = int(R.max())
     assert st.levels == ecc + 1, "%s: %d levels, oracle says %d" % (tag, st.levels, ecc + 1)
     assert st.reached == int((R >= 0).sum()), tag + ": reached pairs"
-    assert st.launches_main >= st.levels and st.launches_aux == st.launches_main + 1, tag + ": launch totals"
     lv = dobfs.stats_levels(st)
+    # one step per pull level, two per push level (scan, expansion), one that finds the end
+    pushes = sum(1 for x in lv if x["dir"] == PUSH)
+    assert st.launches_main >= st.levels + pushes + 1 and st.launches_aux == 0, tag + ": launch totals"
     for L, row in enumerate(lv):
         nf = int((R == L).any(axis=0).sum())
         n_new = int((R == L + 1).any(axis=0).sum())
@@ -206,6 +208,42 @@ def test_batch_forced_schedules_deep(graphs):
         _check(hg, srcs, d, st, tag)
         dirs = [x["dir"] for x in dobfs.stats_levels(st)]
         assert dirs == [int(x) for x in sc[: len(dirs)]], tag
+
+
+def test_batch_step_times(graphs):
+    """Timed steps: every level's pull or expansion step has a time, every push level's scan
+    step too (and only those), and the per-launch totals cover them; no second kernel kind."""
+    for name in ("rmat14", "lattice37"):
+        hg, g = graphs[name]
+        srcs = _sources(hg, 64, 17)
+        st = dobfs.make_stats(1024)
+        depth = torch.empty(64 * g.V, dtype=torch.int32, device="cuda")
+        dobfs.bfs_batch(g, srcs, depth, opt=dobfs.make_options("full", time_kernels=True), stats=st)
+        _check(hg, srcs, depth.cpu().numpy().reshape(64, g.V), st, name + " timed")
+        lv = dobfs.stats_levels(st)
+        assert all(x["ms_main"] > 0 for x in lv), name
+        assert all((x["ms_aux"] > 0) == (x["dir"] == PUSH) for x in lv), name
+        assert st.launches_aux == 0 and st.ms_aux_all == 0, name
+        assert st.ms_main_all >= sum(x["ms_main"] + x["ms_aux"] for x in lv) * (1 - 1e-5), name
+
+
+def test_batch_deep_path_past_the_state_ring():
+    """A 2600-vertex path: push levels take two steps each, so the step count passes the
+    device's ring of 1024 states several times; forced directions cover the first 1024 levels
+    only, later levels follow the rule."""
+    V = 2600
+    hg = gen.from_edges(V, np.arange(V - 1), np.arange(1, V), directed=False, name="path%d" % V)
+    g = upload(hg)
+    srcs = [0, V - 1, V // 2, 7]
+    for mode in ["push_only", "full"]:
+        _say("path%d %s" % (V, mode))
+        d, st = _run(g, srcs, dobfs.make_options(mode), cap=4096)
+        _check(hg, srcs, d, st, "path%d %s" % (V, mode))
+    sc = [PUSH, PULL, PULL] * 400  # 1200 levels asked for
+    d, st = _run(g, srcs, dobfs.make_options("push_only", forced_dirs=sc), cap=4096)
+    _check(hg, srcs, d, st, "path forced")
+    dirs = [x["dir"] for x in dobfs.stats_levels(st)]
+    assert dirs[:1024] == sc[:1024] and set(dirs[1024:]) == {PUSH}
 
 
 def test_batch_wide_pushes_deep():
