@@ -438,6 +438,18 @@ def measure_batched(args, heur, alpha, beta):
         qps_seq[with_parent] = 2 * 64 / (time.perf_counter() - t1)
         del r
     lat_ms = np.array(lat) * 1e3
+    # the same launches with the level loop as one persistent kernel per 64 steps
+    op = dobfs.make_options("full", heur, alpha, beta, persistent=True)
+    dobfs.bfs_batch(gb, srcs, depth, opt=op, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.batched_launches):
+        dobfs.bfs_batch(gb, srcs, depth, opt=op, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    loop = {"step_launches_ms_per_launch": round(1e3 * t_all / args.batched_launches, 4),
+            "persistent_ms_per_launch": round(1e3 * (time.perf_counter() - t1) / args.batched_launches, 4)}
+    rows_p = depth.cpu().numpy().reshape(64, gb.V)
+    assert np.array_equal(rows_p, d), "persistent multi-source rows differ from the step loop's"
     roof = batched_roofline(gb, hb, srcs, d, opt, ws, depth, stream, heur, alpha, beta)
     tuned = None
     if not args.no_autotune:
@@ -462,6 +474,7 @@ def measure_batched(args, heur, alpha, beta):
            "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
            "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 3),
            "launches": args.batched_launches, "rows_checked_against_oracle": 64,
+           "level_loop": loop,
            "roofline": roof,
            "autotuned_direction_rule": tuned}
     log("batched:", json.dumps(res))

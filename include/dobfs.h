@@ -139,10 +139,10 @@ enum {
                                   extended-launch events); fills the *_ms stats. In the
                                   persistent loop a level's time is the difference of the
                                   device clock at the starts of consecutive steps */
-  DOBFS_OPT_PERSISTENT = 2u /* single source: run the level loop as a persistent kernel (one
-                               launch runs up to 64 steps, co-resident blocks sized by the
-                               occupancy query, a grid barrier between steps) instead of one
-                               launch per step. Same results. On MI355X the barrier needs an
+  DOBFS_OPT_PERSISTENT = 2u /* dobfs_bfs, dobfs_bfs_static and dobfs_bfs_batch: run the level
+                               loop as a persistent kernel (one launch runs up to 64 steps,
+                               co-resident blocks sized by the occupancy query, a grid barrier
+                               between steps) instead of one launch per step. Same results. On MI355X the barrier needs an
                                agent-scope L2 write-back and invalidate per block (the XCDs' L2
                                caches are not coherent), which costs more than a kernel
                                boundary, so this is off by default. The environment variable

@@ -513,7 +513,8 @@ struct LoopResult {
 struct PersistentDevice {
   std::mutex mu;
   std::once_flag once;
-  int32_t capacity = 0;       // 0: the persistent loop is not available
+  int32_t capacity = 0;       // blocks of k_steps that fit at once; 0: the loop is not available
+  int32_t capacity_mb = 0;    // the same for k_mb_steps
   double ticks_per_ms = 0.0;  // device wall clock
 };
 PersistentDevice g_persistent[64];
@@ -522,11 +523,13 @@ PersistentDevice* persistent_device(int device) {
   if (device < 0 || device >= 64) return nullptr;
   PersistentDevice* d = &g_persistent[device];
   std::call_once(d->once, [d, device]() {
-    int32_t cap = 0;
+    int32_t cap = 0, cap_mb = 0;
     int khz = 0;
-    if (persistent_capacity(&cap) == hipSuccess &&
-        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0) {
+    if (persistent_capacity(&cap) == hipSuccess && persistent_capacity_mb(&cap_mb) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0 &&
+        cap_mb > 0) {
       d->capacity = cap;
+      d->capacity_mb = cap_mb;
       d->ticks_per_ms = double(khz);
     }
   });
@@ -543,10 +546,13 @@ uint32_t env_u32(const char* name, uint32_t dflt) {
 // How run_steps launches the steps of one traversal kind. step(): step k (rp: this step
 // also writes the batch's report, only where self_report); before_report(): what must run
 // after a batch's last step (k_last) and before its report; persistent(): the persistent
-// form of a batch (single source only).
+// form of a batch (rp as for step()); grid(): blocks of a step launch; capacity(): blocks of
+// the persistent kernel that fit at once.
 struct SingleSteps {
   const BfsArgs& a;
   static constexpr bool self_report = true;
+  int64_t grid() const { return main_blocks(a.nwords); }
+  static int32_t capacity(const PersistentDevice& d) { return d.capacity; }
   hipError_t step(hipStream_t s, int32_t k, hipEvent_t t0, hipEvent_t t1, const StepReportArgs* rp) const {
     return launch_step(s, a, k, t0, t1, rp);
   }
@@ -560,15 +566,17 @@ struct BatchSteps {
   const BatchArgs& a;
   const DepthRows& rows;
   static constexpr bool self_report = false;
+  int64_t grid() const { return std::max<int64_t>(kExpandBlocks, (int64_t(a.nwords) + kMbTileWords - 1) / kMbTileWords); }
+  static int32_t capacity(const PersistentDevice& d) { return d.capacity_mb; }
   hipError_t step(hipStream_t s, int32_t k, hipEvent_t t0, hipEvent_t t1, const StepReportArgs*) const {
     return launch_mb_step(s, a, k, t0, t1);
   }
   // the depth rows: a transpose that exits at once unless the state the batch's last step
   // published says the traversal is over, so the last report already finds the rows final
   hipError_t before_report(hipStream_t s, int32_t k_last) const { return launch_mb_depth(s, a, k_last, rows); }
-  hipError_t persistent(hipStream_t, int32_t, int32_t, int32_t, uint32_t, bool, const StepReportArgs&,
-                        hipEvent_t, hipEvent_t) const {
-    return hipErrorNotSupported;
+  hipError_t persistent(hipStream_t s, int32_t s_first, int32_t n, int32_t blocks, uint32_t spin_limit,
+                        bool timing, const StepReportArgs&, hipEvent_t t0, hipEvent_t t1) const {
+    return launch_mb_steps(s, a, s_first, n, blocks, spin_limit, timing, t0, t1);
   }
 };
 
@@ -580,12 +588,13 @@ struct BatchSteps {
 // at 4 and double. When timing, step k of a batch has events ev_m0(k) /
 // ev_m1(k); a level's scan step counts as its ms_aux, its other step as its
 // ms_main. With `pd` (persistent loop on that device) a batch is one launch of
-// k_steps running the batch's steps, with the same report; per-step times then
-// come from the device clock at each step's start (and the launch's end).
+// the persistent kernel running the batch's steps, with the same report;
+// per-step times then come from the device clock at each step's start (and the
+// launch's end).
 // max_levels: a traversal that reaches that many levels fails with too_deep.
 template <class Steps>
 dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool timing, hipEvent_t* ev,
-                       const Steps& S, const Ctrl* ctrl, int32_t nwords, int64_t max_steps, int64_t max_levels,
+                       const Steps& S, const Ctrl* ctrl, int64_t max_steps, int64_t max_levels,
                        dobfs_status too_deep, const ReportSink& sink, PersistentDevice* pd,
                        dobfs_stats* stats, LoopResult* res) {
   HostReport* rep = sink.host;
@@ -594,12 +603,12 @@ dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool tim
   int32_t batch = std::min(std::max(last_steps.load(std::memory_order_relaxed) + 1, 2), kMaxBatch);
   int32_t next_batch = 4;
   auto E = [&](int i) -> hipEvent_t { return timing ? ev[i] : nullptr; };
-  const int32_t blocks = pd ? int32_t(std::min<int64_t>(main_blocks(nwords),
-                                                        int64_t(env_u32("DOBFS_PERSIST_BLOCKS", uint32_t(pd->capacity)))))
-                            : 0;
+  const int32_t cap = pd ? Steps::capacity(*pd) : 0;
+  const int32_t blocks =
+      pd ? int32_t(std::min<int64_t>(S.grid(), int64_t(env_u32("DOBFS_PERSIST_BLOCKS", uint32_t(cap))))) : 0;
   const uint32_t spin_limit = env_u32("DOBFS_SPIN_LIMIT", 1u << 22);
-  if (pd && (blocks < 1 || blocks > pd->capacity))
-    return fail(DOBFS_ERR_INVALID_ARG, "persistent grid of %d blocks (1 .. %d fit)", blocks, pd->capacity);
+  if (pd && (blocks < 1 || blocks > cap))
+    return fail(DOBFS_ERR_INVALID_ARG, "persistent grid of %d blocks (1 .. %d fit)", blocks, cap);
   if (pd) batch = next_batch = kMaxBatch;  // a launch ends with the traversal: no steps past the end
   while (true) {
     if (s0 + batch > max_steps) batch = int32_t(max_steps - s0);
@@ -607,14 +616,15 @@ dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool tim
     // untimed, the batch's last step writes the report; timed, a report kernel follows the
     // steps so that every step's end event has completed when the host reads it
     const StepReportArgs rp{sink.dev, seq, int32_t(s0), rec_first};
+    const bool self = Steps::self_report && !timing;
     if (pd) {
       std::lock_guard<std::mutex> lk(pd->mu);
       HIPCK(S.persistent(s, int32_t(s0), batch, blocks, spin_limit, timing,
-                         timing ? StepReportArgs{nullptr, 0u, 0, 0} : rp, E(ev_m0(0)), E(ev_m1(0))));
-      if (timing) HIPCK(launch_step_report(s, ctrl, int32_t(s0), batch, rec_first, sink.dev, seq));
+                         self ? rp : StepReportArgs{nullptr, 0u, 0, 0}, E(ev_m0(0)), E(ev_m1(0))));
+      HIPCK(S.before_report(s, int32_t(s0 + batch - 1)));
+      if (!self) HIPCK(launch_step_report(s, ctrl, int32_t(s0), batch, rec_first, sink.dev, seq));
       HIPCK(fetch_report(sink, seq, s));
     } else {
-      const bool self = Steps::self_report && !timing;
       for (int32_t k = 0; k < batch; ++k)
         HIPCK(S.step(s, int32_t(s0 + k), E(ev_m0(k)), E(ev_m1(k)), (self && k == batch - 1) ? &rp : nullptr));
       HIPCK(S.before_report(s, int32_t(s0 + batch - 1)));
@@ -840,7 +850,7 @@ dobfs_status bfs_steps(dobfs_graph g, int32_t source, const dobfs_options& opt, 
     pd = persistent_device(g->device);
     if (!pd) return fail(DOBFS_ERR_UNSUPPORTED, "the persistent level loop is not available on device %d", g->device);
   }
-  dobfs_status st = run_steps(g->last_steps, s, timing, ev, SingleSteps{a}, a.ctrl, a.nwords, max_steps,
+  dobfs_status st = run_steps(g->last_steps, s, timing, ev, SingleSteps{a}, a.ctrl, max_steps,
                               INT64_MAX, DOBFS_ERR_INTERNAL, sink, pd, stats, &res);
   if (st != DOBFS_OK) return st;
   if (stats) {
@@ -1217,8 +1227,13 @@ dobfs_status dobfs::bfs_batch_rows(dobfs_graph g, const int32_t* sources, int32_
   HIPCK(launch_mb_init(s, a, dir0, L.nflags, timing ? ev[kEvInit0] : nullptr,
                        timing ? ev[kEvInit1] : nullptr));
   LoopResult res;
-  st = run_steps(g->last_steps_mb, s, timing, ev, BatchSteps{a, rows}, a.ctrl, a.nwords, max_steps, cap,
-                 cap < int64_t(g->V) + 2 ? DOBFS_ERR_UNSUPPORTED : DOBFS_ERR_INTERNAL, sink, nullptr, stats, &res);
+  PersistentDevice* pd = nullptr;
+  if (opt.flags & DOBFS_OPT_PERSISTENT) {
+    pd = persistent_device(g->device);
+    if (!pd) return fail(DOBFS_ERR_UNSUPPORTED, "the persistent level loop is not available on device %d", g->device);
+  }
+  st = run_steps(g->last_steps_mb, s, timing, ev, BatchSteps{a, rows}, a.ctrl, max_steps, cap,
+                 cap < int64_t(g->V) + 2 ? DOBFS_ERR_UNSUPPORTED : DOBFS_ERR_INTERNAL, sink, pd, stats, &res);
   if (st != DOBFS_OK) return st;
   if (!stats) return DOBFS_OK;
   HIPCK(hipEventRecord(ev[kEvEnd], s));

@@ -109,8 +109,11 @@ __global__ __launch_bounds__(kThreads) void k_mb_init(BatchArgs a, int32_t dir0,
         c->qcount[s] = 0;
         c->mf[s] = 0;
       }
-      c->bar.abort = 0;  // read by the report (no grid barrier waits here)
+      c->bar.abort = 0;  // the persistent loop's grid barrier starts idle
       c->bar.t_end = 0;
+      c->bar.gen = 0;
+      c->bar.top.n = 0;
+      for (int g = 0; g < kBarGroups; ++g) c->bar.group[g].n = 0;
       LevelState st;
       st.dir = dir0;
       st.done = 0;
@@ -147,7 +150,7 @@ struct MbExpandShared {
 // one of the single-source expansion.
 // The expansion step s of level st.level: m_f from the scan step before it, counters into
 // slot s.
-__device__ void mb_expand_body(const BatchArgs& a, const LevelState& st, int32_t s, MbExpandShared& sh) {
+__device__ __forceinline__ void mb_expand_body(const BatchArgs& a, const LevelState& st, int32_t s, MbExpandShared& sh) {
   const int32_t L = st.level;
   const int32_t nf = st.nf;
   const uint32_t m = a.ctrl->mf[s % kSlots];
@@ -292,7 +295,7 @@ struct MbPullShared {
 // row up to kMbMid in-neighbours, then a wave finishes it, 64 per step. The
 // tile's new visited words (old | found), next-frontier words and nonzero
 // bits are written whole; no atomics touch them. Step s's counters go to slot s.
-__device__ void mb_pull_body(const BatchArgs& a, const LevelState& st, int32_t s, int32_t tile,
+__device__ __forceinline__ void mb_pull_body(const BatchArgs& a, const LevelState& st, int32_t s, int32_t tile,
                              MbPullShared& sh) {
   const int tid = threadIdx.x;
   const int32_t L = st.level;
@@ -458,9 +461,10 @@ __device__ __forceinline__ LevelState mb_step_state(const BatchArgs& a, int32_t 
     *prev_out = st;
     return st;
   }
+  // (the counters' loads are left where the compiler puts them, after the state's: holding
+  // them from the start costs this kernel registers, 6 waves per SIMD instead of 7)
   const StripeLanes x = load_stripes(c->slot[(s - 1) % kSlots]);
   const LevelState prev = c->ring[(s - 1) % kRing];
-  stripes_needed(x);
   *prev_out = prev;
   if (prev.done) return prev;  // past the end
   if (prev.phase == kPhaseScan) {  // the expansion the scan step prepared
@@ -485,7 +489,7 @@ __device__ __forceinline__ LevelState mb_step_state(const BatchArgs& a, int32_t 
 // back) sparsely through that level's list. Then the frontier list with its degree prefix
 // (Section 6.2), from the list the push before left or from the non-zero bitmap; m_f goes
 // where the expansion step reads it.
-__device__ void mb_scan_step(const BatchArgs& a, const LevelState& st, const LevelState& prev, int32_t s) {
+__device__ __forceinline__ void mb_scan_step(const BatchArgs& a, const LevelState& st, const LevelState& prev, int32_t s) {
   Ctrl* c = a.ctrl;
   const int32_t L = st.level;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
@@ -573,14 +577,9 @@ union MbShared {
   MbPullShared p;
 };
 
-__global__ __launch_bounds__(kThreads) void k_mb_step(BatchArgs a, int32_t s) {
-  __shared__ MbShared sh;
-  LevelTotals tot;
-  LevelState prev;
-  bool new_level;
-  const LevelState st = mb_step_state(a, s, &tot, &prev, &new_level);
-  if (blockIdx.x == 0) publish_step(a.ctrl, s, st, prev, tot, new_level);
-  if (st.done) return;
+// The work of step s (state st, prev: the state before it) over the launch's grid.
+__device__ __forceinline__ void mb_step_body(const BatchArgs& a, const LevelState& st, const LevelState& prev,
+                                             int32_t s, MbShared& sh) {
   if (st.phase == kPhaseScan) {
     mb_scan_step(a, st, prev, s);
   } else if (st.dir == 0) {
@@ -591,6 +590,61 @@ __global__ __launch_bounds__(kThreads) void k_mb_step(BatchArgs a, int32_t s) {
       __syncthreads();  // LDS of the previous tile is no longer read
       mb_pull_body(a, st, s, t, sh.p);
     }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_mb_step(BatchArgs a, int32_t s) {
+  __shared__ MbShared sh;
+  LevelTotals tot;
+  LevelState prev;
+  bool new_level;
+  const LevelState st = mb_step_state(a, s, &tot, &prev, &new_level);
+  if (blockIdx.x == 0) publish_step(a.ctrl, s, st, prev, tot, new_level);
+  if (st.done) return;
+  mb_step_body(a, st, prev, s, sh);
+}
+
+// The persistent form of the step loop: steps s_first .. s_first + n - 1 in
+// one launch of co-resident blocks, a grid barrier between consecutive steps
+// in place of a kernel boundary. Every body already strides over the grid it
+// is given (expansion chunks, pull tiles, scan tiles by ticket), so the blocks
+// run each step's body once. Block 0 publishes every state (with its start
+// time when timing); when the traversal ends early the launch's remaining
+// states read as the final one, as steps enqueued past the end publish it.
+// A barrier wait that gives up raises the abort flag, which the report
+// passes on; every block then leaves.
+__global__ __launch_bounds__(kThreads) void k_mb_steps(BatchArgs a, int32_t s_first, int32_t n, uint32_t spin_limit,
+                                                       int32_t timing) {
+  __shared__ MbShared sh;
+  __shared__ uint32_t s_gen;
+  GridBar* bar = &a.ctrl->bar;
+  if (threadIdx.x == 0)  // no barrier of this traversal is in progress between launches
+    s_gen = __hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const uint32_t gen0 = s_gen;
+  for (int32_t k = 0; k < n; ++k) {
+    const int32_t s = s_first + k;
+    LevelTotals tot;
+    LevelState prev;
+    bool new_level;
+    LevelState st = mb_step_state(a, s, &tot, &prev, &new_level);
+    if (blockIdx.x == 0) {
+      if (timing) st.t0 = wall_clock64();
+      publish_step(a.ctrl, s, st, prev, tot, new_level);
+      if (st.done)
+        for (int32_t j = 1 + int32_t(threadIdx.x); j < n - k; j += kThreads) a.ctrl->ring[(s + j) % kRing] = st;
+    }
+    if (st.done) break;
+    __syncthreads();  // LDS of the previous step is no longer read
+    mb_step_body(a, st, prev, s, sh);
+    if (k == n - 1) break;  // the kernel boundary ends the last step
+    if (!grid_barrier(bar, gen0 + uint32_t(k) + 1u, spin_limit)) break;
+  }
+  if (timing) {
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_max(&bar->t_end, (unsigned long long)wall_clock64(), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -715,6 +769,22 @@ hipError_t launch_mb_step(hipStream_t s, const BatchArgs& a, int32_t step, hipEv
   const int64_t tiles = (int64_t(a.nwords) + kMbTileWords - 1) / kMbTileWords;
   const dim3 g(unsigned(std::max<int64_t>(kExpandBlocks, tiles)));
   return launch_k(k_mb_step, g, s, t0, t1, a, step);
+}
+
+hipError_t launch_mb_steps(hipStream_t s, const BatchArgs& a, int32_t s_first, int32_t n, int32_t blocks,
+                           uint32_t spin_limit, bool timing, hipEvent_t t0, hipEvent_t t1) {
+  return launch_k(k_mb_steps, dim3(static_cast<unsigned>(blocks)), s, t0, t1, a, s_first, n, spin_limit,
+                  int32_t(timing ? 1 : 0));
+}
+
+hipError_t persistent_capacity_mb(int32_t* blocks) {
+  int dev = 0, cus = 0, per = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_mb_steps, kThreads, 0);
+  if (e != hipSuccess) return e;
+  *blocks = cus * per;
+  return hipSuccess;
 }
 
 hipError_t launch_mb_depth(hipStream_t s, const BatchArgs& a, int32_t step, const DepthRows& rows) {

@@ -634,5 +634,52 @@ __device__ __forceinline__ void publish_step(Ctrl* c, int32_t s, const LevelStat
   for (int k = threadIdx.x; k < kStripes; k += blockDim.x) zero_stripe(c->slot[(s + 2) % kSlots].s[k]);
 }
 
+// Waits until every block of the launch has arrived (see GridBar). Agent-scope
+// fences are whole-cache operations (write back / invalidate the XCD's L2), so
+// only thread 0 of a block issues them: every wave first waits for its own
+// memory operations to complete, then thread 0 releases before its block
+// arrives and acquires once after the wait (the polls themselves are relaxed);
+// the block barrier after it orders the other waves' reads behind that.
+// Returns false when the wait gave up (spin limit, or another block gave up).
+__device__ __forceinline__ bool grid_barrier(GridBar* bar, uint32_t target, uint32_t spin_limit) {
+  __shared__ int s_ok;
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's loads and stores are complete
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the block's writes reach memory
+    const uint32_t G = gridDim.x;
+    const uint32_t groups = G < uint32_t(kBarGroups) ? G : uint32_t(kBarGroups);
+    const uint32_t g = blockIdx.x % groups;
+    const uint32_t members = (G - g + groups - 1) / groups;  // blocks b < G with b % groups == g
+    const unsigned long long o = __hip_atomic_fetch_add(&bar->group[g].n, 1ull, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+    if ((o + 1) % members == 0) {
+      const unsigned long long o2 = __hip_atomic_fetch_add(&bar->top.n, 1ull, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+      if ((o2 + 1) % groups == 0) __hip_atomic_store(&bar->gen, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    int ok = 1;
+    uint32_t polls = 0;
+    while (int32_t(__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+      if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        ok = 0;
+        break;
+      }
+      if (++polls > spin_limit) {
+        __hip_atomic_fetch_or(&bar->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    // released, but another block gave up: it will not arrive again
+    if (ok && __hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // drop stale cache lines
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
 }  // namespace
 }  // namespace dobfs

@@ -101,7 +101,7 @@ struct Ctrl {
   LevelRecord rec[kRing];
   int8_t forced[kRing];          // step loops: forced direction of levels 0 .. n_forced-1
   LevelSlot tail;                // after a traversal: out-degree sum of the reached vertices (edges)
-  GridBar bar;                   // single source: the persistent loop's grid barrier
+  GridBar bar;                   // the persistent loops' grid barrier
 };
 static_assert(sizeof(Stripe) == 128, "stripe layout");
 static_assert(offsetof(Ctrl, slot) % 128 == 0, "slots start on a line");
@@ -454,6 +454,13 @@ hipError_t launch_mb_init(hipStream_t s, const BatchArgs& a, int32_t dir0, int64
 // Step `step` of the multi-source step loop (k_mb_step).
 hipError_t launch_mb_step(hipStream_t s, const BatchArgs& a, int32_t step, hipEvent_t t0 = nullptr,
                           hipEvent_t t1 = nullptr);
+// The persistent form of the multi-source step loop (k_mb_steps): steps s_first .. s_first +
+// n - 1 in one launch of `blocks` co-resident blocks, a grid barrier between steps; the report
+// is written afterwards by launch_step_report.
+hipError_t launch_mb_steps(hipStream_t s, const BatchArgs& a, int32_t s_first, int32_t n, int32_t blocks,
+                           uint32_t spin_limit, bool timing, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+// Blocks of k_mb_steps that fit on the current device at once.
+hipError_t persistent_capacity_mb(int32_t* blocks);
 // Destination of each source's depth row (int32[V], device).
 struct DepthRows {
   int32_t* row[kMaxSources];

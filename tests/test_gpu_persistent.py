@@ -3,7 +3,9 @@ one-launch-per-step loop: depths exact, parents valid and first-hit on pull leve
 per-level sizes, directions and work counts; forced direction schedules; traversals deeper
 than one launch's 64 steps; per-level times from the device clock; the bounded barrier wait
 forced to give up from the host (a spin limit of 0 polls), after which the next call is
-correct again; and the allocation-free call in the persistent form."""
+correct again; and the allocation-free call in the persistent form. The multi-source
+traversal's persistent form gets the same checks: every depth row against the oracle and the
+level sequence against its step loop."""
 import os
 import sys
 
@@ -166,3 +168,89 @@ def test_static_call_persistent(graphs):
     dobfs.bfs_static(g, s, depth, parent, dobfs.make_options("full", persistent=True), stats=st)
     torch.cuda.synchronize()
     _check(hg, s, depth.cpu().numpy(), parent.cpu().numpy(), want, dobfs.stats_levels(st), "static persistent")
+
+
+# ------------------------------------------------------------------ multi-source
+_rows_cache = {}
+
+
+def _rows(hg, sources):
+    out = []
+    for v in sources:
+        key = (hg.name, hg.V, int(v))
+        if key not in _rows_cache:
+            _rows_cache[key] = oracle.bfs(hg, int(v))[0]
+        out.append(_rows_cache[key])
+    return np.stack(out)
+
+
+def _batch(g, sources, opt, cap=4096):
+    k = len(sources)
+    depth = torch.full((k * g.V,), -7, dtype=torch.int32, device="cuda")
+    st = dobfs.make_stats(cap)
+    dobfs.bfs_batch(g, sources, depth, opt=opt, stats=st)
+    return depth.cpu().numpy().reshape(k, g.V), st
+
+
+def _batch_key(st):
+    return [(x["dir"], x["nf"], x["n_new"], x["edges"], x["m_f"]) for x in dobfs.stats_levels(st)]
+
+
+@pytest.mark.parametrize("name", ["rmat14", "directed100003", "lattice37", "grid61x53"])
+def test_batch_modes_match_step_loop_and_oracle(graphs, name):
+    hg, g = graphs[name]
+    srcs = [int(x) for x in gen.sample_sources(hg, 64, seed=31)]
+    want = _rows(hg, srcs)
+    for mode in ("full", "push_only", "pull_only"):
+        for heur, a, b in ((dobfs.HEUR_RATIO, 0.01, 0.01), (dobfs.HEUR_EDGES, 1 / 14, 1 / 24)):
+            tag = "%s batch %s heur=%d" % (name, mode, heur)
+            _say(tag)
+            _, ref = _batch(g, srcs, dobfs.make_options(mode, heur, a, b))
+            d, st = _batch(g, srcs, dobfs.make_options(mode, heur, a, b, persistent=True))
+            bad = int((d != want).sum())
+            assert bad == 0, "%s: %d depths differ" % (tag, bad)
+            assert st.levels == int(want.max()) + 1 and st.reached == int((want >= 0).sum()), tag
+            assert _batch_key(st) == _batch_key(ref), tag
+
+
+def test_batch_forced_and_deep():
+    """Forced schedules over a grid, and a 3000-vertex path (several launches of 64 steps)."""
+    grid = gen.grid2d(61, 53)
+    gg = upload(grid)
+    srcs = [0] + [int(x) for x in gen.sample_sources(grid, 20, seed=41)]
+    want = _rows(grid, srcs)
+    for sc in ([PUSH, PULL] * 70, [PULL, PULL, PUSH] * 50, [PUSH, PUSH, PULL] * 50):
+        tag = "grid forced %s" % "".join(str(x) for x in sc[:6])
+        _say(tag)
+        d, st = _batch(gg, srcs, dobfs.make_options("full", forced_dirs=sc, persistent=True))
+        assert np.array_equal(d, want), tag
+        dirs = [x["dir"] for x in dobfs.stats_levels(st)]
+        assert dirs == sc[: len(dirs)], tag
+    dobfs.graph_destroy(gg)
+    V = 3000
+    path = gen.from_edges(V, np.arange(V - 1), np.arange(1, V), directed=False, name="path3000")
+    gp = upload(path)
+    srcs = [0, V - 1, V // 2]
+    want = _rows(path, srcs)
+    for mode in ("full", "push_only"):
+        _say("path3000 batch", mode)
+        d, st = _batch(gp, srcs, dobfs.make_options(mode, time_kernels=True, persistent=True))
+        assert np.array_equal(d, want), mode
+        lv = dobfs.stats_levels(st)
+        assert len(lv) == V, mode
+        assert all(x["ms_main"] > 0 for x in lv), mode
+    dobfs.graph_destroy(gp)
+
+
+def test_batch_barrier_wait_gives_up_and_recovers(graphs):
+    hg, g = graphs["rmat14"]
+    srcs = [int(x) for x in gen.sample_sources(hg, 64, seed=43)]
+    os.environ["DOBFS_SPIN_LIMIT"] = "0"
+    try:
+        with pytest.raises(dobfs.DobfsError) as e:
+            _batch(g, srcs, dobfs.make_options("full", persistent=True))
+        assert e.value.status == dobfs.ERR_INTERNAL and "barrier" in str(e.value)
+    finally:
+        del os.environ["DOBFS_SPIN_LIMIT"]
+    d, st = _batch(g, srcs, dobfs.make_options("full", persistent=True))
+    assert np.array_equal(d, _rows(hg, srcs)), "after a given-up wait"
