@@ -566,7 +566,9 @@ struct BatchSteps {
   const BatchArgs& a;
   const DepthRows& rows;
   static constexpr bool self_report = false;
-  int64_t grid() const { return std::max<int64_t>(kExpandBlocks, (int64_t(a.nwords) + kMbTileWords - 1) / kMbTileWords); }
+  int64_t grid() const {
+    return std::max<int64_t>(kExpandBlocks, std::min<int64_t>((int64_t(a.nwords) + kMbTileWords - 1) / kMbTileWords, 8192));
+  }
   static int32_t capacity(const PersistentDevice& d) { return d.capacity_mb; }
   hipError_t step(hipStream_t s, int32_t k, hipEvent_t t0, hipEvent_t t1, const StepReportArgs*) const {
     return launch_mb_step(s, a, k, t0, t1);
