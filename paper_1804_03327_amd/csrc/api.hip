@@ -543,17 +543,19 @@ uint32_t env_u32(const char* name, uint32_t dflt) {
   return x > 0xffffffffull ? 0xffffffffu : uint32_t(x);
 }
 
-// How run_steps launches the steps of one traversal kind. step(): step k (rp: this step
-// also writes the batch's report, only where self_report); before_report(): what must run
-// after a batch's last step (k_last) and before its report; persistent(): the persistent
-// form of a batch (rp as for step()); grid(): blocks of a step launch; capacity(): blocks of
-// the persistent kernel that fit at once.
+// How run_steps launches the steps of one traversal kind. step(): step k on `blocks` blocks (0:
+// the kind's full grid; rp: this step also writes the batch's report, only where self_report);
+// before_report(): what must run after a batch's last step (k_last) and before its report;
+// persistent(): the persistent form of a batch (rp as for step()); grid(): the full grid of a
+// step launch; next_grid(): the blocks for the next batch's launches from the report of the
+// batch before (0: the full grid); capacity(): blocks of the persistent kernel that fit at once.
 struct SingleSteps {
   const BfsArgs& a;
   static constexpr bool self_report = true;
   int64_t grid() const { return main_blocks(a.nwords); }
+  int64_t next_grid(const HostReport&, int32_t) const { return 0; }
   static int32_t capacity(const PersistentDevice& d) { return d.capacity; }
-  hipError_t step(hipStream_t s, int32_t k, hipEvent_t t0, hipEvent_t t1, const StepReportArgs* rp) const {
+  hipError_t step(hipStream_t s, int32_t k, int64_t, hipEvent_t t0, hipEvent_t t1, const StepReportArgs* rp) const {
     return launch_step(s, a, k, t0, t1, rp);
   }
   hipError_t before_report(hipStream_t, int32_t) const { return hipSuccess; }
@@ -569,9 +571,32 @@ struct BatchSteps {
   int64_t grid() const {
     return std::max<int64_t>(kExpandBlocks, std::min<int64_t>((int64_t(a.nwords) + kMbTileWords - 1) / kMbTileWords, 8192));
   }
+  // Every block of a step decides the level before its work, so a long run of push levels (a
+  // high-diameter graph) need not pay for a pull's grid: after a batch without a pull, the next
+  // batch's launches get four times the blocks its largest push needed (scan tiles of the
+  // frontiers, edge chunks), at least 256. Every body strides over whatever grid it gets, so a
+  // pull that comes anyway is only slower.
+  int64_t next_grid(const HostReport& r, int32_t batch) const {
+    int64_t need = 0;
+    for (int32_t k = 0; k < batch; ++k) {
+      const LevelState& st = r.steps[k];
+      if (st.done) break;
+      if (st.dir != DOBFS_DIR_PUSH) return 0;
+      need = std::max<int64_t>(need, (int64_t(st.nf) + kScanTile - 1) / kScanTile);
+    }
+    for (int32_t k = 0; k < r.nrec; ++k) {
+      const LevelRecord& x = r.rec[k];
+      if (x.dir != DOBFS_DIR_PUSH) return 0;
+      need = std::max<int64_t>(need, (x.m_f + kExpandChunk - 1) / kExpandChunk);
+      need = std::max<int64_t>(need, (int64_t(x.n_new) + kScanTile - 1) / kScanTile);
+    }
+    const int64_t g = std::max<int64_t>(256, 4 * need);
+    return g < grid() ? g : 0;
+  }
   static int32_t capacity(const PersistentDevice& d) { return d.capacity_mb; }
-  hipError_t step(hipStream_t s, int32_t k, hipEvent_t t0, hipEvent_t t1, const StepReportArgs*) const {
-    return launch_mb_step(s, a, k, t0, t1);
+  hipError_t step(hipStream_t s, int32_t k, int64_t blocks, hipEvent_t t0, hipEvent_t t1,
+                  const StepReportArgs*) const {
+    return launch_mb_step(s, a, k, blocks, t0, t1);
   }
   // the depth rows: a transpose that exits at once unless the state the batch's last step
   // published says the traversal is over, so the last report already finds the rows final
@@ -612,6 +637,7 @@ dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool tim
   if (pd && (blocks < 1 || blocks > cap))
     return fail(DOBFS_ERR_INVALID_ARG, "persistent grid of %d blocks (1 .. %d fit)", blocks, cap);
   if (pd) batch = next_batch = kMaxBatch;  // a launch ends with the traversal: no steps past the end
+  int64_t grid = 0;  // blocks of the step launches (0: the full grid)
   while (true) {
     if (s0 + batch > max_steps) batch = int32_t(max_steps - s0);
     const uint32_t seq = next_report_seq();
@@ -628,7 +654,7 @@ dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool tim
       HIPCK(fetch_report(sink, seq, s));
     } else {
       for (int32_t k = 0; k < batch; ++k)
-        HIPCK(S.step(s, int32_t(s0 + k), E(ev_m0(k)), E(ev_m1(k)), (self && k == batch - 1) ? &rp : nullptr));
+        HIPCK(S.step(s, int32_t(s0 + k), grid, E(ev_m0(k)), E(ev_m1(k)), (self && k == batch - 1) ? &rp : nullptr));
       HIPCK(S.before_report(s, int32_t(s0 + batch - 1)));
       if (!self) HIPCK(launch_step_report(s, ctrl, int32_t(s0), batch, rec_first, sink.dev, seq));
       HIPCK(fetch_report(sink, seq, s));
@@ -672,6 +698,7 @@ dobfs_status run_steps(std::atomic<int32_t>& last_steps, hipStream_t s, bool tim
       }
     }
     rec_first += rep->nrec;
+    grid = S.next_grid(*rep, batch);
     const LevelState& end = rep->end;
     if (end.done) {
       res->levels = end.levels;

@@ -765,11 +765,13 @@ hipError_t launch_mb_init(hipStream_t s, const BatchArgs& a, int32_t dir0, int64
   return launch_k(k_mb_init, dim3(g), s, t0, t1, a, dir0, nflags);
 }
 
-// A block per pull tile, at most 8192: every block of every step derives the step's state first,
-// which on graphs of millions of vertices costs more than a second tile per block.
-hipError_t launch_mb_step(hipStream_t s, const BatchArgs& a, int32_t step, hipEvent_t t0, hipEvent_t t1) {
+// By default a block per pull tile, at most 8192: every block of every step derives the step's
+// state first, which on graphs of millions of vertices costs more than a second tile per block.
+hipError_t launch_mb_step(hipStream_t s, const BatchArgs& a, int32_t step, int64_t blocks, hipEvent_t t0,
+                          hipEvent_t t1) {
   const int64_t tiles = (int64_t(a.nwords) + kMbTileWords - 1) / kMbTileWords;
-  const dim3 g(unsigned(std::max<int64_t>(kExpandBlocks, std::min<int64_t>(tiles, 8192))));
+  const int64_t full = std::max<int64_t>(kExpandBlocks, std::min<int64_t>(tiles, 8192));
+  const dim3 g(unsigned(blocks > 0 && blocks < full ? blocks : full));
   return launch_k(k_mb_step, g, s, t0, t1, a, step);
 }
 

@@ -422,8 +422,8 @@ constexpr int kMaxBatch = 64;
 struct HostReport {
   LevelState end;
   LevelRecord rec[kMaxBatch];
-  LevelState steps[kMaxBatch];  // single source: the state each step of the batch published
-  int32_t nrec;                 // single source: records in rec (levels rec_first ..)
+  LevelState steps[kMaxBatch];  // the state each step of the batch published
+  int32_t nrec;                 // records in rec (levels rec_first ..)
   int32_t error;                // persistent loop: 1 when a grid barrier wait gave up
   unsigned long long t_end;     // persistent loop, timed: device clock when its last block ended
   uint32_t seq;
@@ -451,9 +451,10 @@ hipError_t launch_steps(hipStream_t s, const BfsArgs& a, int32_t s_first, int32_
 hipError_t persistent_capacity(int32_t* blocks);
 hipError_t launch_mb_init(hipStream_t s, const BatchArgs& a, int32_t dir0, int64_t nflags,
                          hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
-// Step `step` of the multi-source step loop (k_mb_step).
-hipError_t launch_mb_step(hipStream_t s, const BatchArgs& a, int32_t step, hipEvent_t t0 = nullptr,
-                          hipEvent_t t1 = nullptr);
+// Step `step` of the multi-source step loop (k_mb_step) on `blocks` blocks (0 or more than
+// the full grid: the full grid).
+hipError_t launch_mb_step(hipStream_t s, const BatchArgs& a, int32_t step, int64_t blocks = 0,
+                          hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 // The persistent form of the multi-source step loop (k_mb_steps): steps s_first .. s_first +
 // n - 1 in one launch of `blocks` co-resident blocks, a grid barrier between steps; the report
 // is written afterwards by launch_step_report.
