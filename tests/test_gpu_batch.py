@@ -246,6 +246,25 @@ def test_batch_deep_path_past_the_state_ring():
     assert dirs[:1024] == sc[:1024] and set(dirs[1024:]) == {PUSH}
 
 
+def test_batch_pull_after_push_only_batches():
+    """A 400 x 400 grid (625 pull tiles) forced to push for 300 levels, then to alternate: the
+    batches of pushes shrink the step launches below the tile count, and the pulls after them
+    run on that smaller grid, a block taking several tiles."""
+    hg = gen.grid2d(400, 400)
+    g = upload(hg)
+    srcs = [0, hg.V - 1] + _sources(hg, 6, 77)
+    sc = [PUSH] * 300 + [PULL, PUSH] * 300
+    for mode in ["full", "push_only"]:
+        tag = "grid400 %s forced" % mode
+        _say(tag)
+        d, st = _run(g, srcs, dobfs.make_options(mode, forced_dirs=sc), cap=2048)
+        _check(hg, srcs, d, st, tag)
+        dirs = [x["dir"] for x in dobfs.stats_levels(st)]
+        assert dirs == sc[: len(dirs)], tag
+    d, st = _run(g, srcs, dobfs.make_options("push_only"), cap=2048)
+    _check(hg, srcs, d, st, "grid400 push_only rule")
+
+
 def test_batch_wide_pushes_deep():
     """Consecutive layers of 200 vertices joined completely, 24 layers: every push level reads
     more than 64 Ki edges, so its winners are marked in the non-zero bitmap rather than listed,

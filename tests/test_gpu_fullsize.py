@@ -157,6 +157,38 @@ def test_rmat20_multi_source_all_rows():
     dobfs.graph_destroy(g)
 
 
+def test_multi_source_large_graphs(rmat22):
+    """Multi-source launches on graphs with more pull tiles than the step launch has blocks
+    (8192): 64 RMAT-22 bench sources, every row; and 8 sources on the 2048^2 grid, whose 4095
+    push levels run over many batches, the later ones on the smaller grid the host sizes from
+    the pushes before (twice: the second call starts from the first call's step count)."""
+    hg, srcs = rmat22
+    g = upload(hg, hubs_first=True)
+    depth = torch.full((64 * g.V,), -7, dtype=torch.int32, device="cuda")
+    dobfs.bfs_batch(g, srcs, depth, opt=dobfs.make_options(**BENCH_OPT))
+    rows = depth.cpu().numpy().reshape(64, g.V)
+    want = _oracle_many(hg, srcs)
+    for b in range(64):
+        assert np.array_equal(rows[b], want[srcs[b]]), "rmat22 row %d (source %d) differs" % (b, srcs[b])
+    _say("rmat22: 64 rows match")
+    dobfs.graph_destroy(g)
+    del depth
+    hgr = gen.grid2d(2048, 2048)
+    g = upload(hgr, hubs_first=True)
+    gs = [0, hgr.V - 1] + [int(x) for x in gen.sample_sources(hgr, 6, seed=9)]
+    want = _oracle_many(hgr, gs)
+    for call in range(2):
+        depth = torch.full((8 * g.V,), -7, dtype=torch.int32, device="cuda")
+        st = dobfs.make_stats(8192)
+        dobfs.bfs_batch(g, gs, depth, opt=dobfs.make_options(**BENCH_OPT), stats=st)
+        rows = depth.cpu().numpy().reshape(8, g.V)
+        for b in range(8):
+            assert np.array_equal(rows[b], want[gs[b]]), "grid2048 call %d row %d differs" % (call, b)
+        assert st.levels == max(int(w.max()) for w in want.values()) + 1
+        _say("grid2048 call %d: 8 rows match over %d levels" % (call, st.levels))
+    dobfs.graph_destroy(g)
+
+
 def test_full_size_persistent_loop(rmat22):
     """The persistent level loop at full size: four RMAT-22 bench sources and two lattice
     sources in the benchmarked configuration, against the oracle and the step-launch loop's
