@@ -344,7 +344,8 @@ dobfs_status dobfs_bfs_batch(dobfs_graph g, const int32_t *sources, int32_t k,
  * while a batch is on the GPU are admitted into the next free slot and run
  * beside it (continuous batching, not a single queue). Graphs whose batches
  * have taken more than 2 ms on average may occupy at most slots - 1 slots at
- * once, so a deep traversal never holds every slot. Admission by memory: the
+ * once, so a deep traversal never holds every slot, and their queries are
+ * batched only once 8 of them are queued (fewer run one per slot). Admission by memory: the
  * server makes one device allocation of mem_budget bytes when it is created
  * and carves every batch's workspace out of it; a batch starts only when its
  * workspace fits in what the running batches leave free, and a batch is cut

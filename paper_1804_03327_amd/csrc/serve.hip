@@ -8,13 +8,15 @@
 // allocation of mem_budget bytes: admission by memory), and runs them as one
 // multi-source traversal whose depth rows are written straight into the
 // callers' buffers. A batch of one runs the single-source traversal instead
-// (depths only): one kernel per level and a smaller workspace, where the
-// multi-source loop takes two kernels per level, which tells on deep graphs.
+// (depths only): a smaller workspace, and on deep graphs fewer launches.
 // Queries that arrive while a batch is on the GPU go to the next free slot,
 // so their traversal overlaps the running one on the device. Graphs whose
 // batches have been taking long (a running mean of their service times above
 // kLongMs) may hold at most slots - 1 slots at once, so one slot stays free for
-// the others' queries instead of queueing them behind deep traversals.
+// the others' queries instead of queueing them behind deep traversals; and
+// their queries are batched only once kLongBatchMin of them are queued, fewer
+// going one per slot: on a deep graph a multi-source traversal of a few
+// sources takes longer than the same single-source traversals side by side.
 
 #include "dobfs.h"
 #include "dobfs_internal.h"
@@ -36,6 +38,10 @@ namespace {
 
 constexpr int kMaxSlots = 16;
 constexpr double kLongMs = 2.0;  // a graph whose batches take longer than this on average is "long"
+// Fewest queued queries of a long graph that one multi-source traversal takes (2048x2048 grid:
+// 2 / 4 / 8 sources take 84 / 100 / 99 ms together, two single-source traversals on two
+// streams 41 ms, one alone 32 ms).
+constexpr int32_t kLongBatchMin = 8;
 
 // First-fit allocator over one device allocation, in 256-byte units.
 struct Pool {
@@ -177,10 +183,14 @@ void worker(dobfs_server s, int slot) {
         ++it;
       }
     }
-    // admission by memory: the batch's workspace must fit in the pool
     int32_t k = int32_t(take.size());
+    if (k < kLongBatchMin && is_long(s->info[size_t(gi)])) k = 1;  // the rest go to other slots
+    // admission by memory: the batch's workspace must fit in the pool
     while (k > 1 && run_bytes(s->graphs[gi], s->opt.opt, k) > s->budget) --k;
-    for (size_t q = take.size(); q > size_t(k); --q) s->pending.push_front(take[q - 1]);  // back to the head, in order
+    if (take.size() > size_t(k)) {  // the rest back to the head, in order, for the other slots
+      for (size_t q = take.size(); q > size_t(k); --q) s->pending.push_front(take[q - 1]);
+      s->cv_work.notify_all();
+    }
     take.resize(size_t(k));
     const size_t need = run_bytes(s->graphs[gi], s->opt.opt, k);
     if (need > s->budget) {  // not even one source fits
