@@ -207,6 +207,39 @@ def test_long_graph_keeps_a_slot_free(graphs):
     dobfs.graph_destroy(g_long)
 
 
+def test_long_graph_batches_only_from_eight_queued(graphs):
+    """Queries of a graph known to be long (a 400 x 400 grid) run one per slot while fewer than 8
+    are queued, and as one multi-source batch once 8 or more are: 5 queries submitted while a
+    query of the graph occupies the only slot run alone, each; 12 run as batches of 8 or more
+    (or the leftover singles). Every depth vector equals the query run alone."""
+    hg = gen.grid2d(400, 400)
+    g = upload(hg)
+    srv = dobfs.Server([g], slots=1, max_batch=64)
+    d0 = torch.full((g.V,), -7, dtype=torch.int32, device="cuda")
+    first = srv.wait(srv.submit(0, 0, d0))  # its service time is now known
+    assert first["t_done_ms"] - first["t_start_ms"] > 2.0
+    for count, seed in ((5, 5000), (12, 6000)):
+        blocker = torch.full((g.V,), -7, dtype=torch.int32, device="cuda")
+        hb = srv.submit(0, hg.V - 1, blocker)  # holds the slot while the others queue up
+        qs = []
+        for n in range(count):
+            s = int(gen.sample_sources(hg, 1, seed=seed + n)[0])
+            depth = torch.full((g.V,), -7, dtype=torch.int32, device="cuda")
+            qs.append((s, depth, srv.submit(0, s, depth)))
+        srv.wait(hb)
+        infos = [srv.wait(q[2]) for q in qs]
+        sizes = [i["batch_size"] for i in infos]
+        if count < 8:
+            assert sizes == [1] * count, sizes
+        else:
+            assert max(sizes) >= 8 and all(k >= 8 or k == 1 for k in sizes), sizes
+        for (s, depth, _), info in zip(qs, infos):
+            assert info["status"] == dobfs.OK
+            assert np.array_equal(depth.cpu().numpy(), _alone(g, s))
+    srv.close()
+    dobfs.graph_destroy(g)
+
+
 def test_two_streams_overlap_on_device():
     """Two deep traversals (a 400 x 400 grid, about 800 levels of small kernels) from two host
     threads on two streams take much less than the two one after the other: their kernels run
