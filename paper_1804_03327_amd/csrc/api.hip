@@ -1,10 +1,11 @@
 // Host runtime and C ABI of libdobfs (declared in include/dobfs.h).
 //
 // The BFS level loop of Algorithm 1 is enqueued from the host in batches of
-// levels; each level's direction (the rule of Section 6.3) is decided on the
-// device from the previous level's counters, and the host reads the state
-// back once per batch from pinned memory. Single-source and multi-source
-// traversals share the loop and differ in their kernels.
+// steps (one kernel launch each, one or two per level); each level's
+// direction (the rule of Section 6.3) is decided on the device from the
+// previous step's counters, and the host reads the states back once per batch
+// from pinned memory. Single-source and multi-source traversals share the
+// loop (run_steps) and differ in their kernels.
 
 #include "dobfs.h"
 #include "dobfs_internal.h"

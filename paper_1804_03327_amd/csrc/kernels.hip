@@ -6,11 +6,14 @@
 // mask lets through, stopping at the first hit (Equation 4, Algorithm 2,
 // Sections 5.2-5.4). Everything is integer / bitwise: no MFMA.
 //
-// A BFS level is exactly two kernels: level_prep decides the level's
-// direction on the device (the rule of Section 6.3, from the previous
-// level's counters) and, for push, turns the frontier into a list with its
-// degree prefix; level_main runs the push expansion or the pull. The host
-// enqueues many levels ahead and reads the state back once per batch.
+// The level loop is a loop of steps, one launch of k_step each: a level is
+// one step (a pull, or a push that shares out its own work inside blocks), or
+// two when its push needs the global degree scan (scan step, expansion step).
+// Every block of a step decides the level itself on the device (the rule of
+// Section 6.3, from the counters the previous step left). The host enqueues
+// many steps ahead and reads the states back once per batch. k_steps runs the
+// same steps in one persistent launch; k_level_prep serves the sort-based
+// push of Table 2's first rows, whose host loop sizes the sort per level.
 //
 // Memory layout (HBM): CSR(A) and CSC(A) int32 arrays; bit vectors as uint32
 // words (bit i = word i>>5, bit i&31); frontier lists as int32.
