@@ -683,6 +683,9 @@ def main():
     ap.add_argument("--profile-batched", type=int, default=0,
                     help="only run this many multi-source launches on the batched workload "
                          "(for rocprofv3), print nothing else")
+    ap.add_argument("--profile-overlap", type=int, default=0,
+                    help="only run N rounds of two 2048x2048 grid traversals from two host threads on two "
+                         "streams (for a rocprofv3 kernel trace of their overlap on the device)")
     ap.add_argument("--profile-serving", action="store_true",
                     help="only run the serving workload at --serve-points (for a rocprofv3 kernel trace)")
     ap.add_argument("--serve-points", default="0.5,1,2,4,8,16",
@@ -740,6 +743,27 @@ def main():
 
     def options(mode, time_kernels=False):
         return dobfs.make_options(mode, heur, alpha, beta, time_kernels=time_kernels)
+
+    if args.profile_overlap:
+        import threading
+        hgr = gen.grid2d(2048, 2048)
+        gr = upload(hgr, device=0)
+        pool = [int(x) for x in gen.sample_sources(hgr, 2, seed=7)]
+        runners = [BfsRunner(gr, with_parent=False) for _ in range(2)]
+        streams = [torch.cuda.Stream() for _ in range(2)]
+        for i in range(2):
+            runners[i].run(pool[i], opt=options("full"), stream=streams[i])
+        torch.cuda.synchronize()
+        for k in range(args.profile_overlap):
+            ths = [threading.Thread(target=runners[i].run, args=(pool[i],),
+                                    kwargs=dict(opt=options("full"), stream=streams[i])) for i in range(2)]
+            for th in ths:
+                th.start()
+            for th in ths:
+                th.join()
+            torch.cuda.synchronize()
+            log("profile overlap round %d done" % k)
+        return
 
     if args.profile_serving:
         res = measure_serving(args, hg, g, heur, alpha, beta)
