@@ -8,10 +8,11 @@ paper-convention figure (nnz(A) / time) is reported beside it. Prints one JSON l
 Also reported: the HBM roofline of the dominant kernel (algorithmic bytes per launch over its
 average execution time, from each kernel's own start/end events in a repeat of the timed
 steps), the CPU oracle on a bounded sample of the same workload, the Table 2 ablation modes,
-the other direction rule, the multi-source measurement (64 sources per launch on RMAT-20
-against the same 64 queries run one at a time) and the query server (four graphs, Poisson
-arrivals at 0.5x, 1x and 2x the sequential capacity, p50/p99 latency against first-in first-out plain
-DOBFS).
+the other direction rule, the autotuner, the 256^3 lattice, the paper's own scale-22 graph (edge
+factor 64) beside its published figure, the multi-source measurement (64 sources per launch on
+RMAT-20 against the same 64 queries run one at a time) and the query server (four graphs,
+Poisson arrivals from 0.5x to 16x the sequential capacity, p50/p99 latency against first-in
+first-out plain DOBFS).
 
 --profile-steps / --profile-batched run only the BFS launches (for rocprofv3); --copy-mb adds
 one device copy of known size as the reference for scaling the PMC byte counters.
@@ -335,6 +336,70 @@ def measure_lattice(args, heur, alpha, beta):
     log("lattice:", json.dumps({k: v for k, v in res.items() if k != "kernels"}))
     dobfs.graph_destroy(gl)
     return res
+
+
+# The paper's own RMAT scale-22 graph has edge factor 64 (483M directed edges): its DOBFS runs it
+# in 4.781 ms, 101.0 GTEPS counted as nnz / time, on one Tesla K40c (Fig. 7 table, Table 3).
+PAPER_RMAT22_EF64 = {"gpu": "Tesla K40c", "dataset": "rmat_s22_e64, 483M directed edges",
+                     "ms_per_bfs": 4.781, "gteps_paper_convention": 101.038,
+                     "where": "Fig. 7 table (This Work), Table 3"}
+
+
+def measure_paper_scale(args, heur, alpha, beta):
+    """Context beside the paper's figure for its scale-22 RMAT graph: the same generator at edge
+    factor 64 (graph seed 1, 16 sources with seed 2), every source checked against the oracle,
+    then timed in the benchmarked mode and rule and under the paper's ratio rule
+    (alpha = beta = 0.01). Other hardware, so a context figure, not a target."""
+    import torch
+    import gen
+    import oracle
+    from paper_1804_03327_amd import dobfs
+    from paper_1804_03327_amd.helpers import BfsRunner, upload
+
+    t0 = time.time()
+    hp = gen.rmat(args.scale, 64, seed=1)
+    log("generated rmat%d ef64: V=%d nnz=%d in %.1fs" % (args.scale, hp.V, hp.nnz, time.time() - t0))
+    srcs = [int(x) for x in gen.sample_sources(hp, 16, seed=2)]
+    gp = upload(hp, device=0, hubs_first=not args.stored_order)
+    r = BfsRunner(gp, with_parent=True)
+    stream = torch.cuda.current_stream()
+    opt = dobfs.make_options("full", heur, alpha, beta)
+    opt_ratio = dobfs.make_options("full", dobfs.HEUR_RATIO, 0.01, 0.01)
+
+    def run_one(s):
+        r.run(s, opt=opt, stream=stream)
+        return r.result()
+
+    want = validate_sources(hp, srcs, run_one)
+    edges = sum(oracle.teps_edges(hp, want[s])["graph500"] for s in srcs)
+    levels = float(np.mean([int(want[s].max()) + 1 for s in srcs]))
+    reps = 5
+    res = {}
+    for name, o in (("benchmarked_rule", opt), ("ratio_rule", opt_ratio)):
+        for s in srcs[:4]:
+            dobfs.bfs(gp, s, r.depth, r.parent, o, r.ws, stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            for s in srcs:
+                dobfs.bfs(gp, s, r.depth, r.parent, o, r.ws, stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        res[name] = {"ms_per_bfs": round(1e3 * dt / (reps * len(srcs)), 4),
+                     "gteps": round(edges * reps / dt / 1e9, 3),
+                     "gteps_paper_convention": round(hp.nnz * reps * len(srcs) / dt / 1e9, 3)}
+    out = {"workload": "rmat%d_ef64 (same a/b/c/d, graph seed 1), 16 sources (seed 2)" % args.scale,
+           "vertices": hp.V, "directed_edges": hp.nnz, "levels_mean": round(levels, 2),
+           "validated_sources": len(want),
+           "heuristic": "%s alpha=%.4g beta=%.4g" % (args.heuristic, alpha, beta),
+           "benchmarked_rule": res["benchmarked_rule"],
+           "ratio_rule_alpha_beta_0.01": res["ratio_rule"],
+           "paper": PAPER_RMAT22_EF64,
+           "x_paper_ms_per_bfs": round(PAPER_RMAT22_EF64["ms_per_bfs"] / res["benchmarked_rule"]["ms_per_bfs"], 1)}
+    log("paper scale:", json.dumps(out))
+    dobfs.graph_destroy(gp)
+    del r
+    return out
 
 
 def batched_roofline(gb, hb, srcs, rows, opt, ws, depth, stream, heur, alpha, beta, reps=5):
@@ -675,6 +740,8 @@ def main():
     ap.add_argument("--no-lattice", action="store_true",
                     help="skip the 256^3 lattice (5%% of edges deleted, 16 sources) measurement")
     ap.add_argument("--lattice-n", type=int, default=256)
+    ap.add_argument("--no-paper-scale", action="store_true",
+                    help="skip the edge-factor-64 RMAT graph timed beside the paper's own figure for it")
     ap.add_argument("--batched-scale", type=int, default=20)
     ap.add_argument("--batched-launches", type=int, default=20)
     ap.add_argument("--no-validate", action="store_true")
@@ -1002,6 +1069,10 @@ def main():
     if not args.no_lattice:
         lattice = measure_lattice(args, heur, alpha, beta)
 
+    paper_scale = None
+    if not args.no_paper_scale:
+        paper_scale = measure_paper_scale(args, heur, alpha, beta)
+
     batched = None
     if not args.no_batched:
         batched = measure_batched(args, heur, alpha, beta)
@@ -1035,6 +1106,7 @@ def main():
         "autotuned": autotuned,
         "validated": validated,
         "lattice": lattice,
+        "paper_scale": paper_scale,
         "batched": batched,
         "serving": serving,
     }

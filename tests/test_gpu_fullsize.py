@@ -5,8 +5,9 @@ alpha = 1/14, beta = 1/24, caller-owned workspace, current stream).
 Every depth vector is compared with the oracle's over all vertices and every parent vector
 passes the validator; under the edge-count rule the direction sequence is the oracle's. The
 benchmark's 64 RMAT-22 sources are all checked in the benchmarked mode, every Table 2 mode the
-benchmark times is checked on two of them, four of the lattice's 16 sources run in three
-modes, and every row of the 64-source RMAT-20 launch is checked."""
+benchmark times is checked on two of them, two sources of the edge-factor-64 RMAT-22 graph run
+under both rules, four of the lattice's 16 sources run in three modes, and every row of the
+64-source RMAT-20 launch is checked."""
 import sys
 from concurrent.futures import ThreadPoolExecutor
 
@@ -109,6 +110,30 @@ def test_rmat22_ablation_modes(rmat22):
     _check(hg, pick[1], want[pick[1]], d, p, "rmat22 stored order, ratio rule")
     dobfs.graph_destroy(g)
     dobfs.graph_destroy(g2)
+
+
+def test_rmat22_ef64_paper_scale():
+    """The paper's own scale-22 RMAT graph (edge factor 64; 483M directed edges in its Table 3),
+    which the benchmark times beside the paper's figure: two of its 16 sources in the
+    benchmarked configuration and under the ratio rule (alpha = beta = 0.01), with the
+    library's Graph500 edge counts."""
+    hg = gen.rmat(22, 64, seed=1)
+    _say("rmat22 ef64 generated: V=%d nnz=%d" % (hg.V, hg.nnz))
+    assert abs(hg.nnz - 483e6) < 0.01 * 483e6
+    srcs = [int(x) for x in gen.sample_sources(hg, 16, seed=2)]
+    pick = [srcs[0], srcs[9]]
+    want = _oracle_many(hg, pick)
+    g = upload(hg, hubs_first=True)
+    r = BfsRunner(g)
+    for s in pick:
+        for o in (BENCH_OPT, dict(mode="full")):
+            tag = "rmat22 ef64 source %d %s" % (s, o)
+            _say(tag)
+            st = r.run(s, **o)
+            d, p = r.result()
+            _check(hg, s, want[s], d, p, tag, o, r.levels())
+            assert st.edges_g500 == oracle.teps_edges(hg, want[s])["graph500"], tag
+    dobfs.graph_destroy(g)
 
 
 def test_lattice256_sources():
