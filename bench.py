@@ -42,14 +42,16 @@ def log(*a):
 
 
 # the sources the single-source kernels (k_bfs_init, k_step) are compiled from: kernels.hip and
-# the headers it includes (the multi-source, sort and host files do not change them)
+# the headers it includes (the multi-source, sort and host files do not change them); the
+# multi-source kernels likewise come from batch.hip and the same headers
 SINGLE_SOURCE_KERNEL_FILES = ("kernels.hip", "device_common.h", "dobfs_internal.h", "dobfs.h")
+MULTI_SOURCE_KERNEL_FILES = ("batch.hip", "device_common.h", "dobfs_internal.h", "dobfs.h")
 
 
-def kernel_source_hash() -> str:
-    """SHA-256 (16 hex digits) over the sources of the single-source kernels."""
+def kernel_source_hash(files=SINGLE_SOURCE_KERNEL_FILES) -> str:
+    """SHA-256 (16 hex digits) over the sources of a group of kernels."""
     h = hashlib.sha256()
-    for name in SINGLE_SOURCE_KERNEL_FILES:
+    for name in files:
         path = os.path.join(KERNEL_DIR, name)
         if not os.path.exists(path):
             path = os.path.join(ROOT, "include", name)
@@ -111,6 +113,23 @@ def load_traffic(kernel: str):
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     return t.get("bytes_per_launch")
+
+
+def load_mb_traffic(levels):
+    """HBM traffic per push or pull step of k_mb_step (scan steps and the steps past the end
+    left out, as in the batched roofline) from the committed PMC summary of one 64-source
+    RMAT-20 launch, or None when absent, taken on other kernel sources, or when that launch's
+    level directions differ from `levels`."""
+    path = os.path.join(ROOT, "profiles", "traffic_mb_step_rmat20.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256_16") != kernel_source_hash(MULTI_SOURCE_KERNEL_FILES):
+        return None
+    if t.get("levels") != list(levels):
+        return None
+    return t.get("bytes_per_push_or_pull_step")
 
 
 def step_roofline(V, heur, runs, cand_tables, traffic):
@@ -411,7 +430,8 @@ def batched_roofline(gb, hb, srcs, rows, opt, ws, depth, stream, heur, alpha, be
       pull: 24 V (Vis read, Vis' and F' written) + 24 n_cand (slab, offset pair) + 12 checks
     where n_cand (rows with a source still expanding that has not reached them, in-degree > 0)
     comes from the 64 oracle-checked depth rows. The scan steps of push levels (merge, clears,
-    degree scan) are reported beside it."""
+    degree scan) are reported beside it; `traffic` is the PMC-counted bytes per push or pull step
+    of the same launch (load_mb_traffic)."""
     from paper_1804_03327_amd import dobfs
     import torch
     ot = dobfs.make_options("full", heur, alpha, beta, time_kernels=True)
@@ -447,7 +467,7 @@ def batched_roofline(gb, hb, srcs, rows, opt, ws, depth, stream, heur, alpha, be
     gbps = tot_bytes / (tot_ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": "k_mb_step (push and pull steps)", "achieved": round(gbps, 1),
             "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBS, 4), "traffic": load_mb_traffic(levels),
             "algorithmic_bytes_per_launch": int(tot_bytes / n_main), "avg_launch_us": round(1e3 * tot_ms / n_main, 3),
             "launches": n_main, "levels": levels,
             "scan_step_avg_us": round(1e3 * tot_scan / max(1, n_scan), 3),
