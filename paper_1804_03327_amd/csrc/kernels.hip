@@ -177,12 +177,38 @@ __device__ __forceinline__ void expand_body(const ExpandArgs& a, ExpandShared& s
 // the unit's edges kExpandChunk at a time, each edge finding its vertex by a
 // search over the unit's prefix; the claim and the winners' bookkeeping are
 // those of expand_body.
+// Local culling (the block-level dedupe Section 7.3 credits Gunrock with): a
+// direct-mapped table in LDS of the targets this block has already sent on to
+// the claim in this step. An edge whose target is found there is dropped
+// before its visited-word load and claim: the edge that entered the target
+// goes on to claim it (or finds it claimed), so the target is still reached
+// at this level, from a frontier vertex, and the depths and the validity of
+// the parents do not change. A collision only overwrites an entry, which
+// costs a redundant claim, never a lost one. Only levels with a frontier of
+// kCullMinFrontier vertices or more cull: smaller ones are bound by their
+// chain of dependent loads, which the table's atomics would only lengthen.
+constexpr int kCullBits = 10;
+constexpr int32_t kCullMinFrontier = 8192;
+constexpr uint32_t kCullNone = 0xffffffffu;  // no vertex id (ids are below 2^31)
+
 struct LocalShared {
   int32_t off[kThreads + 1], beg[kThreads], src[kThreads];
   int32_t buf[kExpandBuf];
   uint16_t list[kPullTileV];  // bitmap push: the block's frontier rows (offsets in its slice)
+  uint32_t cull[1 << kCullBits];
   uint32_t nbuf, base;
 };
+
+// Empties the culling table (all threads; a barrier follows before its first use).
+__device__ __forceinline__ void cull_reset(LocalShared& sh) {
+  for (int i = threadIdx.x; i < (1 << kCullBits); i += kThreads) sh.cull[i] = kCullNone;
+}
+
+// True when target w is new to this block's table (and enters it).
+__device__ __forceinline__ bool cull_enter(LocalShared& sh, int32_t w) {
+  const uint32_t h = (uint32_t(w) * 2654435761u) >> (32 - kCullBits);
+  return atomicExch(&sh.cull[h], uint32_t(w)) != uint32_t(w);
+}
 
 struct LocalAcc {
   unsigned long long won = 0, mnew = 0, insub = 0, edges = 0;
@@ -224,7 +250,7 @@ __device__ __forceinline__ uint32_t local_unit_prefix(const ExpandArgs& a, Local
 // The chunks first, first + step, ... of a unit of n vertices whose prefix
 // local_unit_prefix() wrote.
 __device__ __forceinline__ void local_unit_chunks(const ExpandArgs& a, LocalShared& sh, int32_t n, uint32_t total, uint32_t first,
-                                  uint32_t step, LocalAcc& acc) {
+                                  uint32_t step, bool cull, LocalAcc& acc) {
   const int tid = threadIdx.x;
   for (uint32_t e0 = first; e0 < total; e0 += step) {
     __syncthreads();  // the unit's prefix is written, nbuf is settled
@@ -242,6 +268,11 @@ __device__ __forceinline__ void local_unit_chunks(const ExpandArgs& a, LocalShar
         uu[t] = sh.src[k];
         w[t] = a.colind[sh.beg[k] + int32_t(e - uint32_t(sh.off[k]))];
       }
+    }
+    if (cull) {
+#pragma unroll
+      for (int t = 0; t < kExpandEPT; ++t)
+        if (valid[t]) valid[t] = cull_enter(sh, w[t]);
     }
     uint32_t seen[kExpandEPT];
 #pragma unroll
@@ -311,6 +342,8 @@ __device__ __forceinline__ void local_expand_body(const ExpandArgs& a, LocalShar
   if (bid >= nwork) return;                // no work: no counters to add
   const int tid = threadIdx.x;
   if (tid == 0) sh.nbuf = 0;
+  const bool cull = nf >= kCullMinFrontier;
+  if (cull) cull_reset(sh);
   LocalAcc acc;
   for (int32_t wi = bid; wi < nwork; wi += G) {
     const int32_t u = per_unit == 1 ? wi : wi / per_unit, share = per_unit == 1 ? 0 : wi - u * per_unit;
@@ -318,7 +351,7 @@ __device__ __forceinline__ void local_expand_body(const ExpandArgs& a, LocalShar
     const uint32_t total = local_unit_prefix(a, sh, (tid < unit && i < nf) ? a.Q[i] : -1);
     acc.edges += (tid == 0 && share == 0) ? total : 0;  // each unit's edges counted once
     local_unit_chunks(a, sh, min(unit, nf - u * unit), total, uint32_t(share) * kExpandChunk,
-                      uint32_t(per_unit) * kExpandChunk, acc);
+                      uint32_t(per_unit) * kExpandChunk, cull, acc);
   }
   local_finish(a, sh, acc, 0);
 }
@@ -339,6 +372,8 @@ __device__ __forceinline__ void bitmap_expand_body(const ExpandArgs& a, int32_t 
   const int32_t w1 = min(w0 + wpb, nwords);
   const int tid = threadIdx.x;
   if (tid == 0) sh.nbuf = 0;
+  const bool cull = a.nf >= kCullMinFrontier;
+  if (cull) cull_reset(sh);
   const int32_t w = w0 + tid;
   const bool mine = tid < wpb && w < w1;
   const uint32_t fb = mine ? a.front[w] & valid_bits(w, V) : 0u;
@@ -368,7 +403,7 @@ __device__ __forceinline__ void bitmap_expand_body(const ExpandArgs& a, int32_t 
     const int32_t v = (uint32_t(tid) < unit && i < nfront) ? w0 * 32 + int32_t(sh.list[i]) : -1;
     const uint32_t total = local_unit_prefix(a, sh, v);
     acc.edges += tid == 0 ? total : 0;
-    local_unit_chunks(a, sh, int32_t(min(unit, nfront - u0)), total, 0, kExpandChunk, acc);
+    local_unit_chunks(a, sh, int32_t(min(unit, nfront - u0)), total, 0, kExpandChunk, cull, acc);
   }
   local_finish(a, sh, acc, mu);
 }
