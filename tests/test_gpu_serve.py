@@ -80,7 +80,16 @@ def test_server_mix_equals_alone(graphs):
     for k, (gi, s, depth, _) in enumerate(queries):
         hg, g = graphs[gi]
         d = depth.cpu().numpy()
-        assert np.array_equal(d, _alone(g, s)), "query %d (graph %s, source %d) differs from alone" % (k, hg.name, s)
+        alone = _alone(g, s)
+        if not np.array_equal(d, alone):
+            want = oracle.bfs(hg, s)[0]
+            raise AssertionError(
+                "query %d (graph %s, source %d, batch of %d) differs from alone: the mix %s the oracle "
+                "(%d depths differ), alone %s it (%d differ); first differing vertices %s" % (
+                    k, hg.name, s, infos[k]["batch_size"],
+                    "matches" if np.array_equal(d, want) else "differs from", int((d != want).sum()),
+                    "matches" if np.array_equal(alone, want) else "differs from", int((alone != want).sum()),
+                    [(int(v), int(d[v]), int(alone[v]), int(want[v])) for v in np.nonzero(d != alone)[0][:6]]))
         if k % 20 == 0:
             assert np.array_equal(d, oracle.bfs(hg, s)[0]), "query %d differs from the oracle" % k
     # batching happened, and batches ran side by side on the device
@@ -90,6 +99,33 @@ def test_server_mix_equals_alone(graphs):
     overlap = any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
     _say("batches", len(b), "largest", max(len(v) for v in b.values()), "overlap", overlap)
     assert overlap, "no two batches were in flight at once"
+
+
+def test_one_buffer_across_graphs_and_kinds(graphs):
+    """What the server's pool does to a workspace: one buffer serves single-source and
+    multi-source traversals of different graphs and widths in turn, each starting on what the
+    one before left there. Every result must equal the oracle's."""
+    rnd = random.Random(12)
+    nbytes = max(max(dobfs.bfs_workspace_bytes(g), dobfs.bfs_batch_workspace_bytes(g, 64)) for _, g in graphs)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    want = {}
+    for it in range(48):
+        gi = it % len(graphs) if it < 24 else rnd.randrange(len(graphs))
+        hg, g = graphs[gi]
+        k = [1, 2, 5, 17, 64, 1][it % 6]
+        srcs = [int(x) for x in gen.sample_sources(hg, k, seed=3000 + it)]
+        depth = torch.full((k * g.V,), -7, dtype=torch.int32, device="cuda")
+        if k == 1:
+            dobfs.bfs(g, srcs[0], depth, None, None, ws)
+        else:
+            dobfs.bfs_batch(g, srcs, depth, workspace=ws)
+        d = depth.cpu().numpy().reshape(k, g.V)
+        for b, s in enumerate(srcs):
+            if (gi, s) not in want:
+                want[(gi, s)] = oracle.bfs(hg, s)[0]
+            bad = int((d[b] != want[(gi, s)]).sum())
+            assert bad == 0, "call %d (graph %s, %d sources, row %d, source %d): %d depths differ" % (
+                it, hg.name, k, b, s, bad)
 
 
 def _run_bytes(g, k):
