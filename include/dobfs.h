@@ -386,7 +386,11 @@ dobfs_status dobfs_server_create(const dobfs_graph *graphs, int32_t n_graphs,
 
 /* Queue a BFS from `source` on graphs[graph]; `depth` (device int32[V] of that
  * graph, caller-owned) receives the result and must stay valid until the
- * query is done. *id identifies the query. Never blocks on the GPU. */
+ * query is done. The slots run on streams of their own (non-blocking, not
+ * ordered after any stream of the caller's): work the caller has queued that
+ * writes or reads `depth` must be complete before the call, and the result
+ * may be read once dobfs_server_wait reports the query done. *id identifies
+ * the query. Never blocks on the GPU. */
 dobfs_status dobfs_server_submit(dobfs_server s, int32_t graph, int32_t source, int32_t *depth,
                                  uint64_t *id);
 

@@ -362,7 +362,9 @@ class Server:
         self._keep = {}
 
     def submit(self, graph: int, source: int, depth) -> int:
-        """Queue a BFS; depth is an int32 CUDA tensor of the graph's V elements."""
+        """Queue a BFS; depth is an int32 CUDA tensor of the graph's V elements. The server's
+        slots run on streams of their own, not ordered after torch's: work queued on any stream
+        that writes depth (a fill, say) must be complete before the call."""
         import torch
         g = self.graphs[graph] if 0 <= graph < len(self.graphs) else self.graphs[0]
         d = _dptr(depth, torch.int32, g.V, "depth")

@@ -43,6 +43,15 @@ def graphs():
     return out
 
 
+def _result_buffer(n, fill=-7):
+    """A query's result buffer. torch fills it on its current stream; the server's slots run on
+    streams of their own that are not ordered after that one, so the fill must be complete
+    before the buffer is submitted, or it may land on top of the server's result."""
+    t = torch.full((n,), fill, dtype=torch.int32, device="cuda")
+    torch.cuda.current_stream().synchronize()
+    return t
+
+
 def _alone(g, source):
     r = BfsRunner(g, with_parent=False)
     r.run(source)
@@ -65,7 +74,7 @@ def test_server_mix_equals_alone(graphs):
         gi = rnd.randrange(len(graphs))
         hg, g = graphs[gi]
         s = int(gen.sample_sources(hg, 1, seed=1000 + n)[0])
-        depth = torch.full((g.V,), -7, dtype=torch.int32, device="cuda")
+        depth = _result_buffer(g.V)
         queries.append((gi, s, depth, srv.submit(gi, s, depth)))
         if rnd.random() < 0.3:
             time.sleep(rnd.expovariate(1 / 0.002))  # bursts with pauses of ~2 ms on average
@@ -153,7 +162,7 @@ def test_server_memory_budget(graphs):
     qs = []
     for n in range(120):
         s = int(gen.sample_sources(hg, 1, seed=2000 + n)[0])
-        depth = torch.full((g.V,), -7, dtype=torch.int32, device="cuda")
+        depth = _result_buffer(g.V)
         qs.append((s, depth, srv.submit(0, s, depth)))
     infos = [srv.wait(q[2]) for q in qs]
     srv.close()
@@ -170,7 +179,7 @@ def test_server_memory_budget(graphs):
 def test_server_budget_below_one_source(graphs):
     hg, g = graphs[1]
     srv = dobfs.Server([g], slots=1, mem_budget=1024)
-    depth = torch.zeros(g.V, dtype=torch.int32, device="cuda")
+    depth = _result_buffer(g.V, 0)
     qid = srv.submit(0, 0, depth)
     with pytest.raises(dobfs.DobfsError) as e:
         srv.wait(qid)
@@ -183,7 +192,7 @@ def test_server_destroy_answers_queued(graphs):
     srv = dobfs.Server([g], slots=1, max_batch=4)
     qs = []
     for s in range(0, 200, 7):
-        depth = torch.full((g.V,), -7, dtype=torch.int32, device="cuda")
+        depth = _result_buffer(g.V)
         qs.append((s, depth, srv.submit(0, s, depth)))
     srv.close()  # returns after every submitted query is answered
     for s, depth, _ in qs:
@@ -193,7 +202,7 @@ def test_server_destroy_answers_queued(graphs):
 def test_server_errors(graphs):
     hg, g = graphs[0]
     srv = dobfs.Server([g])
-    depth = torch.zeros(g.V, dtype=torch.int32, device="cuda")
+    depth = _result_buffer(g.V, 0)
     for gi, s in ((1, 0), (-1, 0), (0, g.V), (0, -1)):
         with pytest.raises(dobfs.DobfsError) as e:
             srv.submit(gi, s, depth)
@@ -219,17 +228,17 @@ def test_long_graph_keeps_a_slot_free(graphs):
     g_long = upload(hg_long)
     hg, g = graphs[1]
     srv = dobfs.Server([g_long, g], slots=2, max_batch=1)
-    d0 = torch.full((g_long.V,), -7, dtype=torch.int32, device="cuda")
+    d0 = _result_buffer(g_long.V)
     first = srv.wait(srv.submit(0, 0, d0))  # its service time is now known
     assert first["t_done_ms"] - first["t_start_ms"] > 2.0
     qs = []
     for n in range(8):
         s = int(gen.sample_sources(hg_long, 1, seed=3000 + n)[0])
-        depth = torch.full((g_long.V,), -7, dtype=torch.int32, device="cuda")
+        depth = _result_buffer(g_long.V)
         qs.append((0, s, depth, srv.submit(0, s, depth)))
         for m in range(5):
             s = int(gen.sample_sources(hg, 1, seed=4000 + 5 * n + m)[0])
-            depth = torch.full((g.V,), -7, dtype=torch.int32, device="cuda")
+            depth = _result_buffer(g.V)
             qs.append((1, s, depth, srv.submit(1, s, depth)))
     infos = [srv.wait(q[3]) for q in qs]
     srv.close()
@@ -251,16 +260,16 @@ def test_long_graph_batches_only_from_eight_queued(graphs):
     hg = gen.grid2d(400, 400)
     g = upload(hg)
     srv = dobfs.Server([g], slots=1, max_batch=64)
-    d0 = torch.full((g.V,), -7, dtype=torch.int32, device="cuda")
+    d0 = _result_buffer(g.V)
     first = srv.wait(srv.submit(0, 0, d0))  # its service time is now known
     assert first["t_done_ms"] - first["t_start_ms"] > 2.0
     for count, seed in ((5, 5000), (12, 6000)):
-        blocker = torch.full((g.V,), -7, dtype=torch.int32, device="cuda")
+        blocker = _result_buffer(g.V)
         hb = srv.submit(0, hg.V - 1, blocker)  # holds the slot while the others queue up
         qs = []
         for n in range(count):
             s = int(gen.sample_sources(hg, 1, seed=seed + n)[0])
-            depth = torch.full((g.V,), -7, dtype=torch.int32, device="cuda")
+            depth = _result_buffer(g.V)
             qs.append((s, depth, srv.submit(0, s, depth)))
         srv.wait(hb)
         infos = [srv.wait(q[2]) for q in qs]
