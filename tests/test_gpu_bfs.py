@@ -323,6 +323,51 @@ def test_push_variants(graphs):
     _check(hg, runner, s, "full", want, oracle.first_parent(hg, want, s), "forced pull-push")
 
 
+def test_local_culling_wide_frontiers():
+    """Push levels whose frontier has 8192 vertices or more drop repeated targets in LDS before
+    the claim. A layered graph where every level-1 vertex shares most of its targets with
+    others, with duplicate edges and self-loops kept, pushed from frontiers of 10 000 and
+    ~20 000 vertices: depths, parents and every level's counts still match the oracle, in the
+    step loop and the persistent loop, block-local over the list and over the pull's bits."""
+    rng = np.random.default_rng(31)
+    n1, n2, n3 = 10_000, 20_000, 3_000
+    V = 1 + n1 + 10 * n2 + n3
+    l1 = np.arange(1, 1 + n1)
+    # level 2 every tenth id (isolated vertices between): a pull finds at most ~410 of them per
+    # 4096-row tile, so the push after it can run over the pull's bits
+    l2 = 1 + n1 + 10 * np.arange(n2)
+    l3 = 1 + n1 + 10 * n2 + np.arange(n3)
+    src = [np.zeros(n1, np.int64), np.repeat(l1, 8), np.repeat(l2, 3), l1[:500], l2[:700]]
+    dst = [l1, rng.choice(l2, 8 * n1), rng.choice(l3, 3 * n2), l1[:500], l2[:700]]
+    src.append(np.repeat(l1[:2000], 2))  # duplicate edges
+    dst.append(np.repeat(rng.choice(l2, 2000), 2))
+    hg = gen.from_edges(V, np.concatenate(src), np.concatenate(dst), directed=True,
+                        keep_self_loops=True, keep_duplicates=True, name="layers_culling")
+    g = upload(hg, hubs_first=True)
+    want, _ = oracle.bfs(hg, 0)
+    fp = oracle.first_parent(hg, want, 0)
+    assert int((want == 1).sum()) == n1 and int((want == 2).sum()) > 8192
+    runner = BfsRunner(g)
+    outdeg = hg.out_degree()
+    cases = [dict(mode="push_only"), dict(mode="push_only", persistent=True),
+             dict(forced_dirs=[PUSH, PUSH, PUSH, PUSH]), dict(forced_dirs=[PUSH, PULL, PUSH, PUSH]),
+             dict(forced_dirs=[PUSH, PULL, PUSH, PUSH], persistent=True)]
+    variants = set()
+    for c in cases:
+        tag = "layers %s" % c
+        runner.run(0, **c)
+        _check(hg, runner, 0, "full", want, fp, tag)
+        lv = runner.levels()
+        variants.update(r["variant"] for r in lv[2:3] if r["dir"] == PUSH)
+        for L, r in enumerate(lv):
+            assert r["nf"] == int((want == L).sum()), "%s level %d" % (tag, L)
+            assert r["n_new"] == int((want == L + 1).sum()), "%s level %d" % (tag, L)
+            if r["dir"] == PUSH:
+                assert r["edges"] == int(outdeg[want == L].sum()), "%s level %d" % (tag, L)
+    assert variants == {1, 2}, variants  # the level-2 push over the list and over the pull's bits
+    dobfs.graph_destroy(g)
+
+
 def outdeg_max_at(hg, depth, L):
     return int(hg.out_degree()[depth == L].max(initial=0))
 
