@@ -6,8 +6,9 @@ Every depth vector is compared with the oracle's over all vertices and every par
 passes the validator; under the edge-count rule the direction sequence is the oracle's. The
 benchmark's 64 RMAT-22 sources are all checked in the benchmarked mode, every Table 2 mode the
 benchmark times is checked on two of them, two sources of the edge-factor-64 RMAT-22 graph run
-under both rules, four of the lattice's 16 sources run in three modes, and every row of the
-64-source RMAT-20 launch is checked."""
+under both rules, one source of RMAT-24 with edge factor 64 (just under 2^31 entries), four of
+the lattice's 16 sources run in three modes, and every row of the 64-source RMAT-20 launch is
+checked."""
 import sys
 from concurrent.futures import ThreadPoolExecutor
 
@@ -134,6 +135,25 @@ def test_rmat22_ef64_paper_scale():
             _check(hg, s, want[s], d, p, tag, o, r.levels())
             assert st.edges_g500 == oracle.teps_edges(hg, want[s])["graph500"], tag
     dobfs.graph_destroy(g)
+
+
+def test_rmat24_ef64_near_the_int32_edge_limit():
+    """The largest graph the int32 CSR/CSC boundary admits in practice: RMAT scale 24 with edge
+    factor 64, just under 2^31 directed entries. One source in the benchmarked configuration:
+    depths exact, parents valid, the library's Graph500 edge count equal to the oracle's."""
+    hg = gen.rmat(24, 64, seed=1)
+    _say("rmat24 ef64 generated: V=%d nnz=%d" % (hg.V, hg.nnz))
+    assert 0.9 * 2**31 < hg.nnz < 2**31
+    s = int(gen.sample_sources(hg, 1, seed=2)[0])
+    g = upload(hg, hubs_first=True)
+    r = BfsRunner(g)
+    st = r.run(s, **BENCH_OPT)
+    d, p = r.result()
+    dobfs.graph_destroy(g)
+    del r
+    want, _ = oracle.bfs(hg, s)
+    _check(hg, s, want, d, p, "rmat24 ef64 source %d" % s)
+    assert st.edges_g500 == oracle.teps_edges(hg, want)["graph500"]
 
 
 def test_lattice256_sources():
