@@ -61,3 +61,12 @@ def test_traffic_records_follow_the_sources(tmp_path, monkeypatch):
     with open(csrc / "device_common.h", "a") as f:
         f.write("\n// edited\n")
     assert bench.load_traffic("step") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(bench.ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
