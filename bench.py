@@ -14,7 +14,7 @@ RMAT-20 against the same 64 queries run one at a time) and the query server (fou
 Poisson arrivals from 0.5x to 16x the sequential capacity, p50/p99 latency against first-in
 first-out plain DOBFS).
 
---profile-steps / --profile-batched run only the BFS launches (for rocprofv3); --copy-mb adds
+--profile-steps / --profile-batched / --profile-lattice run only the BFS launches (for rocprofv3); --copy-mb adds
 one device copy of known size as the reference for scaling the PMC byte counters.
 """
 import argparse
@@ -102,10 +102,10 @@ def candidates_per_level(depth, indeg_nz):
     return total - np.cumsum(cnt)  # index L -> candidates at level L
 
 
-def load_traffic(kernel: str):
+def load_traffic(kernel: str, workload: str = "rmat22"):
     """HBM traffic per launch from committed rocprofv3 PMC summaries, or None when absent or
     taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s_rmat22.json" % kernel)
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -310,7 +310,8 @@ def measure_lattice(args, heur, alpha, beta):
     for s, st in zip(srcs, stats):
         dobfs.bfs(gl, s, r.depth, r.parent, opt_t, r.ws, stream=stream, stats=st)
     torch.cuda.synchronize()
-    roof, table, _ = step_roofline(hl.V, heur, list(zip(srcs, stats)), cand, None)
+    roof, table, _ = step_roofline(hl.V, heur, list(zip(srcs, stats)), cand,
+                                   load_traffic("step", "lattice%d" % args.lattice_n))
     levels = [st.levels for st in stats]
     loops = loop_costs(gl, srcs[:4], heur, alpha, beta, 1, stream)
     tuned = None
@@ -773,6 +774,9 @@ def main():
     ap.add_argument("--profile-overlap", type=int, default=0,
                     help="only run N rounds of two 2048x2048 grid traversals from two host threads on two "
                          "streams (for a rocprofv3 kernel trace of their overlap on the device)")
+    ap.add_argument("--profile-lattice", type=int, default=0,
+                    help="only run the lattice's timed configuration from this many of its 16 sources "
+                         "(for rocprofv3), print nothing else")
     ap.add_argument("--profile-serving", action="store_true",
                     help="only run the serving workload at --serve-points (for a rocprofv3 kernel trace)")
     ap.add_argument("--serve-points", default="0.5,1,2,4,8,16",
@@ -796,6 +800,21 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+
+    if args.profile_lattice:  # the configuration of the lattice's roofline pass
+        hl = gen.lattice3d(args.lattice_n, 0.05, seed=3)
+        srcs = [int(x) for x in gen.sample_sources(hl, 16, seed=4)][: args.profile_lattice]
+        gl = upload(hl, device=0, hubs_first=not args.stored_order)
+        r = BfsRunner(gl, with_parent=True)
+        heur_l = dobfs.HEUR_EDGES if args.heuristic == "edges" else dobfs.HEUR_RATIO
+        ol = dobfs.make_options("full", heur_l, args.alpha if args.alpha is not None else (
+            1 / 14 if heur_l == dobfs.HEUR_EDGES else 0.01), args.beta if args.beta is not None else (
+            1 / 24 if heur_l == dobfs.HEUR_EDGES else 0.01), time_kernels=True)
+        for s in srcs:
+            dobfs.bfs(gl, s, r.depth, r.parent, ol, r.ws, stats=dobfs.make_stats(4096))
+            torch.cuda.synchronize()
+            log("profile lattice source %d done" % s)
+        return
 
     if args.profile_batched:
         hb = gen.rmat(args.batched_scale, args.edgefactor, seed=1)
